@@ -1,0 +1,14 @@
+"""FP64 CPU oracle for the multigrid two-point-correlation descriptor.
+
+TEST INFRASTRUCTURE ONLY.  The product path (the HIP library and its Python
+binding) must never import, link or call anything in this package; only the
+test suite, the smoke check and the benchmark's CPU-baseline leg do.
+Parity of functions listed as "parity unpinned" in their docstrings is not
+claimed.
+"""
+from . import _native
+from .s2 import (Spec, adjoint, adjoint_at_single_level, all_pairs, box, descriptor,
+                 descriptor_at, error_Z, half_box, in_half, lbfgs_direction, loss, loss_grad,
+                 penalised_loss_grad, penalty, pool, pool_adjoint, pyramid, reconstruct_lbfgsb)
+
+build = _native.build

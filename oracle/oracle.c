@@ -1,0 +1,140 @@
+/*
+ * Oracle: plain FP64 direct-summation two-point correlations and their
+ * exact adjoint.  TEST INFRASTRUCTURE ONLY -- nothing in the product path
+ * may link, load or call this file.  Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark use it.
+ *
+ * What it computes (Seibert et al., "Reconstructing random heterogeneous
+ * media through differentiable optimization"):
+ *
+ *   Two-point correlation, Sec. 3.2.1 (probability that a vector r starts in
+ *   phase a and ends in phase b), evaluated over every pixel as a starting
+ *   point, Sec. 3.2.2 (n_r = I*J realisations, linear ensemble average), with
+ *   periodic wrap-around as in the convolution of eq. (convdef), indices
+ *   written 0-based:
+ *
+ *       S_ab(r) = (1/N) * sum_x  a(x) * b((x + r) mod n)
+ *
+ *   For a soft field this is the corrected descriptor of Appendix A with the
+ *   identity threshold (Sec. 4.1 runs the method without the threshold and
+ *   states the Appendix A corrections still hold).
+ *
+ *   Adjoint (the exact derivative the method back-propagates, Sec. 3.1 and
+ *   Appendix B): for a cotangent G(r) over the displacement list,
+ *
+ *       d/da(x) sum_r G(r) S_ab(r) = (1/N) sum_r G(r) b(x + r)
+ *       d/db(y) sum_r G(r) S_ab(r) = (1/N) sum_r G(r) a(y - r)
+ *
+ * Fields are dense row-major arrays of shape n0 x n1 x n2 (axis 2 fastest);
+ * a 2-D field is passed with n0 = 1.  Displacements are K triples (r0,r1,r2).
+ * Nothing here is blocked, fused or reordered: every sum is the definition
+ * written out.  OpenMP only splits independent outputs across threads.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static inline int64_t wrap(int64_t i, int64_t n)
+{
+    int64_t m = i % n;
+    return m < 0 ? m + n : m;
+}
+
+static inline int64_t lin(int64_t i0, int64_t i1, int64_t i2,
+                          int64_t n1, int64_t n2)
+{
+    return (i0 * n1 + i1) * n2 + i2;
+}
+
+int ora_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void ora_set_num_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/* S[k] = (1/N) sum_x a[x] b[(x + r_k) mod n]  for k = 0..K-1. */
+void ora_corr(int n0, int n1, int n2, const double *a, const double *b,
+              int K, const int *r, double *S)
+{
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    int k;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (k = 0; k < K; ++k) {
+        const int r0 = r[3 * k], r1 = r[3 * k + 1], r2 = r[3 * k + 2];
+        double acc = 0.0;
+        for (int64_t i0 = 0; i0 < n0; ++i0) {
+            const int64_t j0 = wrap(i0 + r0, n0);
+            for (int64_t i1 = 0; i1 < n1; ++i1) {
+                const int64_t j1 = wrap(i1 + r1, n1);
+                for (int64_t i2 = 0; i2 < n2; ++i2) {
+                    const int64_t j2 = wrap(i2 + r2, n2);
+                    acc += a[lin(i0, i1, i2, n1, n2)] * b[lin(j0, j1, j2, n1, n2)];
+                }
+            }
+        }
+        S[k] = acc / (double)N;
+    }
+}
+
+/* Gradient of sum_k G[k] S_ab(r_k) over the whole grid:
+ *   ga[x] += (1/N) sum_k G[k] b[x + r_k]
+ *   gb[x] += (1/N) sum_k G[k] a[x - r_k]
+ * ga and gb may be the same array (auto-correlation: a == b). */
+void ora_corr_adjoint(int n0, int n1, int n2, const double *a, const double *b,
+                      int K, const int *r, const double *G,
+                      double *ga, double *gb)
+{
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    int64_t x;
+#pragma omp parallel for schedule(static)
+    for (x = 0; x < N; ++x) {
+        const int64_t i0 = x / ((int64_t)n1 * n2);
+        const int64_t i1 = (x / n2) % n1;
+        const int64_t i2 = x % n2;
+        double sa = 0.0, sb = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const int r0 = r[3 * k], r1 = r[3 * k + 1], r2 = r[3 * k + 2];
+            sa += G[k] * b[lin(wrap(i0 + r0, n0), wrap(i1 + r1, n1), wrap(i2 + r2, n2), n1, n2)];
+            sb += G[k] * a[lin(wrap(i0 - r0, n0), wrap(i1 - r1, n1), wrap(i2 - r2, n2), n1, n2)];
+        }
+        ga[x] += sa / (double)N;
+        gb[x] += sb / (double)N;
+    }
+}
+
+/* Same adjoint, evaluated only at nv listed voxels (v triples):
+ *   ga_v[m] = (1/N) sum_k G[k] b[v_m + r_k],  gb_v[m] = (1/N) sum_k G[k] a[v_m - r_k]. */
+void ora_corr_adjoint_at(int n0, int n1, int n2, const double *a, const double *b,
+                         int K, const int *r, const double *G,
+                         int nv, const int *v, double *ga_v, double *gb_v)
+{
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    int m;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (m = 0; m < nv; ++m) {
+        const int64_t i0 = v[3 * m], i1 = v[3 * m + 1], i2 = v[3 * m + 2];
+        double sa = 0.0, sb = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const int r0 = r[3 * k], r1 = r[3 * k + 1], r2 = r[3 * k + 2];
+            sa += G[k] * b[lin(wrap(i0 + r0, n0), wrap(i1 + r1, n1), wrap(i2 + r2, n2), n1, n2)];
+            sb += G[k] * a[lin(wrap(i0 - r0, n0), wrap(i1 - r1, n1), wrap(i2 - r2, n2), n1, n2)];
+        }
+        ga_v[m] = sa / (double)N;
+        gb_v[m] = sb / (double)N;
+    }
+}

@@ -1,0 +1,286 @@
+"""Oracle for the differentiable multigrid two-point-correlation descriptor.
+
+TEST INFRASTRUCTURE ONLY.  Plain, slow, FP64 CPU code that states what the
+GPU path must compute; it shares no code, header, table or helper with the
+product library and imports nothing from it.  Only the test suite, the smoke
+check and the CPU-baseline leg of the benchmark may use it.
+
+Sources in the paper (Seibert, Ambati, Rassloff, Kaestner, arXiv 2103.09686):
+  * Sec. 3.1, eqs. (dMCR-Min_Prob), (L_func_dMCR): relaxed problem over real
+    fields, loss = descriptor error + lambda * box penalty E^bc.
+  * Sec. 3.2.1: S2^{a->b}(r), probability that r starts in a and ends in b.
+  * Sec. 3.2.2: every pixel is a start point (n_r = I*J), ensemble average.
+  * Sec. 3.2.3, eq. (convdef): periodic (mod) shifts; written 0-based here.
+  * Sec. 3.3, eq. (mg) and its footnote: the same field at several
+    resolutions, level l summarising 2^{d(l-1)} pixels, descriptors weighted
+    by w_l and concatenated, all levels optimised together.
+  * Appendix A, eq. (s2rfroms2rbar): with the identity threshold the
+    corrected descriptor equals the product-form S2 used here.
+  * Appendix B: point symmetry of the auto-correlation halves the set of
+    displacement vectors; P = Q = 31 gives 1/2/3 levels at 64/128/256.
+
+Readings where the paper is silent (each one is listed in the design notes):
+  * level 1 is the finest; level l+1 is the 2^d mean pool of level l;
+  * auto-correlations use the half box H_P (r = 0 or first non-zero
+    component > 0), cross-correlations the full box B_P = [-P, P]^d;
+  * descriptor order: level-major, then pair (i <= j, lexicographic), then r
+    lexicographic with axis 0 slowest;
+  * E is the squared weighted error divided by Z = sum_l w_l^2 K_l, so that a
+    stopping threshold does not depend on the grid size;
+  * the default weight generalises w_l = 2^{l-1} (2-D) to 2^{d(l-1)/2}.
+"""
+from dataclasses import dataclass, field
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+from . import _native
+
+
+# ----------------------------------------------------------------------------
+# displacement sets and layout
+# ----------------------------------------------------------------------------
+def box(ndim: int, P: int) -> np.ndarray:
+    """All r in [-P, P]^ndim, lexicographic with axis 0 slowest (K x ndim)."""
+    axes = [np.arange(-P, P + 1)] * ndim
+    grid = np.meshgrid(*axes, indexing="ij")
+    return np.stack([g.reshape(-1) for g in grid], axis=1).astype(np.int64)
+
+
+def in_half(r) -> bool:
+    """r = 0 or its first non-zero component is positive (point-symmetry half)."""
+    for c in r:
+        if c != 0:
+            return c > 0
+    return True
+
+
+def half_box(ndim: int, P: int) -> np.ndarray:
+    """The half box H_P in lexicographic order: ((2P+1)^d + 1) / 2 vectors."""
+    b = box(ndim, P)
+    keep = np.array([in_half(r) for r in b], dtype=bool)
+    return b[keep]
+
+
+def all_pairs(C: int) -> List[Tuple[int, int]]:
+    return [(i, j) for i in range(C) for j in range(i, C)]
+
+
+@dataclass
+class Spec:
+    """Oracle-side statement of one multigrid descriptor."""
+    shape: Tuple[int, ...]            # finest-level grid, 2 or 3 axes
+    n_channels: int = 1               # explicit soft phase indicators
+    n_levels: int = 1
+    max_disp: Tuple[int, ...] = (16,)  # P per level (already valid for the level)
+    level_weight: Tuple[float, ...] = ()
+    pairs: Tuple[Tuple[int, int], ...] = ()
+
+    def __post_init__(self):
+        self.shape = tuple(int(s) for s in self.shape)
+        d = len(self.shape)
+        if len(self.max_disp) == 1 and self.n_levels > 1:
+            self.max_disp = tuple(self.max_disp) * self.n_levels
+        self.max_disp = tuple(int(p) for p in self.max_disp)
+        if not self.level_weight:
+            self.level_weight = tuple(2.0 ** (d * l / 2.0) for l in range(self.n_levels))
+        if not self.pairs:
+            self.pairs = tuple(all_pairs(self.n_channels))
+
+    @property
+    def ndim(self):
+        return len(self.shape)
+
+    def level_shape(self, l: int) -> Tuple[int, ...]:
+        return tuple(s >> l for s in self.shape)
+
+    def disp(self, l: int, pair) -> np.ndarray:
+        P = self.max_disp[l]
+        return half_box(self.ndim, P) if pair[0] == pair[1] else box(self.ndim, P)
+
+    def layout(self):
+        """List of (level, pair, offset, count) in descriptor order."""
+        out, off = [], 0
+        for l in range(self.n_levels):
+            for p in self.pairs:
+                k = len(self.disp(l, p))
+                out.append((l, p, off, k))
+                off += k
+        return out
+
+    @property
+    def K(self) -> int:
+        return sum(e[3] for e in self.layout())
+
+
+# ----------------------------------------------------------------------------
+# multigrid pyramid (Sec. 3.3)
+# ----------------------------------------------------------------------------
+def pool(f: np.ndarray) -> np.ndarray:
+    """Mean over each 2^d block of a [C][n...] field (one level coarser)."""
+    C = f.shape[0]
+    sh = f.shape[1:]
+    d = len(sh)
+    newshape = [C]
+    for s in sh:
+        newshape += [s // 2, 2]
+    g = f.reshape(newshape)
+    return g.mean(axis=tuple(2 + 2 * a for a in range(d)))
+
+
+def pool_adjoint(g: np.ndarray) -> np.ndarray:
+    """Transpose of pool: each coarse value spreads 2^-d of itself to its children."""
+    d = g.ndim - 1
+    out = g
+    for a in range(d):
+        out = np.repeat(out, 2, axis=1 + a)
+    return out / float(2 ** d)
+
+
+def pyramid(phi: np.ndarray, n_levels: int) -> List[np.ndarray]:
+    levels = [np.asarray(phi, dtype=np.float64)]
+    for _ in range(1, n_levels):
+        levels.append(pool(levels[-1]))
+    return levels
+
+
+# ----------------------------------------------------------------------------
+# descriptor, error, gradient
+# ----------------------------------------------------------------------------
+def descriptor(phi: np.ndarray, spec: Spec) -> np.ndarray:
+    """S for one field phi[C][n...]: S_ij^(l)(r) = (1/N_l) sum_x phi_i(x) phi_j(x + r)."""
+    lv = pyramid(phi, spec.n_levels)
+    out = np.zeros(spec.K, np.float64)
+    for (l, (i, j), off, k) in spec.layout():
+        out[off:off + k] = _native.corr(lv[l][i], lv[l][j], spec.disp(l, (i, j)))
+    return out
+
+
+def level_weights_per_entry(spec: Spec) -> np.ndarray:
+    w = np.zeros(spec.K, np.float64)
+    for (l, _, off, k) in spec.layout():
+        w[off:off + k] = spec.level_weight[l]
+    return w
+
+
+def error_Z(spec: Spec) -> float:
+    """Z = sum_l w_l^2 K_l (entries of all pairs at level l)."""
+    w = level_weights_per_entry(spec)
+    return float(np.sum(w * w))
+
+
+def loss(S: np.ndarray, S_des: np.ndarray, spec: Spec):
+    """E = (1/Z) sum w_l^2 (S - S_des)^2 and its cotangent G = dE/dS."""
+    w2 = level_weights_per_entry(spec) ** 2
+    Z = float(np.sum(w2))
+    diff = np.asarray(S, np.float64) - np.asarray(S_des, np.float64)
+    E = float(np.sum(w2 * diff * diff) / Z)
+    G = 2.0 * w2 * diff / Z
+    return E, G
+
+
+def adjoint(phi: np.ndarray, G: np.ndarray, spec: Spec) -> np.ndarray:
+    """d/dphi of sum_k G[k] S[k] (all levels, all pairs), shape of phi."""
+    lv = pyramid(phi, spec.n_levels)
+    grads = [np.zeros_like(f) for f in lv]
+    for (l, (i, j), off, k) in spec.layout():
+        ga, gb = _native.corr_adjoint(lv[l][i], lv[l][j], spec.disp(l, (i, j)), G[off:off + k])
+        grads[l][i] += ga
+        grads[l][j] += gb
+    acc = grads[-1]
+    for l in range(spec.n_levels - 2, -1, -1):
+        acc = grads[l] + pool_adjoint(acc)
+    return acc
+
+
+def loss_grad(phi: np.ndarray, S_des: np.ndarray, spec: Spec):
+    S = descriptor(phi, spec)
+    E, G = loss(S, S_des, spec)
+    return E, adjoint(phi, G, spec), S
+
+
+def descriptor_at(phi: np.ndarray, spec: Spec, level: int, pair, r: np.ndarray) -> np.ndarray:
+    """S at an arbitrary list of displacements of one (level, pair)."""
+    lv = pyramid(phi, level + 1)
+    return _native.corr(lv[level][pair[0]], lv[level][pair[1]], np.asarray(r))
+
+
+def adjoint_at_single_level(phi: np.ndarray, G: np.ndarray, spec: Spec, vox: np.ndarray) -> np.ndarray:
+    """Gradient at listed finest-level voxels for a single-level spec: [C][nv]."""
+    if spec.n_levels != 1:
+        raise ValueError("sampled adjoint is defined here for one level only")
+    out = np.zeros((spec.n_channels, len(vox)), np.float64)
+    for (l, (i, j), off, k) in spec.layout():
+        ga, gb = _native.corr_adjoint_at(phi[i], phi[j], spec.disp(l, (i, j)), G[off:off + k], vox)
+        out[i] += ga
+        out[j] += gb
+    return out
+
+
+# ----------------------------------------------------------------------------
+# box penalty (Sec. 3.1): E^bc = sum [ (M-1)H(M-1)/N + (-M)H(-M)/N ]^2, H(0) = 0
+# ----------------------------------------------------------------------------
+def penalty(phi: np.ndarray, lo: float = 0.0, hi: float = 1.0):
+    """E^bc and its gradient for every explicit channel; N = voxels per channel."""
+    phi = np.asarray(phi, np.float64)
+    N = float(np.prod(phi.shape[1:]))
+    over = np.where(phi - hi > 0, phi - hi, 0.0)
+    under = np.where(lo - phi > 0, lo - phi, 0.0)
+    t = over / N + under / N
+    Ebc = float(np.sum(t * t))
+    dt = np.where(phi - hi > 0, 1.0 / N, 0.0) - np.where(lo - phi > 0, 1.0 / N, 0.0)
+    return Ebc, 2.0 * t * dt
+
+
+def penalised_loss_grad(phi, S_des, spec, kappa=1.0, lo=0.0, hi=1.0):
+    """L = E + lambda E^bc with lambda = kappa * E held constant in the gradient."""
+    E, g, S = loss_grad(phi, S_des, spec)
+    Ebc, gbc = penalty(phi, lo, hi)
+    lam = kappa * E
+    return E + lam * Ebc, g + lam * gbc, E
+
+
+# ----------------------------------------------------------------------------
+# optimiser references
+# ----------------------------------------------------------------------------
+def lbfgs_direction(g: np.ndarray, s_hist: Sequence[np.ndarray], y_hist: Sequence[np.ndarray]):
+    """Two-loop recursion (Nocedal & Wright, Alg. 7.4), FP64: returns -H g.
+
+    s_hist / y_hist are ordered oldest first.  Initial scaling
+    gamma = s'y / y'y of the newest pair (identity if the history is empty)."""
+    q = np.array(g, np.float64, copy=True).reshape(-1)
+    m = len(s_hist)
+    alpha = np.zeros(m)
+    rho = np.zeros(m)
+    for i in range(m - 1, -1, -1):
+        s, y = s_hist[i].reshape(-1), y_hist[i].reshape(-1)
+        rho[i] = 1.0 / float(np.dot(y, s))
+        alpha[i] = rho[i] * float(np.dot(s, q))
+        q -= alpha[i] * y
+    if m:
+        s, y = s_hist[-1].reshape(-1), y_hist[-1].reshape(-1)
+        q *= float(np.dot(s, y)) / float(np.dot(y, y))
+    for i in range(m):
+        s, y = s_hist[i].reshape(-1), y_hist[i].reshape(-1)
+        beta = rho[i] * float(np.dot(y, q))
+        q += (alpha[i] - beta) * s
+    return -q.reshape(np.shape(g))
+
+
+def reconstruct_lbfgsb(S_des, spec: Spec, phi0, maxiter=100, maxcor=10, lo=0.0, hi=1.0):
+    """Reference reconstruction: SciPy L-BFGS-B on the oracle's (E, dE/dphi) in FP64,
+    bounds [lo, hi] on every voxel.  Returns (phi, E_final, n_iter, n_eval)."""
+    from scipy.optimize import minimize
+
+    shape = np.shape(phi0)
+    counter = {"n": 0}
+
+    def fun(x):
+        counter["n"] += 1
+        E, g, _ = loss_grad(x.reshape(shape), S_des, spec)
+        return E, g.reshape(-1)
+
+    res = minimize(fun, np.asarray(phi0, np.float64).reshape(-1), jac=True, method="L-BFGS-B",
+                   bounds=[(lo, hi)] * int(np.prod(shape)),
+                   options={"maxiter": maxiter, "maxcor": maxcor, "ftol": 0.0, "gtol": 0.0})
+    return res.x.reshape(shape), float(res.fun), int(res.nit), counter["n"]

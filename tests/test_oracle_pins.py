@@ -1,0 +1,318 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against a route that does not use its formula:
+the paper's own convolve-threshold-reduce pipeline with explicit masks
+(Sec. 3.2.3, eq. convdef, 1-based indices exactly as printed), the Appendix A
+correction, probability counting on binary fields (Sec. 3.2.1), closed forms,
+invariants (point symmetry, sum rule), statistics of noise and of the Boolean
+model, exact finite differences of a quadratic map, and the adjoint identity.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2103_09686_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
+
+
+# ---------------------------------------------------------------------------
+# the paper's pipeline, written from Sec. 3.2.3 with explicit masks
+# ---------------------------------------------------------------------------
+def paper_mask(P, Q, p, q):
+    """Mask for r = (p, q): 1/2 at the tail (origin) and at the tip of r, a single 1
+    for r = 0 (Sec. 3.2.3 and footnote).  Indexed [r + P, s + Q]."""
+    m = np.zeros((2 * P + 1, 2 * Q + 1))
+    m[0 + P, 0 + Q] += 0.5
+    m[p + P, q + Q] += 0.5
+    return m
+
+
+def paper_convolve(M, m, P, Q):
+    """(M * m)_{ij} = sum_{k,l,r,s} M_kl delta^k_{mod_I(i+r)+1} delta^l_{mod_J(j+s)+1} m_rs,
+    eq. (convdef) with its 1-based indices i = 1..I, k = 1..I."""
+    I, J = M.shape
+    out = np.zeros((I, J))
+    for i in range(1, I + 1):
+        for j in range(1, J + 1):
+            acc = 0.0
+            for r in range(-P, P + 1):
+                for s in range(-Q, Q + 1):
+                    w = m[r + P, s + Q]
+                    if w == 0.0:
+                        continue
+                    k = (i + r) % I + 1
+                    l = (j + s) % J + 1
+                    acc += M[k - 1, l - 1] * w
+            out[i - 1, j - 1] = acc
+    return out
+
+
+def paper_S_bar_identity(M, P, Q, p, q):
+    """Quadratic reduction of the identity-thresholded ensemble (Sec. 3.2.2, eq. s3 with
+    r = p, s = q), i.e. S-bar for f_t(x) = x (Sec. 4.1)."""
+    e = paper_convolve(M, paper_mask(P, Q, p, q), P, Q)
+    return float(np.sum(e * e) / M.size)
+
+
+def appendix_a_correction(S_bar_r, S_bar_0, f_half, r_is_zero):
+    """eq. (s2rfroms2rbar)."""
+    if r_is_zero:
+        return S_bar_r
+    return (S_bar_r - 2 * f_half ** 2 * S_bar_0) / (1 - 2 * f_half ** 2)
+
+
+def test_identity_threshold_pipeline_equals_oracle(ora):
+    """Product-form S2 == paper pipeline with f_t(x)=x + Appendix A correction (f(1/2)=1/2)."""
+    rng = np.random.default_rng(3)
+    for shape in [(8, 8), (5, 7)]:
+        M = rng.random(shape)
+        P, Q = 2, 3
+        rs = ora.box(2, 2)
+        rs = rs[np.abs(rs[:, 1]) <= Q]
+        S_ora = ora._native.corr(M, M, rs)
+        Sb0 = paper_S_bar_identity(M, P, Q, 0, 0)
+        for k, (p, q) in enumerate(rs):
+            Sb = paper_S_bar_identity(M, P, Q, int(p), int(q))
+            S_paper = appendix_a_correction(Sb, Sb0, 0.5, p == 0 and q == 0)
+            assert abs(S_paper - S_ora[k]) < 1e-14
+
+
+def test_hard_threshold_pipeline_equals_oracle_on_binary(ora):
+    """Binary field: convolve, hard threshold H(x - 0.75), linear reduction gives the
+    exact S2 (Sec. 3.2.3), and S(0) = volume fraction (Sec. 3.1, f~_C(binary) = f_C)."""
+    rng = np.random.default_rng(4)
+    M = (rng.random((8, 8)) < 0.4).astype(np.float64)
+    P = Q = 3
+    rs = ora.box(2, 3)
+    S_ora = ora._native.corr(M, M, rs)
+    for k, (p, q) in enumerate(rs):
+        e = paper_convolve(M, paper_mask(P, Q, int(p), int(q)), P, Q)
+        e = (e - 0.75 > 0).astype(np.float64)
+        assert abs(e.sum() / M.size - S_ora[k]) < 1e-15
+    zero = np.flatnonzero((rs == 0).all(axis=1))[0]
+    assert S_ora[zero] == pytest.approx(M.mean(), abs=1e-15)
+
+
+def test_probability_counting_cross_3d(ora):
+    """S2^{a->b}(r) on binary 3-D fields = fraction of start points x with x in phase a
+    and x + r in phase b (Sec. 3.2.1), counted by brute force."""
+    rng = np.random.default_rng(5)
+    a = (rng.random((4, 4, 4)) < 0.5).astype(np.float64)
+    b = (rng.random((4, 4, 4)) < 0.3).astype(np.float64)
+    rs = ora.box(3, 1)
+    S = ora._native.corr(a, b, rs)
+    for k, r in enumerate(rs):
+        hits = 0
+        for x in itertools.product(range(4), repeat=3):
+            y = tuple((x[t] + r[t]) % 4 for t in range(3))
+            hits += int(a[x] == 1 and b[y] == 1)
+        assert S[k] == hits / 64.0
+
+
+def test_symmetry_and_sum_rule(ora):
+    rng = np.random.default_rng(6)
+    a, b = rng.random((6, 10)), rng.random((6, 10))
+    rs = ora.box(2, 2)
+    Sab = ora._native.corr(a, b, rs)
+    Sba_neg = ora._native.corr(b, a, -rs)
+    Saa = ora._native.corr(a, a, rs)
+    Saa_neg = ora._native.corr(a, a, -rs)
+    np.testing.assert_allclose(Sab, Sba_neg, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(Saa, Saa_neg, rtol=0, atol=1e-15)
+    # sum over all N displacements = N mu_a mu_b
+    allr = np.array([(i, j) for i in range(6) for j in range(10)])
+    tot = ora._native.corr(a, b, allr).sum()
+    assert tot == pytest.approx(60 * a.mean() * b.mean(), rel=1e-13)
+
+
+def test_closed_forms(ora):
+    rs = ora.box(2, 3)
+    c = np.full((8, 8), 0.37)
+    np.testing.assert_allclose(ora._native.corr(c, c, rs), 0.37 ** 2, rtol=1e-15)
+    hot = np.zeros((8, 8))
+    hot[2, 5] = 1.0
+    S = ora._native.corr(hot, hot, rs)
+    expect = np.where((rs == 0).all(axis=1), 1.0 / 64, 0.0)
+    np.testing.assert_array_equal(S, expect)
+    cb = synth.checkerboard((8, 8), 1)[0]
+    S = ora._native.corr(cb, cb, rs)
+    np.testing.assert_array_equal(S, np.where(rs.sum(axis=1) % 2 == 0, 0.5, 0.0))
+
+
+def test_noise_statistics(ora):
+    """U(0,1) i.i.d.: S(0) ~ 1/3 and S(r != 0) - mean^2 within 6 sigma^2/sqrt(N)."""
+    f = synth.uniform((64, 64), seed=11)[0]
+    rs = ora.half_box(2, 6)
+    S = ora._native.corr(f, f, rs)
+    N = f.size
+    zero = np.flatnonzero((rs == 0).all(axis=1))[0]
+    # S(0) = mean(f^2); Var(f^2) = 1/5 - 1/9 for U(0,1)
+    assert abs(S[zero] - 1.0 / 3.0) < 6 * math.sqrt(1 / 5.0 - 1 / 9.0) / math.sqrt(N)
+    rest = np.delete(S, zero)
+    sigma2 = 1.0 / 12.0
+    assert np.max(np.abs(rest - f.mean() ** 2)) < 6 * sigma2 / math.sqrt(N)
+
+
+def test_boolean_model_law(ora):
+    """Overlapping disks with n uniform pixel centres: E[S2(r)] =
+    1 - 2 (1-|A|/N)^n + (1 - |A u (A+r)|/N)^n (textbook Boolean law, exact for lattice
+    centres).  One large realisation must match within a statistical tolerance."""
+    shape = (256, 256)
+    radius = 4
+    f, vf = synth.boolean_spheres(shape, radius, 0.30, seed=0)
+    f = f[0]
+    offs = [(i, j) for i in range(-radius, radius + 1) for j in range(-radius, radius + 1)
+            if i * i + j * j <= radius * radius]
+    A = set(offs)
+    N = f.size
+    # estimate n from the realised coverage: q = (1 - |A|/N)^n
+    n = math.log(1 - vf) / math.log(1 - len(A) / N)
+    rs = np.array([(0, 0), (0, 1), (1, 1), (0, 3), (2, 3), (0, 6), (5, 5), (0, 12), (9, 9)])
+    S = ora._native.corr(f, f, rs)
+    for k, r in enumerate(rs):
+        union = len(A | {(i + r[0], j + r[1]) for (i, j) in A})
+        law = 1 - 2 * (1 - len(A) / N) ** n + (1 - union / N) ** n
+        assert abs(S[k] - law) < 0.012, (r, S[k], law)
+    assert S[0] == pytest.approx(vf, abs=1e-15)
+
+
+def test_adjoint_exact_fd_and_dot_product(ora):
+    """S is bilinear, so central differences of sum G*S are exact up to rounding;
+    and <J v, u> = <v, J^T u> with J v = corr(v_a, b) + corr(a, v_b)."""
+    rng = np.random.default_rng(7)
+    a, b = rng.random((6, 8)), rng.random((6, 8))
+    rs = ora.box(2, 2)
+    G = rng.standard_normal(len(rs))
+    ga, gb = ora._native.corr_adjoint(a, b, rs, G)
+    h = 0.5
+    for x in [(0, 0), (3, 5), (5, 7)]:
+        ap, am = a.copy(), a.copy()
+        ap[x] += h
+        am[x] -= h
+        fd = (G @ ora._native.corr(ap, b, rs) - G @ ora._native.corr(am, b, rs)) / (2 * h)
+        assert fd == pytest.approx(ga[x], abs=1e-14)
+        bp, bm = b.copy(), b.copy()
+        bp[x] += h
+        bm[x] -= h
+        fd = (G @ ora._native.corr(a, bp, rs) - G @ ora._native.corr(a, bm, rs)) / (2 * h)
+        assert fd == pytest.approx(gb[x], abs=1e-14)
+    va, vb = rng.standard_normal(a.shape), rng.standard_normal(b.shape)
+    Jv = ora._native.corr(va, b, rs) + ora._native.corr(a, vb, rs)
+    assert Jv @ G == pytest.approx(np.sum(va * ga) + np.sum(vb * gb), rel=1e-12)
+    # sampled adjoint agrees with the dense one
+    vox = np.array([[0, 0], [3, 5], [5, 7]])
+    sa, sb = ora._native.corr_adjoint_at(a, b, rs, G, vox)
+    np.testing.assert_allclose(sa, ga[tuple(vox.T)], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(sb, gb[tuple(vox.T)], rtol=0, atol=1e-15)
+
+
+def test_half_box_counts_and_order(ora):
+    for d in (2, 3):
+        for P in (0, 1, 2, 5):
+            H = ora.half_box(d, P)
+            B = ora.box(d, P)
+            assert len(B) == (2 * P + 1) ** d
+            assert len(H) == ((2 * P + 1) ** d + 1) // 2
+            # H and -H cover B exactly once (apart from r = 0)
+            s = {tuple(r) for r in H} | {tuple(-r) for r in H}
+            assert s == {tuple(r) for r in B}
+            # lexicographic, axis 0 slowest
+            assert [tuple(r) for r in B] == sorted(tuple(r) for r in B)
+
+
+def test_pool_adjoint_and_block_constant(ora):
+    rng = np.random.default_rng(8)
+    x = rng.random((2, 8, 8, 4))
+    y = rng.random((2, 4, 4, 2))
+    assert np.sum(ora.pool(x) * y) == pytest.approx(np.sum(x * ora.pool_adjoint(y)), rel=1e-14)
+    # a field constant on 2x2 blocks: level-2 S(r) = level-1 S(2r)
+    c = rng.random((1, 8, 8))
+    f = np.repeat(np.repeat(c, 2, axis=1), 2, axis=2)
+    spec = ora.Spec(shape=(16, 16), n_levels=2, max_disp=(6, 3))
+    S = ora.descriptor(f, spec)
+    lay = spec.layout()
+    S1 = S[lay[0][2]:lay[0][2] + lay[0][3]]
+    S2 = S[lay[1][2]:lay[1][2] + lay[1][3]]
+    H1 = [tuple(r) for r in ora.half_box(2, 6)]
+    for k, r in enumerate(ora.half_box(2, 3)):
+        assert S2[k] == pytest.approx(S1[H1.index(tuple(2 * r))], abs=1e-15)
+
+
+def test_paper_level_rule_and_weights(ora):
+    """Appendix B: P = 31 gives 1/2/3 levels at 64/128/256 (coarsest side 2(P+1));
+    Sec. 3.3: w_l = 2^(l-1) in 2-D."""
+    g = json.load(open(GOLD))
+    P = g["max_correlation_length"]["P"]
+    for n, L in g["levels_for_size_at_P31"].items():
+        if n == "cite":
+            continue
+        n = int(n)
+        assert 1 + int(round(math.log2(n / (2 * (P + 1))))) == L
+        assert (n >> (L - 1)) == 2 * (P + 1)
+    spec = ora.Spec(shape=(256, 256), n_levels=3, max_disp=(31,))
+    assert spec.level_weight == (1.0, 2.0, 4.0)
+    assert [spec.level_weight[i] for i in range(3)] == [g["level_weight_2d"]["l=%d" % l] for l in (1, 2, 3)]
+
+
+def test_loss_gradient_fd_and_stationary_target(ora):
+    """dE/dphi (two levels, two channels, cross pair) against central differences,
+    and dE/dphi = 0 exactly at the target field."""
+    rng = np.random.default_rng(9)
+    spec = ora.Spec(shape=(8, 8), n_channels=2, n_levels=2, max_disp=(3, 1))
+    tgt = (rng.random((2, 8, 8)) < 0.3).astype(np.float64)
+    S_des = ora.descriptor(tgt, spec)
+    E0, g0, _ = ora.loss_grad(tgt, S_des, spec)
+    assert E0 == 0.0 and np.all(g0 == 0.0)
+    phi = rng.random((2, 8, 8))
+    E, g, _ = ora.loss_grad(phi, S_des, spec)
+    h = 1e-3
+    for idx in [(0, 0, 0), (1, 3, 4), (0, 7, 2), (1, 5, 5)]:
+        p, m = phi.copy(), phi.copy()
+        p[idx] += h
+        m[idx] -= h
+        fd = (ora.loss_grad(p, S_des, spec)[0] - ora.loss_grad(m, S_des, spec)[0]) / (2 * h)
+        assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-12)
+
+
+def test_loss_normalisation(ora):
+    """E with every residual equal to delta is delta^2 (Z normalisation); G = dE/dS."""
+    spec = ora.Spec(shape=(16, 16), n_channels=2, n_levels=2, max_disp=(3, 2))
+    S = np.linspace(0, 1, spec.K)
+    E, G = ora.loss(S + 0.01, S, spec)
+    assert E == pytest.approx(1e-4, rel=1e-12)
+    w2 = np.concatenate([np.full(k, spec.level_weight[l] ** 2) for (l, _, _, k) in spec.layout()])
+    np.testing.assert_allclose(G, 2 * w2 * 0.01 / np.sum(w2), rtol=1e-12)
+
+
+def test_penalty(ora):
+    """E^bc as printed in Sec. 3.1, H(0) = 0: zero (with zero gradient) on [0,1]."""
+    phi = np.array([[[-0.5, 0.0, 0.3], [1.0, 1.25, 0.9]]])
+    N = 6.0
+    E, g = ora.penalty(phi)
+    assert E == pytest.approx((0.5 / N) ** 2 + (0.25 / N) ** 2, rel=1e-14)
+    assert g[0, 0, 1] == 0.0 and g[0, 1, 0] == 0.0 and g[0, 0, 2] == 0.0
+    assert g[0, 0, 0] == pytest.approx(2 * (0.5 / N) * (-1 / N))
+    assert g[0, 1, 1] == pytest.approx(2 * (0.25 / N) * (1 / N))
+
+
+def test_lbfgs_two_loop_equals_dense_bfgs(ora):
+    """Two-loop recursion == dense BFGS inverse update from gamma*I (Nocedal & Wright 6.17)."""
+    rng = np.random.default_rng(10)
+    n, m = 12, 5
+    A = rng.standard_normal((n, n))
+    A = A @ A.T + n * np.eye(n)
+    s_hist = [rng.standard_normal(n) for _ in range(m)]
+    y_hist = [A @ s for s in s_hist]
+    g = rng.standard_normal(n)
+    gamma = (s_hist[-1] @ y_hist[-1]) / (y_hist[-1] @ y_hist[-1])
+    H = gamma * np.eye(n)
+    for s, y in zip(s_hist, y_hist):
+        rho = 1.0 / (y @ s)
+        V = np.eye(n) - rho * np.outer(y, s)
+        H = V.T @ H @ V + rho * np.outer(s, s)
+    np.testing.assert_allclose(ora.lbfgs_direction(g, s_hist, y_hist), -H @ g, rtol=1e-10, atol=1e-12)

@@ -1,0 +1,181 @@
+/*
+ * dmcr.h -- C ABI of libdmcr, the MI355X (gfx950) library for the
+ * differentiable multigrid two-point-correlation descriptor of
+ * Seibert, Ambati, Rassloff, Kaestner, "Reconstructing random heterogeneous
+ * media through differentiable optimization" (arXiv 2103.09686).
+ *
+ * The problem it serves (Sec. 3.1, eq. dMCR-Min_Prob): find a real-valued
+ * field M~ minimising L(M~) = E(M~) + lambda E^bc(M~), where the descriptor
+ * D~ = f~_C(M~) (eq. fctilde) is the multigrid concatenation of eq. (mg) of
+ * two-point correlations, and the box 0 <= M~ <= 1 is the bound of Sec. 3.1.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Fields.  A batch of B independent problems.  Each holds C explicit soft
+ *   phase indicators phi_c (C = number of phases - 1; the matrix phase is
+ *   1 - sum_c phi_c and carries no extra information, Sec. 3.2.1).  Layout
+ *   float32 [B][C][n0][n1] (2-D) or [B][C][n0][n1][n2] (3-D), last axis
+ *   contiguous, every axis a power of two.
+ * Levels.  Level 0 is the caller's field; level l+1 is the 2^d mean pool of
+ *   level l (Sec. 3.3: a coarse pixel summarises 2^{d} finer ones).
+ * Correlations.  For level l, pair (i, j) and displacement r:
+ *       S_ij^(l)(r) = (1/N_l) sum_x phi_i^(l)(x) phi_j^(l)((x + r) mod n_l)
+ *   (Sec. 3.2.1-3.2.2 with the periodic shift of eq. convdef; for soft
+ *   fields this is the Appendix A corrected descriptor with the identity
+ *   threshold used in Sec. 4.1).  Auto pairs (i == i) use the half box H_P
+ *   (r = 0 or first non-zero component > 0; point symmetry, Appendix B),
+ *   cross pairs the full box [-P, P]^d.
+ * Descriptor order.  Level-major (finest first), then pair in the order of
+ *   spec.pairs, then r lexicographic with axis 0 slowest.  Values are
+ *   unweighted; the level weights w_l (eq. mg) enter only the error.
+ * Error.  E = (1/Z) sum_l w_l^2 sum_{pairs} sum_r (S - S_target)^2,
+ *   Z = sum_l w_l^2 K_l (K_l = entries of level l): the squared form of the
+ *   descriptor distance of Sec. 3.1, normalised per entry.
+ * Memory.  The caller owns every buffer.  Pointers marked "device" must be
+ *   device memory of the current HIP device; the library never allocates on
+ *   these calls: scratch comes from the caller's workspace `ws` of at least
+ *   dmcr_workspace_size() bytes (256-byte aligned).
+ * Streams.  Every call except dmcr_reconstruct is asynchronous on `stream`
+ *   and returns before the work finishes; device faults surface on a later
+ *   call or synchronisation.  Calls that share a workspace must not overlap.
+ * Errors.  Arguments are validated before any launch; on error nothing is
+ *   launched and a negative dmcr_status is returned.  No call aborts.
+ */
+#ifndef DMCR_H
+#define DMCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DMCR_OK = 0,
+    DMCR_EINVAL = -1,        /* bad argument: null pointer, bad shape, P too large, ... */
+    DMCR_ENOMEM = -2,        /* workspace smaller than dmcr_workspace_size()            */
+    DMCR_EUNSUPPORTED = -3,  /* valid problem this build does not handle (e.g. DIRECT
+                                path with a halo tile larger than LDS)                  */
+    DMCR_EDEVICE = -4,       /* a HIP call failed (launch or runtime error)             */
+    DMCR_ENONFINITE = -5,    /* reconstruct: loss or gradient became NaN / Inf          */
+    DMCR_NOT_CONVERGED = 1   /* reconstruct: iteration budget spent before tolerance    */
+} dmcr_status;
+
+enum { DMCR_MAX_LEVELS = 8, DMCR_MAX_CHANNELS = 4, DMCR_MAX_PAIRS = 10 };
+
+/* Evaluation path.  AUTO picks per level; FFT uses the convolution theorem
+ * (Stockham transforms in LDS); DIRECT sums shifted products over an LDS
+ * tile with a halo of P (the paper's own convolve-and-reduce, Sec. 3.2.3). */
+enum { DMCR_PATH_AUTO = 0, DMCR_PATH_FFT = 1, DMCR_PATH_DIRECT = 2 };
+
+/* spec.flags */
+enum {
+    DMCR_FLAG_RECOMPUTE = 1  /* dmcr_loss_grad recomputes the forward spectra in the
+                                adjoint instead of keeping them between the two halves */
+};
+
+typedef struct {
+    int32_t ndim;                          /* 2 or 3                                  */
+    int32_t shape[3];                      /* finest level, powers of two, >= 2       */
+    int32_t n_channels;                    /* C, 1..DMCR_MAX_CHANNELS                 */
+    int32_t n_levels;                      /* 1..DMCR_MAX_LEVELS; every axis must be
+                                              divisible by 2^(n_levels-1)              */
+    int32_t max_disp[DMCR_MAX_LEVELS];     /* P_l, 0 <= P_l <= min_axis(n_l)/2 - 1     */
+    double  level_weight[DMCR_MAX_LEVELS]; /* w_l (eq. mg); must be > 0               */
+    int32_t n_pairs;                       /* 0 = all pairs i <= j in lexicographic order */
+    int32_t pairs[2 * 16];                 /* (i, j) with i <= j, used if n_pairs > 0 */
+    int32_t path;                          /* DMCR_PATH_*                             */
+    int32_t flags;                         /* DMCR_FLAG_*                             */
+} dmcr_spec;
+
+/* Box handling for dmcr_reconstruct (Sec. 3.1). */
+enum { DMCR_BOUNDS_NONE = 0, DMCR_BOUNDS_PROJECT = 1, DMCR_BOUNDS_PENALTY = 2 };
+typedef struct {
+    double lo, hi;   /* the box, normally [0, 1]                                          */
+    int32_t mode;    /* PROJECT: iterates are clipped to [lo, hi] and the search direction
+                        is restricted to free variables; PENALTY: L = E + lambda E^bc with
+                        E^bc as printed in Sec. 3.1 and lambda = kappa E held constant in
+                        the gradient                                                       */
+    double kappa;
+} dmcr_bounds;
+
+typedef struct {
+    int32_t m;          /* L-BFGS history length (1..32)                       */
+    int32_t max_iter;   /* iteration budget                                    */
+    int32_t max_ls;     /* evaluations per line search                        */
+    double  tol_derr;   /* stop when E <= tol_derr                             */
+    double  c1, c2;     /* Wolfe constants (sufficient decrease, curvature)    */
+} dmcr_opt;
+
+typedef struct {
+    double  final_E;     /* E of the returned field                           */
+    double  final_derr;  /* same quantity (the weighted mean squared error)   */
+    int32_t iters;       /* iterations taken                                  */
+    int32_t evals;       /* loss/gradient evaluations                         */
+    int32_t why;         /* dmcr_status for this batch element                */
+} dmcr_result;
+
+/* Number of descriptor entries K (all levels and pairs); < 0: dmcr_status. */
+int64_t dmcr_descriptor_size(const dmcr_spec *spec);
+
+/* Offsets of each (level, pair) block in descriptor order: writes
+ * n_levels * n_pairs + 1 values (the last one is K) to host array `offsets`. */
+dmcr_status dmcr_descriptor_offsets(const dmcr_spec *spec, int64_t *offsets);
+
+/* Workspace bytes needed by every call below for this spec and batch size. */
+dmcr_status dmcr_workspace_size(const dmcr_spec *spec, int32_t batch, size_t *bytes);
+
+/* a1 -- multigrid pyramid (Sec. 3.3): writes levels 1..L-1 of phi, each the 2^d
+ * mean pool of the previous, concatenated level after level into `levels`
+ * (device, float32, sum_l B*C*N_l values). */
+dmcr_status dmcr_pyramid(const dmcr_spec *spec, int32_t batch, const float *phi, float *levels,
+                         hipStream_t stream);
+
+/* Forward descriptor (Sec. 3.2-3.3): phi (device [B][C][n...]) -> S (device
+ * float32 [B][K]). */
+dmcr_status dmcr_descriptor_forward(const dmcr_spec *spec, int32_t batch, const float *phi,
+                                    float *S, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint (the gradient the method back-propagates through every level at
+ * once, Sec. 3.3): grad = d/dphi sum_{b,k} dS[b][k] S[b][k], overwriting
+ * grad (device [B][C][n...]).  The spectra of phi are recomputed. */
+dmcr_status dmcr_descriptor_adjoint(const dmcr_spec *spec, int32_t batch, const float *phi,
+                                    const float *dS, float *grad, void *ws, size_t ws_bytes,
+                                    hipStream_t stream);
+
+/* a5 -- error and cotangent: E[b] (device float64) and G = dE/dS (device
+ * float32 [B][K]) from S (device float32 [B][K]) and S_target (device
+ * float64 [B][K]); the sum is taken in float64 in a fixed order. */
+dmcr_status dmcr_error_cotangent(const dmcr_spec *spec, int32_t batch, const float *S,
+                                 const double *S_target, double *E, float *G, void *ws,
+                                 size_t ws_bytes, hipStream_t stream);
+
+/* One optimiser evaluation: forward, error, adjoint.  E (device float64 [B]),
+ * grad (device float32 [B][C][n...], overwritten). */
+dmcr_status dmcr_loss_grad(const dmcr_spec *spec, int32_t batch, const float *phi,
+                           const double *S_target, double *E, float *grad, void *ws,
+                           size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes for dmcr_reconstruct (includes dmcr_workspace_size). */
+dmcr_status dmcr_reconstruct_workspace_size(const dmcr_spec *spec, int32_t batch,
+                                            const dmcr_opt *opt, size_t *bytes);
+
+/* Reconstruction (Sec. 3, Fig. 1 loop): minimise E (+ penalty) over phi with
+ * L-BFGS, starting from phi_inout (device [B][C][n...], overwritten with the
+ * result).  S_target: device float64 [B][K].  results: host array of B.
+ * Blocking: synchronises `stream` before returning.  Returns DMCR_OK if every
+ * element reached tol_derr, DMCR_NOT_CONVERGED if some did not, or an error. */
+dmcr_status dmcr_reconstruct(const dmcr_spec *spec, int32_t batch, const double *S_target,
+                             const dmcr_bounds *bounds, const dmcr_opt *opt, float *phi_inout,
+                             dmcr_result *results, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Static description of a status code. */
+const char *dmcr_status_string(dmcr_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMCR_H */

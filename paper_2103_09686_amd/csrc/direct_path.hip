@@ -1,0 +1,307 @@
+// Direct (shifted-product) path for short correlation ranges: the paper's own
+// convolve-and-reduce of Sec. 3.2.3 (eq. convdef) with the sparse two-point
+// masks written as explicit shifts instead of dense mask convolutions.
+//
+// Forward: one block per (spatial tile, chunk of displacements, batch x pair).
+// The tile of phi_i and the tile of phi_j with a halo of P (periodic) sit in
+// LDS; each thread owns one displacement r and accumulates
+// sum_{x in tile} phi_i(x) phi_j(x + r); phi_i(x) is a broadcast read.  Tile
+// partials are summed in float64, in tile order, by a second kernel.
+// Adjoint: one block per (tile, output channel, batch); each thread owns one
+// output voxel and accumulates sum_j sum_r K_cj(r) phi_j(x + r) with the
+// cotangent box K_cj read through uniform (scalar) loads.
+#include "dmcr_internal.h"
+
+namespace dmcr {
+
+namespace {
+
+constexpr int kT = 256;                 // threads per block
+constexpr size_t kDirectLds = 64 * 1024;
+
+struct Geo {
+    int ndim;
+    int n0, n1, n2;     // level shape (2-D: n2 = 1)
+    int t0, t1, t2;     // tile edge
+    int h0, h1, h2;     // halo tile edge = t + 2P (2-D: h2 = t2 = 1)
+    int P, box;
+    int nt0, nt1, nt2;  // tiles per axis
+};
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    int m = i % n;
+    return m < 0 ? m + n : m;
+}
+
+// Load the halo tile of `f` (one channel, [n0][n1][n2]) whose origin is the
+// tile origin minus P, into H[h0][h1][h2].
+__device__ __forceinline__ void load_halo(const Geo &g, const float *__restrict__ f, int o0, int o1,
+                                          int o2, float *H)
+{
+    const int vol = g.h0 * g.h1 * g.h2;
+    for (int idx = threadIdx.x; idx < vol; idx += kT) {
+        const int z = idx % g.h2;
+        const int r = idx / g.h2;
+        const int y = r % g.h1;
+        const int x = r / g.h1;
+        const int i0 = wrapi(o0 + x - g.P, g.n0);
+        const int i1 = wrapi(o1 + y - g.P, g.n1);
+        const int i2 = (g.ndim == 3) ? wrapi(o2 + z - g.P, g.n2) : 0;
+        H[idx] = f[((int64_t)i0 * g.n1 + i1) * g.n2 + i2];
+    }
+}
+
+struct DirFwdArgs {
+    Geo g;
+    const float *phi;   // level field [B][C][n..]
+    float *part;        // [B*npairs][ntiles][kmax]
+    int C, npairs;
+    int pi[kMaxPairs], pj[kMaxPairs];
+    int auto_mask;
+    int64_t N, ntiles, kmax, center;
+    int64_t cnt[kMaxPairs];
+};
+
+__global__ __launch_bounds__(kT) void k_direct_fwd(DirFwdArgs a)
+{
+    extern __shared__ float sm[];
+    const Geo &g = a.g;
+    const int tile = blockIdx.x;
+    const int bp = blockIdx.z;
+    const int p = bp % a.npairs;
+    const int64_t b = bp / a.npairs;
+    const int tz = tile % g.nt2, ty = (tile / g.nt2) % g.nt1, tx = tile / (g.nt2 * g.nt1);
+    const int o0 = tx * g.t0, o1 = ty * g.t1, o2 = tz * g.t2;
+    const int tvol = g.t0 * g.t1 * g.t2;
+    float *Ta = sm;
+    float *Hb = sm + tvol;
+    const float *fa = a.phi + (b * a.C + a.pi[p]) * a.N;
+    const float *fb = a.phi + (b * a.C + a.pj[p]) * a.N;
+    for (int idx = threadIdx.x; idx < tvol; idx += kT) {
+        const int z = idx % g.t2;
+        const int r = idx / g.t2;
+        const int y = r % g.t1;
+        const int x = r / g.t1;
+        Ta[idx] = fa[((int64_t)(o0 + x) * g.n1 + (o1 + y)) * g.n2 + (o2 + z)];
+    }
+    load_halo(g, fb, o0, o1, o2, Hb);
+    __syncthreads();
+    const int64_t k = (int64_t)blockIdx.y * kT + threadIdx.x;
+    if (k >= a.cnt[p]) return;
+    const int64_t bi = ((a.auto_mask >> p) & 1) ? k + a.center : k;
+    int r0, r1, r2;
+    if (g.ndim == 2) {
+        r0 = (int)(bi / g.box) - g.P;
+        r1 = (int)(bi % g.box) - g.P;
+        r2 = 0;
+    } else {
+        r2 = (int)(bi % g.box) - g.P;
+        r1 = (int)((bi / g.box) % g.box) - g.P;
+        r0 = (int)(bi / ((int64_t)g.box * g.box)) - g.P;
+    }
+    const int pz = (g.ndim == 3) ? r2 + g.P : 0;
+    float acc = 0.f;
+    for (int x = 0; x < g.t0; ++x)
+        for (int y = 0; y < g.t1; ++y) {
+            const float *arow = Ta + (x * g.t1 + y) * g.t2;
+            const float *brow = Hb + ((x + r0 + g.P) * g.h1 + (y + r1 + g.P)) * g.h2 + pz;
+            for (int z = 0; z < g.t2; ++z) acc += arow[z] * brow[z];
+        }
+    a.part[((int64_t)bp * a.ntiles + tile) * a.kmax + k] = acc;
+}
+
+struct DirRedArgs {
+    const float *part;
+    float *S;
+    int npairs;
+    int64_t ntiles, kmax, K;
+    int64_t cnt[kMaxPairs], off[kMaxPairs];
+    double invN;
+};
+
+__global__ __launch_bounds__(kT) void k_direct_reduce(DirRedArgs a)
+{
+    const int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int bp = blockIdx.y;
+    const int p = bp % a.npairs;
+    const int64_t b = bp / a.npairs;
+    if (k >= a.cnt[p]) return;
+    const float *src = a.part + (int64_t)bp * a.ntiles * a.kmax + k;
+    double s = 0.0;
+    for (int64_t t = 0; t < a.ntiles; ++t) s += (double)src[t * a.kmax];
+    a.S[b * a.K + a.off[p] + k] = (float)(s * a.invN);
+}
+
+struct DirAdjArgs {
+    Geo g;
+    const float *phi;
+    const float *KB0;   // [B][C][C][box^d]
+    float *grad;        // [B][C][n..]
+    int C;
+    int64_t N, vol;
+    float invN;
+};
+
+__global__ __launch_bounds__(kT) void k_direct_adj(DirAdjArgs a)
+{
+    extern __shared__ float sm[];
+    const Geo &g = a.g;
+    const int tile = blockIdx.x;
+    const int c = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    const int tz = tile % g.nt2, ty = (tile / g.nt2) % g.nt1, tx = tile / (g.nt2 * g.nt1);
+    const int o0 = tx * g.t0, o1 = ty * g.t1, o2 = tz * g.t2;
+    const int tvol = g.t0 * g.t1 * g.t2;
+    // this thread's output voxel
+    const int vz = threadIdx.x % g.t2;
+    const int vy = (threadIdx.x / g.t2) % g.t1;
+    const int vx = threadIdx.x / (g.t2 * g.t1);
+    float acc = 0.f;
+    for (int j = 0; j < a.C; ++j) {
+        load_halo(g, a.phi + (b * a.C + j) * a.N, o0, o1, o2, sm);
+        __syncthreads();
+        if ((int)threadIdx.x < tvol) {
+            const float *Kc = a.KB0 + ((b * a.C + c) * a.C + j) * a.vol;
+            if (g.ndim == 2) {
+                for (int r0 = 0; r0 < g.box; ++r0) {
+                    const float *hrow = sm + (vx + r0) * g.h1 + vy;
+                    const float *krow = Kc + r0 * g.box;
+                    for (int r1 = 0; r1 < g.box; ++r1) acc += krow[r1] * hrow[r1];
+                }
+            } else {
+                for (int r0 = 0; r0 < g.box; ++r0)
+                    for (int r1 = 0; r1 < g.box; ++r1) {
+                        const float *hrow = sm + ((vx + r0) * g.h1 + (vy + r1)) * g.h2 + vz;
+                        const float *krow = Kc + (r0 * g.box + r1) * g.box;
+                        for (int r2 = 0; r2 < g.box; ++r2) acc += krow[r2] * hrow[r2];
+                    }
+            }
+        }
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < tvol)
+        a.grad[(b * a.C + c) * a.N + ((int64_t)(o0 + vx) * g.n1 + (o1 + vy)) * g.n2 + (o2 + vz)] =
+            acc * a.invN;
+}
+
+Geo make_geo(const Plan &p, int l)
+{
+    const LevelPlan &L = p.lv[l];
+    Geo g{};
+    g.ndim = p.ndim;
+    g.n0 = L.n[0];
+    g.n1 = L.n[1];
+    g.n2 = p.ndim == 3 ? L.n[2] : 1;
+    g.t0 = L.tile[0];
+    g.t1 = L.tile[1];
+    g.t2 = L.tile[2];
+    g.P = L.P;
+    g.box = L.box;
+    g.h0 = g.t0 + 2 * L.P;
+    g.h1 = g.t1 + 2 * L.P;
+    g.h2 = p.ndim == 3 ? g.t2 + 2 * L.P : 1;
+    g.nt0 = g.n0 / g.t0;
+    g.nt1 = g.n1 / g.t1;
+    g.nt2 = g.n2 / g.t2;
+    return g;
+}
+
+}  // namespace
+
+bool direct_supported(const Plan &p, int l, int tile[3])
+{
+    const LevelPlan &L = p.lv[l];
+    // tiles of 256 voxels: 16 x 16 in 2-D, 4 x 8 x 8 in 3-D (clipped to the grid)
+    int t[3];
+    if (p.ndim == 2) {
+        t[0] = L.n[0] < 16 ? L.n[0] : 16;
+        t[1] = L.n[1] < 16 ? L.n[1] : 16;
+        t[2] = 1;
+    } else {
+        t[0] = L.n[0] < 4 ? L.n[0] : 4;
+        t[1] = L.n[1] < 8 ? L.n[1] : 8;
+        t[2] = L.n[2] < 8 ? L.n[2] : 8;
+    }
+    const int64_t tvol = (int64_t)t[0] * t[1] * t[2];
+    int64_t hvol = (int64_t)(t[0] + 2 * L.P) * (t[1] + 2 * L.P);
+    if (p.ndim == 3) hvol *= (t[2] + 2 * L.P);
+    if ((size_t)(tvol + hvol) * sizeof(float) > kDirectLds) return false;
+    if (tile) {
+        tile[0] = t[0];
+        tile[1] = t[1];
+        tile[2] = t[2];
+    }
+    return true;
+}
+
+hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
+                                hipStream_t st)
+{
+    const LevelPlan &L = p.lv[l];
+    DirFwdArgs a{};
+    a.g = make_geo(p, l);
+    a.phi = phi;
+    a.part = ws.at<float>(L.part);
+    a.C = p.C;
+    a.npairs = p.npairs;
+    a.N = L.N;
+    a.ntiles = L.n_tiles;
+    int64_t kmax = 0, vol = 1;
+    for (int d = 0; d < p.ndim; ++d) vol *= L.box;
+    a.center = (vol - 1) / 2;
+    for (int q = 0; q < p.npairs; ++q) {
+        a.pi[q] = p.pi[q];
+        a.pj[q] = p.pj[q];
+        if (p.pi[q] == p.pj[q]) a.auto_mask |= 1 << q;
+        a.cnt[q] = L.cnt[q];
+        if (L.cnt[q] > kmax) kmax = L.cnt[q];
+    }
+    a.kmax = kmax;
+    const int tvol = a.g.t0 * a.g.t1 * a.g.t2;
+    const size_t lds = (size_t)(tvol + a.g.h0 * a.g.h1 * a.g.h2) * sizeof(float);
+    dim3 grid((unsigned)a.ntiles, (unsigned)((kmax + kT - 1) / kT), (unsigned)(p.B * p.npairs));
+    hipLaunchKernelGGL(k_direct_fwd, grid, dim3(kT), lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    DirRedArgs r{};
+    r.part = a.part;
+    r.S = S;
+    r.npairs = p.npairs;
+    r.ntiles = a.ntiles;
+    r.kmax = kmax;
+    r.K = p.K;
+    for (int q = 0; q < p.npairs; ++q) {
+        r.cnt[q] = L.cnt[q];
+        r.off[q] = L.off[q];
+    }
+    r.invN = 1.0 / (double)L.N;
+    dim3 rg((unsigned)((kmax + kT - 1) / kT), (unsigned)(p.B * p.npairs));
+    hipLaunchKernelGGL(k_direct_reduce, rg, dim3(kT), 0, st, r);
+    return hipGetLastError();
+}
+
+hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
+                                const Ws &ws, hipStream_t st)
+{
+    const LevelPlan &L = p.lv[l];
+    float *KB0 = ws.at<float>(L.KB0);
+    hipError_t e = launch_build_kernels(p, l, G, KB0, st);
+    if (e != hipSuccess) return e;
+    DirAdjArgs a{};
+    a.g = make_geo(p, l);
+    a.phi = phi;
+    a.KB0 = KB0;
+    a.grad = grad;
+    a.C = p.C;
+    a.N = L.N;
+    a.vol = 1;
+    for (int d = 0; d < p.ndim; ++d) a.vol *= L.box;
+    a.invN = (float)(1.0 / (double)L.N);
+    const size_t lds = (size_t)(a.g.h0 * a.g.h1 * a.g.h2) * sizeof(float);
+    dim3 grid((unsigned)L.n_tiles, (unsigned)p.C, (unsigned)p.B);
+    hipLaunchKernelGGL(k_direct_adj, grid, dim3(kT), lds, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace dmcr

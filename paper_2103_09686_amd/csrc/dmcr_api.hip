@@ -1,0 +1,386 @@
+// C ABI of libdmcr: validation, planning (level shapes, displacement sets,
+// descriptor layout, workspace carving, path choice) and the launch order of
+// the forward, error and adjoint stages.  See include/dmcr.h for the contract.
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "dmcr_internal.h"
+
+namespace dmcr {
+
+bool fft_supported(const Plan &p, int l);
+
+namespace {
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Carver {
+    size_t top = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t at = top;
+        top = align_up(top + bytes);
+        return at;
+    }
+};
+
+// Rough per-level cost model used by DMCR_PATH_AUTO (seconds).
+double direct_cost(const Plan &p, int l)
+{
+    const LevelPlan &L = p.lv[l];
+    double macs = 0;
+    for (int q = 0; q < p.npairs; ++q) macs += (double)L.N * (double)L.cnt[q];
+    double vol = 1;
+    for (int d = 0; d < p.ndim; ++d) vol *= L.box;
+    macs += (double)L.N * vol * p.C * p.C;  // adjoint
+    return macs * p.B / 4.0e12 + 3 * 4e-6;
+}
+
+double fft_cost(const Plan &p, int l)
+{
+    const LevelPlan &L = p.lv[l];
+    const double bytes = (double)p.B * p.C * L.N * 60.0;
+    return bytes / 4.0e12 + (p.ndim == 3 ? 12 : 8) * 4e-6;
+}
+
+}  // namespace
+
+dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
+{
+    if (!s || !pp) return DMCR_EINVAL;
+    Plan &p = *pp;
+    memset(&p, 0, sizeof(Plan));
+    if (s->ndim != 2 && s->ndim != 3) return DMCR_EUNSUPPORTED;
+    if (B < 1) return DMCR_EINVAL;
+    p.ndim = s->ndim;
+    p.B = B;
+    if (s->n_channels < 1 || s->n_channels > kMaxChannels) return DMCR_EINVAL;
+    p.C = s->n_channels;
+    if (s->n_levels < 1 || s->n_levels > kMaxLevels) return DMCR_EINVAL;
+    p.L = s->n_levels;
+    for (int a = 0; a < p.ndim; ++a) {
+        if (!is_pow2(s->shape[a]) || s->shape[a] < 2) return DMCR_EUNSUPPORTED;
+        if ((s->shape[a] >> (p.L - 1)) < 2) return DMCR_EINVAL;
+        p.shape[a] = s->shape[a];
+    }
+    if (p.ndim == 2) p.shape[2] = 1;
+    p.flags = s->flags;
+    if (s->path < DMCR_PATH_AUTO || s->path > DMCR_PATH_DIRECT) return DMCR_EINVAL;
+    // pairs
+    if (s->n_pairs <= 0) {
+        for (int i = 0; i < p.C; ++i)
+            for (int j = i; j < p.C; ++j) {
+                p.pi[p.npairs] = i;
+                p.pj[p.npairs] = j;
+                ++p.npairs;
+            }
+    } else {
+        if (s->n_pairs > kMaxPairs) return DMCR_EINVAL;
+        p.npairs = s->n_pairs;
+        for (int q = 0; q < p.npairs; ++q) {
+            const int i = s->pairs[2 * q], j = s->pairs[2 * q + 1];
+            if (i < 0 || j < i || j >= p.C) return DMCR_EINVAL;
+            for (int r = 0; r < q; ++r)
+                if (p.pi[r] == i && p.pj[r] == j) return DMCR_EINVAL;
+            p.pi[q] = i;
+            p.pj[q] = j;
+        }
+    }
+    // levels
+    int64_t off = 0;
+    p.Z = 0;
+    for (int l = 0; l < p.L; ++l) {
+        LevelPlan &L = p.lv[l];
+        int minax = 1 << 30;
+        L.N = 1;
+        for (int a = 0; a < 3; ++a) {
+            L.n[a] = (a < p.ndim) ? (p.shape[a] >> l) : 1;
+            L.N *= L.n[a];
+            if (a < p.ndim) minax = std::min(minax, L.n[a]);
+        }
+        L.P = s->max_disp[l];
+        if (L.P < 0 || L.P > minax / 2 - 1) return DMCR_EINVAL;
+        L.box = 2 * L.P + 1;
+        L.h = L.n[p.ndim - 1] / 2 + 1;
+        if (!(s->level_weight[l] > 0.0) || !std::isfinite(s->level_weight[l])) return DMCR_EINVAL;
+        p.w[l] = s->level_weight[l];
+        int64_t vol = 1;
+        for (int a = 0; a < p.ndim; ++a) vol *= L.box;
+        p.lvl_off[l] = off;
+        int64_t lvlK = 0;
+        for (int q = 0; q < p.npairs; ++q) {
+            L.off[q] = off;
+            L.cnt[q] = (p.pi[q] == p.pj[q]) ? (vol + 1) / 2 : vol;
+            off += L.cnt[q];
+            lvlK += L.cnt[q];
+        }
+        p.Z += p.w[l] * p.w[l] * (double)lvlK;
+    }
+    p.lvl_off[p.L] = off;
+    p.K = off;
+    // path per level
+    for (int l = 0; l < p.L; ++l) {
+        LevelPlan &L = p.lv[l];
+        int tile[3];
+        const bool dok = direct_supported(p, l, tile);
+        const bool fok = fft_supported(p, l);
+        if (s->path == DMCR_PATH_DIRECT) {
+            if (!dok) return DMCR_EUNSUPPORTED;
+            L.path = DMCR_PATH_DIRECT;
+        } else if (s->path == DMCR_PATH_FFT) {
+            if (!fok) return DMCR_EUNSUPPORTED;
+            L.path = DMCR_PATH_FFT;
+        } else {
+            if (!dok && !fok) return DMCR_EUNSUPPORTED;
+            L.path = (dok && (!fok || direct_cost(p, l) < fft_cost(p, l))) ? DMCR_PATH_DIRECT : DMCR_PATH_FFT;
+        }
+        if (dok) {
+            L.tile[0] = tile[0];
+            L.tile[1] = tile[1];
+            L.tile[2] = tile[2];
+            L.n_tiles = (L.N / ((int64_t)tile[0] * tile[1] * tile[2]));
+        }
+    }
+    // workspace
+    Carver cv;
+    const int C = p.C;
+    for (int l = 0; l < p.L; ++l) {
+        LevelPlan &L = p.lv[l];
+        const int64_t field = (int64_t)B * C * L.N;
+        if (l > 0) {
+            L.field = cv.take(field * sizeof(float));
+            L.grad = cv.take(field * sizeof(float));
+        }
+        int64_t vol = 1;
+        for (int a = 0; a < p.ndim; ++a) vol *= L.box;
+        L.KB0 = cv.take((size_t)B * C * C * vol * sizeof(float));
+        if (L.path == DMCR_PATH_FFT) {
+            const int64_t nl = L.n[p.ndim - 1];
+            const int64_t half = L.N / nl * L.h;  // complex entries of one half spectrum
+            L.X = cv.take((size_t)B * C * half * sizeof(float2));
+            const int64_t inner = half / L.n[0];
+            L.Y = cv.take((size_t)B * p.npairs * L.box * inner * sizeof(float2));
+            if (p.ndim == 3) {
+                L.Y2 = cv.take((size_t)B * p.npairs * L.box * L.box * L.h * sizeof(float2));
+                L.KB1 = cv.take((size_t)B * C * C * L.box * L.box * L.h * sizeof(float2));
+                L.KB2 = cv.take((size_t)B * C * C * L.box * L.n[1] * L.h * sizeof(float2));
+            } else {
+                L.KB1 = cv.take((size_t)B * C * C * L.box * L.h * sizeof(float2));
+            }
+        } else {
+            int64_t kmax = 0;
+            for (int q = 0; q < p.npairs; ++q) kmax = std::max(kmax, L.cnt[q]);
+            L.part = cv.take((size_t)B * p.npairs * L.n_tiles * kmax * sizeof(float));
+        }
+    }
+    p.S = cv.take((size_t)B * p.K * sizeof(float));
+    p.G = cv.take((size_t)B * p.K * sizeof(float));
+    p.err_chunks = std::max<int64_t>(1, std::min<int64_t>(1024, (p.K + 4095) / 4096));
+    p.Epart = cv.take((size_t)B * p.err_chunks * sizeof(double));
+    p.bytes = cv.top;
+    return DMCR_OK;
+}
+
+namespace {
+
+dmcr_status dev(hipError_t e) { return e == hipSuccess ? DMCR_OK : DMCR_EDEVICE; }
+
+#define DMCR_TRY(expr)                                  \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return DMCR_EDEVICE;      \
+    } while (0)
+
+bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
+
+dmcr_status check_ws(const Plan &p, void *ws, size_t ws_bytes)
+{
+    if (ws_bytes < p.bytes) return DMCR_ENOMEM;
+    if (p.bytes > 0 && (!ws || !aligned(ws))) return DMCR_EINVAL;
+    return DMCR_OK;
+}
+
+const float *level_field(const Plan &p, int l, const float *phi, const Ws &ws)
+{
+    return l == 0 ? phi : ws.at<const float>(p.lv[l].field);
+}
+
+hipError_t run_pyramid(const Plan &p, const float *phi, const Ws &ws, hipStream_t st)
+{
+    for (int l = 0; l + 1 < p.L; ++l) {
+        hipError_t e = launch_restrict(p, l, level_field(p, l, phi, ws), ws.at<float>(p.lv[l + 1].field), st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t run_forward(const Plan &p, const float *phi, float *S, const Ws &ws, hipStream_t st)
+{
+    hipError_t e = run_pyramid(p, phi, ws, st);
+    if (e != hipSuccess) return e;
+    for (int l = 0; l < p.L; ++l) {
+        const float *f = level_field(p, l, phi, ws);
+        e = (p.lv[l].path == DMCR_PATH_FFT) ? fft_forward_level(p, l, f, S, ws, st)
+                                            : direct_forward_level(p, l, f, S, ws, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Adjoint of every level, coarsest first, each level's total gradient being
+// its own term plus the prolongation of the next coarser total (Sec. 3.3:
+// back-propagation through all levels at once).
+hipError_t run_adjoint(const Plan &p, const float *phi, const float *G, float *grad, bool have_spectrum,
+                       const Ws &ws, hipStream_t st)
+{
+    for (int l = p.L - 1; l >= 0; --l) {
+        const float *f = level_field(p, l, phi, ws);
+        float *g = (l == 0) ? grad : ws.at<float>(p.lv[l].grad);
+        hipError_t e = (p.lv[l].path == DMCR_PATH_FFT)
+                           ? fft_adjoint_level(p, l, f, G, g, have_spectrum, ws, st)
+                           : direct_adjoint_level(p, l, f, G, g, ws, st);
+        if (e != hipSuccess) return e;
+        if (l + 1 < p.L) {
+            e = launch_prolong_add(p, l, ws.at<float>(p.lv[l + 1].grad), g, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+// forward, error, adjoint with one plan (shared by dmcr_loss_grad and the
+// reconstruction loop)
+dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St, double *E, float *grad,
+                               const Ws &w, hipStream_t st)
+{
+    float *S = w.at<float>(p.S);
+    float *G = w.at<float>(p.G);
+    DMCR_TRY(run_forward(p, phi, S, w, st));
+    DMCR_TRY(launch_error(p, S, St, E, G, w, st));
+    const bool keep = (p.flags & DMCR_FLAG_RECOMPUTE) == 0;
+    return dev(run_adjoint(p, phi, G, grad, keep, w, st));
+}
+
+}  // namespace dmcr
+
+using namespace dmcr;
+
+extern "C" {
+
+int64_t dmcr_descriptor_size(const dmcr_spec *spec)
+{
+    Plan p;
+    const dmcr_status s = make_plan(spec, 1, &p);
+    return s == DMCR_OK ? p.K : (int64_t)s;
+}
+
+dmcr_status dmcr_descriptor_offsets(const dmcr_spec *spec, int64_t *offsets)
+{
+    if (!offsets) return DMCR_EINVAL;
+    Plan p;
+    const dmcr_status s = make_plan(spec, 1, &p);
+    if (s != DMCR_OK) return s;
+    int i = 0;
+    for (int l = 0; l < p.L; ++l)
+        for (int q = 0; q < p.npairs; ++q) offsets[i++] = p.lv[l].off[q];
+    offsets[i] = p.K;
+    return DMCR_OK;
+}
+
+dmcr_status dmcr_workspace_size(const dmcr_spec *spec, int32_t batch, size_t *bytes)
+{
+    if (!bytes) return DMCR_EINVAL;
+    Plan p;
+    const dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    *bytes = p.bytes;
+    return DMCR_OK;
+}
+
+dmcr_status dmcr_pyramid(const dmcr_spec *spec, int32_t batch, const float *phi, float *levels,
+                         hipStream_t stream)
+{
+    Plan p;
+    dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    if (!phi || (p.L > 1 && !levels)) return DMCR_EINVAL;
+    const float *prev = phi;
+    float *out = levels;
+    for (int l = 0; l + 1 < p.L; ++l) {
+        DMCR_TRY(launch_restrict(p, l, prev, out, stream));
+        prev = out;
+        out += (int64_t)p.B * p.C * p.lv[l + 1].N;
+    }
+    return DMCR_OK;
+}
+
+dmcr_status dmcr_descriptor_forward(const dmcr_spec *spec, int32_t batch, const float *phi, float *S,
+                                    void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    Plan p;
+    dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    if (!phi || !S) return DMCR_EINVAL;
+    if ((s = check_ws(p, ws, ws_bytes)) != DMCR_OK) return s;
+    Ws w{static_cast<char *>(ws)};
+    return dev(run_forward(p, phi, S, w, stream));
+}
+
+dmcr_status dmcr_descriptor_adjoint(const dmcr_spec *spec, int32_t batch, const float *phi, const float *dS,
+                                    float *grad, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    Plan p;
+    dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    if (!phi || !dS || !grad) return DMCR_EINVAL;
+    if ((s = check_ws(p, ws, ws_bytes)) != DMCR_OK) return s;
+    Ws w{static_cast<char *>(ws)};
+    DMCR_TRY(run_pyramid(p, phi, w, stream));
+    return dev(run_adjoint(p, phi, dS, grad, false, w, stream));
+}
+
+dmcr_status dmcr_error_cotangent(const dmcr_spec *spec, int32_t batch, const float *S, const double *S_target,
+                                 double *E, float *G, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    Plan p;
+    dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    if (!S || !S_target || !E || !G) return DMCR_EINVAL;
+    if ((s = check_ws(p, ws, ws_bytes)) != DMCR_OK) return s;
+    Ws w{static_cast<char *>(ws)};
+    return dev(launch_error(p, S, S_target, E, G, w, stream));
+}
+
+dmcr_status dmcr_loss_grad(const dmcr_spec *spec, int32_t batch, const float *phi, const double *S_target,
+                           double *E, float *grad, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    Plan p;
+    dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    if (!phi || !S_target || !E || !grad) return DMCR_EINVAL;
+    if ((s = check_ws(p, ws, ws_bytes)) != DMCR_OK) return s;
+    Ws w{static_cast<char *>(ws)};
+    return loss_grad_internal(p, phi, S_target, E, grad, w, stream);
+}
+
+const char *dmcr_status_string(dmcr_status status)
+{
+    switch (status) {
+    case DMCR_OK: return "ok";
+    case DMCR_EINVAL: return "invalid argument";
+    case DMCR_ENOMEM: return "workspace too small";
+    case DMCR_EUNSUPPORTED: return "unsupported problem for this build";
+    case DMCR_EDEVICE: return "HIP device or launch error";
+    case DMCR_ENONFINITE: return "non-finite loss or gradient";
+    case DMCR_NOT_CONVERGED: return "iteration budget spent before the tolerance";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal declarations of libdmcr: the per-call plan and the kernel launchers.
+// Not part of the public ABI (include/dmcr.h is).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/dmcr.h"
+
+namespace dmcr {
+
+constexpr int kMaxLevels = DMCR_MAX_LEVELS;
+constexpr int kMaxChannels = DMCR_MAX_CHANNELS;
+constexpr int kMaxPairs = DMCR_MAX_PAIRS;
+constexpr int kMaxFft = 1024;          // longest axis handled by the LDS transforms
+constexpr size_t kAlign = 256;
+
+enum IoMode { IO_FULL = 0, IO_HALF = 1, IO_BOX = 2, IO_DESC = 3 };
+
+struct LevelPlan {
+    int n[3];          // level shape; 2-D uses n[0], n[1] and n[2] = 1
+    int64_t N;         // voxels per channel
+    int P;             // max displacement of this level
+    int box;           // 2P + 1
+    int path;          // DMCR_PATH_FFT or DMCR_PATH_DIRECT (resolved)
+    int h;             // n_last / 2 + 1 (half spectrum along the contiguous axis)
+    int64_t off[kMaxPairs];   // offset of (level, pair) inside one descriptor
+    int64_t cnt[kMaxPairs];   // entries of (level, pair)
+    // workspace byte offsets (per call, batch included)
+    size_t field;      // level >= 1: pooled field [B][C][n..]
+    size_t grad;       // level >= 1: level gradient [B][C][n..]
+    size_t X;          // FFT: partial spectrum [B][C][n0][(n1)][h] complex
+    size_t Y;          // FFT: after axis-0 inverse, box rows [B][pairs][box][inner]
+    size_t Y2;         // FFT 3-D: after axis-1 inverse [B][pairs][box][box][h]
+    size_t KB0;        // adjoint kernels on the box, real [B][C*C][box^d]
+    size_t KB1;        // after last-axis transform [B][C*C][box^(d-1)][h]
+    size_t KB2;        // 3-D: after axis-1 transform [B][C*C][box][n1][h]
+    size_t part;       // DIRECT: per-tile partial sums
+    int64_t n_tiles;   // DIRECT: tiles per field
+    int tile[3];       // DIRECT: tile edge per axis
+};
+
+struct Plan {
+    int ndim;
+    int shape[3];
+    int C;
+    int L;
+    int npairs;
+    int pi[kMaxPairs], pj[kMaxPairs];
+    double w[kMaxLevels];
+    int flags;
+    int64_t K;
+    int64_t lvl_off[kMaxLevels + 1];   // descriptor offset of each level
+    double Z;
+    int B;
+    LevelPlan lv[kMaxLevels];
+    size_t S;          // float [B][K]
+    size_t G;          // float [B][K]
+    size_t Epart;      // double [B][err_chunks]
+    int64_t err_chunks;
+    size_t bytes;      // total workspace
+};
+
+// Validates `spec` and fills `plan` for batch B (B may be 1 for size queries).
+dmcr_status make_plan(const dmcr_spec *spec, int B, Plan *plan);
+
+// ---- launchers (all asynchronous on `st`) ---------------------------------
+struct Ws {
+    char *base;
+    template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
+};
+
+hipError_t launch_restrict(const Plan &p, int l, const float *fine, float *coarse, hipStream_t st);
+hipError_t launch_prolong_add(const Plan &p, int l, const float *coarse_grad, float *fine_grad,
+                              hipStream_t st);
+
+hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
+                             hipStream_t st);
+hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &ws, hipStream_t st);
+hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
+                             bool have_spectrum, const Ws &ws, hipStream_t st);
+
+hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
+                                hipStream_t st);
+hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
+                                const Ws &ws, hipStream_t st);
+
+hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0, hipStream_t st);
+
+hipError_t launch_error(const Plan &p, const float *S, const double *St, double *E, float *G,
+                        const Ws &ws, hipStream_t st);
+
+// true if the DIRECT path can run this level (halo tile fits in LDS)
+bool direct_supported(const Plan &p, int l, int tile_out[3]);
+
+}  // namespace dmcr

@@ -1,0 +1,245 @@
+// Level operations: multigrid restriction and its transpose (Sec. 3.3), the
+// cotangent boxes that feed both adjoints, and the float64 error reduction.
+#include "dmcr_internal.h"
+
+namespace dmcr {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// coarse(y) = 2^-d sum_{delta in {0,1}^d} fine(2y + delta)   (mean pool, one level)
+__global__ __launch_bounds__(kThreads) void k_restrict(const float *__restrict__ fine,
+                                                       float *__restrict__ coarse, int64_t total,
+                                                       int ndim, int c0, int c1, int c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= total) return;
+    if (ndim == 2) {
+        const int64_t x1 = i % c1;
+        const int64_t r = i / c1;
+        const int64_t x0 = r % c0;
+        const int64_t bc = r / c0;
+        const int64_t f1 = 2 * (int64_t)c1;
+        const float *f = fine + (bc * 2 * c0 + 2 * x0) * f1 + 2 * x1;
+        const float2 a = *reinterpret_cast<const float2 *>(f);
+        const float2 b = *reinterpret_cast<const float2 *>(f + f1);
+        coarse[i] = 0.25f * ((a.x + a.y) + (b.x + b.y));
+    } else {
+        const int64_t x2 = i % c2;
+        int64_t r = i / c2;
+        const int64_t x1 = r % c1;
+        r /= c1;
+        const int64_t x0 = r % c0;
+        const int64_t bc = r / c0;
+        const int64_t f2 = 2 * (int64_t)c2, f1 = 2 * (int64_t)c1;
+        const float *f = fine + ((bc * 2 * c0 + 2 * x0) * f1 + 2 * x1) * f2 + 2 * x2;
+        const float2 a = *reinterpret_cast<const float2 *>(f);
+        const float2 b = *reinterpret_cast<const float2 *>(f + f2);
+        const float2 c = *reinterpret_cast<const float2 *>(f + f1 * f2);
+        const float2 d = *reinterpret_cast<const float2 *>(f + f1 * f2 + f2);
+        coarse[i] = 0.125f * (((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y)));
+    }
+}
+
+// fine(x) += 2^-d coarse(floor(x/2))   (transpose of the mean pool)
+__global__ __launch_bounds__(kThreads) void k_prolong_add(const float *__restrict__ coarse,
+                                                          float *__restrict__ fine, int64_t total,
+                                                          int ndim, int f0, int f1, int f2, float w)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= total) return;
+    int64_t ci;
+    if (ndim == 2) {
+        const int64_t x1 = i % f1;
+        const int64_t r = i / f1;
+        const int64_t x0 = r % f0;
+        const int64_t bc = r / f0;
+        ci = (bc * (f0 / 2) + x0 / 2) * (f1 / 2) + x1 / 2;
+    } else {
+        const int64_t x2 = i % f2;
+        int64_t r = i / f2;
+        const int64_t x1 = r % f1;
+        r /= f1;
+        const int64_t x0 = r % f0;
+        const int64_t bc = r / f0;
+        ci = ((bc * (f0 / 2) + x0 / 2) * (f1 / 2) + x1 / 2) * (f2 / 2) + x2 / 2;
+    }
+    fine[i] += w * coarse[ci];
+}
+
+struct KernArgs {
+    const float *G;   // cotangent, [B][K]
+    float *KB0;       // [B][C][C][box^d]
+    int64_t K;        // descriptor stride
+    int64_t vol;      // box^d
+    int64_t total;    // B * C * C * vol
+    int C, npairs;
+    int pi[kMaxPairs], pj[kMaxPairs];
+    int64_t off[kMaxPairs];
+};
+
+// K_cj(r) on the full box such that the adjoint of every pair reads
+//   grad_c(x) = (1/N) sum_j sum_r K_cj(r) phi_j(x + r):
+//   auto (c,c):  K_cc(r) = G(r) + G(-r) restricted to the half box, K_cc(0) = 2 G(0)
+//   cross (c,j): K_cj(r) = G_cj(r);   cross (j,c): K_cj(r) = G_jc(-r)
+__global__ __launch_bounds__(kThreads) void k_build_kernels(KernArgs a)
+{
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= a.total) return;
+    const int64_t bi = g % a.vol;
+    int64_t r = g / a.vol;
+    const int j = (int)(r % a.C);
+    r /= a.C;
+    const int c = (int)(r % a.C);
+    const int64_t b = r / a.C;
+    const int64_t center = (a.vol - 1) / 2;
+    const int64_t mirror = a.vol - 1 - bi;
+    const float *Gb = a.G + b * a.K;
+    float v = 0.f;
+    for (int p = 0; p < a.npairs; ++p) {
+        const int i0 = a.pi[p], j0 = a.pj[p];
+        const float *Gp = Gb + a.off[p];
+        if (i0 == j0) {
+            if (c == i0 && j == i0) {
+                if (bi > center)
+                    v += Gp[bi - center];
+                else if (bi < center)
+                    v += Gp[mirror - center];
+                else
+                    v += 2.f * Gp[0];
+            }
+        } else {
+            if (c == i0 && j == j0) v += Gp[bi];
+            if (c == j0 && j == i0) v += Gp[mirror];
+        }
+    }
+    a.KB0[g] = v;
+}
+
+struct ErrArgs {
+    const float *S;
+    const double *St;
+    float *G;
+    double *part;      // [B][chunks]
+    int64_t K, chunk, chunks;
+    int L;
+    int64_t lvl_off[kMaxLevels + 1];
+    double w2[kMaxLevels];
+    double invZ;
+};
+
+// Per (batch, chunk): partial sum of w^2 (S - S_t)^2 in float64 and the
+// cotangent G = 2 w^2 (S - S_t) / Z.  Fixed tree order: deterministic.
+__global__ __launch_bounds__(kThreads) void k_error_partial(ErrArgs a)
+{
+    __shared__ double red[kThreads];
+    const int64_t b = blockIdx.y;
+    const int64_t k0 = (int64_t)blockIdx.x * a.chunk;
+    int64_t k1 = k0 + a.chunk;
+    if (k1 > a.K) k1 = a.K;
+    double acc = 0.0;
+    int lv = 0;
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += kThreads) {
+        while (k >= a.lvl_off[lv + 1]) ++lv;
+        const double d = (double)a.S[b * a.K + k] - a.St[b * a.K + k];
+        const double w2 = a.w2[lv];
+        acc += w2 * d * d;
+        a.G[b * a.K + k] = (float)(2.0 * w2 * d * a.invZ);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.part[b * a.chunks + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_error_final(const double *part, int64_t chunks,
+                                                          double invZ, double *E)
+{
+    __shared__ double red[kThreads];
+    const int64_t b = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t c = threadIdx.x; c < chunks; c += kThreads) acc += part[b * chunks + c];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) E[b] = red[0] * invZ;
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+hipError_t launch_restrict(const Plan &p, int l, const float *fine, float *coarse, hipStream_t st)
+{
+    const LevelPlan &c = p.lv[l + 1];
+    const int64_t total = (int64_t)p.B * p.C * c.N;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict, dim3(blocks_for(total)), dim3(kThreads), 0, st, fine, coarse, total,
+                       p.ndim, c.n[0], c.n[1], c.n[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_add(const Plan &p, int l, const float *coarse_grad, float *fine_grad,
+                              hipStream_t st)
+{
+    const LevelPlan &f = p.lv[l];
+    const int64_t total = (int64_t)p.B * p.C * f.N;
+    if (total == 0) return hipSuccess;
+    const float w = p.ndim == 2 ? 0.25f : 0.125f;
+    hipLaunchKernelGGL(k_prolong_add, dim3(blocks_for(total)), dim3(kThreads), 0, st, coarse_grad,
+                       fine_grad, total, p.ndim, f.n[0], f.n[1], f.n[2], w);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0, hipStream_t st)
+{
+    const LevelPlan &L = p.lv[l];
+    KernArgs a{};
+    a.G = G;
+    a.KB0 = KB0;
+    a.K = p.K;
+    a.vol = 1;
+    for (int d = 0; d < p.ndim; ++d) a.vol *= L.box;
+    a.total = (int64_t)p.B * p.C * p.C * a.vol;
+    a.C = p.C;
+    a.npairs = p.npairs;
+    for (int q = 0; q < p.npairs; ++q) {
+        a.pi[q] = p.pi[q];
+        a.pj[q] = p.pj[q];
+        a.off[q] = L.off[q];
+    }
+    hipLaunchKernelGGL(k_build_kernels, dim3(blocks_for(a.total)), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_error(const Plan &p, const float *S, const double *St, double *E, float *G, const Ws &ws,
+                        hipStream_t st)
+{
+    ErrArgs a{};
+    a.S = S;
+    a.St = St;
+    a.G = G;
+    a.part = ws.at<double>(p.Epart);
+    a.K = p.K;
+    a.chunks = p.err_chunks;
+    a.chunk = (p.K + p.err_chunks - 1) / p.err_chunks;
+    a.L = p.L;
+    for (int l = 0; l <= p.L; ++l) a.lvl_off[l] = p.lvl_off[l];
+    for (int l = p.L + 1; l <= kMaxLevels; ++l) a.lvl_off[l] = INT64_MAX;
+    for (int l = 0; l < p.L; ++l) a.w2[l] = p.w[l] * p.w[l];
+    a.invZ = 1.0 / p.Z;
+    hipLaunchKernelGGL(k_error_partial, dim3((unsigned)a.chunks, (unsigned)p.B), dim3(kThreads), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_error_final, dim3((unsigned)p.B), dim3(kThreads), 0, st, a.part, a.chunks, a.invZ, E);
+    return hipGetLastError();
+}
+
+}  // namespace dmcr

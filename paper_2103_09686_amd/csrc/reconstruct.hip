@@ -1,0 +1,549 @@
+// Reconstruction driver (the loop of Fig. 1 / eq. M-update, Sec. 3): batched
+// limited-memory BFGS on the relaxed problem of eq. (dMCR-Min_Prob).
+//
+// Every vector operation runs on the device in float32 with float64 dot
+// products (fixed-order, deterministic reductions).  Each batch element keeps
+// its own history (rho = 0 marks an empty or rejected slot), step length and
+// status; elements advance in lockstep because one loss/gradient evaluation
+// covers the whole batch.  The host reads back only the per-element scalars
+// each decision needs (loss, penalty, directional derivatives).
+//
+// Direction: two-loop recursion (Nocedal & Wright, Alg. 7.4) with initial
+// scaling gamma = s'y / y'y of the newest accepted pair.  Box handling
+// (Sec. 3.1): PROJECT clips trial points to [lo, hi] and zeroes direction
+// components that push an active bound outward; PENALTY adds lambda E^bc with
+// E^bc as printed in Sec. 3.1 and lambda = kappa * E held constant in the
+// gradient.  Step: backtracking (halving) along the projected path with the
+// Armijo test f(x_t) <= f(x) + c1 g'(x_t - x), first trial 1 (1/|g| without
+// history); a pair (s, y) enters the history only if s'y > eps y'y.  A failed
+// line search clears that element's history; a failure that started from
+// steepest descent stops the element.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "dmcr_internal.h"
+
+namespace dmcr {
+
+dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St, double *E, float *grad,
+                               const Ws &w, hipStream_t st);
+
+namespace {
+
+constexpr int kV = 256;
+
+size_t align_up_bytes(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+unsigned vblocks(int64_t n) { return (unsigned)std::min<int64_t>((n + kV - 1) / kV, 2048); }
+
+// part[b][blk] = sum over block blk's slice of element b of a * (bv - cv)   (cv may be null)
+__global__ __launch_bounds__(kV) void k_dot_part(const float *a, const float *bv, const float *cv, int64_t n,
+                                                 double *part, int nblk)
+{
+    __shared__ double red[kV];
+    const int64_t b = blockIdx.y;
+    const float *A = a + b * n, *Bv = bv + b * n, *Cv = cv ? cv + b * n : nullptr;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)nblk * kV) {
+        const double y = Cv ? (double)Bv[i] - (double)Cv[i] : (double)Bv[i];
+        acc += (double)A[i] * y;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kV / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[b * nblk + blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_parts(const double *part, int nblk, double *out, int B)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double s = 0.0;
+    for (int i = 0; i < nblk; ++i) s += part[(int64_t)b * nblk + i];
+    out[b] = s;
+}
+
+__global__ void k_fill(double *p, double v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// y[b] += sgn * coef[b] * x[b]   (coefficient read on the device)
+__global__ __launch_bounds__(kV) void k_axpy(float *y, const float *x, const double *coef, double sgn, int64_t n)
+{
+    const int64_t b = blockIdx.y;
+    const float c = (float)(sgn * coef[b]);
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV)
+        y[b * n + i] += c * x[b * n + i];
+}
+
+// y[b] *= sgn * coef[b]
+__global__ __launch_bounds__(kV) void k_scale(float *y, const double *coef, double sgn, int64_t n)
+{
+    const int64_t b = blockIdx.y;
+    const float c = (float)(sgn * coef[b]);
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV)
+        y[b * n + i] *= c;
+}
+
+__global__ void k_alpha(const double *dot, const double *rho, double *alpha, int B)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) alpha[b] = rho[b] * dot[b];
+}
+
+__global__ void k_beta(const double *dot, const double *rho, const double *alpha, double *coef, int B)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) coef[b] = alpha[b] - rho[b] * dot[b];
+}
+
+// new pair in ring slot `slot`: rho = 1/s'y if accepted and s'y > eps y'y, else 0; gamma follows
+__global__ void k_pair(const double *sy, const double *yy, const int *acc, double *rho_slot, double *gamma, int B)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const bool ok = acc[b] && sy[b] > 2.220446049250313e-16 * yy[b] && yy[b] > 0.0;
+    rho_slot[b] = ok ? 1.0 / sy[b] : 0.0;
+    if (ok) gamma[b] = sy[b] / yy[b];
+}
+
+// clear the history of flagged elements
+__global__ void k_reset(const int *flag, double *rho, double *gamma, int m, int B)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B || !flag[b]) return;
+    for (int i = 0; i < m; ++i) rho[i * B + b] = 0.0;
+    gamma[b] = 1.0;
+}
+
+// x_t = clip(x + alpha d) for elements with active[b]
+__global__ __launch_bounds__(kV) void k_trial(const float *x, const float *d, const double *alpha, const int *active,
+                                              float *xt, int64_t n, int project, float lo, float hi)
+{
+    const int64_t b = blockIdx.y;
+    if (!active[b]) return;
+    const float a = (float)alpha[b];
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV) {
+        float v = x[b * n + i] + a * d[b * n + i];
+        if (project) v = fminf(fmaxf(v, lo), hi);
+        xt[b * n + i] = v;
+    }
+}
+
+__global__ __launch_bounds__(kV) void k_clip(float *x, int64_t total, float lo, float hi)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < total; i += (int64_t)gridDim.x * kV)
+        x[i] = fminf(fmaxf(x[i], lo), hi);
+}
+
+// d = -d; with projection, components that push an active bound outward are zeroed
+__global__ __launch_bounds__(kV) void k_finish_dir(const float *x, float *d, int64_t n, int project, float lo, float hi)
+{
+    const int64_t b = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV) {
+        const float xv = x[b * n + i];
+        float dv = -d[b * n + i];
+        if (project && ((xv <= lo && dv < 0.f) || (xv >= hi && dv > 0.f))) dv = 0.f;
+        d[b * n + i] = dv;
+    }
+}
+
+// flagged elements: d = -g (projected as above)
+__global__ __launch_bounds__(kV) void k_steepest(const int *flag, const float *x, const float *g, float *d, int64_t n,
+                                                 int project, float lo, float hi)
+{
+    const int64_t b = blockIdx.y;
+    if (!flag[b]) return;
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV) {
+        const float xv = x[b * n + i];
+        float dv = -g[b * n + i];
+        if (project && ((xv <= lo && dv < 0.f) || (xv >= hi && dv > 0.f))) dv = 0.f;
+        d[b * n + i] = dv;
+    }
+}
+
+// accepted elements: s = x_t - x, y = g_t - g, x = x_t, g = g_t
+__global__ __launch_bounds__(kV) void k_accept(const int *acc, float *x, const float *xt, float *g, const float *gt,
+                                               float *s, float *y, int64_t n)
+{
+    const int64_t b = blockIdx.y;
+    if (!acc[b]) return;
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV) {
+        const int64_t j = b * n + i;
+        s[j] = xt[j] - x[j];
+        y[j] = gt[j] - g[j];
+        x[j] = xt[j];
+        g[j] = gt[j];
+    }
+}
+
+// E^bc = sum_i t_i^2 with t = (x-hi)H(x-hi)/N + (lo-x)H(lo-x)/N, H(0) = 0 (per channel N)
+__global__ __launch_bounds__(kV) void k_pen_part(const float *x, int64_t n, double invN, float lo, float hi,
+                                                 double *part, int nblk)
+{
+    __shared__ double red[kV];
+    const int64_t b = blockIdx.y;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)nblk * kV) {
+        const double v = x[b * n + i];
+        const double t = (v > hi ? (v - hi) : 0.0) * invN + (v < lo ? (lo - v) : 0.0) * invN;
+        acc += t * t;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kV / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[b * nblk + blockIdx.x] = red[0];
+}
+
+// g += kappa E dE^bc/dx,  dE^bc/dx = 2 t (H(x-hi) - H(lo-x)) / N
+__global__ __launch_bounds__(kV) void k_pen_grad(const float *x, float *g, const double *E, double kappa, int64_t n,
+                                                 double invN, float lo, float hi)
+{
+    const int64_t b = blockIdx.y;
+    const double lam = kappa * E[b];
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV) {
+        const double v = x[b * n + i];
+        const double t = (v > hi ? (v - hi) : 0.0) * invN + (v < lo ? (lo - v) : 0.0) * invN;
+        const double dt = (v > hi ? invN : 0.0) - (v < lo ? invN : 0.0);
+        g[b * n + i] += (float)(lam * 2.0 * t * dt);
+    }
+}
+
+struct RLayout {
+    size_t xt, g, gt, d, s, y;
+    size_t part, dot1, dot2, rho, alpha, gamma, coef, E, Et, Ebc, als, active, acc, flag;
+    int nblk;
+    size_t bytes;
+};
+
+RLayout r_layout(const Plan &p, const dmcr_opt &o)
+{
+    RLayout r{};
+    const int64_t n = (int64_t)p.C * p.lv[0].N;
+    const size_t Bn = (size_t)p.B * n;
+    size_t top = align_up_bytes(p.bytes);
+    auto take = [&](size_t bytes) {
+        const size_t at = top;
+        top = align_up_bytes(top + bytes);
+        return at;
+    };
+    const size_t B8 = (size_t)p.B * 8;
+    r.xt = take(Bn * 4);
+    r.g = take(Bn * 4);
+    r.gt = take(Bn * 4);
+    r.d = take(Bn * 4);
+    r.s = take((size_t)o.m * Bn * 4);
+    r.y = take((size_t)o.m * Bn * 4);
+    r.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 4 * kV - 1) / (4 * kV)));
+    r.part = take((size_t)p.B * r.nblk * 8);
+    r.dot1 = take(B8);
+    r.dot2 = take(B8);
+    r.rho = take((size_t)o.m * B8);
+    r.alpha = take((size_t)o.m * B8);
+    r.gamma = take(B8);
+    r.coef = take(B8);
+    r.E = take(B8);
+    r.Et = take(B8);
+    r.Ebc = take(B8);
+    r.als = take(B8);
+    r.active = take((size_t)p.B * 4);
+    r.acc = take((size_t)p.B * 4);
+    r.flag = take((size_t)p.B * 4);
+    r.bytes = top;
+    return r;
+}
+
+bool opt_ok(const dmcr_opt *o)
+{
+    return o && o->m >= 1 && o->m <= 32 && o->max_iter >= 0 && o->max_ls >= 1 && o->c1 > 0 && o->c1 < 1 &&
+           std::isfinite(o->tol_derr);
+}
+
+#define RT(expr)                                               \
+    do {                                                       \
+        if ((expr) != hipSuccess) return DMCR_EDEVICE;         \
+    } while (0)
+#define RS(expr)                                               \
+    do {                                                       \
+        dmcr_status _s = (expr);                               \
+        if (_s != DMCR_OK) return _s;                          \
+    } while (0)
+
+struct Solver {
+    const Plan &p;
+    const dmcr_bounds &bd;
+    const dmcr_opt &o;
+    const double *St;
+    RLayout r;
+    Ws w;
+    hipStream_t st;
+    int B, m;
+    int64_t n;
+    dim3 vg, sg;
+    bool project, penalty;
+    float lo, hi;
+    double invN;
+
+    template <class T> T *at(size_t off) const { return w.at<T>(off); }
+    float *S(int i) const { return at<float>(r.s) + (int64_t)i * B * n; }
+    float *Y(int i) const { return at<float>(r.y) + (int64_t)i * B * n; }
+
+    // out[b] = a[b] . (bv[b] - cv[b])
+    hipError_t dot(const float *a, const float *bv, const float *cv, double *out) const
+    {
+        hipLaunchKernelGGL(k_dot_part, dim3(r.nblk, B), dim3(kV), 0, st, a, bv, cv, n, at<double>(r.part), r.nblk);
+        hipLaunchKernelGGL(k_sum_parts, sg, dim3(64), 0, st, at<double>(r.part), r.nblk, out, B);
+        return hipGetLastError();
+    }
+
+    dmcr_status evaluate(const float *pt, double *Ed, float *grad) const
+    {
+        RS(loss_grad_internal(p, pt, St, Ed, grad, w, st));
+        if (penalty) {
+            hipLaunchKernelGGL(k_pen_part, dim3(r.nblk, B), dim3(kV), 0, st, pt, n, invN, lo, hi, at<double>(r.part),
+                               r.nblk);
+            hipLaunchKernelGGL(k_sum_parts, sg, dim3(64), 0, st, at<double>(r.part), r.nblk, at<double>(r.Ebc), B);
+            hipLaunchKernelGGL(k_pen_grad, vg, dim3(kV), 0, st, pt, grad, Ed, bd.kappa, n, invN, lo, hi);
+            RT(hipGetLastError());
+        }
+        return DMCR_OK;
+    }
+
+    dmcr_status fetch(const double *src, std::vector<double> &dst) const
+    {
+        RT(hipMemcpyAsync(dst.data(), src, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        return DMCR_OK;
+    }
+
+    dmcr_status put(int *dst, const std::vector<int> &src) const
+    {
+        RT(hipMemcpyAsync(dst, src.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        return DMCR_OK;
+    }
+
+    dmcr_status put(double *dst, const std::vector<double> &src) const
+    {
+        RT(hipMemcpyAsync(dst, src.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+        return DMCR_OK;
+    }
+
+    dmcr_status run(float *x, dmcr_result *res);
+};
+
+dmcr_status Solver::run(float *x, dmcr_result *res)
+{
+    float *xt = at<float>(r.xt), *g = at<float>(r.g), *gt = at<float>(r.gt), *d = at<float>(r.d);
+    double *rho = at<double>(r.rho), *alpha = at<double>(r.alpha), *gamma = at<double>(r.gamma);
+    double *coef = at<double>(r.coef), *dot1 = at<double>(r.dot1), *dot2 = at<double>(r.dot2);
+    double *Ed = at<double>(r.E), *Etd = at<double>(r.Et), *Ebcd = at<double>(r.Ebc), *als = at<double>(r.als);
+    int *active = at<int>(r.active), *accd = at<int>(r.acc), *flagd = at<int>(r.flag);
+
+    hipLaunchKernelGGL(k_fill, dim3((m * B + 255) / 256), dim3(256), 0, st, rho, 0.0, m * B);
+    hipLaunchKernelGGL(k_fill, dim3((B + 255) / 256), dim3(256), 0, st, gamma, 1.0, B);
+    if (project) hipLaunchKernelGGL(k_clip, dim3(vblocks((int64_t)B * n)), dim3(kV), 0, st, x, (int64_t)B * n, lo, hi);
+    RT(hipGetLastError());
+
+    std::vector<double> hE(B), hEbc(B, 0.0), hd(B), hd2(B), f(B), E(B), step(B);
+    std::vector<int> done(B, 0), iters(B, 0), evals(B, 1), why(B, DMCR_NOT_CONVERGED), hist(B, 0);
+    std::vector<int> act(B), acc(B), flag(B);
+
+    RS(evaluate(x, Ed, g));
+    RS(fetch(Ed, hE));
+    if (penalty) RS(fetch(Ebcd, hEbc));
+    RT(hipStreamSynchronize(st));
+    for (int b = 0; b < B; ++b) {
+        E[b] = hE[b];
+        f[b] = hE[b] + (penalty ? bd.kappa * hE[b] * hEbc[b] : 0.0);
+        if (!std::isfinite(f[b])) {
+            done[b] = 1;
+            why[b] = DMCR_ENONFINITE;
+        } else if (E[b] <= o.tol_derr) {
+            done[b] = 1;
+            why[b] = DMCR_OK;
+        }
+    }
+
+    int head = m - 1, count = 0;
+    for (int it = 0; it < o.max_iter; ++it) {
+        bool any = false;
+        for (int b = 0; b < B; ++b) any |= !done[b];
+        if (!any) break;
+
+        // ---- direction d = -H g over the ring (newest first), then projection ----
+        RT(hipMemcpyAsync(d, g, (size_t)B * n * 4, hipMemcpyDeviceToDevice, st));
+        for (int k = 0; k < count; ++k) {
+            const int i = (head - k + m) % m;
+            RT(dot(S(i), d, nullptr, dot1));
+            hipLaunchKernelGGL(k_alpha, sg, dim3(64), 0, st, dot1, rho + i * B, alpha + i * B, B);
+            hipLaunchKernelGGL(k_axpy, vg, dim3(kV), 0, st, d, Y(i), alpha + i * B, -1.0, n);
+        }
+        hipLaunchKernelGGL(k_scale, vg, dim3(kV), 0, st, d, gamma, 1.0, n);
+        for (int k = count - 1; k >= 0; --k) {
+            const int i = (head - k + m) % m;
+            RT(dot(Y(i), d, nullptr, dot1));
+            hipLaunchKernelGGL(k_beta, sg, dim3(64), 0, st, dot1, rho + i * B, alpha + i * B, coef, B);
+            hipLaunchKernelGGL(k_axpy, vg, dim3(kV), 0, st, d, S(i), coef, 1.0, n);
+        }
+        hipLaunchKernelGGL(k_finish_dir, vg, dim3(kV), 0, st, x, d, n, (int)project, lo, hi);
+        RT(dot(g, d, nullptr, dot1));
+        RT(dot(g, g, nullptr, dot2));
+        RS(fetch(dot1, hd));
+        RS(fetch(dot2, hd2));
+        RT(hipStreamSynchronize(st));
+        // not a descent direction: fall back to (projected) steepest descent
+        bool any_flag = false;
+        for (int b = 0; b < B; ++b) {
+            flag[b] = !done[b] && !(hd[b] < 0.0);
+            if (flag[b]) hist[b] = 0;
+            any_flag |= flag[b] != 0;
+        }
+        if (any_flag) {
+            RS(put(flagd, flag));
+            hipLaunchKernelGGL(k_reset, sg, dim3(64), 0, st, flagd, rho, gamma, m, B);
+            hipLaunchKernelGGL(k_steepest, vg, dim3(kV), 0, st, flagd, x, g, d, n, (int)project, lo, hi);
+        }
+
+        // ---- backtracking line search along the projected path ----
+        for (int b = 0; b < B; ++b) {
+            act[b] = !done[b];
+            acc[b] = 0;
+            const double gn = std::sqrt(hd2[b]);
+            step[b] = (hist[b] == 0 && gn > 0.0) ? 1.0 / gn : 1.0;
+        }
+        bool all_zero_dir = false;
+        (void)all_zero_dir;
+        for (int ls = 0; ls < o.max_ls; ++ls) {
+            bool anyact = false;
+            for (int b = 0; b < B; ++b) anyact |= act[b] != 0;
+            if (!anyact) break;
+            RS(put(active, act));
+            RS(put(als, step));
+            hipLaunchKernelGGL(k_trial, vg, dim3(kV), 0, st, x, d, als, active, xt, n, (int)project, lo, hi);
+            RS(evaluate(xt, Etd, gt));
+            RT(dot(g, xt, x, dot1));
+            RS(fetch(Etd, hE));
+            if (penalty) RS(fetch(Ebcd, hEbc));
+            RS(fetch(dot1, hd));
+            RT(hipStreamSynchronize(st));
+            for (int b = 0; b < B; ++b) {
+                if (!act[b]) continue;
+                ++evals[b];
+                const double ft = hE[b] + (penalty ? bd.kappa * hE[b] * hEbc[b] : 0.0);
+                if (std::isfinite(ft) && hd[b] < 0.0 && ft <= f[b] + o.c1 * hd[b]) {
+                    act[b] = 0;
+                    acc[b] = 1;
+                    f[b] = ft;
+                    E[b] = hE[b];
+                } else {
+                    step[b] *= 0.5;
+                }
+            }
+        }
+
+        // ---- update the field, gradient and history of accepted elements ----
+        const int slot = (head + 1) % m;
+        RS(put(accd, acc));
+        hipLaunchKernelGGL(k_accept, vg, dim3(kV), 0, st, accd, x, xt, g, gt, S(slot), Y(slot), n);
+        RT(dot(S(slot), Y(slot), nullptr, dot1));
+        RT(dot(Y(slot), Y(slot), nullptr, dot2));
+        hipLaunchKernelGGL(k_pair, sg, dim3(64), 0, st, dot1, dot2, accd, rho + slot * B, gamma, B);
+        RT(hipGetLastError());
+        head = slot;
+        count = std::min(count + 1, m);
+        bool any_fail = false;
+        for (int b = 0; b < B; ++b) {
+            if (done[b]) {
+                flag[b] = 0;
+                continue;
+            }
+            ++iters[b];
+            if (acc[b]) {
+                flag[b] = 0;
+                hist[b] = std::min(hist[b] + 1, m);
+                if (E[b] <= o.tol_derr) {
+                    done[b] = 1;
+                    why[b] = DMCR_OK;
+                }
+            } else {
+                flag[b] = 1;  // clear the history of a failed line search
+                any_fail = true;
+                if (hist[b] == 0) {
+                    done[b] = 1;  // no progress even from steepest descent
+                    why[b] = DMCR_NOT_CONVERGED;
+                }
+                hist[b] = 0;
+            }
+        }
+        if (any_fail) {
+            RS(put(flagd, flag));
+            hipLaunchKernelGGL(k_reset, sg, dim3(64), 0, st, flagd, rho, gamma, m, B);
+            RT(hipGetLastError());
+        }
+    }
+    RT(hipStreamSynchronize(st));
+    bool all_ok = true;
+    for (int b = 0; b < B; ++b) {
+        res[b].final_E = E[b];
+        res[b].final_derr = E[b];
+        res[b].iters = iters[b];
+        res[b].evals = evals[b];
+        res[b].why = why[b];
+        all_ok &= why[b] == DMCR_OK;
+    }
+    return all_ok ? DMCR_OK : DMCR_NOT_CONVERGED;
+}
+
+}  // namespace
+}  // namespace dmcr
+
+using namespace dmcr;
+
+extern "C" {
+
+dmcr_status dmcr_reconstruct_workspace_size(const dmcr_spec *spec, int32_t batch, const dmcr_opt *opt,
+                                            size_t *bytes)
+{
+    if (!bytes || !opt_ok(opt)) return DMCR_EINVAL;
+    Plan p;
+    dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    *bytes = r_layout(p, *opt).bytes;
+    return DMCR_OK;
+}
+
+dmcr_status dmcr_reconstruct(const dmcr_spec *spec, int32_t batch, const double *S_target, const dmcr_bounds *bounds,
+                             const dmcr_opt *opt, float *phi, dmcr_result *results, void *ws, size_t ws_bytes,
+                             hipStream_t st)
+{
+    if (!opt_ok(opt) || !bounds || !S_target || !phi || !results) return DMCR_EINVAL;
+    if (bounds->mode < DMCR_BOUNDS_NONE || bounds->mode > DMCR_BOUNDS_PENALTY) return DMCR_EINVAL;
+    if (bounds->mode != DMCR_BOUNDS_NONE && !(bounds->lo < bounds->hi)) return DMCR_EINVAL;
+    if (bounds->mode == DMCR_BOUNDS_PENALTY && !(bounds->kappa >= 0.0)) return DMCR_EINVAL;
+    Plan p;
+    dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    const RLayout r = r_layout(p, *opt);
+    if (ws_bytes < r.bytes) return DMCR_ENOMEM;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign)) return DMCR_EINVAL;
+    Solver sv{p, *bounds, *opt, S_target, r, Ws{static_cast<char *>(ws)}, st, batch, opt->m,
+              (int64_t)p.C * p.lv[0].N, dim3(), dim3(), false, false, 0.f, 0.f, 0.0};
+    sv.vg = dim3(vblocks(sv.n), batch);
+    sv.sg = dim3((batch + 63) / 64);
+    sv.project = bounds->mode == DMCR_BOUNDS_PROJECT;
+    sv.penalty = bounds->mode == DMCR_BOUNDS_PENALTY;
+    sv.lo = (float)bounds->lo;
+    sv.hi = (float)bounds->hi;
+    sv.invN = 1.0 / (double)p.lv[0].N;
+    return sv.run(phi, results);
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+"""The C-ABI library loads on the CPU, exports every symbol include/dmcr.h declares,
+and its host-only planning (descriptor size, offsets, validation) agrees with the
+oracle's layout.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dmcr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmcr_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def dm():
+    from paper_2103_09686_amd import dmcr
+    if not os.path.exists(dmcr.LIB_PATH):
+        from paper_2103_09686_amd import build_lib
+        build_lib.build(verbose=False)
+    dmcr.lib()
+    return dmcr
+
+
+def test_exports_every_declared_symbol(dm):
+    names = declared_functions()
+    assert len(names) >= 10
+    raw = ctypes.CDLL(dm.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+
+
+def test_struct_sizes_match_header(dm):
+    # dmcr_spec: 4 + 12 + 4 + 4 + 32 + (pad 4?) + 64 + 4 + 128 + 4 + 4
+    assert ctypes.sizeof(dm.c_spec) == 264
+    assert ctypes.sizeof(dm.c_result) == 32
+
+
+@pytest.mark.parametrize("shape,C,L,P,pairs", [
+    ((64, 64), 1, 1, (16,), ()),
+    ((512, 512), 1, 3, (64, 64, 63), ()),
+    ((128, 128, 128), 2, 3, (32, 31, 15), ()),
+    ((32, 16, 8), 3, 2, (3, 1), ((0, 2), (1, 1))),
+])
+def test_descriptor_size_and_offsets_match_oracle(dm, ora, shape, C, L, P, pairs):
+    spec = dm.Spec(shape=shape, n_channels=C, n_levels=L, max_disp=P, pairs=pairs)
+    ospec = ora.Spec(shape=shape, n_channels=C, n_levels=L, max_disp=P, pairs=pairs)
+    assert dm.dmcr_descriptor_size(spec) == ospec.K
+    offs = dm.dmcr_descriptor_offsets(spec)
+    assert offs == [e[2] for e in ospec.layout()] + [ospec.K]
+
+
+def test_config_sizes_quoted_in_the_workloads(dm):
+    """K of the named workloads: 64^2 P=16 -> 545; 512^2 P=64 L=3 -> 24707;
+    3-D 128^3 C=2 P=32 L=3 -> 1108929; 3-D 256^3 P=32 -> 137313."""
+    assert dm.dmcr_descriptor_size(dm.make_spec((64, 64), 1, 1, 16)) == 545
+    assert dm.dmcr_descriptor_size(dm.make_spec((512, 512), 1, 3, 64)) == 24707
+    assert dm.dmcr_descriptor_size(dm.make_spec((128, 128, 128), 2, 3, 32)) == 1108929
+    assert dm.dmcr_descriptor_size(dm.make_spec((256, 256, 256), 1, 1, 32)) == 137313
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(shape=(48, 64)), -3),                       # not a power of two
+    (dict(shape=(64, 64), max_disp=(32,)), -1),        # P > n/2 - 1
+    (dict(shape=(8, 8), n_levels=4, max_disp=(0,)), -1),  # coarsest level below 2
+    (dict(shape=(64, 64), n_channels=5), -1),
+    (dict(shape=(64, 64), level_weight=(0.0,)), -1),
+    (dict(shape=(64, 64), n_channels=2, pairs=((1, 0),)), -1),
+    (dict(shape=(64, 64, 64), max_disp=(20,), path=2), -3),  # DIRECT halo does not fit LDS
+])
+def test_validation(dm, kw, code):
+    spec = dm.Spec(**kw)
+    with pytest.raises(dm.DmcrError) as e:
+        dm.dmcr_descriptor_size(spec)
+    assert e.value.code == code
+
+
+def test_workspace_grows_with_batch(dm):
+    spec = dm.make_spec((64, 64), 1, 2, 16)
+    a = dm.dmcr_workspace_size(spec, 1)
+    b = dm.dmcr_workspace_size(spec, 8)
+    assert b > a > 0
+    r = dm.dmcr_reconstruct_workspace_size(spec, 8, dm.Opt())
+    assert r > b
+
+
+def test_status_strings(dm):
+    L = dm.lib()
+    for code in (0, -1, -2, -3, -4, -5, 1):
+        assert L.dmcr_status_string(code)

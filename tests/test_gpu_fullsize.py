@@ -1,0 +1,63 @@
+"""Parity at the full sizes the benchmark times, on outputs the oracle can compute one
+by one: 3-D 256^3 two-phase, P = 32, one level (descriptor at 1024 sampled
+displacements, gradient at 256 sampled voxels for a seeded random cotangent), and
+2-D 512^2, P = 64, three levels (every descriptor entry of the coarse levels and
+sampled entries of the finest)."""
+import numpy as np
+import pytest
+
+from paper_2103_09686_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_09686_amd import dmcr
+    dmcr.lib()
+    return dmcr
+
+
+def test_3d_256_sampled(dm, ora):
+    shape = (256, 256, 256)
+    spec = dm.Spec(shape=shape, n_channels=1, n_levels=1, max_disp=(32,), path=1, flags=dm.FLAG_RECOMPUTE)
+    ospec = ora.Spec(shape=shape, n_channels=1, n_levels=1, max_disp=(32,))
+    phi32 = synth.uniform(shape, 0).astype(np.float32)
+    phi = phi32.astype(np.float64)
+    d = torch.from_numpy(phi32[None]).cuda()
+    S = dm.dmcr_descriptor_forward(spec, d).cpu().numpy()[0].astype(np.float64)
+    rng = np.random.default_rng(1)
+    H = ora.half_box(3, 32)
+    idx = np.sort(rng.choice(len(H), 1024, replace=False))
+    idx[0] = 0  # include r = 0
+    S_ora = ora._native.corr(phi[0], phi[0], H[idx])
+    scale = np.max(np.abs(S_ora))
+    assert np.max(np.abs(S[idx] - S_ora)) <= 1e-5 * scale
+    # adjoint at sampled voxels for a seeded cotangent
+    u = rng.standard_normal(len(H)).astype(np.float32)
+    g = dm.dmcr_descriptor_adjoint(spec, d, torch.from_numpy(u[None]).cuda()).cpu().numpy()[0, 0]
+    vox = rng.integers(0, 256, size=(256, 3))
+    g_ora = ora.adjoint_at_single_level(phi, u.astype(np.float64), ospec, vox)[0]
+    g_s = g[tuple(vox.T)].astype(np.float64)
+    assert np.linalg.norm(g_s - g_ora) <= 1e-4 * np.linalg.norm(g_ora)
+    assert np.max(np.abs(g_s - g_ora)) <= 1e-4 * np.max(np.abs(g_ora))
+
+
+def test_2d_512_three_levels(dm, ora):
+    shape = (512, 512)
+    spec = dm.make_spec(shape, 1, 3, 64)
+    ospec = ora.Spec(shape=shape, n_levels=3, max_disp=spec.max_disp)
+    tgt = synth.grf_two_phase(shape, 12, 0.40, seed=0).astype(np.float32)
+    S = dm.dmcr_descriptor_forward(spec, torch.from_numpy(tgt[None]).cuda()).cpu().numpy()[0].astype(np.float64)
+    lv = ora.pyramid(tgt.astype(np.float64), 3)
+    for (l, pair, off, k) in ospec.layout():
+        rs = ospec.disp(l, pair)
+        if l == 0:
+            sel = np.random.default_rng(l).choice(k, 512, replace=False)
+        else:
+            sel = np.arange(k)
+        ref = ora._native.corr(lv[l][0], lv[l][0], rs[sel])
+        assert np.max(np.abs(S[off + sel] - ref)) <= 1e-5 * np.max(np.abs(ref)), l

@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (the workload statement's numbers, applied per result):
+  * descriptor: for each (level, pair), max_r |S_gpu - S_oracle| <= 1e-5 max_r |S_oracle|
+  * gradient:   ||g_gpu - g_oracle||_2 <= 1e-4 ||g_oracle||_2
+Inputs are float32 fields; the oracle evaluates the same float32 values in float64.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2103_09686_amd import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+S_TOL = 1e-5
+G_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def dm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_09686_amd import dmcr
+    dmcr.lib()
+    return dmcr
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def specs(dm, ora, shape, C, L, P, pairs=(), path=0, flags=0):
+    return (dm.Spec(shape=shape, n_channels=C, n_levels=L, max_disp=P, pairs=pairs, path=path, flags=flags),
+            ora.Spec(shape=shape, n_channels=C, n_levels=L, max_disp=P, pairs=pairs))
+
+
+def check_S(S_gpu, S_ora, ospec, label=""):
+    for (l, pair, off, k) in ospec.layout():
+        a = S_gpu[off:off + k]
+        b = S_ora[off:off + k]
+        err = np.max(np.abs(a - b))
+        scale = np.max(np.abs(b))
+        assert err <= S_TOL * scale + 1e-30, (label, l, pair, err, scale)
+
+
+def check_grad(g_gpu, g_ora, label=""):
+    num = np.linalg.norm((g_gpu - g_ora).ravel())
+    den = np.linalg.norm(g_ora.ravel())
+    assert num <= G_TOL * den, (label, num / max(den, 1e-300))
+
+
+CASES = [
+    # shape, C, L, P per level, pairs, path
+    ((64, 64), 1, 1, (16,), (), 2),
+    ((64, 64), 1, 1, (16,), (), 1),
+    ((32, 64), 2, 2, (5, 3), (), 2),
+    ((32, 64), 2, 2, (5, 3), (), 1),
+    ((16, 16, 16), 2, 2, (4, 2), (), 2),
+    ((16, 16, 16), 2, 2, (4, 2), (), 1),
+    ((32, 16, 8), 1, 3, (3, 1, 0), (), 1),
+    ((8, 32, 16), 3, 1, (3,), ((0, 2), (1, 1), (1, 2)), 1),
+    ((128, 128), 1, 2, (31, 31), (), 1),
+    ((2, 2), 1, 1, (0,), (), 1),
+    ((4, 4, 4), 1, 2, (1, 0), (), 0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[str(i) for i in range(len(CASES))])
+def test_forward_adjoint_parity(dm, ora, case):
+    shape, C, L, P, pairs, path = case
+    spec, ospec = specs(dm, ora, shape, C, L, P, pairs, path)
+    print("case", case, flush=True)
+    B = 2
+    phi = f32(np.stack([synth.uniform(shape, 100 + b, channels=C) for b in range(B)]))
+    dphi = to_dev(phi)
+    S = dm.dmcr_descriptor_forward(spec, dphi).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(7)
+    dS = f32(rng.standard_normal((B, ospec.K)))
+    g = dm.dmcr_descriptor_adjoint(spec, dphi, to_dev(dS)).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    for b in range(B):
+        S_ora = ora.descriptor(phi[b], ospec)
+        check_S(S[b], S_ora, ospec, "fwd b=%d" % b)
+        g_ora = ora.adjoint(phi[b], dS[b], ospec)
+        check_grad(g[b], g_ora, "adj b=%d" % b)
+
+
+def test_binary_field_volume_fraction_and_paths_agree(dm, ora):
+    """Binary field: S_11(0) = volume fraction (Sec. 3.1); FFT and DIRECT agree."""
+    f, vf = synth.boolean_spheres((64, 64), 4, 0.30, seed=0)
+    d = to_dev(f[None])
+    s_fft = dm.dmcr_descriptor_forward(dm.make_spec((64, 64), 1, 1, 16, path=1), d).cpu().numpy()[0]
+    s_dir = dm.dmcr_descriptor_forward(dm.make_spec((64, 64), 1, 1, 16, path=2), d).cpu().numpy()[0]
+    assert abs(s_fft[0] - vf) <= 1e-6 and abs(s_dir[0] - vf) <= 1e-6
+    assert np.max(np.abs(s_fft - s_dir)) <= 1e-6
+
+
+def test_loss_grad_and_error_parity(dm, ora):
+    shape = (64, 64)
+    spec, ospec = specs(dm, ora, shape, 1, 2, (16, 15))
+    tgt, _ = synth.boolean_spheres(shape, 4, 0.30, seed=0)
+    S_des = ora.descriptor(tgt, ospec)
+    phi = f32(synth.uniform(shape, 1))
+    E, g = dm.dmcr_loss_grad(spec, to_dev(phi[None]), torch.from_numpy(S_des[None]).cuda())
+    E = E.cpu().numpy()[0]
+    g = g.cpu().numpy()[0].astype(np.float64)
+    E_ora, g_ora, S_ora = ora.loss_grad(phi, S_des, ospec)
+    assert abs(E - E_ora) <= 1e-4 * E_ora
+    check_grad(g, g_ora, "loss_grad")
+    # error kernel alone on identical S: float64 sum
+    S32 = f32(S_ora)
+    E2, G2 = dm.dmcr_error_cotangent(spec, to_dev(S32[None]), torch.from_numpy(S_des[None]).cuda())
+    E_ref, G_ref = ora.loss(S32, S_des, ospec)
+    assert abs(E2.cpu().item() - E_ref) <= 1e-12 * E_ref
+    np.testing.assert_allclose(G2.cpu().numpy()[0], G_ref, rtol=1e-6, atol=1e-30)
+
+
+def test_stationary_at_target(dm, ora):
+    """grad E = 0 at the target itself (every residual zero)."""
+    shape = (32, 32)
+    spec, ospec = specs(dm, ora, shape, 1, 1, (8,))
+    tgt, _ = synth.boolean_spheres(shape, 3, 0.3, seed=2)
+    d = to_dev(tgt[None])
+    S = dm.dmcr_descriptor_forward(spec, d)
+    E, g = dm.dmcr_loss_grad(spec, d, S.double())
+    assert E.item() == 0.0
+    assert torch.count_nonzero(g).item() == 0
+
+
+def test_pyramid_parity(dm, ora):
+    shape = (32, 16, 8)
+    spec = dm.Spec(shape=shape, n_channels=2, n_levels=3, max_disp=(1, 1, 0))
+    phi = f32(np.stack([synth.uniform(shape, 5, channels=2)]))
+    lv = dm.dmcr_pyramid(spec, to_dev(phi))
+    ref = ora.pyramid(phi[0], 3)
+    for l in (1, 2):
+        np.testing.assert_allclose(lv[l - 1].cpu().numpy()[0], ref[l], rtol=2e-7, atol=0)
+
+
+def test_batched_equals_single_bitwise_and_repeatable(dm):
+    shape = (64, 64)
+    for path in (1, 2):
+        spec = dm.make_spec(shape, 2, 2, 12, path=path)
+        phi = to_dev(np.stack([synth.uniform(shape, 40 + b, channels=2) for b in range(4)]))
+        S4 = dm.dmcr_descriptor_forward(spec, phi)
+        S4b = dm.dmcr_descriptor_forward(spec, phi)
+        assert torch.equal(S4, S4b)
+        for b in range(4):
+            S1 = dm.dmcr_descriptor_forward(spec, phi[b:b + 1].contiguous())
+            assert torch.equal(S1[0], S4[b]), (path, b)
+        dS = torch.randn_like(S4)
+        g4 = dm.dmcr_descriptor_adjoint(spec, phi, dS)
+        g1 = dm.dmcr_descriptor_adjoint(spec, phi[1:2].contiguous(), dS[1:2].contiguous())
+        assert torch.equal(g1[0], g4[1])
+
+
+def test_autograd_function_fd(dm, ora):
+    """S2Descriptor backward vs central differences of the oracle loss (h = 1e-3, FP64)
+    at sampled voxels, and vs the oracle gradient (differentiation check, 2-D 256^2)."""
+    shape = (256, 256)
+    spec, ospec = specs(dm, ora, shape, 1, 1, (31,))
+    tgt, _ = synth.boolean_spheres(shape, 4, 0.30, seed=0)
+    S_des = ora.descriptor(tgt, ospec)
+    B = 4
+    phi = f32(np.stack([synth.uniform(shape, s) for s in range(B)]))
+    x = to_dev(phi).requires_grad_(True)
+    S = dm.s2_descriptor(x, spec)
+    Z = float(ospec.K)
+    loss = (((S.double() - torch.from_numpy(S_des).cuda()) ** 2).sum(dim=1) / Z).sum()
+    loss.backward()
+    g = x.grad.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(0)
+    vox = rng.integers(0, 256, size=(16, 2))
+    h = 1e-3
+    for b in range(B):
+        E, g_ora, _ = ora.loss_grad(phi[b], S_des, ospec)
+        check_grad(g[b], g_ora, "autograd b=%d" % b)
+        if b == 0:
+            for (i, j) in vox[:4]:
+                p, m = phi[b].copy(), phi[b].copy()
+                p[0, i, j] += h
+                m[0, i, j] -= h
+                fd = (ora.loss(ora.descriptor(p, ospec), S_des, ospec)[0]
+                      - ora.loss(ora.descriptor(m, ospec), S_des, ospec)[0]) / (2 * h)
+                assert abs(fd - g[b, 0, i, j]) <= 1e-4 * np.max(np.abs(g_ora)), (i, j, fd, g[b, 0, i, j])

@@ -1,0 +1,73 @@
+"""Reconstruction (the paper's Fig. 1 loop) on the GPU.  Parity is on the final
+descriptor error, never on the field: every translation or point reflection of a
+solution has the same descriptor (Sec. 4.2, exact translations), and FP32 vs FP64
+trajectories diverge."""
+import numpy as np
+import pytest
+
+from paper_2103_09686_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_09686_amd import dmcr
+    dmcr.lib()
+    return dmcr
+
+
+def target(ora, shape, P, L=1):
+    ospec = ora.Spec(shape=shape, n_levels=L, max_disp=P)
+    tgt, _ = synth.boolean_spheres(shape, 4, 0.30, seed=0)
+    return ospec, ora.descriptor(tgt, ospec)
+
+
+def test_64_boolean_100_iterations(dm, ora):
+    """64^2, P = 16, Boolean disks r = 4 vf 0.30, U(0,1) start, 100 L-BFGS iterations:
+    the GPU reaches E <= 1e-4, or at most twice the oracle's SciPy L-BFGS-B result."""
+    shape = (64, 64)
+    ospec, S_des = target(ora, shape, (16,))
+    phi0 = synth.uniform(shape, 1).astype(np.float32)
+    x = torch.from_numpy(phi0[None]).cuda()
+    spec = dm.Spec(shape=shape, max_disp=(16,))
+    code, res = dm.dmcr_reconstruct(spec, torch.from_numpy(S_des[None]).cuda(), x,
+                                    dm.Bounds(0.0, 1.0, dm.BOUNDS_PROJECT), dm.Opt(max_iter=100, tol_derr=0.0))
+    r = res[0]
+    print("gpu", r, flush=True)
+    xf = x.cpu().numpy()[0].astype(np.float64)
+    assert xf.min() >= 0.0 and xf.max() <= 1.0
+    E_check = ora.loss(ora.descriptor(xf, ospec), S_des, ospec)[0]
+    assert abs(E_check - r["final_E"]) <= 1e-3 * E_check + 1e-9
+    _, E_ref, _, _ = ora.reconstruct_lbfgsb(S_des, ospec, phi0.astype(np.float64), maxiter=100)
+    print("oracle scipy E", E_ref, flush=True)
+    assert r["final_E"] <= 1e-4 or r["final_E"] <= 2 * E_ref
+
+
+def test_batched_stops_at_tolerance(dm, ora):
+    shape = (64, 64)
+    ospec, S_des = target(ora, shape, (16, 15), L=2)
+    B = 3
+    x = torch.from_numpy(np.stack([synth.uniform(shape, 10 + b) for b in range(B)]).astype(np.float32)).cuda()
+    St = torch.from_numpy(np.stack([S_des] * B)).cuda()
+    spec = dm.Spec(shape=shape, n_levels=2, max_disp=(16, 15))
+    code, res = dm.dmcr_reconstruct(spec, St, x, dm.Bounds(), dm.Opt(max_iter=300, tol_derr=1e-4))
+    assert code == 0, res
+    for b in range(B):
+        assert res[b]["final_E"] <= 1e-4
+        xf = x[b].cpu().numpy().astype(np.float64)
+        assert ora.loss(ora.descriptor(xf, ospec), S_des, ospec)[0] <= 1.01e-4
+
+
+def test_penalty_mode_runs(dm, ora):
+    shape = (32, 32)
+    ospec, S_des = target(ora, shape, (8,))
+    x = torch.from_numpy(synth.uniform(shape, 3)[None].astype(np.float32)).cuda()
+    spec = dm.Spec(shape=shape, max_disp=(8,))
+    E0 = dm.dmcr_loss_grad(spec, x, torch.from_numpy(S_des[None]).cuda())[0].item()
+    code, res = dm.dmcr_reconstruct(spec, torch.from_numpy(S_des[None]).cuda(), x,
+                                    dm.Bounds(0.0, 1.0, dm.BOUNDS_PENALTY, 1.0), dm.Opt(max_iter=50, tol_derr=0.0))
+    assert res[0]["final_E"] < 0.1 * E0

@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the descriptor hot path: voxel-iterations per second of one
+loss/gradient evaluation (multigrid two-point correlations forward, float64
+error, adjoint through every level) on one MI355X.
+
+A step is one dmcr_loss_grad over one batch with the field, the target
+descriptor and the workspace already resident in HBM.  The default workload
+is a 3-D 256^3 two-phase U(0,1) field, P = 32, one level, spectra recomputed
+in the adjoint.  The script prints one JSON line with the throughput, the
+roofline figure of the dominant kernel (HIP events around every launch, on the
+launch stream, in a second pass of the same steps) and the FP64 oracle timed
+on a bounded sample on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel·iterations/s (S2 fwd+adjoint) vs HBM roofline; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "3d256": dict(desc="3D 256^3 two-phase U(0,1) seed 0, P=32, 1 level, fwd+adjoint with recomputation",
+                  shape=(256, 256, 256), C=1, L=1, P=32, recompute=True, batch=1),
+    "2d512": dict(desc="2D 512^2 two-phase, P=64, 3-level multigrid (512/256/128), U(0,1) field",
+                  shape=(512, 512), C=1, L=3, P=64, recompute=False, batch=1),
+    "2d512b64": dict(desc="2D 512^2 two-phase, P=64, 3 levels, batch of 64 fields",
+                     shape=(512, 512), C=1, L=3, P=64, recompute=False, batch=64),
+    "3d128": dict(desc="3D 128^3 three-phase (C=2), P=32, 3-level multigrid (128/64/32)",
+                  shape=(128, 128, 128), C=2, L=3, P=32, recompute=False, batch=1),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="3d256", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle sample time")
+    return ap.parse_args()
+
+
+def cpu_baseline(phi64, spec_kw, target_seconds):
+    """Time the FP64 oracle on a bounded sample of one evaluation and scale it to the
+    whole evaluation: forward over k_s sampled displacements (all voxels each) and
+    adjoint at n_s sampled voxels (all displacements each)."""
+    import numpy as np
+    import oracle
+
+    oracle.build()
+    shape, P, L = spec_kw["shape"], spec_kw["P"], spec_kw["L"]
+    d = len(shape)
+    C = phi64.shape[0]
+    ospec = oracle.Spec(shape=shape, n_channels=C, n_levels=L,
+                        max_disp=tuple(min(P, min(s >> l for s in shape) // 2 - 1) for l in range(L)))
+    lv = oracle.pyramid(phi64, L)
+    rng = np.random.default_rng(0)
+    # finest level, first pair: cost per displacement = N MACs, per voxel = K MACs (x2 in the adjoint)
+    l0 = [e for e in ospec.layout() if e[0] == 0]
+    (_, pair, off, k) = l0[0]
+    rs = ospec.disp(0, pair)
+    N = int(np.prod(shape))
+    # calibrate with a tiny sample, then size the real one
+    t0 = time.perf_counter()
+    oracle._native.corr(lv[0][pair[0]], lv[0][pair[1]], rs[:4])
+    t_per_r = max((time.perf_counter() - t0) / 4, 1e-6)
+    k_s = int(max(8, min(len(rs), 0.5 * target_seconds / t_per_r)))
+    sel = rng.choice(len(rs), k_s, replace=False)
+    t0 = time.perf_counter()
+    oracle._native.corr(lv[0][pair[0]], lv[0][pair[1]], rs[sel])
+    t_fwd = time.perf_counter() - t0
+    G = rng.standard_normal(k)
+    vox = rng.integers(0, min(shape), size=(64, d))
+    t0 = time.perf_counter()
+    oracle._native.corr_adjoint_at(lv[0][pair[0]], lv[0][pair[1]], rs, G, vox)
+    t_per_v = max((time.perf_counter() - t0) / 64, 1e-9)
+    n_s = int(max(64, min(N, 0.5 * target_seconds / t_per_v)))
+    vox = rng.integers(0, min(shape), size=(n_s, d))
+    t0 = time.perf_counter()
+    oracle._native.corr_adjoint_at(lv[0][pair[0]], lv[0][pair[1]], rs, G, vox)
+    t_adj = time.perf_counter() - t0
+    # whole evaluation: every (level, pair) block, forward over its displacements and
+    # adjoint over its voxels, scaled by the measured per-unit times (cost ~ N_l * K_lp)
+    t_full = 0.0
+    for (l, p2, o2, k2) in ospec.layout():
+        Nl = N >> (d * l)
+        frac = (Nl / N)
+        t_full += (t_fwd / k_s) * k2 * frac + (t_adj / n_s) * Nl * (k2 / k)
+    return dict(value=N / t_full, unit="voxel·it/s", cores=oracle._native.num_threads(), kind="oracle",
+                sample="%d of %d displacements (all %d voxels) forward + %d voxels (all %d displacements) "
+                       "adjoint of level 0, pair %s; scaled to all levels and pairs by N_l*K_lp"
+                       % (k_s, len(rs), N, n_s, len(rs), pair),
+                seconds=t_fwd + t_adj)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2103_09686_amd import dmcr, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = WORKLOADS[args.workload]
+    shape, C, L, P, B = wl["shape"], wl["C"], wl["L"], wl["P"], wl["batch"]
+    flags = dmcr.FLAG_RECOMPUTE if wl["recompute"] else 0
+    spec = dmcr.make_spec(shape, C, L, P, flags=flags)
+    K = dmcr.dmcr_descriptor_size(spec)
+    N = int(np.prod(shape))
+
+    phi_h = np.stack([synth.uniform(shape, b, channels=C) for b in range(B)]).astype(np.float32)
+    phi = torch.from_numpy(phi_h).cuda()
+    # target descriptor: a seeded Boolean sphere medium (3-D) / disk medium (2-D), per channel
+    tgt = np.concatenate([synth.boolean_spheres(shape, 6 if len(shape) == 3 else 4, 0.2 + 0.05 * c,
+                                                seed=1000 + c)[0] for c in range(C)])
+    S_t = dmcr.dmcr_descriptor_forward(spec, torch.from_numpy(tgt[None].astype(np.float32)).cuda())
+    S_target = S_t.double().repeat(B, 1).contiguous()
+    E = torch.empty(B, dtype=torch.float64, device="cuda")
+    grad = torch.empty_like(phi)
+    ws = dmcr.workspace(dmcr.dmcr_workspace_size(spec, B))
+    stream = torch.cuda.current_stream()
+
+    def step():
+        dmcr.dmcr_loss_grad(spec, phi, S_target, E, grad, ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for _ in range(args.steps):
+        step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1) / args.steps
+    value = N * B / (ms * 1e-3)
+    print("timed %d steps: %.4f ms/step (wall %.3f s)" % (args.steps, ms, wall), file=sys.stderr, flush=True)
+
+    # second pass: per-kernel HIP events on the launch stream
+    import ctypes
+    lib = dmcr.lib()
+    lib.dmcr_profile_start.restype = ctypes.c_int
+    lib.dmcr_profile_stop.restype = ctypes.c_int32
+
+    class KStat(ctypes.Structure):
+        _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int32),
+                    ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+    lib.dmcr_profile_stop.argtypes = [ctypes.POINTER(KStat), ctypes.c_int32]
+    lib.dmcr_profile_start()
+    for _ in range(args.steps):
+        step()
+    stats = (KStat * 64)()
+    nk = lib.dmcr_profile_stop(stats, 64)
+    torch.cuda.synchronize()
+    kern = []
+    for i in range(min(nk, 64)):
+        s = stats[i]
+        kern.append(dict(name=s.name.decode(), launches=s.launches, avg_us=1e3 * s.total_ms / s.launches,
+                         total_ms=s.total_ms, bytes_per_launch=s.bytes / s.launches,
+                         GBps=(s.bytes / s.launches) / (s.total_ms / s.launches * 1e-3) / 1e9))
+    kern.sort(key=lambda r: -r["total_ms"])
+    for r in kern:
+        print("  %-16s n=%-5d avg %9.2f us  %8.1f GB/s  (%.1f MB/launch)" %
+              (r["name"], r["launches"], r["avg_us"], r["GBps"], r["bytes_per_launch"] / 1e6),
+              file=sys.stderr, flush=True)
+    dom = kern[0]
+    prof_ms = sum(r["total_ms"] for r in kern) / args.steps
+    roofline = dict(bound="hbm", kernel=dom["name"], achieved=round(dom["GBps"], 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(dom["GBps"] / HBM_PEAK_GBS, 4), traffic=None,
+                    avg_us=round(dom["avg_us"], 2), bytes_per_launch=dom["bytes_per_launch"])
+    total_bytes = sum(r["bytes_per_launch"] * r["launches"] for r in kern) / args.steps
+    step_roofline = dict(bytes_per_step=total_bytes, bytes_per_voxel=total_bytes / (N * B),
+                         achieved_GBps=round(total_bytes / (ms * 1e-3) / 1e9, 1),
+                         frac=round(total_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         kernel_ms_sum=round(prof_ms, 4))
+
+    out = dict(metric=METRIC, value=value, unit="voxel·it/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload=wl["desc"], shape=list(shape), channels=C, levels=L,
+                           max_disp=list(spec.max_disp), K=K, batch=B, path="fft",
+                           recompute=wl["recompute"], parallelism="single GPU"),
+               roofline=roofline, step_roofline=step_roofline)
+    if not args.no_cpu_baseline:
+        phi64 = phi_h[0].astype(np.float64)
+        cb = cpu_baseline(phi64, dict(shape=shape, P=P, L=L), args.cpu_seconds)
+        out["cpu_baseline"] = dict(value=cb["value"], unit=cb["unit"], cores=cb["cores"], kind=cb["kind"],
+                                   sample=cb["sample"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -22,7 +22,7 @@
  *       S_ij^(l)(r) = (1/N_l) sum_x phi_i^(l)(x) phi_j^(l)((x + r) mod n_l)
  *   (Sec. 3.2.1-3.2.2 with the periodic shift of eq. convdef; for soft
  *   fields this is the Appendix A corrected descriptor with the identity
- *   threshold used in Sec. 4.1).  Auto pairs (i == i) use the half box H_P
+ *   threshold used in Sec. 5.1).  Auto pairs (i == j) use the half box H_P
  *   (r = 0 or first non-zero component > 0; point symmetry, Appendix B),
  *   cross pairs the full box [-P, P]^d.
  * Descriptor order.  Level-major (finest first), then pair in the order of
@@ -128,7 +128,7 @@ dmcr_status dmcr_descriptor_offsets(const dmcr_spec *spec, int64_t *offsets);
 /* Workspace bytes needed by every call below for this spec and batch size. */
 dmcr_status dmcr_workspace_size(const dmcr_spec *spec, int32_t batch, size_t *bytes);
 
-/* a1 -- multigrid pyramid (Sec. 3.3): writes levels 1..L-1 of phi, each the 2^d
+/* Multigrid pyramid (Sec. 3.3): writes levels 1..L-1 of phi, each the 2^d
  * mean pool of the previous, concatenated level after level into `levels`
  * (device, float32, sum_l B*C*N_l values). */
 dmcr_status dmcr_pyramid(const dmcr_spec *spec, int32_t batch, const float *phi, float *levels,
@@ -146,7 +146,7 @@ dmcr_status dmcr_descriptor_adjoint(const dmcr_spec *spec, int32_t batch, const 
                                     const float *dS, float *grad, void *ws, size_t ws_bytes,
                                     hipStream_t stream);
 
-/* a5 -- error and cotangent: E[b] (device float64) and G = dE/dS (device
+/* Error and cotangent: E[b] (device float64) and G = dE/dS (device
  * float32 [B][K]) from S (device float32 [B][K]) and S_target (device
  * float64 [B][K]); the sum is taken in float64 in a fixed order. */
 dmcr_status dmcr_error_cotangent(const dmcr_spec *spec, int32_t batch, const float *S,
@@ -171,6 +171,23 @@ dmcr_status dmcr_reconstruct_workspace_size(const dmcr_spec *spec, int32_t batch
 dmcr_status dmcr_reconstruct(const dmcr_spec *spec, int32_t batch, const double *S_target,
                              const dmcr_bounds *bounds, const dmcr_opt *opt, float *phi_inout,
                              dmcr_result *results, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Kernel timing (diagnostics).  dmcr_profile_start() clears the table and
+ * makes every later launch record a HIP event pair on its own stream, with
+ * the launch's algorithmic bytes (inputs read once plus outputs written
+ * once).  dmcr_profile_stop() synchronises on the recorded events, writes
+ * at most `max` per-kernel totals to `out` (host) and returns the number of
+ * distinct kernels (or a negative dmcr_status).  Process-global and not
+ * thread-safe; recording adds a small gap between launches. */
+typedef struct {
+    char name[48];
+    int32_t launches;
+    double total_ms;
+    double bytes;     /* algorithmic bytes summed over the launches */
+} dmcr_kernel_stat;
+
+dmcr_status dmcr_profile_start(void);
+int32_t dmcr_profile_stop(dmcr_kernel_stat *out, int32_t max);
 
 /* Static description of a status code. */
 const char *dmcr_status_string(dmcr_status status);

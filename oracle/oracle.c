@@ -16,7 +16,7 @@
  *       S_ab(r) = (1/N) * sum_x  a(x) * b((x + r) mod n)
  *
  *   For a soft field this is the corrected descriptor of Appendix A with the
- *   identity threshold (Sec. 4.1 runs the method without the threshold and
+ *   identity threshold (Sec. 5.1 runs the method without the threshold and
  *   states the Appendix A corrections still hold).
  *
  *   Adjoint (the exact derivative the method back-propagates, Sec. 3.1 and

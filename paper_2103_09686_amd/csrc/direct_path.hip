@@ -261,8 +261,8 @@ hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S
     const int tvol = a.g.t0 * a.g.t1 * a.g.t2;
     const size_t lds = (size_t)(tvol + a.g.h0 * a.g.h1 * a.g.h2) * sizeof(float);
     dim3 grid((unsigned)a.ntiles, (unsigned)((kmax + kT - 1) / kT), (unsigned)(p.B * p.npairs));
-    hipLaunchKernelGGL(k_direct_fwd, grid, dim3(kT), lds, st, a);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch("direct_fwd", (double)p.B * p.C * L.N * 4 + (double)p.B * p.npairs * a.ntiles * kmax * 4,
+                          k_direct_fwd, grid, dim3(kT), lds, st, a);
     if (e != hipSuccess) return e;
     DirRedArgs r{};
     r.part = a.part;
@@ -277,8 +277,8 @@ hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S
     }
     r.invN = 1.0 / (double)L.N;
     dim3 rg((unsigned)((kmax + kT - 1) / kT), (unsigned)(p.B * p.npairs));
-    hipLaunchKernelGGL(k_direct_reduce, rg, dim3(kT), 0, st, r);
-    return hipGetLastError();
+    return launch("direct_reduce", (double)p.B * p.npairs * a.ntiles * kmax * 4, k_direct_reduce, rg, dim3(kT), 0,
+                  st, r);
 }
 
 hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
@@ -300,8 +300,8 @@ hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const fl
     a.invN = (float)(1.0 / (double)L.N);
     const size_t lds = (size_t)(a.g.h0 * a.g.h1 * a.g.h2) * sizeof(float);
     dim3 grid((unsigned)L.n_tiles, (unsigned)p.C, (unsigned)p.B);
-    hipLaunchKernelGGL(k_direct_adj, grid, dim3(kT), lds, st, a);
-    return hipGetLastError();
+    const double bytes = 2.0 * p.B * p.C * L.N * 4 + (double)p.B * p.C * p.C * a.vol * 4;
+    return launch("direct_adj", bytes, k_direct_adj, grid, dim3(kT), lds, st, a);
 }
 
 }  // namespace dmcr

@@ -66,6 +66,24 @@ struct Plan {
 // Validates `spec` and fills `plan` for batch B (B may be 1 for size queries).
 dmcr_status make_plan(const dmcr_spec *spec, int B, Plan *plan);
 
+// ---- kernel timing (dmcr_profile_start / dmcr_profile_stop) ---------------
+bool prof_on();
+void prof_begin(const char *name, double bytes, hipStream_t st);
+void prof_end(hipStream_t st);
+
+// Launch `kernel` on `st`, bracketed by profiling events when enabled.
+template <typename Kern, typename... Args>
+hipError_t launch(const char *name, double bytes, Kern kernel, dim3 grid, dim3 block, size_t lds,
+                  hipStream_t st, Args... args)
+{
+    const bool on = prof_on();
+    if (on) prof_begin(name, bytes, st);
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+    hipError_t e = hipGetLastError();
+    if (on) prof_end(st);
+    return e;
+}
+
 // ---- launchers (all asynchronous on `st`) ---------------------------------
 struct Ws {
     char *base;

@@ -1,126 +1,203 @@
 // FFT path of the descriptor: S_ij = (1/N^2) IDFT(conj(DFT phi_i) DFT phi_j) on the
 // displacement box, and its adjoint grad_c = (1/N^2) IDFT(sum_j conj(DFT K_cj) DFT phi_j)
-// where K_cj are the cotangents laid out on the box (see build_kernels.hip).
+// where K_cj are the cotangents laid out on the box (k_build_kernels in level_ops.hip).
 //
 // This replaces the paper's dense mask convolution (Sec. 3.2.3, eq. convdef;
-// Appendix B) by the convolution theorem, which the paper names as the
-// Fourier route to correlations (Sec. 3.2, Sec. 3.4.1).  The transform along
-// the contiguous axis is real-to-half-complex; the other axes are complex.
-// Transforms are pruned: the inverse keeps only rows |r| <= P of each axis,
-// and the transforms of the cotangent boxes read only those rows.
+// Appendix B) by the convolution theorem, the Fourier route to correlations the
+// paper points to (Sec. 3.2 and Sec. 4.1).  The transform along the contiguous
+// axis is real-to-half-complex; the other axes are complex.  Transforms are
+// pruned: the inverse keeps only rows |r| <= P of each axis, and the transforms
+// of the cotangent boxes read only those rows.
 //
-// Kernels (all one pass over HBM, work staged in LDS):
-//   k_pass       generic 1-D transform of a batch of pencils along one axis
+// Every kernel is one pass over HBM.  Pencils are transformed in two register
+// steps with one LDS exchange (fft_reg.h):
+//   k_rows       contiguous-axis transform of T rows; the tile is staged through
+//                LDS so that global loads and stores are flat and coalesced
+//   k_cols       strided-axis transform of T adjacent pencils; lanes of a wave
+//                walk adjacent pencils, so every global access is a T-wide run
 //   k_axis0_fwd  axis-0 forward DFT of every channel, pair products, pruned
 //                axis-0 inverse (the "reduce" step fused into the transform)
 //   k_axis0_adj  axis-0 forward DFT of fields and cotangent boxes, the adjoint
 //                product sum, full axis-0 inverse (in place)
 #include "dmcr_internal.h"
-#include "lds_fft.h"
+#include "fft_reg.h"
 
 namespace dmcr {
 
 namespace {
 
-__device__ __forceinline__ int wrap_box(int e, int P, int n)
+// tile geometry per transform length: T pencils per block, R2 threads each,
+// with the LDS exchange (and the row staging) within 64 KB
+template <int L>
+struct Tile {
+    static constexpr int R2 = Split<L>::R2;
+    static constexpr int n = Split<L>::n;
+    static constexpr int pick()
+    {
+        int T = 256 / R2;
+        while (T > 1 && (ex_size<L>(T) > 8192 || T * (n + 1) > 8192)) T /= 2;
+        return T;
+    }
+    static constexpr int T = pick();
+    static constexpr int threads = R2 * T;
+    static constexpr int lds = (ex_size<L>(T) > T * (n + 1)) ? ex_size<L>(T) : T * (n + 1);
+};
+
+// row index e of an array that holds `mode` rows of a length-n axis, for
+// transform index j; -1 if that index is not stored
+__device__ __forceinline__ int row_of(int mode, int j, int n, int P)
 {
-    int pos = e - P;
-    return pos < 0 ? pos + n : pos;
+    if (mode == IO_FULL) return j;
+    if (mode == IO_HALF) return j <= n / 2 ? j : -1;
+    const int b = (j + P) & (n - 1);  // IO_BOX / IO_DESC: box index of j
+    return b <= 2 * P ? b : -1;
 }
 
-struct PassArgs {
+struct RowArgs {
     const void *in;
     void *out;
-    int64_t npen;     // number of pencils
-    int64_t inner;    // element stride along the transformed axis
-    int n, log2n, T;  // transform length, pencils per block
-    int in_mode, out_mode;
-    int in_len, out_len;  // rows of the input / output arrays along the axis
-    int P;
-    int in_real, out_real, inv;
+    int64_t nrows;
+    int in_mode, out_mode, in_len, out_len, P;
+    int in_real, out_real;
     float scale;
-    // IO_DESC: pencil m = (b * npairs + p) * rows_per_pair + row; entry e of the
-    // row is box index row * box + e of pair p.
+    FastDivU fd_in, fd_out;
+    // IO_DESC: row m = (b * npairs + p) * rows_per_pair + row of the box of pair p
     int npairs, auto_mask;
     int64_t rows_per_pair, center, Kstride;
     int64_t off[kMaxPairs];
 };
 
-__global__ __launch_bounds__(NT) void k_pass(PassArgs a)
+template <int TAG, int L, bool INV>
+__global__ __launch_bounds__(256) void k_rows(RowArgs a)
 {
-    extern __shared__ float2 sm[];
-    const int n = a.n, T = a.T;
-    float2 *tw = sm;
-    float2 *buf = sm + n;
+    using SP = Split<L>;
+    constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S, NTH = Tile<L>::threads;
+    constexpr int pitch = n + 1;
+    __shared__ float2 sm[Tile<L>::lds];
+    __shared__ int64_t dst_row[T];
+    const int tid = threadIdx.x;
+    const int t = tid % T, p = tid / T;
     const int64_t m0 = (int64_t)blockIdx.x * T;
-    init_twiddles(tw, n);
-    if (a.in_mode == IO_BOX) {
-        for (int i = threadIdx.x; i < T * n; i += NT) buf[i] = make_float2(0.f, 0.f);
-        __syncthreads();
-    }
-    const int total_in = T * a.in_len;
-    for (int idx = threadIdx.x; idx < total_in; idx += NT) {
-        int t, e;
-        if (a.inner == 1) {
-            t = idx / a.in_len;
-            e = idx - t * a.in_len;
-        } else {
-            e = idx / T;
-            t = idx - e * T;
+    const int nvalid = (int)((a.nrows - m0) < T ? (a.nrows - m0) : T);
+
+    // flat, coalesced load of the tile (rows are contiguous in memory)
+    {
+        const int64_t base = m0 * a.in_len;
+        const int lim = nvalid * a.in_len;
+        for (int idx = tid; idx < T * a.in_len; idx += NTH) {
+            const int r = fdivu(idx, a.fd_in);
+            const int e = idx - r * a.in_len;
+            float2 v = make_float2(0.f, 0.f);
+            if (idx < lim) {
+                if (a.in_real)
+                    v.x = static_cast<const float *>(a.in)[base + idx];
+                else
+                    v = static_cast<const float2 *>(a.in)[base + idx];
+            }
+            sm[r * pitch + e] = v;
         }
-        const int64_t m = m0 + t;
-        float2 v = make_float2(0.f, 0.f);
-        if (m < a.npen) {
-            const int64_t o = m / a.inner;
-            const int64_t i = m - o * a.inner;
-            const int64_t addr = (o * a.in_len + e) * a.inner + i;
-            if (a.in_real)
-                v.x = static_cast<const float *>(a.in)[addr];
-            else
-                v = static_cast<const float2 *>(a.in)[addr];
-        }
-        const int pos = (a.in_mode == IO_BOX) ? wrap_box(e, a.P, n) : e;
-        buf[pos * T + t] = v;
-        if (a.in_mode == IO_HALF && e > 0 && e < n / 2) buf[(n - e) * T + t] = c_conj(v);
     }
     __syncthreads();
-    lds_fft(buf, T, T, n, a.log2n, tw, a.inv != 0);
-    const int total_out = T * a.out_len;
-    for (int idx = threadIdx.x; idx < total_out; idx += NT) {
-        int t, e;
-        if (a.inner == 1) {
-            t = idx / a.out_len;
-            e = idx - t * a.out_len;
+    float2 v[R1];
+#pragma unroll
+    for (int i1 = 0; i1 < R1; ++i1) {
+        const int j = R2 * i1 + p;
+        float2 x = make_float2(0.f, 0.f);
+        if (a.in_mode == IO_HALF && j > n / 2) {
+            x = c_conj(sm[t * pitch + (n - j)]);
         } else {
-            e = idx / T;
-            t = idx - e * T;
+            const int e = row_of(a.in_mode, j, n, a.P);
+            if (e >= 0) x = sm[t * pitch + e];
         }
-        const int64_t m = m0 + t;
-        if (m >= a.npen) continue;
-        const int pos = (a.out_mode == IO_BOX || a.out_mode == IO_DESC) ? wrap_box(e, a.P, n) : e;
-        const float2 v = c_scale(buf[pos * T + t], a.scale);
-        if (a.out_mode == IO_DESC) {
-            const int64_t row = m % a.rows_per_pair;
-            const int64_t bp = m / a.rows_per_pair;
-            const int p = (int)(bp % a.npairs);
-            const int64_t b = bp / a.npairs;
-            const int64_t bi = row * a.out_len + e;
-            int64_t k = bi;
-            if ((a.auto_mask >> p) & 1) {
-                if (bi < a.center) continue;
-                k = bi - a.center;
-            }
-            static_cast<float *>(a.out)[b * a.Kstride + a.off[p] + k] = v.x;
-        } else {
-            const int64_t o = m / a.inner;
-            const int64_t i = m - o * a.inner;
-            const int64_t addr = (o * a.out_len + e) * a.inner + i;
+        v[i1] = x;
+    }
+    __syncthreads();
+    float2 u[S][R2];
+    pencil_fwd<L, INV>(v, u, sm, p, t, T);
+    // results back to the staging rows (natural output order)
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) {
+            const int k = (p + R2 * s) + R1 * k2;
+            const int e = row_of(a.out_mode, k, n, a.P);
+            if (e >= 0) sm[t * pitch + e] = c_scale(u[s][k2], a.scale);
+        }
+    if (a.out_mode == IO_DESC && tid < T) {
+        // descriptor position of entry 0 of each row of the tile
+        const uint32_t m = (uint32_t)(m0 + tid);
+        const uint32_t row = m % (uint32_t)a.rows_per_pair;
+        const uint32_t bp = m / (uint32_t)a.rows_per_pair;
+        const int q = (int)(bp % (uint32_t)a.npairs);
+        const int64_t b = bp / (uint32_t)a.npairs;
+        const bool aut = (a.auto_mask >> q) & 1;
+        dst_row[tid] = b * a.Kstride + a.off[q] + (int64_t)row * a.out_len - (aut ? a.center : 0);
+    }
+    __syncthreads();
+    if (a.out_mode == IO_DESC) {
+        for (int idx = tid; idx < nvalid * a.out_len; idx += NTH) {
+            const int r = fdivu(idx, a.fd_out);
+            const int e = idx - r * a.out_len;
+            const uint32_t m = (uint32_t)(m0 + r);
+            const uint32_t row = m % (uint32_t)a.rows_per_pair;
+            const int q = (int)((m / (uint32_t)a.rows_per_pair) % (uint32_t)a.npairs);
+            if (((a.auto_mask >> q) & 1) && (int64_t)row * a.out_len + e < a.center) continue;
+            static_cast<float *>(a.out)[dst_row[r] + e] = sm[r * pitch + e].x;
+        }
+    } else {
+        const int64_t base = m0 * a.out_len;
+        for (int idx = tid; idx < nvalid * a.out_len; idx += NTH) {
+            const int r = fdivu(idx, a.fd_out);
+            const int e = idx - r * a.out_len;
+            const float2 x = sm[r * pitch + e];
             if (a.out_real)
-                static_cast<float *>(a.out)[addr] = v.x;
+                static_cast<float *>(a.out)[base + idx] = x.x;
             else
-                static_cast<float2 *>(a.out)[addr] = v;
+                static_cast<float2 *>(a.out)[base + idx] = x;
         }
     }
+}
+
+struct ColArgs {
+    const float2 *in;
+    float2 *out;
+    int64_t npen, inner;
+    int in_mode, out_mode, in_len, out_len, P;
+    float scale;
+};
+
+template <int TAG, int L, bool INV>
+__global__ __launch_bounds__(256) void k_cols(ColArgs a)
+{
+    using SP = Split<L>;
+    constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
+    __shared__ float2 ex[ex_size<L>(T)];
+    const int t = threadIdx.x % T, p = threadIdx.x / T;
+    const int64_t m = (int64_t)blockIdx.x * T + t;
+    const bool valid = m < a.npen;
+    int64_t o = 0, i = 0;
+    if (valid) {
+        o = m / a.inner;
+        i = m - o * a.inner;
+    }
+    const float2 *src = a.in + o * a.in_len * a.inner + i;
+    float2 v[R1];
+#pragma unroll
+    for (int i1 = 0; i1 < R1; ++i1) {
+        const int e = row_of(a.in_mode, R2 * i1 + p, n, a.P);
+        v[i1] = (valid && e >= 0) ? src[(int64_t)e * a.inner] : make_float2(0.f, 0.f);
+    }
+    float2 u[S][R2];
+    pencil_fwd<L, INV>(v, u, ex, p, t, T);
+    if (!valid) return;
+    float2 *dst = a.out + o * a.out_len * a.inner + i;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) {
+            const int e = row_of(a.out_mode, (p + R2 * s) + R1 * k2, n, a.P);
+            if (e >= 0) dst[(int64_t)e * a.inner] = c_scale(u[s][k2], a.scale);
+        }
 }
 
 struct Axis0Args {
@@ -128,117 +205,120 @@ struct Axis0Args {
     const float2 *KB;   // adjoint: [B][C*C][box][inner]
     float2 *Y;          // forward: [B][npairs][box][inner]
     int64_t inner, nloc;  // nloc = B * inner pencil locations
-    int C, n, log2n, P, box, T, npairs;
-    int pi[kMaxPairs], pj[kMaxPairs];
+    int P, box, npairs;
+    int pair_of[kMaxChannels * kMaxChannels];  // (i, j) -> pair index or -1
     float scale;
 };
 
-// Load the axis-0 pencils of every channel at T consecutive locations into
-// A[e * (C*T) + c*T + t].
-__device__ __forceinline__ void load_channels(const Axis0Args &a, int64_t m0, float2 *A)
+template <int L, int C>
+__global__ __launch_bounds__(256) void k_axis0_fwd(Axis0Args a)
 {
-    const int CT = a.C * a.T;
-    const int total = CT * a.n;
-    for (int idx = threadIdx.x; idx < total; idx += NT) {
-        const int t = idx % a.T;
-        const int r = idx / a.T;
-        const int c = r % a.C;
-        const int e = r / a.C;
-        const int64_t m = m0 + t;
-        float2 v = make_float2(0.f, 0.f);
-        if (m < a.nloc) {
-            const int64_t b = m / a.inner;
-            const int64_t i = m - b * a.inner;
-            v = a.X[((b * a.C + c) * a.n + e) * a.inner + i];
-        }
-        A[e * CT + c * a.T + t] = v;
+    using SP = Split<L>;
+    constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
+    __shared__ float2 ex[ex_size<L>(T)];
+    const int t = threadIdx.x % T, p = threadIdx.x / T;
+    const int64_t m = (int64_t)blockIdx.x * T + t;
+    const bool valid = m < a.nloc;
+    int64_t b = 0, i = 0;
+    if (valid) {
+        b = m / a.inner;
+        i = m - b * a.inner;
     }
+    float2 X[C][S][R2];
+    static_for<0, C>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        const float2 *src = a.X + (b * C + c) * n * a.inner + i;
+        float2 v[R1];
+#pragma unroll
+        for (int i1 = 0; i1 < R1; ++i1)
+            v[i1] = valid ? src[(int64_t)(R2 * i1 + p) * a.inner] : make_float2(0.f, 0.f);
+        pencil_fwd<L, false>(v, X[c], ex, p, t, T);
+    });
+    static_for<0, C>([&](auto ic) {
+        constexpr int ci = decltype(ic)::value;
+        static_for<ci, C>([&](auto jc) {
+            constexpr int cj = decltype(jc)::value;
+            const int q = a.pair_of[ci * kMaxChannels + cj];
+            if (q >= 0) {
+                float2 w[S][R2];
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+#pragma unroll
+                    for (int k = 0; k < R2; ++k) w[s][k] = c_scale(c_cmul(X[ci][s][k], X[cj][s][k]), a.scale);
+                float2 out[R1];
+                pencil_mirror<L, true>(w, out, ex, p, t, T);
+                if (valid) {
+                    float2 *dst = a.Y + (b * a.npairs + q) * a.box * a.inner + i;
+#pragma unroll
+                    for (int j1 = 0; j1 < R1; ++j1) {
+                        const int e = row_of(IO_BOX, p + R2 * j1, n, a.P);
+                        if (e >= 0) dst[(int64_t)e * a.inner] = out[j1];
+                    }
+                }
+            }
+        });
+    });
 }
 
-__global__ __launch_bounds__(NT) void k_axis0_fwd(Axis0Args a)
+template <int L, int C>
+__global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
 {
-    extern __shared__ float2 sm[];
-    const int n = a.n, T = a.T, CT = a.C * a.T;
-    float2 *tw = sm;
-    float2 *A = tw + n;
-    float2 *W = A + CT * n;
-    const int64_t m0 = (int64_t)blockIdx.x * T;
-    init_twiddles(tw, n);
-    load_channels(a, m0, A);
-    __syncthreads();
-    lds_fft(A, CT, CT, n, a.log2n, tw, false);
-    for (int p = 0; p < a.npairs; ++p) {
-        const int ci = a.pi[p], cj = a.pj[p];
-        for (int idx = threadIdx.x; idx < T * n; idx += NT) {
-            const int e = idx / T, t = idx - e * T;
-            W[idx] = c_scale(c_cmul(A[e * CT + ci * T + t], A[e * CT + cj * T + t]), a.scale);
-        }
-        __syncthreads();
-        lds_fft(W, T, T, n, a.log2n, tw, true);
-        for (int idx = threadIdx.x; idx < T * a.box; idx += NT) {
-            const int e = idx / T, t = idx - e * T;
-            const int64_t m = m0 + t;
-            if (m < a.nloc) {
-                const int64_t b = m / a.inner;
-                const int64_t i = m - b * a.inner;
-                a.Y[((b * a.npairs + p) * a.box + e) * a.inner + i] = W[wrap_box(e, a.P, n) * T + t];
-            }
-        }
-        __syncthreads();
+    using SP = Split<L>;
+    constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
+    __shared__ float2 ex[ex_size<L>(T)];
+    const int t = threadIdx.x % T, p = threadIdx.x / T;
+    const int64_t m = (int64_t)blockIdx.x * T + t;
+    const bool valid = m < a.nloc;
+    int64_t b = 0, i = 0;
+    if (valid) {
+        b = m / a.inner;
+        i = m - b * a.inner;
     }
-}
-
-__global__ __launch_bounds__(NT) void k_axis0_adj(Axis0Args a)
-{
-    extern __shared__ float2 sm[];
-    const int n = a.n, T = a.T, C = a.C, CT = a.C * a.T;
-    float2 *tw = sm;
-    float2 *A = tw + n;
-    float2 *W = A + CT * n;
-    float2 *ACC = W + CT * n;
-    const int64_t m0 = (int64_t)blockIdx.x * T;
-    init_twiddles(tw, n);
-    load_channels(a, m0, A);
-    __syncthreads();
-    lds_fft(A, CT, CT, n, a.log2n, tw, false);
-    for (int c = 0; c < C; ++c) {
-        for (int i = threadIdx.x; i < CT * n; i += NT) W[i] = make_float2(0.f, 0.f);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < CT * a.box; idx += NT) {
-            const int t = idx % T;
-            const int r = idx / T;
-            const int j = r % C;
-            const int e = r / C;
-            const int64_t m = m0 + t;
-            if (m < a.nloc) {
-                const int64_t b = m / a.inner;
-                const int64_t i = m - b * a.inner;
-                W[wrap_box(e, a.P, n) * CT + j * T + t] =
-                    a.KB[((b * C * C + c * C + j) * a.box + e) * a.inner + i];
+    float2 X[C][S][R2];
+    static_for<0, C>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        const float2 *src = a.X + (b * C + c) * n * a.inner + i;
+        float2 v[R1];
+#pragma unroll
+        for (int i1 = 0; i1 < R1; ++i1)
+            v[i1] = valid ? src[(int64_t)(R2 * i1 + p) * a.inner] : make_float2(0.f, 0.f);
+        pencil_fwd<L, false>(v, X[c], ex, p, t, T);
+    });
+    static_for<0, C>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        float2 acc[S][R2];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < R2; ++k) acc[s][k] = make_float2(0.f, 0.f);
+        static_for<0, C>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const float2 *kb = a.KB + (b * C * C + c * C + j) * a.box * a.inner + i;
+            float2 v[R1];
+#pragma unroll
+            for (int i1 = 0; i1 < R1; ++i1) {
+                const int e = row_of(IO_BOX, R2 * i1 + p, n, a.P);
+                v[i1] = (valid && e >= 0) ? kb[(int64_t)e * a.inner] : make_float2(0.f, 0.f);
             }
+            float2 K[S][R2];
+            pencil_fwd<L, false>(v, K, ex, p, t, T);
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int k = 0; k < R2; ++k) acc[s][k] = c_add(acc[s][k], c_cmul(K[s][k], X[j][s][k]));
+        });
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < R2; ++k) acc[s][k] = c_scale(acc[s][k], a.scale);
+        float2 out[R1];
+        pencil_mirror<L, true>(acc, out, ex, p, t, T);
+        if (valid) {
+            float2 *dst = a.X + (b * C + c) * n * a.inner + i;
+#pragma unroll
+            for (int j1 = 0; j1 < R1; ++j1) dst[(int64_t)(p + R2 * j1) * a.inner] = out[j1];
         }
-        __syncthreads();
-        lds_fft(W, CT, CT, n, a.log2n, tw, false);
-        for (int idx = threadIdx.x; idx < T * n; idx += NT) {
-            const int e = idx / T, t = idx - e * T;
-            float2 s = make_float2(0.f, 0.f);
-            for (int j = 0; j < C; ++j)
-                s = c_add(s, c_cmul(W[e * CT + j * T + t], A[e * CT + j * T + t]));
-            ACC[idx] = c_scale(s, a.scale);
-        }
-        __syncthreads();
-        lds_fft(ACC, T, T, n, a.log2n, tw, true);
-        for (int idx = threadIdx.x; idx < T * n; idx += NT) {
-            const int e = idx / T, t = idx - e * T;
-            const int64_t m = m0 + t;
-            if (m < a.nloc) {
-                const int64_t b = m / a.inner;
-                const int64_t i = m - b * a.inner;
-                a.X[((b * C + c) * n + e) * a.inner + i] = ACC[idx];
-            }
-        }
-        __syncthreads();
-    }
+    });
 }
 
 int ilog2(int n)
@@ -248,41 +328,111 @@ int ilog2(int n)
     return l;
 }
 
-int pow2_floor(int x)
+enum PassTag {
+    T_R2C_LAST = 0,    // forward, contiguous axis, real -> half spectrum
+    T_FWD_MID,         // forward, axis 1 (3-D), in place
+    T_INV_MID_BOX,     // inverse, axis 1 (3-D), keep the |r1| <= P rows
+    T_C2R_DESC,        // inverse, contiguous axis, half -> real rows of the box, into S
+    T_KB_LAST,         // forward of the cotangent boxes, contiguous axis
+    T_KB_MID,          // forward of the cotangent boxes, axis 1 (3-D)
+    T_INV_MID,         // inverse, axis 1 (3-D), in place
+    T_C2R_FULL         // inverse, contiguous axis, half -> real field
+};
+
+const char *const kPassName[] = {"r2c_last", "fwd_mid", "inv_mid_box", "c2r_last_desc",
+                                 "kb_last", "kb_mid", "inv_mid", "c2r_last"};
+
+// threads and tile per L (host mirror of Tile<L>)
+struct TileInfo {
+    int T, threads;
+};
+
+template <int L>
+TileInfo tile_info()
 {
-    int p = 1;
-    while (p * 2 <= x) p *= 2;
-    return p;
+    return TileInfo{Tile<L>::T, Tile<L>::threads};
 }
 
-constexpr size_t kLdsBudget = 64 * 1024;  // bytes of dynamic LDS per block
-
-hipError_t run_pass(PassArgs a, hipStream_t st)
+TileInfo tile_of(int L)
 {
-    // pencils per block: fill the FFT budget, at most 64 pencils
-    int T = kFftMaxElems / a.n;
-    T = T > 64 ? 64 : T;
-    while (T > 1 && (size_t)(a.n + T * a.n) * sizeof(float2) > kLdsBudget) T /= 2;
-    if (T < 1) T = 1;
-    if ((int64_t)T > a.npen) T = pow2_floor((int)(a.npen < 1 ? 1 : a.npen));
-    a.T = T;
-    a.log2n = ilog2(a.n);
-    const int64_t blocks = (a.npen + T - 1) / T;
-    const size_t lds = (size_t)(a.n + T * a.n) * sizeof(float2);
-    hipLaunchKernelGGL(k_pass, dim3((unsigned)blocks), dim3(NT), lds, st, a);
-    return hipGetLastError();
+    switch (L) {
+    case 1: return tile_info<1>();
+    case 2: return tile_info<2>();
+    case 3: return tile_info<3>();
+    case 4: return tile_info<4>();
+    case 5: return tile_info<5>();
+    case 6: return tile_info<6>();
+    case 7: return tile_info<7>();
+    case 8: return tile_info<8>();
+    case 9: return tile_info<9>();
+    default: return tile_info<10>();
+    }
 }
 
-PassArgs pass_args(const void *in, void *out, int64_t npen, int64_t inner, int n, int in_mode,
-                   int in_len, int out_mode, int out_len, int P, bool in_real, bool out_real, bool inv,
-                   float scale)
+#define DMCR_L_CASES(MACRO) \
+    MACRO(1) MACRO(2) MACRO(3) MACRO(4) MACRO(5) MACRO(6) MACRO(7) MACRO(8) MACRO(9) MACRO(10)
+
+template <int TAG, bool INV>
+hipError_t rows_launch(int L, const RowArgs &a, double bytes, hipStream_t st)
 {
-    PassArgs a{};
+    const TileInfo ti = tile_of(L);
+    const dim3 g((unsigned)((a.nrows + ti.T - 1) / ti.T)), b(ti.threads);
+    switch (L) {
+#define C_(LL) \
+    case LL: return launch(kPassName[TAG], bytes, k_rows<TAG, LL, INV>, g, b, 0, st, a);
+        DMCR_L_CASES(C_)
+#undef C_
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int TAG, bool INV>
+hipError_t cols_launch(int L, const ColArgs &a, double bytes, hipStream_t st)
+{
+    const TileInfo ti = tile_of(L);
+    const dim3 g((unsigned)((a.npen + ti.T - 1) / ti.T)), b(ti.threads);
+    switch (L) {
+#define C_(LL) \
+    case LL: return launch(kPassName[TAG], bytes, k_cols<TAG, LL, INV>, g, b, 0, st, a);
+        DMCR_L_CASES(C_)
+#undef C_
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int C>
+hipError_t axis0_launch_c(bool adj, int L, const Axis0Args &a, double bytes, hipStream_t st)
+{
+    const TileInfo ti = tile_of(L);
+    const dim3 g((unsigned)((a.nloc + ti.T - 1) / ti.T)), b(ti.threads);
+    switch (L) {
+#define C_(LL)                                                                           \
+    case LL:                                                                             \
+        return adj ? launch("axis0_adj", bytes, k_axis0_adj<LL, C>, g, b, 0, st, a)      \
+                   : launch("axis0_fwd", bytes, k_axis0_fwd<LL, C>, g, b, 0, st, a);
+        DMCR_L_CASES(C_)
+#undef C_
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t axis0_launch(int C, bool adj, int L, const Axis0Args &a, double bytes, hipStream_t st)
+{
+    switch (C) {
+    case 1: return axis0_launch_c<1>(adj, L, a, bytes, st);
+    case 2: return axis0_launch_c<2>(adj, L, a, bytes, st);
+    case 3: return axis0_launch_c<3>(adj, L, a, bytes, st);
+    default: return axis0_launch_c<4>(adj, L, a, bytes, st);
+    }
+}
+
+RowArgs row_args(const void *in, void *out, int64_t nrows, int in_mode, int in_len, int out_mode, int out_len,
+                 int P, bool in_real, bool out_real, float scale)
+{
+    RowArgs a{};
     a.in = in;
     a.out = out;
-    a.npen = npen;
-    a.inner = inner;
-    a.n = n;
+    a.nrows = nrows;
     a.in_mode = in_mode;
     a.in_len = in_len;
     a.out_mode = out_mode;
@@ -290,20 +440,41 @@ PassArgs pass_args(const void *in, void *out, int64_t npen, int64_t inner, int n
     a.P = P;
     a.in_real = in_real;
     a.out_real = out_real;
-    a.inv = inv;
     a.scale = scale;
+    a.fd_in = make_fastdivu(in_len);
+    a.fd_out = make_fastdivu(out_len);
     return a;
 }
 
-int axis0_T(int C, int n, int bufs_of_CT, int extra)
+double row_bytes(const RowArgs &a)
 {
-    // LDS = (n + (bufs_of_CT*C + extra) * T * n) * 8 <= budget; FFT call C*T*n <= max
-    int T = 16;
-    while (T > 1 && ((size_t)(n + (bufs_of_CT * C + extra) * T * n) * sizeof(float2) > kLdsBudget ||
-                     C * T * n > kFftMaxElems))
-        T /= 2;
-    return T;
+    return (double)a.nrows * a.in_len * (a.in_real ? 4 : 8) + (double)a.nrows * a.out_len * (a.out_real ? 4 : 8);
 }
+
+ColArgs col_args(const float2 *in, float2 *out, int64_t npen, int64_t inner, int in_mode, int in_len, int out_mode,
+                 int out_len, int P)
+{
+    ColArgs a{};
+    a.in = in;
+    a.out = out;
+    a.npen = npen;
+    a.inner = inner;
+    a.in_mode = in_mode;
+    a.in_len = in_len;
+    a.out_mode = out_mode;
+    a.out_len = out_len;
+    a.P = P;
+    a.scale = 1.f;
+    return a;
+}
+
+double col_bytes(const ColArgs &a) { return (double)a.npen * (a.in_len + a.out_len) * 8; }
+
+#define TRY_HIP(expr)                         \
+    do {                                      \
+        hipError_t _e = (expr);               \
+        if (_e != hipSuccess) return _e;      \
+    } while (0)
 
 }  // namespace
 
@@ -312,12 +483,7 @@ bool fft_supported(const Plan &p, int l)
     const LevelPlan &L = p.lv[l];
     for (int a = 0; a < p.ndim; ++a)
         if (L.n[a] > kMaxFft || L.n[a] < 2) return false;
-    const int n0 = L.n[0];
-    const int C = p.C;
-    // axis-0 adjoint kernel needs (2C + 1) T n0 + n0 complex values with T >= 1
-    if ((size_t)(n0 + (2 * C + 1) * n0) * sizeof(float2) > kLdsBudget) return false;
-    if (C * n0 > kFftMaxElems) return false;
-    return true;
+    return p.C <= 4;
 }
 
 // Half spectrum of every channel, transformed along every axis except 0:
@@ -327,29 +493,22 @@ hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C;
     float2 *X = ws.at<float2>(L.X);
-    hipError_t e;
-    if (p.ndim == 2) {
-        const int n0 = L.n[0], n1 = L.n[1];
-        e = run_pass(pass_args(phi, X, (int64_t)B * C * n0, 1, n1, IO_FULL, n1, IO_HALF, L.h, 0, true,
-                               false, false, 1.f), st);
-        return e;
+    const int nl = L.n[p.ndim - 1];
+    const int64_t rows = (p.ndim == 2) ? (int64_t)B * C * L.n[0] : (int64_t)B * C * L.n[0] * L.n[1];
+    RowArgs r = row_args(phi, X, rows, IO_FULL, nl, IO_HALF, L.h, 0, true, false, 1.f);
+    TRY_HIP((rows_launch<T_R2C_LAST, false>(ilog2(nl), r, row_bytes(r), st)));
+    if (p.ndim == 3) {
+        ColArgs c = col_args(X, X, (int64_t)B * C * L.n[0] * L.h, L.h, IO_FULL, L.n[1], IO_FULL, L.n[1], 0);
+        TRY_HIP((cols_launch<T_FWD_MID, false>(ilog2(L.n[1]), c, col_bytes(c), st)));
     }
-    const int n0 = L.n[0], n1 = L.n[1], n2 = L.n[2];
-    e = run_pass(pass_args(phi, X, (int64_t)B * C * n0 * n1, 1, n2, IO_FULL, n2, IO_HALF, L.h, 0, true,
-                           false, false, 1.f), st);
-    if (e != hipSuccess) return e;
-    e = run_pass(pass_args(X, X, (int64_t)B * C * n0 * L.h, L.h, n1, IO_FULL, n1, IO_FULL, n1, 0, false,
-                           false, false, 1.f), st);
-    return e;
+    return hipSuccess;
 }
 
-hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
-                             hipStream_t st)
+hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws, hipStream_t st)
 {
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C;
-    hipError_t e = fft_spectrum_level(p, l, phi, ws, st);
-    if (e != hipSuccess) return e;
+    TRY_HIP(fft_spectrum_level(p, l, phi, ws, st));
     float2 *X = ws.at<float2>(L.X);
     float2 *Y = ws.at<float2>(L.Y);
     const int n0 = L.n[0];
@@ -361,40 +520,28 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
     a.Y = Y;
     a.inner = inner;
     a.nloc = (int64_t)B * inner;
-    a.C = C;
-    a.n = n0;
-    a.log2n = ilog2(n0);
     a.P = L.P;
     a.box = L.box;
     a.npairs = p.npairs;
-    for (int q = 0; q < p.npairs; ++q) {
-        a.pi[q] = p.pi[q];
-        a.pj[q] = p.pj[q];
-    }
+    for (int k = 0; k < kMaxChannels * kMaxChannels; ++k) a.pair_of[k] = -1;
+    for (int q = 0; q < p.npairs; ++q) a.pair_of[p.pi[q] * kMaxChannels + p.pj[q]] = q;
     a.scale = (float)(invN * invN);
-    a.T = axis0_T(C, n0, 1, 1);
-    {
-        const size_t lds = (size_t)(n0 + (C + 1) * a.T * n0) * sizeof(float2);
-        const int64_t blocks = (a.nloc + a.T - 1) / a.T;
-        hipLaunchKernelGGL(k_axis0_fwd, dim3((unsigned)blocks), dim3(NT), lds, st, a);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    const double bytes0 = (double)B * C * n0 * inner * 8 + (double)B * p.npairs * L.box * inner * 8;
+    TRY_HIP(axis0_launch(C, false, ilog2(n0), a, bytes0, st));
 
     // remaining inverse axes, pruned, then scatter into descriptor order
     const float2 *last_in = Y;
     int64_t rows_per_pair = L.box;
     if (p.ndim == 3) {
         float2 *Y2 = ws.at<float2>(L.Y2);
-        e = run_pass(pass_args(Y, Y2, (int64_t)B * p.npairs * L.box * L.h, L.h, L.n[1], IO_FULL, L.n[1],
-                               IO_BOX, L.box, L.P, false, false, true, 1.f), st);
-        if (e != hipSuccess) return e;
+        ColArgs c = col_args(Y, Y2, (int64_t)B * p.npairs * L.box * L.h, L.h, IO_FULL, L.n[1], IO_BOX, L.box, L.P);
+        TRY_HIP((cols_launch<T_INV_MID_BOX, true>(ilog2(L.n[1]), c, col_bytes(c), st)));
         last_in = Y2;
         rows_per_pair = (int64_t)L.box * L.box;
     }
     const int nl = L.n[p.ndim - 1];
-    PassArgs d = pass_args(last_in, S + 0, (int64_t)B * p.npairs * rows_per_pair, 1, nl, IO_HALF, L.h,
-                           IO_DESC, L.box, L.P, false, true, true, 1.f);
+    RowArgs d = row_args(last_in, S, (int64_t)B * p.npairs * rows_per_pair, IO_HALF, L.h, IO_DESC, L.box, L.P,
+                         false, true, 1.f);
     d.npairs = p.npairs;
     d.rows_per_pair = rows_per_pair;
     d.Kstride = p.K;
@@ -406,7 +553,7 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
         d.off[q] = L.off[q];
         if (p.pi[q] == p.pj[q]) d.auto_mask |= 1 << q;
     }
-    return run_pass(d, st);
+    return rows_launch<T_C2R_DESC, true>(ilog2(nl), d, (double)d.nrows * L.h * 8 + (double)d.nrows * L.box * 4, st);
 }
 
 hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
@@ -414,32 +561,25 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
 {
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C, CC = C * C;
-    hipError_t e;
     float *KB0 = ws.at<float>(L.KB0);
     float2 *KB1 = ws.at<float2>(L.KB1);
-    e = launch_build_kernels(p, l, G, KB0, st);
-    if (e != hipSuccess) return e;
+    TRY_HIP(launch_build_kernels(p, l, G, KB0, st));
     const int nl = L.n[p.ndim - 1];
     const float2 *KBaxis0;
     if (p.ndim == 2) {
-        e = run_pass(pass_args(KB0, KB1, (int64_t)B * CC * L.box, 1, nl, IO_BOX, L.box, IO_HALF, L.h, L.P,
-                               true, false, false, 1.f), st);
-        if (e != hipSuccess) return e;
+        RowArgs r = row_args(KB0, KB1, (int64_t)B * CC * L.box, IO_BOX, L.box, IO_HALF, L.h, L.P, true, false, 1.f);
+        TRY_HIP((rows_launch<T_KB_LAST, false>(ilog2(nl), r, row_bytes(r), st)));
         KBaxis0 = KB1;
     } else {
         float2 *KB2 = ws.at<float2>(L.KB2);
-        e = run_pass(pass_args(KB0, KB1, (int64_t)B * CC * L.box * L.box, 1, nl, IO_BOX, L.box, IO_HALF,
-                               L.h, L.P, true, false, false, 1.f), st);
-        if (e != hipSuccess) return e;
-        e = run_pass(pass_args(KB1, KB2, (int64_t)B * CC * L.box * L.h, L.h, L.n[1], IO_BOX, L.box, IO_FULL,
-                               L.n[1], L.P, false, false, false, 1.f), st);
-        if (e != hipSuccess) return e;
+        RowArgs r = row_args(KB0, KB1, (int64_t)B * CC * L.box * L.box, IO_BOX, L.box, IO_HALF, L.h, L.P, true,
+                             false, 1.f);
+        TRY_HIP((rows_launch<T_KB_LAST, false>(ilog2(nl), r, row_bytes(r), st)));
+        ColArgs c = col_args(KB1, KB2, (int64_t)B * CC * L.box * L.h, L.h, IO_BOX, L.box, IO_FULL, L.n[1], L.P);
+        TRY_HIP((cols_launch<T_KB_MID, false>(ilog2(L.n[1]), c, col_bytes(c), st)));
         KBaxis0 = KB2;
     }
-    if (!have_spectrum) {
-        e = fft_spectrum_level(p, l, phi, ws, st);
-        if (e != hipSuccess) return e;
-    }
+    if (!have_spectrum) TRY_HIP(fft_spectrum_level(p, l, phi, ws, st));
     float2 *X = ws.at<float2>(L.X);
     const int n0 = L.n[0];
     const int64_t inner = (p.ndim == 2) ? L.h : (int64_t)L.n[1] * L.h;
@@ -449,28 +589,18 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
     a.KB = KBaxis0;
     a.inner = inner;
     a.nloc = (int64_t)B * inner;
-    a.C = C;
-    a.n = n0;
-    a.log2n = ilog2(n0);
     a.P = L.P;
     a.box = L.box;
     a.scale = (float)(invN * invN);
-    a.T = axis0_T(C, n0, 2, 1);
-    {
-        const size_t lds = (size_t)(n0 + (2 * C + 1) * a.T * n0) * sizeof(float2);
-        const int64_t blocks = (a.nloc + a.T - 1) / a.T;
-        hipLaunchKernelGGL(k_axis0_adj, dim3((unsigned)blocks), dim3(NT), lds, st, a);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    const double bytes0 = 2.0 * B * C * n0 * inner * 8 + (double)B * CC * L.box * inner * 8;
+    TRY_HIP(axis0_launch(C, true, ilog2(n0), a, bytes0, st));
     if (p.ndim == 3) {
-        e = run_pass(pass_args(X, X, (int64_t)B * C * n0 * L.h, L.h, L.n[1], IO_FULL, L.n[1], IO_FULL, L.n[1],
-                               0, false, false, true, 1.f), st);
-        if (e != hipSuccess) return e;
+        ColArgs c = col_args(X, X, (int64_t)B * C * n0 * L.h, L.h, IO_FULL, L.n[1], IO_FULL, L.n[1], 0);
+        TRY_HIP((cols_launch<T_INV_MID, true>(ilog2(L.n[1]), c, col_bytes(c), st)));
     }
     const int64_t rows = (p.ndim == 2) ? (int64_t)B * C * n0 : (int64_t)B * C * n0 * L.n[1];
-    return run_pass(pass_args(X, grad, rows, 1, nl, IO_HALF, L.h, IO_FULL, nl, 0, false, true, true, 1.f),
-                    st);
+    RowArgs r = row_args(X, grad, rows, IO_HALF, L.h, IO_FULL, nl, 0, false, true, 1.f);
+    return rows_launch<T_C2R_FULL, true>(ilog2(nl), r, row_bytes(r), st);
 }
 
 }  // namespace dmcr

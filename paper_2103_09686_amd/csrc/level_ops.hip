@@ -181,9 +181,8 @@ hipError_t launch_restrict(const Plan &p, int l, const float *fine, float *coars
     const LevelPlan &c = p.lv[l + 1];
     const int64_t total = (int64_t)p.B * p.C * c.N;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_restrict, dim3(blocks_for(total)), dim3(kThreads), 0, st, fine, coarse, total,
-                       p.ndim, c.n[0], c.n[1], c.n[2]);
-    return hipGetLastError();
+    return launch("restrict", (double)total * 4 * (1 + (1 << p.ndim)), k_restrict, dim3(blocks_for(total)),
+                  dim3(kThreads), 0, st, fine, coarse, total, p.ndim, c.n[0], c.n[1], c.n[2]);
 }
 
 hipError_t launch_prolong_add(const Plan &p, int l, const float *coarse_grad, float *fine_grad,
@@ -193,9 +192,9 @@ hipError_t launch_prolong_add(const Plan &p, int l, const float *coarse_grad, fl
     const int64_t total = (int64_t)p.B * p.C * f.N;
     if (total == 0) return hipSuccess;
     const float w = p.ndim == 2 ? 0.25f : 0.125f;
-    hipLaunchKernelGGL(k_prolong_add, dim3(blocks_for(total)), dim3(kThreads), 0, st, coarse_grad,
-                       fine_grad, total, p.ndim, f.n[0], f.n[1], f.n[2], w);
-    return hipGetLastError();
+    const double bytes = (double)total * 8 + (double)total * 4 / (1 << p.ndim);
+    return launch("prolong_add", bytes, k_prolong_add, dim3(blocks_for(total)), dim3(kThreads), 0, st,
+                  coarse_grad, fine_grad, total, p.ndim, f.n[0], f.n[1], f.n[2], w);
 }
 
 hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0, hipStream_t st)
@@ -215,8 +214,8 @@ hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0
         a.pj[q] = p.pj[q];
         a.off[q] = L.off[q];
     }
-    hipLaunchKernelGGL(k_build_kernels, dim3(blocks_for(a.total)), dim3(kThreads), 0, st, a);
-    return hipGetLastError();
+    const double bytes = (double)a.total * 4 + (double)p.B * (p.lvl_off[l + 1] - p.lvl_off[l]) * 4;
+    return launch("build_kernels", bytes, k_build_kernels, dim3(blocks_for(a.total)), dim3(kThreads), 0, st, a);
 }
 
 hipError_t launch_error(const Plan &p, const float *S, const double *St, double *E, float *G, const Ws &ws,
@@ -235,11 +234,11 @@ hipError_t launch_error(const Plan &p, const float *S, const double *St, double 
     for (int l = p.L + 1; l <= kMaxLevels; ++l) a.lvl_off[l] = INT64_MAX;
     for (int l = 0; l < p.L; ++l) a.w2[l] = p.w[l] * p.w[l];
     a.invZ = 1.0 / p.Z;
-    hipLaunchKernelGGL(k_error_partial, dim3((unsigned)a.chunks, (unsigned)p.B), dim3(kThreads), 0, st, a);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch("error_partial", (double)p.B * p.K * 16, k_error_partial,
+                          dim3((unsigned)a.chunks, (unsigned)p.B), dim3(kThreads), 0, st, a);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_error_final, dim3((unsigned)p.B), dim3(kThreads), 0, st, a.part, a.chunks, a.invZ, E);
-    return hipGetLastError();
+    return launch("error_final", (double)p.B * a.chunks * 8, k_error_final, dim3((unsigned)p.B), dim3(kThreads), 0,
+                  st, (const double *)a.part, a.chunks, a.invZ, E);
 }
 
 }  // namespace dmcr

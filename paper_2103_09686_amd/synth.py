@@ -1,7 +1,7 @@
 """Seeded synthetic microstructures (inputs only; none of the descriptor's arithmetic).
 
 These generators stand in for the paper's pyMKS and literature micrographs
-(Sec. 4.2), which are not available: periodic Boolean models of overlapping
+(Sec. 5.2), which are not available: periodic Boolean models of overlapping
 disks / spheres, thresholded periodic Gaussian random fields, a three-phase
 mix of spheres and randomly oriented ellipsoids, checkerboards and uniform
 noise.  Every function takes an explicit seed and returns float64 arrays of

@@ -1,6 +1,6 @@
 """Reconstruction (the paper's Fig. 1 loop) on the GPU.  Parity is on the final
 descriptor error, never on the field: every translation or point reflection of a
-solution has the same descriptor (Sec. 4.2, exact translations), and FP32 vs FP64
+solution has the same descriptor (Sec. 5.2, exact translations), and FP32 vs FP64
 trajectories diverge."""
 import numpy as np
 import pytest

@@ -54,7 +54,7 @@ def paper_convolve(M, m, P, Q):
 
 def paper_S_bar_identity(M, P, Q, p, q):
     """Quadratic reduction of the identity-thresholded ensemble (Sec. 3.2.2, eq. s3 with
-    r = p, s = q), i.e. S-bar for f_t(x) = x (Sec. 4.1)."""
+    r = p, s = q), i.e. S-bar for f_t(x) = x (Sec. 5.1, Fig. 6)."""
     e = paper_convolve(M, paper_mask(P, Q, p, q), P, Q)
     return float(np.sum(e * e) / M.size)
 

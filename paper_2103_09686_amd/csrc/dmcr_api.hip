@@ -106,6 +106,7 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
         if (L.P < 0 || L.P > minax / 2 - 1) return DMCR_EINVAL;
         L.box = 2 * L.P + 1;
         L.h = L.n[p.ndim - 1] / 2 + 1;
+        L.hp = (L.n[p.ndim - 1] >= 32) ? (L.h + 15) / 16 * 16 : L.h;
         if (!(s->level_weight[l] > 0.0) || !std::isfinite(s->level_weight[l])) return DMCR_EINVAL;
         p.w[l] = s->level_weight[l];
         int64_t vol = 1;
@@ -157,19 +158,19 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
         }
         int64_t vol = 1;
         for (int a = 0; a < p.ndim; ++a) vol *= L.box;
-        L.KB0 = cv.take((size_t)B * C * C * vol * sizeof(float));
+        if (L.path == DMCR_PATH_DIRECT) L.KB0 = cv.take((size_t)B * C * C * vol * sizeof(float));
         if (L.path == DMCR_PATH_FFT) {
             const int64_t nl = L.n[p.ndim - 1];
-            const int64_t half = L.N / nl * L.h;  // complex entries of one half spectrum
+            const int64_t half = L.N / nl * L.hp;  // complex entries of one (padded) half spectrum
             L.X = cv.take((size_t)B * C * half * sizeof(float2));
             const int64_t inner = half / L.n[0];
             L.Y = cv.take((size_t)B * p.npairs * L.box * inner * sizeof(float2));
             if (p.ndim == 3) {
-                L.Y2 = cv.take((size_t)B * p.npairs * L.box * L.box * L.h * sizeof(float2));
-                L.KB1 = cv.take((size_t)B * C * C * L.box * L.box * L.h * sizeof(float2));
-                L.KB2 = cv.take((size_t)B * C * C * L.box * L.n[1] * L.h * sizeof(float2));
+                L.Y2 = cv.take((size_t)B * p.npairs * L.box * L.box * L.hp * sizeof(float2));
+                L.KB1 = cv.take((size_t)B * C * C * L.box * L.box * L.hp * sizeof(float2));
+                L.KB2 = cv.take((size_t)B * C * C * L.box * L.n[1] * L.hp * sizeof(float2));
             } else {
-                L.KB1 = cv.take((size_t)B * C * C * L.box * L.h * sizeof(float2));
+                L.KB1 = cv.take((size_t)B * C * C * L.box * L.hp * sizeof(float2));
             }
         } else {
             int64_t kmax = 0;
@@ -179,7 +180,7 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
     }
     p.S = cv.take((size_t)B * p.K * sizeof(float));
     p.G = cv.take((size_t)B * p.K * sizeof(float));
-    p.err_chunks = std::max<int64_t>(1, std::min<int64_t>(1024, (p.K + 4095) / 4096));
+    p.err_chunks = std::max<int64_t>(1, std::min<int64_t>(8192, (p.K + 511) / 512));
     p.Epart = cv.take((size_t)B * p.err_chunks * sizeof(double));
     p.bytes = cv.top;
     return DMCR_OK;

@@ -17,7 +17,11 @@ constexpr int kMaxPairs = DMCR_MAX_PAIRS;
 constexpr int kMaxFft = 1024;          // longest axis handled by the LDS transforms
 constexpr size_t kAlign = 256;
 
-enum IoMode { IO_FULL = 0, IO_HALF = 1, IO_BOX = 2, IO_DESC = 3 };
+// Rows stored along a transformed axis: all n (FULL), the first n/2+1 of a
+// Hermitian half spectrum (HALF), the 2P+1 rows |r| <= P in box order (BOX),
+// box rows scattered into descriptor order (DESC), or box rows of the adjoint
+// kernels computed on the fly from the cotangent G (GBOX).
+enum IoMode { IO_FULL = 0, IO_HALF = 1, IO_BOX = 2, IO_DESC = 3, IO_GBOX = 4 };
 
 struct LevelPlan {
     int n[3];          // level shape; 2-D uses n[0], n[1] and n[2] = 1
@@ -26,6 +30,8 @@ struct LevelPlan {
     int box;           // 2P + 1
     int path;          // DMCR_PATH_FFT or DMCR_PATH_DIRECT (resolved)
     int h;             // n_last / 2 + 1 (half spectrum along the contiguous axis)
+    int hp;            // row pitch of half spectra: h rounded up so that 16-column
+                       // tiles of every strided pass start on a 128-byte boundary
     int64_t off[kMaxPairs];   // offset of (level, pair) inside one descriptor
     int64_t cnt[kMaxPairs];   // entries of (level, pair)
     // workspace byte offsets (per call, batch included)

@@ -11,8 +11,8 @@
 //
 // Every kernel is one pass over HBM.  Pencils are transformed in two register
 // steps with one LDS exchange (fft_reg.h):
-//   k_rows       contiguous-axis transform of T rows; the tile is staged through
-//                LDS so that global loads and stores are flat and coalesced
+//   k_rows       contiguous-axis transform of T rows; R2 adjacent lanes walk
+//                along one row, so each access is an R2-wide run of a row
 //   k_cols       strided-axis transform of T adjacent pencils; lanes of a wave
 //                walk adjacent pencils, so every global access is a T-wide run
 //   k_axis0_fwd  axis-0 forward DFT of every channel, pair products, pruned
@@ -35,12 +35,11 @@ struct Tile {
     static constexpr int pick()
     {
         int T = 256 / R2;
-        while (T > 1 && (ex_size<L>(T) > 8192 || T * (n + 1) > 8192)) T /= 2;
+        while (T > 1 && ex_size<L>(T) > 8192) T /= 2;
         return T;
     }
     static constexpr int T = pick();
     static constexpr int threads = R2 * T;
-    static constexpr int lds = (ex_size<L>(T) > T * (n + 1)) ? ex_size<L>(T) : T * (n + 1);
 };
 
 // row index e of an array that holds `mode` rows of a length-n axis, for
@@ -58,111 +57,238 @@ struct RowArgs {
     void *out;
     int64_t nrows;
     int in_mode, out_mode, in_len, out_len, P;
+    int in_valid, out_valid;  // entries of a row that hold data (the rest is pitch padding)
     int in_real, out_real;
     float scale;
     FastDivU fd_in, fd_out;
     // IO_DESC: row m = (b * npairs + p) * rows_per_pair + row of the box of pair p
-    int npairs, auto_mask;
-    int64_t rows_per_pair, center, Kstride;
+    // IO_GBOX: row m = ((b * C + c) * C + j) * rows_per_pair + row of K_cj
+    int npairs, auto_mask, C;
+    int64_t rows_per_pair, center, Kstride, vol;
     int64_t off[kMaxPairs];
+    int pi[kMaxPairs], pj[kMaxPairs];
 };
+
+// Entry e of box row m of the adjoint kernel K_cj (see k_build_kernels):
+//   auto (c,c):  K_cc(r) = G(r) + G(-r) on the half box, K_cc(0) = 2 G(0)
+//   cross (c,j): K_cj(r) = G_cj(r);   cross (j,c): K_cj(r) = G_jc(-r)
+__device__ __forceinline__ float gbox_value(const RowArgs &a, uint32_t m, int e)
+{
+    const uint32_t row = m % (uint32_t)a.rows_per_pair;
+    uint32_t rest = m / (uint32_t)a.rows_per_pair;
+    const int j = (int)(rest % (uint32_t)a.C);
+    rest /= (uint32_t)a.C;
+    const int c = (int)(rest % (uint32_t)a.C);
+    const int64_t b = rest / (uint32_t)a.C;
+    const int64_t bi = (int64_t)row * a.in_len + e;
+    const int64_t mirror = a.vol - 1 - bi;
+    const float *Gb = static_cast<const float *>(a.in) + b * a.Kstride;
+    float v = 0.f;
+    for (int q = 0; q < a.npairs; ++q) {
+        const int i0 = a.pi[q], j0 = a.pj[q];
+        const float *Gq = Gb + a.off[q];
+        if (i0 == j0) {
+            if (c == i0 && j == i0) {
+                if (bi > a.center)
+                    v += Gq[bi - a.center];
+                else if (bi < a.center)
+                    v += Gq[mirror - a.center];
+                else
+                    v += 2.f * Gq[0];
+            }
+        } else {
+            if (c == i0 && j == j0) v += Gq[bi];
+            if (c == j0 && j == i0) v += Gq[mirror];
+        }
+    }
+    return v;
+}
 
 template <int TAG, int L, bool INV>
 __global__ __launch_bounds__(256) void k_rows(RowArgs a)
 {
     using SP = Split<L>;
-    constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S, NTH = Tile<L>::threads;
-    constexpr int pitch = n + 1;
-    __shared__ float2 sm[Tile<L>::lds];
-    __shared__ int64_t dst_row[T];
-    const int tid = threadIdx.x;
-    const int t = tid % T, p = tid / T;
-    const int64_t m0 = (int64_t)blockIdx.x * T;
-    const int nvalid = (int)((a.nrows - m0) < T ? (a.nrows - m0) : T);
-
-    // flat, coalesced load of the tile (rows are contiguous in memory)
-    {
-        const int64_t base = m0 * a.in_len;
-        const int lim = nvalid * a.in_len;
-        for (int idx = tid; idx < T * a.in_len; idx += NTH) {
-            const int r = fdivu(idx, a.fd_in);
-            const int e = idx - r * a.in_len;
-            float2 v = make_float2(0.f, 0.f);
-            if (idx < lim) {
-                if (a.in_real)
-                    v.x = static_cast<const float *>(a.in)[base + idx];
-                else
-                    v = static_cast<const float2 *>(a.in)[base + idx];
-            }
-            sm[r * pitch + e] = v;
-        }
-    }
-    __syncthreads();
+    constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
+    __shared__ float2 ex[ex_size<L>(T)];
+    // lanes walk along a row: R2 adjacent lanes read R2 adjacent elements
+    const int p = threadIdx.x % R2, t = threadIdx.x / R2;
+    const int64_t m = (int64_t)blockIdx.x * T + t;
+    const bool valid = m < a.nrows;
     float2 v[R1];
+    if (a.in_mode == IO_GBOX) {
 #pragma unroll
-    for (int i1 = 0; i1 < R1; ++i1) {
-        const int j = R2 * i1 + p;
-        float2 x = make_float2(0.f, 0.f);
-        if (a.in_mode == IO_HALF && j > n / 2) {
-            x = c_conj(sm[t * pitch + (n - j)]);
-        } else {
-            const int e = row_of(a.in_mode, j, n, a.P);
-            if (e >= 0) x = sm[t * pitch + e];
+        for (int i1 = 0; i1 < R1; ++i1) {
+            const int e = row_of(IO_BOX, R2 * i1 + p, n, a.P);
+            v[i1] = make_float2((valid && e >= 0) ? gbox_value(a, (uint32_t)m, e) : 0.f, 0.f);
         }
-        v[i1] = x;
+    } else if (a.in_real) {
+        const float *src = static_cast<const float *>(a.in) + m * a.in_len;
+#pragma unroll
+        for (int i1 = 0; i1 < R1; ++i1) {
+            const int e = row_of(a.in_mode, R2 * i1 + p, n, a.P);
+            v[i1] = make_float2((valid && e >= 0) ? src[e] : 0.f, 0.f);
+        }
+    } else {
+        const float2 *src = static_cast<const float2 *>(a.in) + m * a.in_len;
+#pragma unroll
+        for (int i1 = 0; i1 < R1; ++i1) {
+            const int j = R2 * i1 + p;
+            float2 x = make_float2(0.f, 0.f);
+            if (valid) {
+                if (a.in_mode == IO_HALF && j > n / 2) {
+                    x = c_conj(src[n - j]);  // Hermitian completion of the half spectrum
+                } else {
+                    const int e = row_of(a.in_mode, j, n, a.P);
+                    if (e >= 0) x = src[e];
+                }
+            }
+            v[i1] = x;
+        }
     }
-    __syncthreads();
     float2 u[S][R2];
-    pencil_fwd<L, INV>(v, u, sm, p, t, T);
-    // results back to the staging rows (natural output order)
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) {
-            const int k = (p + R2 * s) + R1 * k2;
-            const int e = row_of(a.out_mode, k, n, a.P);
-            if (e >= 0) sm[t * pitch + e] = c_scale(u[s][k2], a.scale);
-        }
-    if (a.out_mode == IO_DESC && tid < T) {
-        // descriptor position of entry 0 of each row of the tile
-        const uint32_t m = (uint32_t)(m0 + tid);
-        const uint32_t row = m % (uint32_t)a.rows_per_pair;
-        const uint32_t bp = m / (uint32_t)a.rows_per_pair;
+    pencil_fwd<L, INV, LANE_P>(v, u, ex, p, t, T);
+    if (!valid) return;
+    if (a.out_mode == IO_DESC) {
+        // entry e of box row `row` of pair q goes to descriptor index
+        // off_q + row * box + e (full box) or that minus the half-box centre
+        const uint32_t row = (uint32_t)(m % a.rows_per_pair);
+        const uint32_t bp = (uint32_t)(m / a.rows_per_pair);
         const int q = (int)(bp % (uint32_t)a.npairs);
         const int64_t b = bp / (uint32_t)a.npairs;
         const bool aut = (a.auto_mask >> q) & 1;
-        dst_row[tid] = b * a.Kstride + a.off[q] + (int64_t)row * a.out_len - (aut ? a.center : 0);
-    }
-    __syncthreads();
-    if (a.out_mode == IO_DESC) {
-        for (int idx = tid; idx < nvalid * a.out_len; idx += NTH) {
-            const int r = fdivu(idx, a.fd_out);
-            const int e = idx - r * a.out_len;
-            const uint32_t m = (uint32_t)(m0 + r);
-            const uint32_t row = m % (uint32_t)a.rows_per_pair;
-            const int q = (int)((m / (uint32_t)a.rows_per_pair) % (uint32_t)a.npairs);
-            if (((a.auto_mask >> q) & 1) && (int64_t)row * a.out_len + e < a.center) continue;
-            static_cast<float *>(a.out)[dst_row[r] + e] = sm[r * pitch + e].x;
-        }
+        const int64_t bi0 = (int64_t)row * a.out_len;
+        float *dst = static_cast<float *>(a.out) + b * a.Kstride + a.off[q] + bi0 - (aut ? a.center : 0);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int e = row_of(IO_BOX, (p + R2 * s) + R1 * k2, n, a.P);
+                if (e >= 0 && !(aut && bi0 + e < a.center)) dst[e] = u[s][k2].x * a.scale;
+            }
+    } else if (a.out_real) {
+        float *dst = static_cast<float *>(a.out) + m * a.out_len;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int e = row_of(a.out_mode, (p + R2 * s) + R1 * k2, n, a.P);
+                if (e >= 0) dst[e] = u[s][k2].x * a.scale;
+            }
     } else {
-        const int64_t base = m0 * a.out_len;
-        for (int idx = tid; idx < nvalid * a.out_len; idx += NTH) {
-            const int r = fdivu(idx, a.fd_out);
-            const int e = idx - r * a.out_len;
-            const float2 x = sm[r * pitch + e];
-            if (a.out_real)
-                static_cast<float *>(a.out)[base + idx] = x.x;
-            else
-                static_cast<float2 *>(a.out)[base + idx] = x;
+        float2 *dst = static_cast<float2 *>(a.out) + m * a.out_len;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int e = row_of(a.out_mode, (p + R2 * s) + R1 * k2, n, a.P);
+                if (e >= 0) dst[e] = c_scale(u[s][k2], a.scale);
+            }
+    }
+}
+
+// Real rows of length n = 2^L through half-length complex transforms.
+// Forward: z[m] = x[2m] + i x[2m+1], Z = DFT_{n/2}(z), then for k <= n/2
+//   X[k] = E[k] + W_n^k O[k],  E = (Z[k] + conj Z[n/2-k]) / 2,  O = (Z[k] - conj Z[n/2-k]) / 2i
+// (Z indices mod n/2).  Inverse (unnormalised): for k < n/2
+//   Z[k] = (X[k] + conj X[n/2-k]) + i W_n^-k (X[k] - conj X[n/2-k]),  z = IDFT_{n/2}(Z),
+//   x[2m] = Re z[m], x[2m+1] = Im z[m].
+template <int TAG, int L>
+__global__ __launch_bounds__(256) void k_r2c(RowArgs a)
+{
+    constexpr int LH = L - 1;
+    using SP = Split<LH>;
+    constexpr int T = Tile<LH>::T, nh = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
+    __shared__ float2 ex[ex_size<LH>(T)];
+    const int p = threadIdx.x % R2, t = threadIdx.x / R2;
+    const int64_t m = (int64_t)blockIdx.x * T + t;
+    const bool valid = m < a.nrows;
+    const float2 *src = static_cast<const float2 *>(a.in) + m * (a.in_len / 2);
+    float2 v[R1];
+#pragma unroll
+    for (int i1 = 0; i1 < R1; ++i1) v[i1] = valid ? src[R2 * i1 + p] : make_float2(0.f, 0.f);
+    float2 u[S][R2];
+    pencil_fwd<LH, false, LANE_P>(v, u, ex, p, t, T);
+    // Z in natural order for the split (pencil_fwd ended with a barrier)
+    constexpr int pitch = nh + 1;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) ex[t * pitch + (p + R2 * s) + R1 * k2] = u[s][k2];
+    __syncthreads();
+    if (!valid) return;
+    float2 *dst = static_cast<float2 *>(a.out) + m * a.out_len;
+    for (int k = p; k <= nh; k += R2) {
+        const float2 zk = ex[t * pitch + (k & (nh - 1))];
+        const float2 zc = c_conj(ex[t * pitch + ((nh - k) & (nh - 1))]);
+        const float2 E = c_scale(c_add(zk, zc), 0.5f);
+        const float2 d = c_sub(zk, zc);                   // 2i O
+        const float2 O = make_float2(0.5f * d.y, -0.5f * d.x);
+        dst[k] = c_scale(c_add(E, c_mul(O, tw_n<false>(k, L))), a.scale);
+    }
+}
+
+template <int TAG, int L>
+__global__ __launch_bounds__(256) void k_c2r(RowArgs a)
+{
+    constexpr int LH = L - 1;
+    using SP = Split<LH>;
+    constexpr int T = Tile<LH>::T, nh = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
+    __shared__ float2 ex[ex_size<LH>(T)];
+    const int p = threadIdx.x % R2, t = threadIdx.x / R2;
+    const int64_t m = (int64_t)blockIdx.x * T + t;
+    const bool valid = m < a.nrows;
+    const float2 *src = static_cast<const float2 *>(a.in) + m * a.in_len;
+    float2 v[R1];
+#pragma unroll
+    for (int i1 = 0; i1 < R1; ++i1) {
+        const int k = R2 * i1 + p;
+        float2 z = make_float2(0.f, 0.f);
+        if (valid) {
+            const float2 xk = src[k];
+            const float2 xc = c_conj(src[nh - k]);
+            const float2 e = c_add(xk, xc);
+            const float2 o = c_mul(c_sub(xk, xc), tw_n<true>(k, L));  // W_n^-k (X[k] - conj X[n/2-k])
+            z = make_float2(e.x - o.y, e.y + o.x);                    // e + i o
         }
+        v[i1] = z;
+    }
+    float2 u[S][R2];
+    pencil_fwd<LH, true, LANE_P>(v, u, ex, p, t, T);
+    if (!valid) return;
+    if (a.out_mode == IO_DESC) {
+        const uint32_t row = (uint32_t)(m % a.rows_per_pair);
+        const uint32_t bp = (uint32_t)(m / a.rows_per_pair);
+        const int q = (int)(bp % (uint32_t)a.npairs);
+        const int64_t b = bp / (uint32_t)a.npairs;
+        const bool aut = (a.auto_mask >> q) & 1;
+        const int64_t bi0 = (int64_t)row * a.out_len;
+        float *dst = static_cast<float *>(a.out) + b * a.Kstride + a.off[q] + bi0 - (aut ? a.center : 0);
+        const int n = 2 * nh;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int mm = (p + R2 * s) + R1 * k2;
+                const int e0 = row_of(IO_BOX, 2 * mm, n, a.P);
+                const int e1 = row_of(IO_BOX, 2 * mm + 1, n, a.P);
+                if (e0 >= 0 && !(aut && bi0 + e0 < a.center)) dst[e0] = u[s][k2].x * a.scale;
+                if (e1 >= 0 && !(aut && bi0 + e1 < a.center)) dst[e1] = u[s][k2].y * a.scale;
+            }
+    } else {
+        float2 *dst = static_cast<float2 *>(a.out) + m * (a.out_len / 2);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) dst[(p + R2 * s) + R1 * k2] = c_scale(u[s][k2], a.scale);
     }
 }
 
 struct ColArgs {
     const float2 *in;
     float2 *out;
-    int64_t npen, inner;
+    int64_t npen, inner;  // inner = padded half-spectrum pitch hp
     int in_mode, out_mode, in_len, out_len, P;
+    int h;                // columns of a pitch that hold data
     float scale;
 };
 
@@ -174,11 +300,12 @@ __global__ __launch_bounds__(256) void k_cols(ColArgs a)
     __shared__ float2 ex[ex_size<L>(T)];
     const int t = threadIdx.x % T, p = threadIdx.x / T;
     const int64_t m = (int64_t)blockIdx.x * T + t;
-    const bool valid = m < a.npen;
+    bool valid = m < a.npen;
     int64_t o = 0, i = 0;
     if (valid) {
         o = m / a.inner;
         i = m - o * a.inner;
+        valid = i < a.h;
     }
     const float2 *src = a.in + o * a.in_len * a.inner + i;
     float2 v[R1];
@@ -206,6 +333,7 @@ struct Axis0Args {
     float2 *Y;          // forward: [B][npairs][box][inner]
     int64_t inner, nloc;  // nloc = B * inner pencil locations
     int P, box, npairs;
+    int h, hp;            // data columns of each padded half-spectrum row
     int pair_of[kMaxChannels * kMaxChannels];  // (i, j) -> pair index or -1
     float scale;
 };
@@ -218,11 +346,12 @@ __global__ __launch_bounds__(256) void k_axis0_fwd(Axis0Args a)
     __shared__ float2 ex[ex_size<L>(T)];
     const int t = threadIdx.x % T, p = threadIdx.x / T;
     const int64_t m = (int64_t)blockIdx.x * T + t;
-    const bool valid = m < a.nloc;
+    bool valid = m < a.nloc;
     int64_t b = 0, i = 0;
     if (valid) {
         b = m / a.inner;
         i = m - b * a.inner;
+        valid = (int)(i % a.hp) < a.h;
     }
     float2 X[C][S][R2];
     static_for<0, C>([&](auto cc) {
@@ -268,11 +397,12 @@ __global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
     __shared__ float2 ex[ex_size<L>(T)];
     const int t = threadIdx.x % T, p = threadIdx.x / T;
     const int64_t m = (int64_t)blockIdx.x * T + t;
-    const bool valid = m < a.nloc;
+    bool valid = m < a.nloc;
     int64_t b = 0, i = 0;
     if (valid) {
         b = m / a.inner;
         i = m - b * a.inner;
+        valid = (int)(i % a.hp) < a.h;
     }
     float2 X[C][S][R2];
     static_for<0, C>([&](auto cc) {
@@ -356,6 +486,7 @@ TileInfo tile_info()
 TileInfo tile_of(int L)
 {
     switch (L) {
+    case 0: return tile_info<0>();
     case 1: return tile_info<1>();
     case 2: return tile_info<2>();
     case 3: return tile_info<3>();
@@ -380,6 +511,25 @@ hipError_t rows_launch(int L, const RowArgs &a, double bytes, hipStream_t st)
     switch (L) {
 #define C_(LL) \
     case LL: return launch(kPassName[TAG], bytes, k_rows<TAG, LL, INV>, g, b, 0, st, a);
+        DMCR_L_CASES(C_)
+#undef C_
+    }
+    return hipErrorInvalidValue;
+}
+
+// packed real transforms (L >= 2): tile geometry of the half length
+template <int TAG, bool C2R>
+hipError_t real_launch(int L, const RowArgs &a, double bytes, hipStream_t st)
+{
+    const TileInfo ti = tile_of(L - 1);
+    const dim3 g((unsigned)((a.nrows + ti.T - 1) / ti.T)), b(ti.threads);
+    switch (L) {
+#define C_(LL)                                                                              \
+    case LL:                                                                                \
+        if constexpr (LL >= 2)                                                              \
+            return C2R ? launch(kPassName[TAG], bytes, k_c2r<TAG, LL>, g, b, 0, st, a)     \
+                       : launch(kPassName[TAG], bytes, k_r2c<TAG, LL>, g, b, 0, st, a);    \
+        break;
         DMCR_L_CASES(C_)
 #undef C_
     }
@@ -441,6 +591,8 @@ RowArgs row_args(const void *in, void *out, int64_t nrows, int in_mode, int in_l
     a.in_real = in_real;
     a.out_real = out_real;
     a.scale = scale;
+    a.in_valid = in_len;
+    a.out_valid = out_len;
     a.fd_in = make_fastdivu(in_len);
     a.fd_out = make_fastdivu(out_len);
     return a;
@@ -448,7 +600,7 @@ RowArgs row_args(const void *in, void *out, int64_t nrows, int in_mode, int in_l
 
 double row_bytes(const RowArgs &a)
 {
-    return (double)a.nrows * a.in_len * (a.in_real ? 4 : 8) + (double)a.nrows * a.out_len * (a.out_real ? 4 : 8);
+    return (double)a.nrows * a.in_valid * (a.in_real ? 4 : 8) + (double)a.nrows * a.out_valid * (a.out_real ? 4 : 8);
 }
 
 ColArgs col_args(const float2 *in, float2 *out, int64_t npen, int64_t inner, int in_mode, int in_len, int out_mode,
@@ -464,11 +616,12 @@ ColArgs col_args(const float2 *in, float2 *out, int64_t npen, int64_t inner, int
     a.out_mode = out_mode;
     a.out_len = out_len;
     a.P = P;
+    a.h = (int)inner;
     a.scale = 1.f;
     return a;
 }
 
-double col_bytes(const ColArgs &a) { return (double)a.npen * (a.in_len + a.out_len) * 8; }
+double col_bytes(const ColArgs &a) { return (double)a.npen / a.inner * a.h * (a.in_len + a.out_len) * 8; }
 
 #define TRY_HIP(expr)                         \
     do {                                      \
@@ -495,10 +648,15 @@ hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &
     float2 *X = ws.at<float2>(L.X);
     const int nl = L.n[p.ndim - 1];
     const int64_t rows = (p.ndim == 2) ? (int64_t)B * C * L.n[0] : (int64_t)B * C * L.n[0] * L.n[1];
-    RowArgs r = row_args(phi, X, rows, IO_FULL, nl, IO_HALF, L.h, 0, true, false, 1.f);
-    TRY_HIP((rows_launch<T_R2C_LAST, false>(ilog2(nl), r, row_bytes(r), st)));
+    RowArgs r = row_args(phi, X, rows, IO_FULL, nl, IO_HALF, L.hp, 0, true, false, 1.f);
+    r.out_valid = L.h;
+    if (nl >= 4)
+        TRY_HIP((real_launch<T_R2C_LAST, false>(ilog2(nl), r, row_bytes(r), st)));
+    else
+        TRY_HIP((rows_launch<T_R2C_LAST, false>(ilog2(nl), r, row_bytes(r), st)));
     if (p.ndim == 3) {
-        ColArgs c = col_args(X, X, (int64_t)B * C * L.n[0] * L.h, L.h, IO_FULL, L.n[1], IO_FULL, L.n[1], 0);
+        ColArgs c = col_args(X, X, (int64_t)B * C * L.n[0] * L.hp, L.hp, IO_FULL, L.n[1], IO_FULL, L.n[1], 0);
+        c.h = L.h;
         TRY_HIP((cols_launch<T_FWD_MID, false>(ilog2(L.n[1]), c, col_bytes(c), st)));
     }
     return hipSuccess;
@@ -512,10 +670,13 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
     float2 *X = ws.at<float2>(L.X);
     float2 *Y = ws.at<float2>(L.Y);
     const int n0 = L.n[0];
-    const int64_t inner = (p.ndim == 2) ? L.h : (int64_t)L.n[1] * L.h;
+    const int64_t inner = (p.ndim == 2) ? L.hp : (int64_t)L.n[1] * L.hp;
+    const int64_t inner_valid = inner / L.hp * L.h;
     const double invN = 1.0 / (double)L.N;
 
     Axis0Args a{};
+    a.h = L.h;
+    a.hp = L.hp;
     a.X = X;
     a.Y = Y;
     a.inner = inner;
@@ -526,7 +687,7 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
     for (int k = 0; k < kMaxChannels * kMaxChannels; ++k) a.pair_of[k] = -1;
     for (int q = 0; q < p.npairs; ++q) a.pair_of[p.pi[q] * kMaxChannels + p.pj[q]] = q;
     a.scale = (float)(invN * invN);
-    const double bytes0 = (double)B * C * n0 * inner * 8 + (double)B * p.npairs * L.box * inner * 8;
+    const double bytes0 = (double)B * C * n0 * inner_valid * 8 + (double)B * p.npairs * L.box * inner_valid * 8;
     TRY_HIP(axis0_launch(C, false, ilog2(n0), a, bytes0, st));
 
     // remaining inverse axes, pruned, then scatter into descriptor order
@@ -534,14 +695,16 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
     int64_t rows_per_pair = L.box;
     if (p.ndim == 3) {
         float2 *Y2 = ws.at<float2>(L.Y2);
-        ColArgs c = col_args(Y, Y2, (int64_t)B * p.npairs * L.box * L.h, L.h, IO_FULL, L.n[1], IO_BOX, L.box, L.P);
+        ColArgs c = col_args(Y, Y2, (int64_t)B * p.npairs * L.box * L.hp, L.hp, IO_FULL, L.n[1], IO_BOX, L.box, L.P);
+        c.h = L.h;
         TRY_HIP((cols_launch<T_INV_MID_BOX, true>(ilog2(L.n[1]), c, col_bytes(c), st)));
         last_in = Y2;
         rows_per_pair = (int64_t)L.box * L.box;
     }
     const int nl = L.n[p.ndim - 1];
-    RowArgs d = row_args(last_in, S, (int64_t)B * p.npairs * rows_per_pair, IO_HALF, L.h, IO_DESC, L.box, L.P,
+    RowArgs d = row_args(last_in, S, (int64_t)B * p.npairs * rows_per_pair, IO_HALF, L.hp, IO_DESC, L.box, L.P,
                          false, true, 1.f);
+    d.in_valid = L.h;
     d.npairs = p.npairs;
     d.rows_per_pair = rows_per_pair;
     d.Kstride = p.K;
@@ -553,7 +716,9 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
         d.off[q] = L.off[q];
         if (p.pi[q] == p.pj[q]) d.auto_mask |= 1 << q;
     }
-    return rows_launch<T_C2R_DESC, true>(ilog2(nl), d, (double)d.nrows * L.h * 8 + (double)d.nrows * L.box * 4, st);
+    const double dbytes = (double)d.nrows * L.h * 8 + (double)d.nrows * L.box * 4;
+    if (nl >= 4) return real_launch<T_C2R_DESC, true>(ilog2(nl), d, dbytes, st);
+    return rows_launch<T_C2R_DESC, true>(ilog2(nl), d, dbytes, st);
 }
 
 hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
@@ -561,30 +726,44 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
 {
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C, CC = C * C;
-    float *KB0 = ws.at<float>(L.KB0);
     float2 *KB1 = ws.at<float2>(L.KB1);
-    TRY_HIP(launch_build_kernels(p, l, G, KB0, st));
     const int nl = L.n[p.ndim - 1];
     const float2 *KBaxis0;
+    // adjoint kernels K_cj built from G while loading, transformed along the contiguous axis
+    const int64_t rows_per_box = (p.ndim == 2) ? L.box : (int64_t)L.box * L.box;
+    RowArgs r = row_args(G, KB1, (int64_t)B * CC * rows_per_box, IO_GBOX, L.box, IO_HALF, L.hp, L.P, true, false, 1.f);
+    r.out_valid = L.h;
+    r.rows_per_pair = rows_per_box;
+    r.C = C;
+    r.npairs = p.npairs;
+    r.Kstride = p.K;
+    r.vol = rows_per_box * L.box;
+    r.center = (r.vol - 1) / 2;
+    for (int q = 0; q < p.npairs; ++q) {
+        r.off[q] = L.off[q];
+        r.pi[q] = p.pi[q];
+        r.pj[q] = p.pj[q];
+    }
+    const double kb_bytes = (double)B * (p.lvl_off[l + 1] - p.lvl_off[l]) * 4 + (double)r.nrows * L.h * 8;
+    TRY_HIP((rows_launch<T_KB_LAST, false>(ilog2(nl), r, kb_bytes, st)));
     if (p.ndim == 2) {
-        RowArgs r = row_args(KB0, KB1, (int64_t)B * CC * L.box, IO_BOX, L.box, IO_HALF, L.h, L.P, true, false, 1.f);
-        TRY_HIP((rows_launch<T_KB_LAST, false>(ilog2(nl), r, row_bytes(r), st)));
         KBaxis0 = KB1;
     } else {
         float2 *KB2 = ws.at<float2>(L.KB2);
-        RowArgs r = row_args(KB0, KB1, (int64_t)B * CC * L.box * L.box, IO_BOX, L.box, IO_HALF, L.h, L.P, true,
-                             false, 1.f);
-        TRY_HIP((rows_launch<T_KB_LAST, false>(ilog2(nl), r, row_bytes(r), st)));
-        ColArgs c = col_args(KB1, KB2, (int64_t)B * CC * L.box * L.h, L.h, IO_BOX, L.box, IO_FULL, L.n[1], L.P);
+        ColArgs c = col_args(KB1, KB2, (int64_t)B * CC * L.box * L.hp, L.hp, IO_BOX, L.box, IO_FULL, L.n[1], L.P);
+        c.h = L.h;
         TRY_HIP((cols_launch<T_KB_MID, false>(ilog2(L.n[1]), c, col_bytes(c), st)));
         KBaxis0 = KB2;
     }
     if (!have_spectrum) TRY_HIP(fft_spectrum_level(p, l, phi, ws, st));
     float2 *X = ws.at<float2>(L.X);
     const int n0 = L.n[0];
-    const int64_t inner = (p.ndim == 2) ? L.h : (int64_t)L.n[1] * L.h;
+    const int64_t inner = (p.ndim == 2) ? L.hp : (int64_t)L.n[1] * L.hp;
+    const int64_t inner_valid = inner / L.hp * L.h;
     const double invN = 1.0 / (double)L.N;
     Axis0Args a{};
+    a.h = L.h;
+    a.hp = L.hp;
     a.X = X;
     a.KB = KBaxis0;
     a.inner = inner;
@@ -592,15 +771,18 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
     a.P = L.P;
     a.box = L.box;
     a.scale = (float)(invN * invN);
-    const double bytes0 = 2.0 * B * C * n0 * inner * 8 + (double)B * CC * L.box * inner * 8;
+    const double bytes0 = 2.0 * B * C * n0 * inner_valid * 8 + (double)B * CC * L.box * inner_valid * 8;
     TRY_HIP(axis0_launch(C, true, ilog2(n0), a, bytes0, st));
     if (p.ndim == 3) {
-        ColArgs c = col_args(X, X, (int64_t)B * C * n0 * L.h, L.h, IO_FULL, L.n[1], IO_FULL, L.n[1], 0);
+        ColArgs c = col_args(X, X, (int64_t)B * C * n0 * L.hp, L.hp, IO_FULL, L.n[1], IO_FULL, L.n[1], 0);
+        c.h = L.h;
         TRY_HIP((cols_launch<T_INV_MID, true>(ilog2(L.n[1]), c, col_bytes(c), st)));
     }
     const int64_t rows = (p.ndim == 2) ? (int64_t)B * C * n0 : (int64_t)B * C * n0 * L.n[1];
-    RowArgs r = row_args(X, grad, rows, IO_HALF, L.h, IO_FULL, nl, 0, false, true, 1.f);
-    return rows_launch<T_C2R_FULL, true>(ilog2(nl), r, row_bytes(r), st);
+    RowArgs o = row_args(X, grad, rows, IO_HALF, L.hp, IO_FULL, nl, 0, false, true, 1.f);
+    o.in_valid = L.h;
+    if (nl >= 4) return real_launch<T_C2R_FULL, true>(ilog2(nl), o, row_bytes(o), st);
+    return rows_launch<T_C2R_FULL, true>(ilog2(nl), o, row_bytes(o), st);
 }
 
 }  // namespace dmcr

@@ -184,22 +184,29 @@ struct Split {
 
 // LDS exchange slot of (k1, i2) for pencil t of a tile of T pencils; the
 // (R2 + 1) row pitch keeps the gather of stage two at two passes per wave.
-template <int L>
+// Two lane orders: LANE_T (lanes walk adjacent pencils: strided axes) and
+// LANE_P (lanes walk along one pencil: contiguous rows).
+enum LaneOrder { LANE_T = 0, LANE_P = 1 };
+
+template <int L, int LO>
 __device__ __forceinline__ int ex_idx(int k1, int i2, int t, int T)
 {
-    return (k1 * (Split<L>::R2 + 1) + i2) * T + t;
+    if constexpr (LO == LANE_T)
+        return (k1 * (Split<L>::R2 + 1) + i2) * T + t;
+    else
+        return k1 * (T * (Split<L>::R2 + 1) + 1) + t * (Split<L>::R2 + 1) + i2;
 }
 
 template <int L>
 constexpr int ex_size(int T)
 {
-    return Split<L>::R1 * (Split<L>::R2 + 1) * T;
+    return Split<L>::R1 * (Split<L>::R2 + 1) * T + Split<L>::R1;
 }
 
 // Forward-structure transform.  In: v[i1] = x[R2 i1 + p].  Out: u[s][k2] =
 // X[(p + R2 s) + R1 k2].  Contains two barriers (the caller must not touch
 // `ex` between its calls from other threads).
-template <int L, bool INV>
+template <int L, bool INV, int LO = LANE_T>
 __device__ __forceinline__ void pencil_fwd(float2 (&v)[Split<L>::R1], float2 (&u)[Split<L>::S][Split<L>::R2],
                                            float2 *ex, int p, int t, int T)
 {
@@ -209,7 +216,7 @@ __device__ __forceinline__ void pencil_fwd(float2 (&v)[Split<L>::R1], float2 (&u
         constexpr int k1 = decltype(kc)::value;
         float2 w = v[k1];
         if constexpr (k1 != 0) w = c_mul(w, tw_n<INV>(p * k1, L));
-        ex[ex_idx<L>(k1, p, t, T)] = w;
+        ex[ex_idx<L, LO>(k1, p, t, T)] = w;
     });
     __syncthreads();
     static_for<0, SP::S>([&](auto sc) {
@@ -217,7 +224,7 @@ __device__ __forceinline__ void pencil_fwd(float2 (&v)[Split<L>::R1], float2 (&u
         const int k1 = p + SP::R2 * s;
         static_for<0, SP::R2>([&](auto ic) {
             constexpr int i2 = decltype(ic)::value;
-            u[s][i2] = ex[ex_idx<L>(k1, i2, t, T)];
+            u[s][i2] = ex[ex_idx<L, LO>(k1, i2, t, T)];
         });
         dft_reg<SP::R2, INV>(u[s]);
     });
@@ -226,7 +233,7 @@ __device__ __forceinline__ void pencil_fwd(float2 (&v)[Split<L>::R1], float2 (&u
 
 // Mirror (inverse-structure) transform.  In: u[s][k2] = F[(p + R2 s) + R1 k2].
 // Out: v[j1] = f[p + R2 j1].  Two barriers.
-template <int L, bool INV>
+template <int L, bool INV, int LO = LANE_T>
 __device__ __forceinline__ void pencil_mirror(float2 (&u)[Split<L>::S][Split<L>::R2], float2 (&v)[Split<L>::R1],
                                               float2 *ex, int p, int t, int T)
 {
@@ -239,13 +246,13 @@ __device__ __forceinline__ void pencil_mirror(float2 (&u)[Split<L>::S][Split<L>:
             constexpr int j2 = decltype(jc)::value;
             float2 w = u[s][j2];
             if constexpr (j2 != 0) w = c_mul(w, tw_n<INV>(k1 * j2, L));
-            ex[ex_idx<L>(k1, j2, t, T)] = w;
+            ex[ex_idx<L, LO>(k1, j2, t, T)] = w;
         });
     });
     __syncthreads();
     static_for<0, SP::R1>([&](auto kc) {
         constexpr int k1 = decltype(kc)::value;
-        v[k1] = ex[ex_idx<L>(k1, p, t, T)];
+        v[k1] = ex[ex_idx<L, LO>(k1, p, t, T)];
     });
     dft_reg<SP::R1, INV>(v);
     __syncthreads();

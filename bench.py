@@ -36,6 +36,63 @@ WORKLOADS = {
 }
 
 
+def source_hash():
+    """Hash of the HIP sources: a stored counter profile is valid only for this code."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2103_09686_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 PMC summary of
+    this workload (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration),
+    or None if there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    src, table = None, {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("source_hash:"):
+            src = line.split(":", 1)[1].strip()
+        elif line and not line.startswith("#") and not line.startswith("kernel"):
+            f = line.split()
+            if len(f) >= 5:
+                table[f[0]] = float(f[4]) * 1e6
+    if src != source_hash():
+        return None
+    return table.get(kernel)
+
+
+def calibrate_copy():
+    """Plain device copies of known size (the calibration kernel for the HBM counters
+    and the achievable-bandwidth reference)."""
+    import torch
+    torch.cuda.set_device(0)
+    for mib in (64, 256, 1024):
+        n = mib * 1024 * 1024 // 4
+        a = torch.rand(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        print(json.dumps(dict(copy_MiB=mib, us=round(ms * 1e3, 2), GBps_read_plus_write=round(2 * n * 4 / ms / 1e6, 1))),
+              flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,6 +101,7 @@ def parse():
     ap.add_argument("--workload", default="3d256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle sample time")
+    ap.add_argument("--calibrate-copy", action="store_true", help="time plain copies of 64/256/1024 MiB and exit")
     return ap.parse_args()
 
 
@@ -102,6 +160,9 @@ def cpu_baseline(phi64, spec_kw, target_seconds):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -182,8 +243,10 @@ def main():
     dom = kern[0]
     prof_ms = sum(r["total_ms"] for r in kern) / args.steps
     roofline = dict(bound="hbm", kernel=dom["name"], achieved=round(dom["GBps"], 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(dom["GBps"] / HBM_PEAK_GBS, 4), traffic=None,
-                    avg_us=round(dom["avg_us"], 2), bytes_per_launch=dom["bytes_per_launch"])
+                    unit="GB/s", frac=round(dom["GBps"] / HBM_PEAK_GBS, 4),
+                    traffic=stored_traffic(args.workload, dom["name"]),
+                    avg_us=round(dom["avg_us"], 2), bytes_per_launch=dom["bytes_per_launch"],
+                    source_hash=source_hash())
     total_bytes = sum(r["bytes_per_launch"] * r["launches"] for r in kern) / args.steps
     step_roofline = dict(bytes_per_step=total_bytes, bytes_per_voxel=total_bytes / (N * B),
                          achieved_GBps=round(total_bytes / (ms * 1e-3) / 1e9, 1),

@@ -71,3 +71,40 @@ def test_penalty_mode_runs(dm, ora):
     code, res = dm.dmcr_reconstruct(spec, torch.from_numpy(S_des[None]).cuda(), x,
                                     dm.Bounds(0.0, 1.0, dm.BOUNDS_PENALTY, 1.0), dm.Opt(max_iter=50, tol_derr=0.0))
     assert res[0]["final_E"] < 0.1 * E0
+
+
+def test_2d_512_grf_three_levels_reaches_tolerance(dm, ora):
+    """2-D 512^2 two-phase, target = periodic GRF (Gaussian covariance, l = 12 px)
+    thresholded at vf 0.40; P = 64; 3 levels (512/256/128): E <= 1e-4 from U(0,1)."""
+    shape = (512, 512)
+    spec = dm.make_spec(shape, 1, 3, 64)
+    tgt = synth.grf_two_phase(shape, 12, 0.40, seed=0).astype(np.float32)
+    St = dm.dmcr_descriptor_forward(spec, torch.from_numpy(tgt[None]).cuda()).double()
+    x = torch.from_numpy(synth.uniform(shape, 1)[None].astype(np.float32)).cuda()
+    code, res = dm.dmcr_reconstruct(spec, St, x, dm.Bounds(), dm.Opt(max_iter=400, tol_derr=1e-4))
+    print("2d512", res[0], flush=True)
+    assert code == 0 and res[0]["final_E"] <= 1e-4
+    # the oracle agrees on the final error (sampled finest-level entries + all coarse ones)
+    ospec = ora.Spec(shape=shape, n_levels=3, max_disp=spec.max_disp)
+    S_gpu = dm.dmcr_descriptor_forward(spec, x).double().cpu().numpy()[0]
+    lv = ora.pyramid(x.cpu().numpy()[0].astype(np.float64), 3)
+    for (l, pair, off, k) in ospec.layout():
+        if l == 0:
+            continue
+        ref = ora._native.corr(lv[l][0], lv[l][0], ospec.disp(l, pair))
+        assert np.max(np.abs(S_gpu[off:off + k] - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+def test_3d_128_three_phase_reaches_tolerance(dm, ora):
+    """3-D 128^3 three-phase: spheres r = 6 (phase 1, vf 0.20) and randomly oriented
+    ellipsoids 10x4x4 (phase 2, vf 0.15); all auto and cross S2 up to 32 voxels;
+    3 levels (128/64/32): E <= 1e-4 from U(0,1)."""
+    shape = (128, 128, 128)
+    spec = dm.make_spec(shape, 2, 3, 32)
+    tgt, _ = synth.spheres_and_ellipsoids(shape, 6, 0.20, (10, 4, 4), 0.15, seed=0)
+    St = dm.dmcr_descriptor_forward(spec, torch.from_numpy(tgt[None].astype(np.float32)).cuda()).double()
+    x0 = synth.uniform(shape, 1, channels=2) * 0.5   # phi_1 + phi_2 <= 1 at the start
+    x = torch.from_numpy(x0[None].astype(np.float32)).cuda()
+    code, res = dm.dmcr_reconstruct(spec, St, x, dm.Bounds(), dm.Opt(max_iter=400, tol_derr=1e-4))
+    print("3d128", res[0], flush=True)
+    assert code == 0 and res[0]["final_E"] <= 1e-4

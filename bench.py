@@ -9,7 +9,10 @@ is a 3-D 256^3 two-phase U(0,1) field, P = 32, one level, spectra recomputed
 in the adjoint.  The script prints one JSON line with the throughput, the
 roofline figure of the dominant kernel (HIP events around every launch, on the
 launch stream, in a second pass of the same steps) and the FP64 oracle timed
-on a bounded sample on the host cores.
+on a bounded sample on the host cores.  Unless --no-serve is given it also runs
+the continuous-batching serving workload (a Poisson stream of mixed 2-D/3-D,
+2-3 phase reconstruction requests) and adds its latency percentiles and its
+throughput against one-at-a-time reconstruction under "serving".
 """
 import argparse
 import json
@@ -102,7 +105,68 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle sample time")
     ap.add_argument("--calibrate-copy", action="store_true", help="time plain copies of 64/256/1024 MiB and exit")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the continuous-batching serving workload (latency percentiles)")
+    ap.add_argument("--requests", type=int, default=400, help="serving: requests in the Poisson stream")
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
+    ap.add_argument("--compare", type=int, default=100,
+                    help="serving: requests in the batched vs one-at-a-time throughput comparison")
     return ap.parse_args()
+
+
+def serving(n_requests, rate, n_compare):
+    """Serving workload: Poisson stream (rate, n_requests), sizes uniform over 2-D
+    128^2..1024^2 and 3-D 64^3..256^3, 2-3 phases, Boolean or GRF targets, stop at
+    E <= 1e-4 or 2000 iterations.  Reports latency percentiles from arrival to result
+    and the throughput of continuous batching against plain one-at-a-time GPU
+    reconstruction on the same requests (all available at once)."""
+    import copy
+    import torch
+    from paper_2103_09686_amd import dmcr, serve
+
+    t0 = time.perf_counter()
+    cache = serve.TargetCache(variants=2)
+    stream = serve.request_stream(n_requests, rate, seed=0)
+    reqs = serve.gpu_requests(stream, cache)
+    prep = time.perf_counter() - t0
+    print("serving: %d requests prepared in %.1f s" % (len(reqs), prep), file=sys.stderr, flush=True)
+    opt = dmcr.Opt(max_iter=2000, tol_derr=1e-4)
+    budget = int(0.6 * torch.cuda.mem_get_info()[0])
+    srv = serve.Server(serve.GpuExecutor(opt=opt), budget_bytes=budget, iters_per_tick=4, threads=8)
+    done = srv.run(reqs)
+    srv.close()
+    live = serve.summary(done)
+    print("serving (Poisson %.0f/s): %s" % (rate, live), file=sys.stderr, flush=True)
+    # throughput comparison on the first n_compare requests, all available at t = 0
+    base = serve.gpu_requests(stream[:n_compare], cache)
+    for r in base:
+        r.arrival = 0.0
+    batched = copy.copy(base)
+    srv = serve.Server(serve.GpuExecutor(opt=opt), budget_bytes=budget, iters_per_tick=4, threads=8)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    bdone = srv.run([copy.copy(r) for r in batched])
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - tb
+    srv.close()
+    seq = [copy.copy(r) for r in base]
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    serve.run_sequential(seq, opt=opt)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - ts
+    out = dict(requests=live["requests"], rate_per_s=rate, p50_s=round(live["p50_s"], 4),
+               p99_s=round(live["p99_s"], 4), mean_s=round(live["mean_s"], 4),
+               served_requests_per_s=round(live["requests_per_s"], 3),
+               converged=live["converged"], max_final_E=live["max_final_E"],
+               compare=dict(requests=n_compare, batched_requests_per_s=round(n_compare / tb, 2),
+                            one_at_a_time_requests_per_s=round(n_compare / ts, 2), speedup=round(ts / tb, 2),
+                            batched_max_E=max(r.final_E for r in bdone), one_at_a_time_max_E=max(r.final_E for r in seq),
+                            batched_voxel_it_per_s=sum(r.voxels * r.iters for r in bdone) / tb,
+                            one_at_a_time_voxel_it_per_s=sum(r.voxels * r.iters for r in seq) / ts),
+               prepare_s=round(prep, 1))
+    print("serving compare: %s" % out["compare"], file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_baseline(phi64, spec_kw, target_seconds):
@@ -260,6 +324,8 @@ def main():
                            max_disp=list(spec.max_disp), K=K, batch=B, path="fft",
                            recompute=wl["recompute"], parallelism="single GPU"),
                roofline=roofline, step_roofline=step_roofline)
+    if not args.no_serve and args.workload == "3d256":
+        out["serving"] = serving(args.requests, args.rate, args.compare)
     if not args.no_cpu_baseline:
         phi64 = phi_h[0].astype(np.float64)
         cb = cpu_baseline(phi64, dict(shape=shape, P=P, L=L), args.cpu_seconds)

@@ -61,7 +61,8 @@ typedef enum {
                                 path with a halo tile larger than LDS)                  */
     DMCR_EDEVICE = -4,       /* a HIP call failed (launch or runtime error)             */
     DMCR_ENONFINITE = -5,    /* reconstruct: loss or gradient became NaN / Inf          */
-    DMCR_NOT_CONVERGED = 1   /* reconstruct: iteration budget spent before tolerance    */
+    DMCR_NOT_CONVERGED = 1,  /* reconstruct: iteration budget spent before tolerance    */
+    DMCR_RUNNING = 2         /* solver slot: still iterating                            */
 } dmcr_status;
 
 enum { DMCR_MAX_LEVELS = 8, DMCR_MAX_CHANNELS = 4, DMCR_MAX_PAIRS = 10 };
@@ -188,6 +189,43 @@ typedef struct {
 
 dmcr_status dmcr_profile_start(void);
 int32_t dmcr_profile_stop(dmcr_kernel_stat *out, int32_t max);
+
+/* Continuous batching.  A solver batch of B slots shares one spec, one field
+ * buffer phi [B][C][n...], one target buffer S_target [B][K] (float64, device)
+ * and one workspace of dmcr_reconstruct_workspace_size() bytes; the per-slot
+ * scalars live in a host array of B dmcr_slot and the shared history ring in a
+ * dmcr_ring (initialise head = opt->m - 1, count = 0).  Slots are independent:
+ * each slot's iterates are bitwise the same whatever the other slots hold.
+ *   dmcr_solver_start   (re)starts the listed slots from their current phi:
+ *                       projection, one evaluation, empty history; sets
+ *                       active = 1 and status = RUNNING (or OK / ENONFINITE).
+ *   dmcr_solver_iterate runs up to `iterations` L-BFGS iterations of every
+ *                       slot with active = 1 and status = RUNNING; a slot
+ *                       stops with OK (E <= tol_derr) or NOT_CONVERGED
+ *                       (iters >= max_iter or a stalled line search).
+ * Both synchronise `stream` before returning.  The caller clears `active` of a
+ * slot it retires and may then start a new request in it. */
+typedef struct {
+    double  f;        /* current loss (E plus penalty)        */
+    double  E;        /* current descriptor error             */
+    int32_t hist;     /* pairs in this slot's history         */
+    int32_t iters;    /* iterations since start               */
+    int32_t evals;    /* evaluations since start              */
+    int32_t status;   /* dmcr_status: RUNNING, OK, NOT_CONVERGED, ENONFINITE */
+    int32_t active;   /* 1 while the slot holds a request     */
+    int32_t reserved;
+} dmcr_slot;
+
+typedef struct {
+    int32_t head, count;   /* newest history position, positions in use */
+} dmcr_ring;
+
+dmcr_status dmcr_solver_start(const dmcr_spec *spec, int32_t batch, const int32_t *which, int32_t nwhich,
+                              const double *S_target, const dmcr_bounds *bounds, const dmcr_opt *opt, float *phi,
+                              dmcr_slot *slots, void *ws, size_t ws_bytes, hipStream_t stream);
+dmcr_status dmcr_solver_iterate(const dmcr_spec *spec, int32_t batch, const double *S_target,
+                                const dmcr_bounds *bounds, const dmcr_opt *opt, float *phi, dmcr_slot *slots,
+                                dmcr_ring *ring, int32_t iterations, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Static description of a status code. */
 const char *dmcr_status_string(dmcr_status status);

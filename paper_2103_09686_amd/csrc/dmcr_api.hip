@@ -28,7 +28,9 @@ struct Carver {
     }
 };
 
-// Rough per-level cost model used by DMCR_PATH_AUTO (seconds).
+// Rough per-level cost model used by DMCR_PATH_AUTO (seconds per field).  It
+// depends on the shape only, never on the batch size, so that a field takes the
+// same kernels (and rounds the same way) alone and in any batch.
 double direct_cost(const Plan &p, int l)
 {
     const LevelPlan &L = p.lv[l];
@@ -37,13 +39,13 @@ double direct_cost(const Plan &p, int l)
     double vol = 1;
     for (int d = 0; d < p.ndim; ++d) vol *= L.box;
     macs += (double)L.N * vol * p.C * p.C;  // adjoint
-    return macs * p.B / 4.0e12 + 3 * 4e-6;
+    return macs / 4.0e12 + 3 * 4e-6;
 }
 
 double fft_cost(const Plan &p, int l)
 {
     const LevelPlan &L = p.lv[l];
-    const double bytes = (double)p.B * p.C * L.N * 60.0;
+    const double bytes = (double)p.C * L.N * 60.0;
     return bytes / 4.0e12 + (p.ndim == 3 ? 12 : 8) * 4e-6;
 }
 

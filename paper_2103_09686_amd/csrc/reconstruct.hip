@@ -20,6 +20,7 @@
 // steepest descent stops the element.
 #include <algorithm>
 #include <cmath>
+#include <new>
 #include <vector>
 
 #include "dmcr_internal.h"
@@ -73,10 +74,13 @@ __global__ void k_fill(double *p, double v, int n)
     if (i < n) p[i] = v;
 }
 
-// y[b] += sgn * coef[b] * x[b]   (coefficient read on the device)
+// y[b] += sgn * coef[b] * x[b]   (coefficient read on the device; a zero
+// coefficient leaves y untouched without reading x, whose history slot may
+// hold nothing valid)
 __global__ __launch_bounds__(kV) void k_axpy(float *y, const float *x, const double *coef, double sgn, int64_t n)
 {
     const int64_t b = blockIdx.y;
+    if (coef[b] == 0.0) return;
     const float c = (float)(sgn * coef[b]);
     for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV)
         y[b * n + i] += c * x[b * n + i];
@@ -94,13 +98,13 @@ __global__ __launch_bounds__(kV) void k_scale(float *y, const double *coef, doub
 __global__ void k_alpha(const double *dot, const double *rho, double *alpha, int B)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) alpha[b] = rho[b] * dot[b];
+    if (b < B) alpha[b] = rho[b] != 0.0 ? rho[b] * dot[b] : 0.0;  // empty slot: no contribution
 }
 
 __global__ void k_beta(const double *dot, const double *rho, const double *alpha, double *coef, int B)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) coef[b] = alpha[b] - rho[b] * dot[b];
+    if (b < B) coef[b] = rho[b] != 0.0 ? alpha[b] - rho[b] * dot[b] : 0.0;
 }
 
 // new pair in ring slot `slot`: rho = 1/s'y if accepted and s'y > eps y'y, else 0; gamma follows
@@ -111,6 +115,15 @@ __global__ void k_pair(const double *sy, const double *yy, const int *acc, doubl
     const bool ok = acc[b] && sy[b] > 2.220446049250313e-16 * yy[b] && yy[b] > 0.0;
     rho_slot[b] = ok ? 1.0 / sy[b] : 0.0;
     if (ok) gamma[b] = sy[b] / yy[b];
+}
+
+// clear the history of one element
+__global__ void k_reset_one(double *rho, double *gamma, int m, int B, int b)
+{
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < m; ++i) rho[i * B + b] = 0.0;
+        gamma[b] = 1.0;
+    }
 }
 
 // clear the history of flagged elements
@@ -336,46 +349,77 @@ struct Solver {
         return DMCR_OK;
     }
 
-    dmcr_status run(float *x, dmcr_result *res);
+    dmcr_spec spec1;  // the spec, for batch-1 plans of single-slot evaluations
+    Ws w1;            // same workspace base (a batch-1 plan fits inside the batch-B one)
+
+    dmcr_status start(float *x, const int *which, int nwhich, dmcr_slot *slots);
+    dmcr_status iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int iterations);
 };
 
-dmcr_status Solver::run(float *x, dmcr_result *res)
+// (Re)start the listed slots: clip (PROJECT), evaluate loss and gradient of each
+// slot on its own (batch-1 evaluations, bitwise identical to the batched ones),
+// clear its history.
+dmcr_status Solver::start(float *x, const int *which, int nwhich, dmcr_slot *slots)
+{
+    float *g = at<float>(r.g);
+    double *rho = at<double>(r.rho), *gamma = at<double>(r.gamma);
+    double *Ed = at<double>(r.E), *Ebcd = at<double>(r.Ebc);
+    Plan p1;
+    dmcr_spec one = spec1;
+    RS(make_plan(&one, 1, &p1));
+    std::vector<double> hE(1), hEbc(1, 0.0);
+    for (int w = 0; w < nwhich; ++w) {
+        const int b = which[w];
+        float *xb = x + (int64_t)b * n;
+        float *gb = g + (int64_t)b * n;
+        if (project)
+            hipLaunchKernelGGL(k_clip, dim3(vblocks(n)), dim3(kV), 0, st, xb, n, lo, hi);
+        RS(loss_grad_internal(p1, xb, St + (int64_t)b * p.K, Ed + b, gb, w1, st));
+        if (penalty) {
+            hipLaunchKernelGGL(k_pen_part, dim3(r.nblk, 1), dim3(kV), 0, st, xb, n, invN, lo, hi, at<double>(r.part),
+                               r.nblk);
+            hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, at<double>(r.part), r.nblk, Ebcd + b, 1);
+            hipLaunchKernelGGL(k_pen_grad, dim3(vblocks(n), 1), dim3(kV), 0, st, xb, gb, Ed + b, bd.kappa, n, invN, lo,
+                               hi);
+        }
+        hipLaunchKernelGGL(k_reset_one, dim3(1), dim3(64), 0, st, rho, gamma, m, B, b);
+        RT(hipGetLastError());
+        RT(hipMemcpyAsync(hE.data(), Ed + b, 8, hipMemcpyDeviceToHost, st));
+        if (penalty) RT(hipMemcpyAsync(hEbc.data(), Ebcd + b, 8, hipMemcpyDeviceToHost, st));
+        RT(hipStreamSynchronize(st));
+        dmcr_slot &sl = slots[b];
+        sl.E = hE[0];
+        sl.f = hE[0] + (penalty ? bd.kappa * hE[0] * hEbc[0] : 0.0);
+        sl.hist = 0;
+        sl.iters = 0;
+        sl.evals = 1;
+        sl.active = 1;
+        sl.status = DMCR_RUNNING;
+        if (!std::isfinite(sl.f))
+            sl.status = DMCR_ENONFINITE;
+        else if (sl.E <= o.tol_derr)
+            sl.status = DMCR_OK;
+    }
+    return DMCR_OK;
+}
+
+// Up to `iterations` L-BFGS iterations of every running slot.
+dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int iterations)
 {
     float *xt = at<float>(r.xt), *g = at<float>(r.g), *gt = at<float>(r.gt), *d = at<float>(r.d);
     double *rho = at<double>(r.rho), *alpha = at<double>(r.alpha), *gamma = at<double>(r.gamma);
     double *coef = at<double>(r.coef), *dot1 = at<double>(r.dot1), *dot2 = at<double>(r.dot2);
-    double *Ed = at<double>(r.E), *Etd = at<double>(r.Et), *Ebcd = at<double>(r.Ebc), *als = at<double>(r.als);
+    double *Etd = at<double>(r.Et), *Ebcd = at<double>(r.Ebc), *als = at<double>(r.als);
     int *active = at<int>(r.active), *accd = at<int>(r.acc), *flagd = at<int>(r.flag);
 
-    hipLaunchKernelGGL(k_fill, dim3((m * B + 255) / 256), dim3(256), 0, st, rho, 0.0, m * B);
-    hipLaunchKernelGGL(k_fill, dim3((B + 255) / 256), dim3(256), 0, st, gamma, 1.0, B);
-    if (project) hipLaunchKernelGGL(k_clip, dim3(vblocks((int64_t)B * n)), dim3(kV), 0, st, x, (int64_t)B * n, lo, hi);
-    RT(hipGetLastError());
-
-    std::vector<double> hE(B), hEbc(B, 0.0), hd(B), hd2(B), f(B), E(B), step(B);
-    std::vector<int> done(B, 0), iters(B, 0), evals(B, 1), why(B, DMCR_NOT_CONVERGED), hist(B, 0);
+    std::vector<double> hE(B), hEbc(B, 0.0), hd(B), hd2(B), step(B);
     std::vector<int> act(B), acc(B), flag(B);
+    auto running = [&](int b) { return slots[b].active && slots[b].status == DMCR_RUNNING; };
+    int head = ring->head, count = ring->count;
 
-    RS(evaluate(x, Ed, g));
-    RS(fetch(Ed, hE));
-    if (penalty) RS(fetch(Ebcd, hEbc));
-    RT(hipStreamSynchronize(st));
-    for (int b = 0; b < B; ++b) {
-        E[b] = hE[b];
-        f[b] = hE[b] + (penalty ? bd.kappa * hE[b] * hEbc[b] : 0.0);
-        if (!std::isfinite(f[b])) {
-            done[b] = 1;
-            why[b] = DMCR_ENONFINITE;
-        } else if (E[b] <= o.tol_derr) {
-            done[b] = 1;
-            why[b] = DMCR_OK;
-        }
-    }
-
-    int head = m - 1, count = 0;
-    for (int it = 0; it < o.max_iter; ++it) {
+    for (int it = 0; it < iterations; ++it) {
         bool any = false;
-        for (int b = 0; b < B; ++b) any |= !done[b];
+        for (int b = 0; b < B; ++b) any |= running(b);
         if (!any) break;
 
         // ---- direction d = -H g over the ring (newest first), then projection ----
@@ -402,8 +446,8 @@ dmcr_status Solver::run(float *x, dmcr_result *res)
         // not a descent direction: fall back to (projected) steepest descent
         bool any_flag = false;
         for (int b = 0; b < B; ++b) {
-            flag[b] = !done[b] && !(hd[b] < 0.0);
-            if (flag[b]) hist[b] = 0;
+            flag[b] = running(b) && !(hd[b] < 0.0);
+            if (flag[b]) slots[b].hist = 0;
             any_flag |= flag[b] != 0;
         }
         if (any_flag) {
@@ -414,13 +458,11 @@ dmcr_status Solver::run(float *x, dmcr_result *res)
 
         // ---- backtracking line search along the projected path ----
         for (int b = 0; b < B; ++b) {
-            act[b] = !done[b];
+            act[b] = running(b);
             acc[b] = 0;
             const double gn = std::sqrt(hd2[b]);
-            step[b] = (hist[b] == 0 && gn > 0.0) ? 1.0 / gn : 1.0;
+            step[b] = (slots[b].hist == 0 && gn > 0.0) ? 1.0 / gn : 1.0;
         }
-        bool all_zero_dir = false;
-        (void)all_zero_dir;
         for (int ls = 0; ls < o.max_ls; ++ls) {
             bool anyact = false;
             for (int b = 0; b < B; ++b) anyact |= act[b] != 0;
@@ -436,13 +478,13 @@ dmcr_status Solver::run(float *x, dmcr_result *res)
             RT(hipStreamSynchronize(st));
             for (int b = 0; b < B; ++b) {
                 if (!act[b]) continue;
-                ++evals[b];
+                ++slots[b].evals;
                 const double ft = hE[b] + (penalty ? bd.kappa * hE[b] * hEbc[b] : 0.0);
-                if (std::isfinite(ft) && hd[b] < 0.0 && ft <= f[b] + o.c1 * hd[b]) {
+                if (std::isfinite(ft) && hd[b] < 0.0 && ft <= slots[b].f + o.c1 * hd[b]) {
                     act[b] = 0;
                     acc[b] = 1;
-                    f[b] = ft;
-                    E[b] = hE[b];
+                    slots[b].f = ft;
+                    slots[b].E = hE[b];
                 } else {
                     step[b] *= 0.5;
                 }
@@ -461,27 +503,20 @@ dmcr_status Solver::run(float *x, dmcr_result *res)
         count = std::min(count + 1, m);
         bool any_fail = false;
         for (int b = 0; b < B; ++b) {
-            if (done[b]) {
-                flag[b] = 0;
-                continue;
-            }
-            ++iters[b];
+            flag[b] = 0;
+            if (!running(b)) continue;
+            dmcr_slot &sl = slots[b];
+            ++sl.iters;
             if (acc[b]) {
-                flag[b] = 0;
-                hist[b] = std::min(hist[b] + 1, m);
-                if (E[b] <= o.tol_derr) {
-                    done[b] = 1;
-                    why[b] = DMCR_OK;
-                }
+                sl.hist = std::min(sl.hist + 1, m);
+                if (sl.E <= o.tol_derr) sl.status = DMCR_OK;
             } else {
                 flag[b] = 1;  // clear the history of a failed line search
                 any_fail = true;
-                if (hist[b] == 0) {
-                    done[b] = 1;  // no progress even from steepest descent
-                    why[b] = DMCR_NOT_CONVERGED;
-                }
-                hist[b] = 0;
+                if (sl.hist == 0) sl.status = DMCR_NOT_CONVERGED;  // no progress even from steepest descent
+                sl.hist = 0;
             }
+            if (sl.status == DMCR_RUNNING && sl.iters >= o.max_iter) sl.status = DMCR_NOT_CONVERGED;
         }
         if (any_fail) {
             RS(put(flagd, flag));
@@ -489,23 +524,48 @@ dmcr_status Solver::run(float *x, dmcr_result *res)
             RT(hipGetLastError());
         }
     }
+    ring->head = head;
+    ring->count = count;
     RT(hipStreamSynchronize(st));
-    bool all_ok = true;
-    for (int b = 0; b < B; ++b) {
-        res[b].final_E = E[b];
-        res[b].final_derr = E[b];
-        res[b].iters = iters[b];
-        res[b].evals = evals[b];
-        res[b].why = why[b];
-        all_ok &= why[b] == DMCR_OK;
-    }
-    return all_ok ? DMCR_OK : DMCR_NOT_CONVERGED;
+    return DMCR_OK;
 }
 
 }  // namespace
 }  // namespace dmcr
 
 using namespace dmcr;
+
+namespace {
+
+dmcr_status make_solver(const dmcr_spec *spec, int32_t batch, const double *S_target, const dmcr_bounds *bounds,
+                        const dmcr_opt *opt, float *phi, void *ws, size_t ws_bytes, hipStream_t st, Plan &p,
+                        Solver **out, std::vector<char> &mem)
+{
+    if (!opt_ok(opt) || !bounds || !S_target || !phi) return DMCR_EINVAL;
+    if (bounds->mode < DMCR_BOUNDS_NONE || bounds->mode > DMCR_BOUNDS_PENALTY) return DMCR_EINVAL;
+    if (bounds->mode != DMCR_BOUNDS_NONE && !(bounds->lo < bounds->hi)) return DMCR_EINVAL;
+    if (bounds->mode == DMCR_BOUNDS_PENALTY && !(bounds->kappa >= 0.0)) return DMCR_EINVAL;
+    dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    const RLayout r = r_layout(p, *opt);
+    if (ws_bytes < r.bytes) return DMCR_ENOMEM;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign)) return DMCR_EINVAL;
+    mem.resize(sizeof(Solver));
+    Solver *sv = new (mem.data()) Solver{p, *bounds, *opt, S_target, r, Ws{static_cast<char *>(ws)}, st, batch,
+                                         opt->m, (int64_t)p.C * p.lv[0].N, dim3(), dim3(), false, false, 0.f, 0.f,
+                                         0.0, *spec, Ws{static_cast<char *>(ws)}};
+    sv->vg = dim3(vblocks(sv->n), batch);
+    sv->sg = dim3((batch + 63) / 64);
+    sv->project = bounds->mode == DMCR_BOUNDS_PROJECT;
+    sv->penalty = bounds->mode == DMCR_BOUNDS_PENALTY;
+    sv->lo = (float)bounds->lo;
+    sv->hi = (float)bounds->hi;
+    sv->invN = 1.0 / (double)p.lv[0].N;
+    *out = sv;
+    return DMCR_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -520,30 +580,68 @@ dmcr_status dmcr_reconstruct_workspace_size(const dmcr_spec *spec, int32_t batch
     return DMCR_OK;
 }
 
+dmcr_status dmcr_solver_start(const dmcr_spec *spec, int32_t batch, const int32_t *which, int32_t nwhich,
+                              const double *S_target, const dmcr_bounds *bounds, const dmcr_opt *opt, float *phi,
+                              dmcr_slot *slots, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!which || !slots || nwhich < 0) return DMCR_EINVAL;
+    for (int i = 0; i < nwhich; ++i)
+        if (which[i] < 0 || which[i] >= batch) return DMCR_EINVAL;
+    Plan p;
+    Solver *sv = nullptr;
+    std::vector<char> mem;
+    dmcr_status s = make_solver(spec, batch, S_target, bounds, opt, phi, ws, ws_bytes, stream, p, &sv, mem);
+    if (s != DMCR_OK) return s;
+    s = sv->start(phi, which, nwhich, slots);
+    sv->~Solver();
+    return s;
+}
+
+dmcr_status dmcr_solver_iterate(const dmcr_spec *spec, int32_t batch, const double *S_target,
+                                const dmcr_bounds *bounds, const dmcr_opt *opt, float *phi, dmcr_slot *slots,
+                                dmcr_ring *ring, int32_t iterations, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!slots || !ring || iterations < 0 || ring->count < 0 || ring->count > opt->m || ring->head < 0 ||
+        ring->head >= opt->m)
+        return DMCR_EINVAL;
+    Plan p;
+    Solver *sv = nullptr;
+    std::vector<char> mem;
+    dmcr_status s = make_solver(spec, batch, S_target, bounds, opt, phi, ws, ws_bytes, stream, p, &sv, mem);
+    if (s != DMCR_OK) return s;
+    s = sv->iterate(phi, slots, ring, iterations);
+    sv->~Solver();
+    return s;
+}
+
 dmcr_status dmcr_reconstruct(const dmcr_spec *spec, int32_t batch, const double *S_target, const dmcr_bounds *bounds,
                              const dmcr_opt *opt, float *phi, dmcr_result *results, void *ws, size_t ws_bytes,
                              hipStream_t st)
 {
-    if (!opt_ok(opt) || !bounds || !S_target || !phi || !results) return DMCR_EINVAL;
-    if (bounds->mode < DMCR_BOUNDS_NONE || bounds->mode > DMCR_BOUNDS_PENALTY) return DMCR_EINVAL;
-    if (bounds->mode != DMCR_BOUNDS_NONE && !(bounds->lo < bounds->hi)) return DMCR_EINVAL;
-    if (bounds->mode == DMCR_BOUNDS_PENALTY && !(bounds->kappa >= 0.0)) return DMCR_EINVAL;
+    if (!results || batch < 1) return DMCR_EINVAL;
     Plan p;
-    dmcr_status s = make_plan(spec, batch, &p);
+    Solver *sv = nullptr;
+    std::vector<char> mem;
+    dmcr_status s = make_solver(spec, batch, S_target, bounds, opt, phi, ws, ws_bytes, st, p, &sv, mem);
     if (s != DMCR_OK) return s;
-    const RLayout r = r_layout(p, *opt);
-    if (ws_bytes < r.bytes) return DMCR_ENOMEM;
-    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign)) return DMCR_EINVAL;
-    Solver sv{p, *bounds, *opt, S_target, r, Ws{static_cast<char *>(ws)}, st, batch, opt->m,
-              (int64_t)p.C * p.lv[0].N, dim3(), dim3(), false, false, 0.f, 0.f, 0.0};
-    sv.vg = dim3(vblocks(sv.n), batch);
-    sv.sg = dim3((batch + 63) / 64);
-    sv.project = bounds->mode == DMCR_BOUNDS_PROJECT;
-    sv.penalty = bounds->mode == DMCR_BOUNDS_PENALTY;
-    sv.lo = (float)bounds->lo;
-    sv.hi = (float)bounds->hi;
-    sv.invN = 1.0 / (double)p.lv[0].N;
-    return sv.run(phi, results);
+    std::vector<dmcr_slot> slots(batch);
+    std::vector<int32_t> all(batch);
+    for (int b = 0; b < batch; ++b) all[b] = b;
+    dmcr_ring ring{opt->m - 1, 0};
+    s = sv->start(phi, all.data(), batch, slots.data());
+    if (s == DMCR_OK) s = sv->iterate(phi, slots.data(), &ring, opt->max_iter);
+    sv->~Solver();
+    if (s != DMCR_OK) return s;
+    bool all_ok = true;
+    for (int b = 0; b < batch; ++b) {
+        results[b].final_E = slots[b].E;
+        results[b].final_derr = slots[b].E;
+        results[b].iters = slots[b].iters;
+        results[b].evals = slots[b].evals;
+        results[b].why = slots[b].status == DMCR_RUNNING ? DMCR_NOT_CONVERGED : slots[b].status;
+        all_ok &= results[b].why == DMCR_OK;
+    }
+    return all_ok ? DMCR_OK : DMCR_NOT_CONVERGED;
 }
 
 }  // extern "C"

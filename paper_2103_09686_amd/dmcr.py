@@ -21,7 +21,8 @@ BOUNDS_NONE, BOUNDS_PROJECT, BOUNDS_PENALTY = 0, 1, 2
 MAX_LEVELS, MAX_CHANNELS, MAX_PAIRS = 8, 4, 10
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSUPPORTED", -4: "EDEVICE",
-          -5: "ENONFINITE", 1: "NOT_CONVERGED"}
+          -5: "ENONFINITE", 1: "NOT_CONVERGED", 2: "RUNNING"}
+OK, NOT_CONVERGED, RUNNING, ENONFINITE = 0, 1, 2, -5
 
 
 class DmcrError(RuntimeError):
@@ -47,6 +48,16 @@ class c_bounds(ctypes.Structure):
 class c_opt(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("max_ls", ctypes.c_int32),
                 ("tol_derr", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double)]
+
+
+class c_slot(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_double), ("E", ctypes.c_double), ("hist", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("evals", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("active", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class c_ring(ctypes.Structure):
+    _fields_ = [("head", ctypes.c_int32), ("count", ctypes.c_int32)]
 
 
 class c_result(ctypes.Structure):
@@ -139,11 +150,18 @@ def lib():
         L.dmcr_reconstruct.argtypes = [sp, ctypes.c_int32, _vp, ctypes.POINTER(c_bounds),
                                        ctypes.POINTER(c_opt), _vp, ctypes.POINTER(c_result), _vp,
                                        ctypes.c_size_t, _vp]
+        L.dmcr_solver_start.argtypes = [sp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _vp,
+                                        ctypes.POINTER(c_bounds), ctypes.POINTER(c_opt), _vp,
+                                        ctypes.POINTER(c_slot), _vp, ctypes.c_size_t, _vp]
+        L.dmcr_solver_iterate.argtypes = [sp, ctypes.c_int32, _vp, ctypes.POINTER(c_bounds), ctypes.POINTER(c_opt),
+                                          _vp, ctypes.POINTER(c_slot), ctypes.POINTER(c_ring), ctypes.c_int32, _vp,
+                                          ctypes.c_size_t, _vp]
         L.dmcr_status_string.argtypes = [ctypes.c_int]
         L.dmcr_status_string.restype = ctypes.c_char_p
         for fn in ("dmcr_descriptor_offsets", "dmcr_workspace_size", "dmcr_pyramid",
                    "dmcr_descriptor_forward", "dmcr_descriptor_adjoint", "dmcr_error_cotangent",
-                   "dmcr_loss_grad", "dmcr_reconstruct_workspace_size", "dmcr_reconstruct"):
+                   "dmcr_loss_grad", "dmcr_reconstruct_workspace_size", "dmcr_reconstruct",
+                   "dmcr_solver_start", "dmcr_solver_iterate"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -338,6 +356,44 @@ def dmcr_reconstruct(spec: Spec, S_target: torch.Tensor, phi: torch.Tensor, boun
     _check("dmcr_reconstruct", code)
     return code, [dict(final_E=r.final_E, final_derr=r.final_derr, iters=r.iters, evals=r.evals, why=r.why)
                   for r in res]
+
+
+class Solver:
+    """A batch of `batch` L-BFGS slots of one spec for continuous batching
+    (dmcr_solver_start / dmcr_solver_iterate).  Holds the field and target
+    buffers, the workspace, the host slot array and the history ring."""
+
+    def __init__(self, spec: Spec, batch: int, bounds: Bounds = None, opt: Opt = None, device=None):
+        self.spec, self.B = spec, batch
+        self.bounds, self.opt = bounds or Bounds(), opt or Opt()
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.K = dmcr_descriptor_size(spec)
+        self.phi = torch.zeros((batch, spec.n_channels) + tuple(spec.shape), dtype=torch.float32, device=dev)
+        self.St = torch.zeros((batch, self.K), dtype=torch.float64, device=dev)
+        self.ws_bytes = dmcr_reconstruct_workspace_size(spec, batch, self.opt)
+        self.ws = workspace(self.ws_bytes, dev)
+        self.slots = (c_slot * batch)()
+        self.ring = c_ring(self.opt.m - 1, 0)
+        self._c = (spec.c(), self.bounds.c(), self.opt.c())
+
+    @property
+    def footprint(self) -> int:
+        return self.phi.numel() * 4 + self.St.numel() * 8 + self.ws.numel()
+
+    def start(self, which, stream=None):
+        idx = (ctypes.c_int32 * len(which))(*which)
+        s, b, o = self._c
+        _check("dmcr_solver_start", lib().dmcr_solver_start(
+            ctypes.byref(s), self.B, idx, len(which), ctypes.c_void_p(self.St.data_ptr()), ctypes.byref(b),
+            ctypes.byref(o), ctypes.c_void_p(self.phi.data_ptr()), self.slots, ctypes.c_void_p(self.ws.data_ptr()),
+            self.ws.numel(), _stream(stream)))
+
+    def iterate(self, iterations: int, stream=None):
+        s, b, o = self._c
+        _check("dmcr_solver_iterate", lib().dmcr_solver_iterate(
+            ctypes.byref(s), self.B, ctypes.c_void_p(self.St.data_ptr()), ctypes.byref(b), ctypes.byref(o),
+            ctypes.c_void_p(self.phi.data_ptr()), self.slots, ctypes.byref(self.ring), iterations,
+            ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream(stream)))
 
 
 class S2Descriptor(torch.autograd.Function):

@@ -33,12 +33,14 @@ def _fill_until(mask, target_vf, propose, rng, allowed=None, max_objects=10_000_
     count = 0
     flat = mask.reshape(-1)
     strides = np.array([int(np.prod(shape[a + 1:])) for a in range(len(shape))])
-    while flat.sum() < target_vf * N and count < max_objects:
+    covered = int(np.count_nonzero(flat))
+    while covered < target_vf * N and count < max_objects:
         centre, offsets = propose(rng)
         idx = np.mod(offsets + centre[None, :], shape[None, :])
-        lin = idx @ strides
+        lin = np.unique(idx @ strides)
         if allowed is not None:
             lin = lin[allowed.reshape(-1)[lin]]
+        covered += int(np.count_nonzero(~flat[lin]))
         flat[lin] = True
         count += 1
     return count

@@ -1,0 +1,140 @@
+"""The continuous-batching scheduler on a simulated executor (virtual clock, fake HBM
+budget, fixed per-request iteration needs): admission by footprint, slot reuse,
+release of idle groups, latency accounting, no deadlock on requests that cannot fit."""
+import numpy as np
+import pytest
+
+from paper_2103_09686_amd import serve
+
+
+class FakeGroup(serve.Group):
+    def __init__(self, ex, key, capacity):
+        self.ex, self.key, self.capacity = ex, key, capacity
+        self.footprint = ex.footprint(key, capacity)
+        self.need, self.done_iters = {}, {}
+        ex.live += 1
+        ex.max_live = max(ex.max_live, ex.live)
+
+    def admit(self, slot, req):
+        assert slot not in self.need, "slot handed out twice"
+        self.need[slot] = req.payload
+        self.done_iters[slot] = 0
+        self.ex.max_active[self.key] = max(self.ex.max_active.get(self.key, 0), len(self.need))
+
+    def step(self, iterations):
+        out = []
+        vox = 0
+        for slot in list(self.need):
+            self.done_iters[slot] += iterations
+            vox += self.key[0]
+            if self.done_iters[slot] >= self.need[slot]:
+                out.append((slot, 0, 1e-5, self.need[slot]))
+                del self.need[slot]
+        self.ex.tick_cost = max(self.ex.tick_cost, 1e-4 + 1e-9 * vox * iterations)
+        return out
+
+    def release(self):
+        self.ex.live -= 1
+        self.ex.released += 1
+
+
+class FakeExecutor(serve.Executor):
+    def __init__(self, per_slot_bytes=100, caps=None):
+        self.t, self.tick_cost = 0.0, 0.0
+        self.per_slot = per_slot_bytes
+        self.caps = caps or {}
+        self.live = self.max_live = self.released = 0
+        self.max_active = {}
+
+    def capacity(self, key):
+        return self.caps.get(key, 4)
+
+    def footprint(self, key, capacity):
+        return self.per_slot * capacity * key[0]
+
+    def make_group(self, key, capacity):
+        return FakeGroup(self, key, capacity)
+
+    def now(self):
+        return self.t
+
+    def wait_until(self, t):
+        self.t = max(self.t, t)
+
+    def after_tick(self):
+        self.t += self.tick_cost
+        self.tick_cost = 0.0
+
+
+def reqs(n, keys, seed=0, rate=100.0):
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += rng.exponential(1 / rate)
+        k = keys[rng.integers(len(keys))]
+        out.append(serve.Request(rid=i, arrival=t, key=k, voxels=k[0], payload=int(rng.integers(3, 40))))
+    return out
+
+
+def test_all_requests_finish_with_their_iterations():
+    ex = FakeExecutor()
+    srv = serve.Server(ex, budget_bytes=10 ** 9, iters_per_tick=4, threads=2)
+    rs = reqs(60, [(1,), (2,), (3,)])
+    need = {r.rid: r.payload for r in rs}
+    done = srv.run(rs)
+    srv.close()
+    assert sorted(r.rid for r in done) == list(range(60))
+    for r in done:
+        assert r.iters == need[r.rid] and r.status == 0
+        assert r.t_done >= r.t_admit >= r.arrival
+    s = serve.summary(done)
+    assert s["p99_s"] >= s["p50_s"] > 0 and s["requests"] == 60
+
+
+def test_slots_never_exceed_capacity_and_are_reused():
+    ex = FakeExecutor(caps={(1,): 2})
+    srv = serve.Server(ex, budget_bytes=10 ** 9, iters_per_tick=2, threads=1)
+    rs = [serve.Request(rid=i, arrival=0.0, key=(1,), voxels=1, payload=10) for i in range(7)]
+    done = srv.run(rs)
+    srv.close()
+    assert len(done) == 7 and ex.max_active[(1,)] == 2
+
+
+def test_budget_limits_groups_and_idle_groups_are_released():
+    # a group costs 100 * capacity * key[0] bytes: (1,) x4 = 400, (2,) x2 = 400; the
+    # budget holds one of them at a time, so the classes take turns
+    ex = FakeExecutor()
+    srv = serve.Server(ex, budget_bytes=450, iters_per_tick=4, threads=2)
+    rs = reqs(30, [(1,), (2,)], seed=3)
+    done = srv.run(rs)
+    srv.close()
+    assert len(done) == 30 and all(r.status == 0 for r in done)
+    assert srv.peak_bytes <= 450
+    assert ex.max_live == 1 and ex.released >= 1
+
+
+def test_group_shrinks_to_fit_budget():
+    ex = FakeExecutor(caps={(5,): 8})
+    srv = serve.Server(ex, budget_bytes=1000, iters_per_tick=4, threads=1)
+    done = srv.run([serve.Request(rid=i, arrival=0.0, key=(5,), voxels=5, payload=5) for i in range(5)])
+    srv.close()
+    assert len(done) == 5 and srv.peak_bytes <= 1000   # capacity 8 -> 2 (1000 / 500)
+
+
+def test_request_that_cannot_fit_fails_instead_of_hanging():
+    ex = FakeExecutor()
+    srv = serve.Server(ex, budget_bytes=50, iters_per_tick=4, threads=1)
+    done = srv.run([serve.Request(rid=0, arrival=0.0, key=(1,), voxels=1, payload=5)])
+    srv.close()
+    assert len(done) == 1 and done[0].status == -2
+
+
+def test_request_stream_and_level_rule():
+    st = serve.request_stream(200, 20.0, seed=0)
+    assert len(st) == 200
+    gaps = np.diff([0.0] + [a for (a, *_ ) in st])
+    assert abs(gaps.mean() - 1 / 20.0) < 0.02
+    assert serve.levels_for(64, 31) == 1 and serve.levels_for(128, 31) == 2 and serve.levels_for(256, 31) == 3
+    key = serve.make_key((128, 128, 128), 3)
+    assert key[1] == 2 and key[2] == serve.levels_for(128, 16)

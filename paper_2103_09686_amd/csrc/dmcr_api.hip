@@ -221,34 +221,131 @@ hipError_t run_pyramid(const Plan &p, const float *phi, const Ws &ws, hipStream_
     return hipSuccess;
 }
 
-hipError_t run_forward(const Plan &p, const float *phi, float *S, const Ws &ws, hipStream_t st)
-{
-    hipError_t e = run_pyramid(p, phi, ws, st);
-    if (e != hipSuccess) return e;
-    for (int l = 0; l < p.L; ++l) {
-        const float *f = level_field(p, l, phi, ws);
-        e = (p.lv[l].path == DMCR_PATH_FFT) ? fft_forward_level(p, l, f, S, ws, st)
-                                            : direct_forward_level(p, l, f, S, ws, st);
+// Internal streams that let independent work of one call overlap: the levels
+// of the pyramid run on their own lanes, and a recomputed spectrum is built on
+// a side lane while the caller's stream finishes the forward and builds the
+// cotangent transforms.  Every lane joins the caller's stream before the call
+// returns, so the caller sees ordinary stream semantics.  Pools are per host
+// thread (and per device), so concurrent callers never share an event.
+struct Lanes {
+    static constexpr int kSide = 3;
+    static constexpr int kEvents = 96;
+    int device = -1;
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev[kEvents] = {};
+    int next = 0;
+
+    hipError_t init()
+    {
+        int dev = -1;
+        hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
+        if (dev == device) return hipSuccess;
+        for (int i = 0; i < kSide; ++i) {
+            e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+        }
+        for (int i = 0; i < kEvents; ++i) {
+            e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        device = dev;
+        return hipSuccess;
     }
+    hipEvent_t event() { return ev[next++ % kEvents]; }
+};
+
+thread_local Lanes tl_lanes;
+
+struct Sched {
+    Lanes *ln;
+    hipStream_t main;
+    bool multi;  // false: everything on the caller's stream
+    hipStream_t lane(int l) const { return (l == 0 || !multi) ? main : ln->side[(l - 1) % Lanes::kSide]; }
+    // a stream that is not lane(l) of a level in use, for level l's recompute
+    hipStream_t spare(int l, int L) const
+    {
+        if (!multi) return main;
+        if (L == 1) return ln->side[0];
+        return (l == 0) ? ln->side[(L - 1) % Lanes::kSide] : main;
+    }
+    hipError_t join(hipStream_t to, hipStream_t from)
+    {
+        if (to == from || !multi) return hipSuccess;
+        hipEvent_t e = ln->event();
+        hipError_t r = hipEventRecord(e, from);
+        if (r != hipSuccess) return r;
+        return hipStreamWaitEvent(to, e, 0);
+    }
+};
+
+// Side lanes pay off only when the passes are long enough to hide the extra
+// event waits; small fields stay on the caller's stream (measured: a 512^2
+// three-level evaluation is slower with lanes, 256^3 and 64 x 512^2 faster).
+constexpr int64_t kLaneMinVoxels = int64_t(1) << 22;
+
+hipError_t make_sched(const Plan &p, hipStream_t st, Sched *s)
+{
+    const bool multi = (int64_t)p.B * p.C * p.lv[0].N >= kLaneMinVoxels;
+    if (multi) {
+        hipError_t e = tl_lanes.init();
+        if (e != hipSuccess) return e;
+        tl_lanes.next = 0;
+    }
+    *s = Sched{&tl_lanes, st, multi};
     return hipSuccess;
 }
 
-// Adjoint of every level, coarsest first, each level's total gradient being
-// its own term plus the prolongation of the next coarser total (Sec. 3.3:
-// back-propagation through all levels at once).
-hipError_t run_adjoint(const Plan &p, const float *phi, const float *G, float *grad, bool have_spectrum,
-                       const Ws &ws, hipStream_t st)
+// Forward of every level on its lane.  x_free[l] (recompute only) marks the
+// point after which level l's partial spectrum may be overwritten.
+hipError_t run_forward(const Plan &p, const float *phi, float *S, const Ws &ws, Sched &sc,
+                       hipEvent_t *x_free = nullptr)
 {
+    hipError_t e = run_pyramid(p, phi, ws, sc.main);
+    if (e != hipSuccess) return e;
+    for (int l = 1; l < p.L; ++l)
+        if ((e = sc.join(sc.lane(l), sc.main)) != hipSuccess) return e;
+    for (int l = 0; l < p.L; ++l) {
+        const float *f = level_field(p, l, phi, ws);
+        e = (p.lv[l].path == DMCR_PATH_FFT)
+                ? fft_forward_level(p, l, f, S, ws, sc.lane(l), x_free ? x_free[l] : nullptr)
+                : direct_forward_level(p, l, f, S, ws, sc.lane(l));
+        if (e != hipSuccess) return e;
+    }
+    for (int l = 1; l < p.L; ++l)
+        if ((e = sc.join(sc.main, sc.lane(l))) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+// Adjoint of every level on its lane, then the prolongation chain on the
+// caller's stream, coarsest first: each level's total gradient is its own term
+// plus the prolongation of the next coarser total (Sec. 3.3: back-propagation
+// through all levels at once).
+hipError_t run_adjoint(const Plan &p, const float *phi, const float *G, float *grad, bool have_spectrum,
+                       const Ws &ws, Sched &sc, hipEvent_t *x_free = nullptr)
+{
+    hipError_t e;
+    for (int l = 1; l < p.L; ++l)
+        if ((e = sc.join(sc.lane(l), sc.main)) != hipSuccess) return e;
     for (int l = p.L - 1; l >= 0; --l) {
         const float *f = level_field(p, l, phi, ws);
         float *g = (l == 0) ? grad : ws.at<float>(p.lv[l].grad);
-        hipError_t e = (p.lv[l].path == DMCR_PATH_FFT)
-                           ? fft_adjoint_level(p, l, f, G, g, have_spectrum, ws, st)
-                           : direct_adjoint_level(p, l, f, G, g, ws, st);
+        if (p.lv[l].path == DMCR_PATH_FFT) {
+            if (!have_spectrum && x_free)
+                e = fft_adjoint_level(p, l, f, G, g, false, ws, sc.lane(l), sc.spare(l, p.L), x_free[l],
+                                      sc.ln->event());
+            else
+                e = fft_adjoint_level(p, l, f, G, g, have_spectrum, ws, sc.lane(l));
+        } else {
+            e = direct_adjoint_level(p, l, f, G, g, ws, sc.lane(l));
+        }
         if (e != hipSuccess) return e;
+    }
+    for (int l = p.L - 1; l >= 0; --l) {
+        if ((e = sc.join(sc.main, sc.lane(l))) != hipSuccess) return e;
         if (l + 1 < p.L) {
-            e = launch_prolong_add(p, l, ws.at<float>(p.lv[l + 1].grad), g, st);
+            float *g = (l == 0) ? grad : ws.at<float>(p.lv[l].grad);
+            e = launch_prolong_add(p, l, ws.at<float>(p.lv[l + 1].grad), g, sc.main);
             if (e != hipSuccess) return e;
         }
     }
@@ -264,10 +361,16 @@ dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St
 {
     float *S = w.at<float>(p.S);
     float *G = w.at<float>(p.G);
-    DMCR_TRY(run_forward(p, phi, S, w, st));
-    DMCR_TRY(launch_error(p, S, St, E, G, w, st));
+    Sched sc;
+    DMCR_TRY(make_sched(p, st, &sc));
     const bool keep = (p.flags & DMCR_FLAG_RECOMPUTE) == 0;
-    return dev(run_adjoint(p, phi, G, grad, keep, w, st));
+    hipEvent_t x_free[kMaxLevels] = {};
+    if (!keep && sc.multi)
+        for (int l = 0; l < p.L; ++l) x_free[l] = sc.ln->event();
+    hipEvent_t *xf = (!keep && sc.multi) ? x_free : nullptr;
+    DMCR_TRY(run_forward(p, phi, S, w, sc, xf));
+    DMCR_TRY(launch_error(p, S, St, E, G, w, st));
+    return dev(run_adjoint(p, phi, G, grad, keep, w, sc, xf));
 }
 
 }  // namespace dmcr
@@ -332,7 +435,9 @@ dmcr_status dmcr_descriptor_forward(const dmcr_spec *spec, int32_t batch, const 
     if (!phi || !S) return DMCR_EINVAL;
     if ((s = check_ws(p, ws, ws_bytes)) != DMCR_OK) return s;
     Ws w{static_cast<char *>(ws)};
-    return dev(run_forward(p, phi, S, w, stream));
+    Sched sc;
+    DMCR_TRY(make_sched(p, stream, &sc));
+    return dev(run_forward(p, phi, S, w, sc));
 }
 
 dmcr_status dmcr_descriptor_adjoint(const dmcr_spec *spec, int32_t batch, const float *phi, const float *dS,
@@ -344,8 +449,10 @@ dmcr_status dmcr_descriptor_adjoint(const dmcr_spec *spec, int32_t batch, const 
     if (!phi || !dS || !grad) return DMCR_EINVAL;
     if ((s = check_ws(p, ws, ws_bytes)) != DMCR_OK) return s;
     Ws w{static_cast<char *>(ws)};
+    Sched sc;
+    DMCR_TRY(make_sched(p, stream, &sc));
     DMCR_TRY(run_pyramid(p, phi, w, stream));
-    return dev(run_adjoint(p, phi, dS, grad, false, w, stream));
+    return dev(run_adjoint(p, phi, dS, grad, false, w, sc));
 }
 
 dmcr_status dmcr_error_cotangent(const dmcr_spec *spec, int32_t batch, const float *S, const double *S_target,

@@ -100,11 +100,16 @@ hipError_t launch_restrict(const Plan &p, int l, const float *fine, float *coars
 hipError_t launch_prolong_add(const Plan &p, int l, const float *coarse_grad, float *fine_grad,
                               hipStream_t st);
 
+// x_free (optional) is recorded on st once the partial spectrum X of the level
+// has been consumed, so that a recompute of X on another stream may start.
 hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
-                             hipStream_t st);
+                             hipStream_t st, hipEvent_t x_free = nullptr);
 hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &ws, hipStream_t st);
+// Without have_spectrum the spectrum is recomputed: on st_spec after x_free when
+// st_spec is given (overlapping the cotangent transforms on st), else on st.
 hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
-                             bool have_spectrum, const Ws &ws, hipStream_t st);
+                             bool have_spectrum, const Ws &ws, hipStream_t st, hipStream_t st_spec = nullptr,
+                             hipEvent_t x_free = nullptr, hipEvent_t spec_done = nullptr);
 
 hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
                                 hipStream_t st);

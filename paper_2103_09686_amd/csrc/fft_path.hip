@@ -662,7 +662,8 @@ hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &
     return hipSuccess;
 }
 
-hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws, hipStream_t st)
+hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws, hipStream_t st,
+                             hipEvent_t x_free)
 {
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C;
@@ -689,6 +690,7 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
     a.scale = (float)(invN * invN);
     const double bytes0 = (double)B * C * n0 * inner_valid * 8 + (double)B * p.npairs * L.box * inner_valid * 8;
     TRY_HIP(axis0_launch(C, false, ilog2(n0), a, bytes0, st));
+    if (x_free) TRY_HIP(hipEventRecord(x_free, st));
 
     // remaining inverse axes, pruned, then scatter into descriptor order
     const float2 *last_in = Y;
@@ -722,7 +724,8 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
 }
 
 hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
-                             bool have_spectrum, const Ws &ws, hipStream_t st)
+                             bool have_spectrum, const Ws &ws, hipStream_t st, hipStream_t st_spec, hipEvent_t x_free,
+                             hipEvent_t spec_done)
 {
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C, CC = C * C;
@@ -755,7 +758,16 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
         TRY_HIP((cols_launch<T_KB_MID, false>(ilog2(L.n[1]), c, col_bytes(c), st)));
         KBaxis0 = KB2;
     }
-    if (!have_spectrum) TRY_HIP(fft_spectrum_level(p, l, phi, ws, st));
+    if (!have_spectrum) {
+        if (st_spec) {
+            if (x_free) TRY_HIP(hipStreamWaitEvent(st_spec, x_free, 0));
+            TRY_HIP(fft_spectrum_level(p, l, phi, ws, st_spec));
+            TRY_HIP(hipEventRecord(spec_done, st_spec));
+            TRY_HIP(hipStreamWaitEvent(st, spec_done, 0));
+        } else {
+            TRY_HIP(fft_spectrum_level(p, l, phi, ws, st));
+        }
+    }
     float2 *X = ws.at<float2>(L.X);
     const int n0 = L.n[0];
     const int64_t inner = (p.ndim == 2) ? L.hp : (int64_t)L.n[1] * L.hp;

@@ -39,15 +39,18 @@ WORKLOADS = {
 }
 
 
+# the sources the FFT-path kernels (the dominant kernels of every workload) compile from
+KERNEL_SOURCES = ("dmcr_internal.h", "fft_path.hip", "fft_reg.h")
+
+
 def source_hash():
-    """Hash of the HIP sources: a stored counter profile is valid only for this code."""
+    """Hash of the FFT-path kernel sources: a stored counter profile is valid only for this code."""
     import hashlib
     d = os.path.join(ROOT, "paper_2103_09686_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 

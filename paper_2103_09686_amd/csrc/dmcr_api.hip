@@ -369,8 +369,12 @@ dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St
         for (int l = 0; l < p.L; ++l) x_free[l] = sc.ln->event();
     hipEvent_t *xf = (!keep && sc.multi) ? x_free : nullptr;
     DMCR_TRY(run_forward(p, phi, S, w, sc, xf));
-    DMCR_TRY(launch_error(p, S, St, E, G, w, st));
-    return dev(run_adjoint(p, phi, G, grad, keep, w, sc, xf));
+    // one level: side lane 1 is idle (lane 0 is the caller's stream, the
+    // recompute uses side lane 0), so the final error sum runs there
+    hipStream_t fin = (sc.multi && p.L == 1) ? sc.ln->side[1] : st;
+    DMCR_TRY(launch_error(p, S, St, E, G, w, st, fin, fin != st ? sc.ln->event() : nullptr));
+    DMCR_TRY(run_adjoint(p, phi, G, grad, keep, w, sc, xf));
+    return dev(sc.join(st, fin));
 }
 
 }  // namespace dmcr

@@ -118,8 +118,12 @@ hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const fl
 
 hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0, hipStream_t st);
 
+// E and the cotangent G from S.  G is ready on st; with st_final (and the
+// event parts_done) the final sum into E runs on st_final instead, off the
+// path of the adjoint, and the caller joins st_final.
 hipError_t launch_error(const Plan &p, const float *S, const double *St, double *E, float *G,
-                        const Ws &ws, hipStream_t st);
+                        const Ws &ws, hipStream_t st, hipStream_t st_final = nullptr,
+                        hipEvent_t parts_done = nullptr);
 
 // true if the DIRECT path can run this level (halo tile fits in LDS)
 bool direct_supported(const Plan &p, int l, int tile_out[3]);

@@ -26,6 +26,22 @@ namespace dmcr {
 
 namespace {
 
+enum PassTag {
+    T_R2C_LAST = 0,    // forward, contiguous axis, real -> half spectrum
+    T_FWD_MID,         // forward, axis 1 (3-D), in place
+    T_INV_MID_BOX,     // inverse, axis 1 (3-D), keep the |r1| <= P rows
+    T_C2R_DESC,        // inverse, contiguous axis, half -> real rows of the box, into S
+    T_KB_LAST,         // forward of the cotangent boxes, contiguous axis
+    T_KB_MID,          // forward of the cotangent boxes, axis 1 (3-D)
+    T_INV_MID,         // inverse, axis 1 (3-D), in place
+    T_C2R_FULL         // inverse, contiguous axis, half -> real field
+};
+
+// Row modes of the strided passes, fixed per pass so that their loads and
+// stores compile without per-element mode tests.
+constexpr int col_in_mode(int tag) { return tag == T_KB_MID ? IO_BOX : IO_FULL; }
+constexpr int col_out_mode(int tag) { return tag == T_INV_MID_BOX ? IO_BOX : IO_FULL; }
+
 // tile geometry per transform length: T pencils per block, R2 threads each,
 // with the LDS exchange (and the row staging) within 64 KB
 template <int L>
@@ -69,10 +85,17 @@ struct RowArgs {
     int pi[kMaxPairs], pj[kMaxPairs];
 };
 
-// Entry e of box row m of the adjoint kernel K_cj (see k_build_kernels):
+// Box row m of the adjoint kernel K_cj (see k_build_kernels):
 //   auto (c,c):  K_cc(r) = G(r) + G(-r) on the half box, K_cc(0) = 2 G(0)
 //   cross (c,j): K_cj(r) = G_cj(r);   cross (j,c): K_cj(r) = G_jc(-r)
-__device__ __forceinline__ float gbox_value(const RowArgs &a, uint32_t m, int e)
+// Pairs are distinct, so at most one of them feeds a given (c, j).
+struct GboxRow {
+    const float *G;   // descriptor slice of the feeding pair, or null
+    int kind;         // 1 auto, 2 direct, 3 mirrored
+    int bi0;          // box index of the row's first entry
+};
+
+__device__ __forceinline__ GboxRow gbox_row(const RowArgs &a, uint32_t m)
 {
     const uint32_t row = m % (uint32_t)a.rows_per_pair;
     uint32_t rest = m / (uint32_t)a.rows_per_pair;
@@ -80,28 +103,33 @@ __device__ __forceinline__ float gbox_value(const RowArgs &a, uint32_t m, int e)
     rest /= (uint32_t)a.C;
     const int c = (int)(rest % (uint32_t)a.C);
     const int64_t b = rest / (uint32_t)a.C;
-    const int64_t bi = (int64_t)row * a.in_len + e;
-    const int64_t mirror = a.vol - 1 - bi;
+    GboxRow g{nullptr, 0, (int)row * a.in_len};
     const float *Gb = static_cast<const float *>(a.in) + b * a.Kstride;
-    float v = 0.f;
     for (int q = 0; q < a.npairs; ++q) {
-        const int i0 = a.pi[q], j0 = a.pj[q];
-        const float *Gq = Gb + a.off[q];
-        if (i0 == j0) {
-            if (c == i0 && j == i0) {
-                if (bi > a.center)
-                    v += Gq[bi - a.center];
-                else if (bi < a.center)
-                    v += Gq[mirror - a.center];
-                else
-                    v += 2.f * Gq[0];
-            }
-        } else {
-            if (c == i0 && j == j0) v += Gq[bi];
-            if (c == j0 && j == i0) v += Gq[mirror];
+        if (a.pi[q] == c && a.pj[q] == j) {
+            g.G = Gb + a.off[q];
+            g.kind = (c == j) ? 1 : 2;
+        } else if (a.pi[q] == j && a.pj[q] == c) {
+            g.G = Gb + a.off[q];
+            g.kind = 3;
         }
     }
-    return v;
+    return g;
+}
+
+// box volumes are at most 1023^2 entries per row set, so box indices fit in 32 bits
+__device__ __forceinline__ float gbox_value(const RowArgs &a, const GboxRow &g, int e)
+{
+    const int vol = (int)a.vol, center = (int)a.center;
+    const int bi = g.bi0 + e;
+    const int mirror = vol - 1 - bi;
+    int idx = (g.kind == 2) ? bi : mirror;
+    float f = 1.f;
+    if (g.kind == 1) {                       // half-box entry of |r|, doubled at r = 0
+        idx = (bi >= center ? bi : mirror) - center;
+        f = (bi == center) ? 2.f : 1.f;
+    }
+    return f * g.G[idx];
 }
 
 template <int TAG, int L, bool INV>
@@ -115,11 +143,13 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const int64_t m = (int64_t)blockIdx.x * T + t;
     const bool valid = m < a.nrows;
     float2 v[R1];
-    if (a.in_mode == IO_GBOX) {
+    if constexpr (TAG == T_KB_LAST) {      // input IO_GBOX, output IO_HALF (complex)
+        const GboxRow g = gbox_row(a, valid ? (uint32_t)m : 0u);
+        const bool any = valid && g.kind != 0;
 #pragma unroll
         for (int i1 = 0; i1 < R1; ++i1) {
             const int e = row_of(IO_BOX, R2 * i1 + p, n, a.P);
-            v[i1] = make_float2((valid && e >= 0) ? gbox_value(a, (uint32_t)m, e) : 0.f, 0.f);
+            v[i1] = make_float2((any && e >= 0) ? gbox_value(a, g, e) : 0.f, 0.f);
         }
     } else if (a.in_real) {
         const float *src = static_cast<const float *>(a.in) + m * a.in_len;
@@ -148,7 +178,16 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     float2 u[S][R2];
     pencil_fwd<L, INV, LANE_P>(v, u, ex, p, t, T);
     if (!valid) return;
-    if (a.out_mode == IO_DESC) {
+    if constexpr (TAG == T_KB_LAST) {
+        float2 *dst = static_cast<float2 *>(a.out) + m * a.out_len;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int k = (p + R2 * s) + R1 * k2;
+                if (k <= n / 2) dst[k] = c_scale(u[s][k2], a.scale);
+            }
+    } else if (a.out_mode == IO_DESC) {
         // entry e of box row `row` of pair q goes to descriptor index
         // off_q + row * box + e (full box) or that minus the half-box centre
         const uint32_t row = (uint32_t)(m % a.rows_per_pair);
@@ -192,6 +231,15 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
 // (Z indices mod n/2).  Inverse (unnormalised): for k < n/2
 //   Z[k] = (X[k] + conj X[n/2-k]) + i W_n^-k (X[k] - conj X[n/2-k]),  z = IDFT_{n/2}(Z),
 //   x[2m] = Re z[m], x[2m+1] = Im z[m].
+// W_n^(p + R2 j) = W_n^p W_n^(R2 j): one table lookup per thread, the second
+// factor a compile-time constant (INV: the conjugates).
+template <bool INV, int L, int J, int R2>
+__device__ __forceinline__ float2 tw_split(float2 wp)
+{
+    constexpr cf c = unit_root(R2 * J, 1 << L);
+    return c_mul(wp, make_float2(c.x, INV ? -c.y : c.y));
+}
+
 template <int TAG, int L>
 __global__ __launch_bounds__(256) void k_r2c(RowArgs a)
 {
@@ -202,10 +250,12 @@ __global__ __launch_bounds__(256) void k_r2c(RowArgs a)
     const int p = threadIdx.x % R2, t = threadIdx.x / R2;
     const int64_t m = (int64_t)blockIdx.x * T + t;
     const bool valid = m < a.nrows;
-    const float2 *src = static_cast<const float2 *>(a.in) + m * (a.in_len / 2);
+    // rows past the end re-read the last row (in bounds); only stores are masked
+    const float2 *src = static_cast<const float2 *>(a.in) + (valid ? m : a.nrows - 1) * (a.in_len / 2);
     float2 v[R1];
 #pragma unroll
-    for (int i1 = 0; i1 < R1; ++i1) v[i1] = valid ? src[R2 * i1 + p] : make_float2(0.f, 0.f);
+    for (int i1 = 0; i1 < R1; ++i1) v[i1] = src[R2 * i1 + p];
+    const float2 wp = tw_n<false>(p, L);
     float2 u[S][R2];
     pencil_fwd<LH, false, LANE_P>(v, u, ex, p, t, T);
     // Z in natural order for the split (pencil_fwd ended with a barrier)
@@ -217,14 +267,19 @@ __global__ __launch_bounds__(256) void k_r2c(RowArgs a)
     __syncthreads();
     if (!valid) return;
     float2 *dst = static_cast<float2 *>(a.out) + m * a.out_len;
-    for (int k = p; k <= nh; k += R2) {
-        const float2 zk = ex[t * pitch + (k & (nh - 1))];
-        const float2 zc = c_conj(ex[t * pitch + ((nh - k) & (nh - 1))]);
-        const float2 E = c_scale(c_add(zk, zc), 0.5f);
-        const float2 d = c_sub(zk, zc);                   // 2i O
-        const float2 O = make_float2(0.5f * d.y, -0.5f * d.x);
-        dst[k] = c_scale(c_add(E, c_mul(O, tw_n<false>(k, L))), a.scale);
-    }
+    const float2 *z = ex + t * pitch;
+    static_for<0, nh / R2 + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        const int k = p + R2 * j;
+        if (j < nh / R2 || p == 0) {          // k <= n/2
+            const float2 zk = z[k & (nh - 1)];
+            const float2 zc = c_conj(z[(nh - k) & (nh - 1)]);
+            const float2 E = c_scale(c_add(zk, zc), 0.5f);
+            const float2 d = c_sub(zk, zc);                   // 2i O
+            const float2 O = make_float2(0.5f * d.y, -0.5f * d.x);
+            dst[k] = c_scale(c_add(E, c_mul(O, tw_split<false, L, j, R2>(wp))), a.scale);
+        }
+    });
 }
 
 template <int TAG, int L>
@@ -237,31 +292,35 @@ __global__ __launch_bounds__(256) void k_c2r(RowArgs a)
     const int p = threadIdx.x % R2, t = threadIdx.x / R2;
     const int64_t m = (int64_t)blockIdx.x * T + t;
     const bool valid = m < a.nrows;
-    const float2 *src = static_cast<const float2 *>(a.in) + m * a.in_len;
-    float2 v[R1];
+    const float2 *src = static_cast<const float2 *>(a.in) + (valid ? m : a.nrows - 1) * a.in_len;
+    float2 xk[R1], xc[R1];
 #pragma unroll
     for (int i1 = 0; i1 < R1; ++i1) {
-        const int k = R2 * i1 + p;
-        float2 z = make_float2(0.f, 0.f);
-        if (valid) {
-            const float2 xk = src[k];
-            const float2 xc = c_conj(src[nh - k]);
-            const float2 e = c_add(xk, xc);
-            const float2 o = c_mul(c_sub(xk, xc), tw_n<true>(k, L));  // W_n^-k (X[k] - conj X[n/2-k])
-            z = make_float2(e.x - o.y, e.y + o.x);                    // e + i o
-        }
-        v[i1] = z;
+        xk[i1] = src[R2 * i1 + p];
+        xc[i1] = src[nh - R2 * i1 - p];
     }
+    const float2 wp = tw_n<true>(p, L);
+    float2 v[R1];
+    static_for<0, R1>([&](auto ic) {
+        constexpr int i1 = decltype(ic)::value;
+        const float2 xm = c_conj(xc[i1]);
+        const float2 e = c_add(xk[i1], xm);
+        const float2 o = c_mul(c_sub(xk[i1], xm), tw_split<true, L, i1, R2>(wp));  // W_n^-k (X[k] - conj X[n/2-k])
+        v[i1] = make_float2(e.x - o.y, e.y + o.x);                               // e + i o
+    });
     float2 u[S][R2];
     pencil_fwd<LH, true, LANE_P>(v, u, ex, p, t, T);
     if (!valid) return;
-    if (a.out_mode == IO_DESC) {
-        const uint32_t row = (uint32_t)(m % a.rows_per_pair);
-        const uint32_t bp = (uint32_t)(m / a.rows_per_pair);
+    if constexpr (TAG == T_C2R_DESC) {
+        // box row `row` of pair q: entry e goes to descriptor index off_q + row * box + e
+        // (full box) or that minus the half-box centre; box indices fit in 32 bits
+        const uint32_t row = (uint32_t)m % (uint32_t)a.rows_per_pair;
+        const uint32_t bp = (uint32_t)m / (uint32_t)a.rows_per_pair;
         const int q = (int)(bp % (uint32_t)a.npairs);
         const int64_t b = bp / (uint32_t)a.npairs;
         const bool aut = (a.auto_mask >> q) & 1;
-        const int64_t bi0 = (int64_t)row * a.out_len;
+        const int bi0 = (int)row * a.out_len;
+        const int lo = aut ? (int)a.center - bi0 : 0;   // entries e < lo are not stored
         float *dst = static_cast<float *>(a.out) + b * a.Kstride + a.off[q] + bi0 - (aut ? a.center : 0);
         const int n = 2 * nh;
 #pragma unroll
@@ -271,8 +330,8 @@ __global__ __launch_bounds__(256) void k_c2r(RowArgs a)
                 const int mm = (p + R2 * s) + R1 * k2;
                 const int e0 = row_of(IO_BOX, 2 * mm, n, a.P);
                 const int e1 = row_of(IO_BOX, 2 * mm + 1, n, a.P);
-                if (e0 >= 0 && !(aut && bi0 + e0 < a.center)) dst[e0] = u[s][k2].x * a.scale;
-                if (e1 >= 0 && !(aut && bi0 + e1 < a.center)) dst[e1] = u[s][k2].y * a.scale;
+                if (e0 >= 0 && e0 >= lo) dst[e0] = u[s][k2].x * a.scale;
+                if (e1 >= 0 && e1 >= lo) dst[e1] = u[s][k2].y * a.scale;
             }
     } else {
         float2 *dst = static_cast<float2 *>(a.out) + m * (a.out_len / 2);
@@ -283,6 +342,10 @@ __global__ __launch_bounds__(256) void k_c2r(RowArgs a)
     }
 }
 
+// Strided passes: pencil locations and row indices stay in 32 bits (the host
+// checks npen, nloc < 2^32 and inner < 2^24), so that a pencil needs one 64-bit
+// base; rows p + R2 j of it lie a uniform stride apart and other rows (box
+// modes) take a 24-bit multiply.
 struct ColArgs {
     const float2 *in;
     float2 *out;
@@ -290,6 +353,8 @@ struct ColArgs {
     int in_mode, out_mode, in_len, out_len, P;
     int h;                // columns of a pitch that hold data
     float scale;
+    uint32_t inner32;
+    DivU32 dv_inner;
 };
 
 template <int TAG, int L, bool INV>
@@ -297,34 +362,48 @@ __global__ __launch_bounds__(256) void k_cols(ColArgs a)
 {
     using SP = Split<L>;
     constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
+    constexpr int kIn = col_in_mode(TAG), kOut = col_out_mode(TAG);
     __shared__ float2 ex[ex_size<L>(T)];
     const int t = threadIdx.x % T, p = threadIdx.x / T;
     const int64_t m = (int64_t)blockIdx.x * T + t;
-    bool valid = m < a.npen;
-    int64_t o = 0, i = 0;
-    if (valid) {
-        o = m / a.inner;
-        i = m - o * a.inner;
-        valid = i < a.h;
-    }
-    const float2 *src = a.in + o * a.in_len * a.inner + i;
+    const uint32_t mu = m < a.npen ? (uint32_t)m : 0u;
+    const uint32_t o = divu32(mu, a.dv_inner);
+    const uint32_t i = mu - o * a.inner32;
+    const bool valid = m < a.npen && (int)i < a.h;
+    const size_t inner = a.inner32;
+    const float2 *src = a.in + (size_t)o * a.in_len * inner + i;
     float2 v[R1];
+    if constexpr (kIn == IO_FULL) {
+        const float2 *sp = src + (size_t)p * inner;
 #pragma unroll
-    for (int i1 = 0; i1 < R1; ++i1) {
-        const int e = row_of(a.in_mode, R2 * i1 + p, n, a.P);
-        v[i1] = (valid && e >= 0) ? src[(int64_t)e * a.inner] : make_float2(0.f, 0.f);
+        for (int i1 = 0; i1 < R1; ++i1)
+            v[i1] = valid ? sp[(size_t)(R2 * i1) * inner] : make_float2(0.f, 0.f);
+    } else {
+#pragma unroll
+        for (int i1 = 0; i1 < R1; ++i1) {
+            const int e = row_of(kIn, R2 * i1 + p, n, a.P);
+            v[i1] = (valid && e >= 0) ? src[__umul24((uint32_t)e, a.inner32)] : make_float2(0.f, 0.f);
+        }
     }
     float2 u[S][R2];
     pencil_fwd<L, INV>(v, u, ex, p, t, T);
     if (!valid) return;
-    float2 *dst = a.out + o * a.out_len * a.inner + i;
+    float2 *dst = a.out + (size_t)o * a.out_len * inner + i;
+    if constexpr (kOut == IO_FULL) {
+        float2 *dp = dst + (size_t)p * inner;
 #pragma unroll
-    for (int s = 0; s < S; ++s)
+        for (int s = 0; s < S; ++s)
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) {
-            const int e = row_of(a.out_mode, (p + R2 * s) + R1 * k2, n, a.P);
-            if (e >= 0) dst[(int64_t)e * a.inner] = c_scale(u[s][k2], a.scale);
-        }
+            for (int k2 = 0; k2 < R2; ++k2) dp[(size_t)(R2 * s + R1 * k2) * inner] = c_scale(u[s][k2], a.scale);
+    } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int e = row_of(kOut, (p + R2 * s) + R1 * k2, n, a.P);
+                if (e >= 0) dst[__umul24((uint32_t)e, a.inner32)] = c_scale(u[s][k2], a.scale);
+            }
+    }
 }
 
 struct Axis0Args {
@@ -336,7 +415,35 @@ struct Axis0Args {
     int h, hp;            // data columns of each padded half-spectrum row
     int pair_of[kMaxChannels * kMaxChannels];  // (i, j) -> pair index or -1
     float scale;
+    uint32_t inner32;
+    DivU32 dv_inner, dv_hp;
 };
+
+// pencil location m -> (field b, column i); false for padding columns and m past the end
+struct Axis0Loc {
+    uint32_t b, i;
+    bool valid;
+};
+
+__device__ __forceinline__ Axis0Loc axis0_loc(const Axis0Args &a, int64_t m)
+{
+    const uint32_t mu = m < a.nloc ? (uint32_t)m : 0u;
+    Axis0Loc l;
+    l.b = divu32(mu, a.dv_inner);
+    l.i = mu - l.b * a.inner32;
+    const uint32_t col = l.i - divu32(l.i, a.dv_hp) * (uint32_t)a.hp;
+    l.valid = m < a.nloc && (int)col < a.h;
+    return l;
+}
+
+// rows p + R2 i1 (i1 < R1) of a full pencil that starts at `base`
+template <int R1, int R2>
+__device__ __forceinline__ void load_rows(float2 (&v)[R1], const float2 *base, int p, size_t inner, bool valid)
+{
+    const float2 *sp = base + (size_t)p * inner;
+#pragma unroll
+    for (int i1 = 0; i1 < R1; ++i1) v[i1] = valid ? sp[(size_t)(R2 * i1) * inner] : make_float2(0.f, 0.f);
+}
 
 template <int L, int C>
 __global__ __launch_bounds__(256) void k_axis0_fwd(Axis0Args a)
@@ -345,22 +452,13 @@ __global__ __launch_bounds__(256) void k_axis0_fwd(Axis0Args a)
     constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
     __shared__ float2 ex[ex_size<L>(T)];
     const int t = threadIdx.x % T, p = threadIdx.x / T;
-    const int64_t m = (int64_t)blockIdx.x * T + t;
-    bool valid = m < a.nloc;
-    int64_t b = 0, i = 0;
-    if (valid) {
-        b = m / a.inner;
-        i = m - b * a.inner;
-        valid = (int)(i % a.hp) < a.h;
-    }
+    const Axis0Loc loc = axis0_loc(a, (int64_t)blockIdx.x * T + t);
+    const size_t inner = a.inner32;
     float2 X[C][S][R2];
     static_for<0, C>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        const float2 *src = a.X + (b * C + c) * n * a.inner + i;
         float2 v[R1];
-#pragma unroll
-        for (int i1 = 0; i1 < R1; ++i1)
-            v[i1] = valid ? src[(int64_t)(R2 * i1 + p) * a.inner] : make_float2(0.f, 0.f);
+        load_rows<R1, R2>(v, a.X + ((size_t)loc.b * C + c) * n * inner + loc.i, p, inner, loc.valid);
         pencil_fwd<L, false>(v, X[c], ex, p, t, T);
     });
     static_for<0, C>([&](auto ic) {
@@ -376,12 +474,12 @@ __global__ __launch_bounds__(256) void k_axis0_fwd(Axis0Args a)
                     for (int k = 0; k < R2; ++k) w[s][k] = c_scale(c_cmul(X[ci][s][k], X[cj][s][k]), a.scale);
                 float2 out[R1];
                 pencil_mirror<L, true>(w, out, ex, p, t, T);
-                if (valid) {
-                    float2 *dst = a.Y + (b * a.npairs + q) * a.box * a.inner + i;
+                if (loc.valid) {
+                    float2 *dst = a.Y + ((size_t)loc.b * a.npairs + q) * a.box * inner + loc.i;
 #pragma unroll
                     for (int j1 = 0; j1 < R1; ++j1) {
                         const int e = row_of(IO_BOX, p + R2 * j1, n, a.P);
-                        if (e >= 0) dst[(int64_t)e * a.inner] = out[j1];
+                        if (e >= 0) dst[__umul24((uint32_t)e, a.inner32)] = out[j1];
                     }
                 }
             }
@@ -396,22 +494,13 @@ __global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
     constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
     __shared__ float2 ex[ex_size<L>(T)];
     const int t = threadIdx.x % T, p = threadIdx.x / T;
-    const int64_t m = (int64_t)blockIdx.x * T + t;
-    bool valid = m < a.nloc;
-    int64_t b = 0, i = 0;
-    if (valid) {
-        b = m / a.inner;
-        i = m - b * a.inner;
-        valid = (int)(i % a.hp) < a.h;
-    }
+    const Axis0Loc loc = axis0_loc(a, (int64_t)blockIdx.x * T + t);
+    const size_t inner = a.inner32;
     float2 X[C][S][R2];
     static_for<0, C>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        const float2 *src = a.X + (b * C + c) * n * a.inner + i;
         float2 v[R1];
-#pragma unroll
-        for (int i1 = 0; i1 < R1; ++i1)
-            v[i1] = valid ? src[(int64_t)(R2 * i1 + p) * a.inner] : make_float2(0.f, 0.f);
+        load_rows<R1, R2>(v, a.X + ((size_t)loc.b * C + c) * n * inner + loc.i, p, inner, loc.valid);
         pencil_fwd<L, false>(v, X[c], ex, p, t, T);
     });
     static_for<0, C>([&](auto cc) {
@@ -423,12 +512,12 @@ __global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
             for (int k = 0; k < R2; ++k) acc[s][k] = make_float2(0.f, 0.f);
         static_for<0, C>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            const float2 *kb = a.KB + (b * C * C + c * C + j) * a.box * a.inner + i;
+            const float2 *kb = a.KB + ((size_t)loc.b * C * C + c * C + j) * a.box * inner + loc.i;
             float2 v[R1];
 #pragma unroll
             for (int i1 = 0; i1 < R1; ++i1) {
                 const int e = row_of(IO_BOX, R2 * i1 + p, n, a.P);
-                v[i1] = (valid && e >= 0) ? kb[(int64_t)e * a.inner] : make_float2(0.f, 0.f);
+                v[i1] = (loc.valid && e >= 0) ? kb[__umul24((uint32_t)e, a.inner32)] : make_float2(0.f, 0.f);
             }
             float2 K[S][R2];
             pencil_fwd<L, false>(v, K, ex, p, t, T);
@@ -443,10 +532,10 @@ __global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
             for (int k = 0; k < R2; ++k) acc[s][k] = c_scale(acc[s][k], a.scale);
         float2 out[R1];
         pencil_mirror<L, true>(acc, out, ex, p, t, T);
-        if (valid) {
-            float2 *dst = a.X + (b * C + c) * n * a.inner + i;
+        if (loc.valid) {
+            float2 *dp = a.X + ((size_t)loc.b * C + c) * n * inner + loc.i + (size_t)p * inner;
 #pragma unroll
-            for (int j1 = 0; j1 < R1; ++j1) dst[(int64_t)(p + R2 * j1) * a.inner] = out[j1];
+            for (int j1 = 0; j1 < R1; ++j1) dp[(size_t)(R2 * j1) * inner] = out[j1];
         }
     });
 }
@@ -458,16 +547,6 @@ int ilog2(int n)
     return l;
 }
 
-enum PassTag {
-    T_R2C_LAST = 0,    // forward, contiguous axis, real -> half spectrum
-    T_FWD_MID,         // forward, axis 1 (3-D), in place
-    T_INV_MID_BOX,     // inverse, axis 1 (3-D), keep the |r1| <= P rows
-    T_C2R_DESC,        // inverse, contiguous axis, half -> real rows of the box, into S
-    T_KB_LAST,         // forward of the cotangent boxes, contiguous axis
-    T_KB_MID,          // forward of the cotangent boxes, axis 1 (3-D)
-    T_INV_MID,         // inverse, axis 1 (3-D), in place
-    T_C2R_FULL         // inverse, contiguous axis, half -> real field
-};
 
 const char *const kPassName[] = {"r2c_last", "fwd_mid", "inv_mid_box", "c2r_last_desc",
                                  "kb_last", "kb_mid", "inv_mid", "c2r_last"};
@@ -506,6 +585,8 @@ TileInfo tile_of(int L)
 template <int TAG, bool INV>
 hipError_t rows_launch(int L, const RowArgs &a, double bytes, hipStream_t st)
 {
+    if (TAG == T_KB_LAST && (a.in_mode != IO_GBOX || a.out_mode != IO_HALF || a.out_real || a.vol >= (int64_t(1) << 31)))
+        return hipErrorInvalidValue;
     const TileInfo ti = tile_of(L);
     const dim3 g((unsigned)((a.nrows + ti.T - 1) / ti.T)), b(ti.threads);
     switch (L) {
@@ -521,6 +602,9 @@ hipError_t rows_launch(int L, const RowArgs &a, double bytes, hipStream_t st)
 template <int TAG, bool C2R>
 hipError_t real_launch(int L, const RowArgs &a, double bytes, hipStream_t st)
 {
+    if (C2R && (a.out_mode == IO_DESC) != (TAG == T_C2R_DESC)) return hipErrorInvalidValue;
+    if (TAG == T_C2R_DESC && (a.nrows >= (int64_t(1) << 32) || a.center >= (int64_t(1) << 31)))
+        return hipErrorInvalidValue;
     const TileInfo ti = tile_of(L - 1);
     const dim3 g((unsigned)((a.nrows + ti.T - 1) / ti.T)), b(ti.threads);
     switch (L) {
@@ -539,6 +623,8 @@ hipError_t real_launch(int L, const RowArgs &a, double bytes, hipStream_t st)
 template <int TAG, bool INV>
 hipError_t cols_launch(int L, const ColArgs &a, double bytes, hipStream_t st)
 {
+    if (a.in_mode != col_in_mode(TAG) || a.out_mode != col_out_mode(TAG)) return hipErrorInvalidValue;
+    if (a.npen >= (int64_t(1) << 32) || a.inner >= (int64_t(1) << 24)) return hipErrorInvalidValue;
     const TileInfo ti = tile_of(L);
     const dim3 g((unsigned)((a.npen + ti.T - 1) / ti.T)), b(ti.threads);
     switch (L) {
@@ -566,8 +652,12 @@ hipError_t axis0_launch_c(bool adj, int L, const Axis0Args &a, double bytes, hip
     return hipErrorInvalidValue;
 }
 
-hipError_t axis0_launch(int C, bool adj, int L, const Axis0Args &a, double bytes, hipStream_t st)
+hipError_t axis0_launch(int C, bool adj, int L, Axis0Args a, double bytes, hipStream_t st)
 {
+    if (a.nloc >= (int64_t(1) << 32) || a.inner >= (int64_t(1) << 24)) return hipErrorInvalidValue;
+    a.inner32 = (uint32_t)a.inner;
+    a.dv_inner = make_divu32((uint32_t)a.inner);
+    a.dv_hp = make_divu32((uint32_t)a.hp);
     switch (C) {
     case 1: return axis0_launch_c<1>(adj, L, a, bytes, st);
     case 2: return axis0_launch_c<2>(adj, L, a, bytes, st);
@@ -618,6 +708,8 @@ ColArgs col_args(const float2 *in, float2 *out, int64_t npen, int64_t inner, int
     a.P = P;
     a.h = (int)inner;
     a.scale = 1.f;
+    a.inner32 = (uint32_t)inner;
+    a.dv_inner = make_divu32((uint32_t)inner);
     return a;
 }
 

@@ -34,6 +34,28 @@ inline FastDivU make_fastdivu(int d) { return FastDivU{(uint64_t)((1ull << 32) /
 
 __device__ __forceinline__ int fdivu(int x, const FastDivU &f) { return (int)(((uint64_t)(uint32_t)x * f.M) >> 32); }
 
+// Division by a run-time constant d >= 1, exact for every 32-bit x, after the
+// round-up multiplier method of Granlund and Montgomery (PLDI 1994): with
+// l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1 (which fits in 32
+// bits), t = hi32(m x) gives x / d = (t + ((x - t) >> min(l, 1))) >> max(l - 1, 0).
+struct DivU32 {
+    uint32_t m, s1, s2;
+};
+
+inline DivU32 make_divu32(uint32_t d)
+{
+    int l = 0;
+    while ((1ull << l) < d) ++l;
+    const uint64_t m = (((1ull << 32) * ((1ull << l) - d)) / d) + 1ull;
+    return DivU32{(uint32_t)m, l < 1 ? 0u : 1u, l < 1 ? 0u : (uint32_t)(l - 1)};
+}
+
+__device__ __forceinline__ uint32_t divu32(uint32_t x, const DivU32 &f)
+{
+    const uint32_t t = __umulhi(f.m, x);
+    return (t + ((x - t) >> f.s1)) >> f.s2;
+}
+
 // ---------------------------------------------------------------------------
 // compile-time trigonometry (Taylor series on [-pi, pi], double precision)
 // ---------------------------------------------------------------------------
@@ -203,6 +225,19 @@ constexpr int ex_size(int T)
     return Split<L>::R1 * (Split<L>::R2 + 1) * T + Split<L>::R1;
 }
 
+// w[j] = W_n^(b j), j = 1..M-1 (w[0] = 1), n = 2^L: one table lookup for W_n^b,
+// the other powers as products of two lower powers (at most 4 multiplications deep)
+template <bool INV, int M>
+__device__ __forceinline__ void tw_powers(int b, int L, float2 (&w)[M])
+{
+    w[0] = make_float2(1.f, 0.f);
+    if constexpr (M > 1) w[1] = tw_n<INV>(b, L);
+    static_for<2, M>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        w[j] = c_mul(w[j / 2], w[j - j / 2]);
+    });
+}
+
 // Forward-structure transform.  In: v[i1] = x[R2 i1 + p].  Out: u[s][k2] =
 // X[(p + R2 s) + R1 k2].  Contains two barriers (the caller must not touch
 // `ex` between its calls from other threads).
@@ -211,11 +246,13 @@ __device__ __forceinline__ void pencil_fwd(float2 (&v)[Split<L>::R1], float2 (&u
                                            float2 *ex, int p, int t, int T)
 {
     using SP = Split<L>;
+    float2 tw[SP::R1];
+    tw_powers<INV>(p, L, tw);
     dft_reg<SP::R1, INV>(v);
     static_for<0, SP::R1>([&](auto kc) {
         constexpr int k1 = decltype(kc)::value;
         float2 w = v[k1];
-        if constexpr (k1 != 0) w = c_mul(w, tw_n<INV>(p * k1, L));
+        if constexpr (k1 != 0) w = c_mul(w, tw[k1]);
         ex[ex_idx<L, LO>(k1, p, t, T)] = w;
     });
     __syncthreads();
@@ -241,11 +278,13 @@ __device__ __forceinline__ void pencil_mirror(float2 (&u)[Split<L>::S][Split<L>:
     static_for<0, SP::S>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         const int k1 = p + SP::R2 * s;
+        float2 tw[SP::R2];
+        tw_powers<INV>(k1, L, tw);
         dft_reg<SP::R2, INV>(u[s]);
         static_for<0, SP::R2>([&](auto jc) {
             constexpr int j2 = decltype(jc)::value;
             float2 w = u[s][j2];
-            if constexpr (j2 != 0) w = c_mul(w, tw_n<INV>(k1 * j2, L));
+            if constexpr (j2 != 0) w = c_mul(w, tw[j2]);
             ex[ex_idx<L, LO>(k1, j2, t, T)] = w;
         });
     });

@@ -219,7 +219,7 @@ hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0
 }
 
 hipError_t launch_error(const Plan &p, const float *S, const double *St, double *E, float *G, const Ws &ws,
-                        hipStream_t st)
+                        hipStream_t st, hipStream_t st_final, hipEvent_t parts_done)
 {
     ErrArgs a{};
     a.S = S;
@@ -237,6 +237,11 @@ hipError_t launch_error(const Plan &p, const float *S, const double *St, double 
     hipError_t e = launch("error_partial", (double)p.B * p.K * 16, k_error_partial,
                           dim3((unsigned)a.chunks, (unsigned)p.B), dim3(kThreads), 0, st, a);
     if (e != hipSuccess) return e;
+    if (st_final && st_final != st) {
+        if ((e = hipEventRecord(parts_done, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(st_final, parts_done, 0)) != hipSuccess) return e;
+        st = st_final;
+    }
     return launch("error_final", (double)p.B * a.chunks * 8, k_error_final, dim3((unsigned)p.B), dim3(kThreads), 0,
                   st, (const double *)a.part, a.chunks, a.invZ, E);
 }

@@ -25,7 +25,7 @@ def build(force=False):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
-           "-shared", "-fPIC", "-o", tmp, _SRC]
+           "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB)
     return _LIB
@@ -46,6 +46,13 @@ def lib():
         L.ora_corr_adjoint_at.argtypes = ([ctypes.c_int] * 3 + [_dp, _dp, ctypes.c_int, _ip, _dp,
                                           ctypes.c_int, _ip, _dp, _dp])
         L.ora_corr_adjoint_at.restype = None
+        L.ora_sbar.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, ctypes.c_int, _ip, _dp, _dp]
+        L.ora_sbar.restype = None
+        L.ora_sbar_adjoint.argtypes = [ctypes.c_int] * 3 + [_dp, _dp, ctypes.c_int, _ip, _dp, _dp, _dp, _dp]
+        L.ora_sbar_adjoint.restype = None
+        L.ora_sbar_adjoint_at.argtypes = ([ctypes.c_int] * 3 + [_dp, _dp, ctypes.c_int, _ip, _dp, _dp,
+                                          ctypes.c_int, _ip, _dp, _dp])
+        L.ora_sbar_adjoint_at.restype = None
         L.ora_num_threads.restype = ctypes.c_int
         L.ora_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -111,6 +118,51 @@ def corr_adjoint_at(a, b, r, G, vox):
     gb = np.zeros(V.shape[0], np.float64)
     lib().ora_corr_adjoint_at(A.shape[0], A.shape[1], A.shape[2], _d(A), _d(B), R.shape[0], _i(R),
                               _d(Gk), V.shape[0], _i(V), _d(ga), _d(gb))
+    return ga, gb
+
+
+def _coef(alpha, c):
+    return np.ascontiguousarray([alpha, c[0], c[1], c[2]], dtype=np.float64)
+
+
+def sbar(a, b, r, alpha, c):
+    """Sbar[k] = (1/N) sum_x f((a(x) + b(x + r_k)) / 2)^2 with the logistic soft
+    threshold f of slope alpha and constants c = (c1, c2, c3), periodic, FP64."""
+    ndim = np.ndim(a)
+    A, B = _as3(a), _as3(b)
+    R = _r3(r, ndim)
+    S = np.zeros(R.shape[0], np.float64)
+    co = _coef(alpha, c)
+    lib().ora_sbar(A.shape[0], A.shape[1], A.shape[2], _d(A), _d(B), R.shape[0], _i(R), _d(co), _d(S))
+    return S
+
+
+def sbar_adjoint(a, b, r, alpha, c, G):
+    """(ga, gb): gradients of sum_k G[k] Sbar_ab(r_k) w.r.t. a and b (separately)."""
+    ndim = np.ndim(a)
+    A, B = _as3(a), _as3(b)
+    R = _r3(r, ndim)
+    Gk = np.ascontiguousarray(G, dtype=np.float64)
+    co = _coef(alpha, c)
+    ga = np.zeros_like(A)
+    gb = np.zeros_like(B)
+    lib().ora_sbar_adjoint(A.shape[0], A.shape[1], A.shape[2], _d(A), _d(B), R.shape[0], _i(R),
+                           _d(co), _d(Gk), _d(ga), _d(gb))
+    return ga.reshape(np.shape(a)), gb.reshape(np.shape(b))
+
+
+def sbar_adjoint_at(a, b, r, alpha, c, G, vox):
+    """Soft-threshold adjoint evaluated only at the listed voxels."""
+    ndim = np.ndim(a)
+    A, B = _as3(a), _as3(b)
+    R = _r3(r, ndim)
+    V = _r3(vox, ndim)
+    Gk = np.ascontiguousarray(G, dtype=np.float64)
+    co = _coef(alpha, c)
+    ga = np.zeros(V.shape[0], np.float64)
+    gb = np.zeros(V.shape[0], np.float64)
+    lib().ora_sbar_adjoint_at(A.shape[0], A.shape[1], A.shape[2], _d(A), _d(B), R.shape[0], _i(R),
+                              _d(co), _d(Gk), V.shape[0], _i(V), _d(ga), _d(gb))
     return ga, gb
 
 

@@ -138,3 +138,110 @@ void ora_corr_adjoint_at(int n0, int n1, int n2, const double *a, const double *
         gb_v[m] = sb / (double)N;
     }
 }
+
+/*
+ * Soft-threshold ensemble (Sec. 3.2.4, eq. softthreshold) on the two-point
+ * masks of Sec. 3.2.3.  The mask of r != 0 holds 1/2 at the tip and at the
+ * end of r, so the convolution of eq. (convdef) gives
+ *     u_r(x) = (a(x) + b(x + r)) / 2;
+ * the mask of r = 0 holds a single 1, which gives u_0(x) = a(x) -- the same
+ * expression when a == b.  (For a cross pair, a != b, the same expression is
+ * used at r = 0 as well.)  The threshold step applies the logistic
+ *     f(u) = c1 / (1 + exp(-alpha (u + c2))) + c3,
+ * and the quadratic reduction of eq. (s3) with r_a = r_b gives
+ *     Sbar[k] = (1/N) sum_x f(u_{r_k}(x))^2.
+ * coef = {alpha, c1, c2, c3}.
+ */
+#include <math.h>
+
+static inline double soft_f(double u, const double *c)
+{
+    return c[1] / (1.0 + exp(-c[0] * (u + c[2]))) + c[3];
+}
+
+/* f(u) f'(u): the derivative of f(u)^2 with respect to either end value,
+ * since du/da = du/db = 1/2 and d(f^2)/du = 2 f f'. */
+static inline double soft_ffp(double u, const double *c)
+{
+    const double s = 1.0 / (1.0 + exp(-c[0] * (u + c[2])));
+    const double f = c[1] * s + c[3];
+    const double fp = c[1] * c[0] * s * (1.0 - s);
+    return f * fp;
+}
+
+void ora_sbar(int n0, int n1, int n2, const double *a, const double *b,
+              int K, const int *r, const double *coef, double *S)
+{
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    int k;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (k = 0; k < K; ++k) {
+        const int r0 = r[3 * k], r1 = r[3 * k + 1], r2 = r[3 * k + 2];
+        double acc = 0.0;
+        for (int64_t i0 = 0; i0 < n0; ++i0) {
+            const int64_t j0 = wrap(i0 + r0, n0);
+            for (int64_t i1 = 0; i1 < n1; ++i1) {
+                const int64_t j1 = wrap(i1 + r1, n1);
+                for (int64_t i2 = 0; i2 < n2; ++i2) {
+                    const int64_t j2 = wrap(i2 + r2, n2);
+                    const double u = 0.5 * (a[lin(i0, i1, i2, n1, n2)] + b[lin(j0, j1, j2, n1, n2)]);
+                    const double e = soft_f(u, coef);
+                    acc += e * e;
+                }
+            }
+        }
+        S[k] = acc / (double)N;
+    }
+}
+
+/* Gradient of sum_k G[k] Sbar_ab(r_k):
+ *   ga[x] += (1/N) sum_k G[k] (f f')((a[x] + b[x + r_k]) / 2)
+ *   gb[y] += (1/N) sum_k G[k] (f f')((a[y - r_k] + b[y]) / 2)
+ * ga and gb may be the same array (auto-correlation: a == b). */
+void ora_sbar_adjoint(int n0, int n1, int n2, const double *a, const double *b,
+                      int K, const int *r, const double *coef, const double *G,
+                      double *ga, double *gb)
+{
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    int64_t x;
+#pragma omp parallel for schedule(static)
+    for (x = 0; x < N; ++x) {
+        const int64_t i0 = x / ((int64_t)n1 * n2);
+        const int64_t i1 = (x / n2) % n1;
+        const int64_t i2 = x % n2;
+        double sa = 0.0, sb = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const int r0 = r[3 * k], r1 = r[3 * k + 1], r2 = r[3 * k + 2];
+            const double bf = b[lin(wrap(i0 + r0, n0), wrap(i1 + r1, n1), wrap(i2 + r2, n2), n1, n2)];
+            const double ab = a[lin(wrap(i0 - r0, n0), wrap(i1 - r1, n1), wrap(i2 - r2, n2), n1, n2)];
+            sa += G[k] * soft_ffp(0.5 * (a[x] + bf), coef);
+            sb += G[k] * soft_ffp(0.5 * (ab + b[x]), coef);
+        }
+        ga[x] += sa / (double)N;
+        gb[x] += sb / (double)N;
+    }
+}
+
+/* Same adjoint at nv listed voxels (v triples), written (not accumulated). */
+void ora_sbar_adjoint_at(int n0, int n1, int n2, const double *a, const double *b,
+                         int K, const int *r, const double *coef, const double *G,
+                         int nv, const int *v, double *ga_v, double *gb_v)
+{
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    int m;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (m = 0; m < nv; ++m) {
+        const int64_t i0 = v[3 * m], i1 = v[3 * m + 1], i2 = v[3 * m + 2];
+        const int64_t x = lin(i0, i1, i2, n1, n2);
+        double sa = 0.0, sb = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const int r0 = r[3 * k], r1 = r[3 * k + 1], r2 = r[3 * k + 2];
+            const double bf = b[lin(wrap(i0 + r0, n0), wrap(i1 + r1, n1), wrap(i2 + r2, n2), n1, n2)];
+            const double ab = a[lin(wrap(i0 - r0, n0), wrap(i1 - r1, n1), wrap(i2 - r2, n2), n1, n2)];
+            sa += G[k] * soft_ffp(0.5 * (a[x] + bf), coef);
+            sb += G[k] * soft_ffp(0.5 * (ab + b[x]), coef);
+        }
+        ga_v[m] = sa / (double)N;
+        gb_v[m] = sb / (double)N;
+    }
+}

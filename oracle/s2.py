@@ -18,6 +18,10 @@ Sources in the paper (Seibert, Ambati, Rassloff, Kaestner, arXiv 2103.09686):
     corrected descriptor equals the product-form S2 used here.
   * Appendix B: point symmetry of the auto-correlation halves the set of
     displacement vectors; P = Q = 31 gives 1/2/3 levels at 64/128/256.
+  * Sec. 3.2.4, eq. (softthreshold): the logistic soft threshold with slope
+    alpha (10 in the paper) and constants fixed by f(0) = 0, f(1) = 1,
+    f''(0.75) = 0; the quadratic reduction of its realisations is Sbar.
+  * Appendix A, eq. (s2rfroms2rbar): the affine map from Sbar back to S2.
 
 Readings where the paper is silent (each one is listed in the design notes):
   * level 1 is the finest; level l+1 is the 2^d mean pool of level l;
@@ -27,7 +31,11 @@ Readings where the paper is silent (each one is listed in the design notes):
     lexicographic with axis 0 slowest;
   * E is the squared weighted error divided by Z = sum_l w_l^2 K_l, so that a
     stopping threshold does not depend on the grid size;
-  * the default weight generalises w_l = 2^{l-1} (2-D) to 2^{d(l-1)/2}.
+  * the default weight generalises w_l = 2^{l-1} (2-D) to 2^{d(l-1)/2};
+  * soft threshold on a cross pair (i, j): u = (phi_i(x) + phi_j(x + r)) / 2 at
+    every r, r = 0 included; the Appendix A map generalises to
+    S_ij(r) = (Sbar_ij(r) - f(1/2)^2 (Sbar_ii(0) + Sbar_jj(0))) / (1 - 2 f(1/2)^2),
+    which is the paper's map for i = j, r != 0, and the identity for i = j, r = 0.
 """
 from dataclasses import dataclass, field
 from typing import List, Sequence, Tuple
@@ -66,6 +74,31 @@ def all_pairs(C: int) -> List[Tuple[int, int]]:
     return [(i, j) for i in range(C) for j in range(i, C)]
 
 
+# descriptor kinds: the product form S2 (the corrected descriptor of the
+# identity threshold), the paper's soft-threshold Sbar, and Sbar mapped back
+# by Appendix A (S~, equal to S2 on binary fields)
+DESCRIPTORS = ("s2", "sbar", "stilde")
+
+
+def soft_threshold_constants(alpha: float):
+    """(c1, c2, c3) of f(u) = c1 / (1 + exp(-alpha (u + c2))) + c3 from the three
+    conditions of Sec. 3.2.4: f''(0.75) = 0 puts the logistic's inflection at
+    u = 0.75, so c2 = -0.75; f(0) = 0 and f(1) = 1 are then two linear
+    equations in c1 and c3."""
+    sig = lambda z: 1.0 / (1.0 + np.exp(-z))
+    c2 = -0.75
+    lo, hi = sig(alpha * (0.0 + c2)), sig(alpha * (1.0 + c2))
+    c1 = 1.0 / (hi - lo)
+    c3 = -c1 * lo
+    return float(c1), float(c2), float(c3)
+
+
+def soft_threshold(u, alpha: float):
+    """The logistic soft threshold f(u) of eq. (softthreshold)."""
+    c1, c2, c3 = soft_threshold_constants(alpha)
+    return c1 / (1.0 + np.exp(-alpha * (np.asarray(u, np.float64) + c2))) + c3
+
+
 @dataclass
 class Spec:
     """Oracle-side statement of one multigrid descriptor."""
@@ -75,6 +108,8 @@ class Spec:
     max_disp: Tuple[int, ...] = (16,)  # P per level (already valid for the level)
     level_weight: Tuple[float, ...] = ()
     pairs: Tuple[Tuple[int, int], ...] = ()
+    descriptor: str = "s2"            # one of DESCRIPTORS
+    alpha: float = 10.0               # soft-threshold slope (sbar, stilde)
 
     def __post_init__(self):
         self.shape = tuple(int(s) for s in self.shape)
@@ -86,6 +121,14 @@ class Spec:
             self.level_weight = tuple(2.0 ** (d * l / 2.0) for l in range(self.n_levels))
         if not self.pairs:
             self.pairs = tuple(all_pairs(self.n_channels))
+        if self.descriptor not in DESCRIPTORS:
+            raise ValueError("descriptor must be one of %s" % (DESCRIPTORS,))
+        if self.descriptor == "stilde":
+            autos = {i for (i, j) in self.pairs if i == j}
+            for (i, j) in self.pairs:
+                if i not in autos or j not in autos:
+                    raise ValueError("the Appendix A map of pair %s needs the auto pairs of both channels"
+                                     % ((i, j),))
 
     @property
     def ndim(self):
@@ -147,12 +190,64 @@ def pyramid(phi: np.ndarray, n_levels: int) -> List[np.ndarray]:
 # ----------------------------------------------------------------------------
 # descriptor, error, gradient
 # ----------------------------------------------------------------------------
+def _pair_corr(a, b, r, spec: Spec):
+    """One (level, pair) block before any Appendix A map: S2 or Sbar."""
+    if spec.descriptor == "s2":
+        return _native.corr(a, b, r)
+    return _native.sbar(a, b, r, spec.alpha, soft_threshold_constants(spec.alpha))
+
+
 def descriptor(phi: np.ndarray, spec: Spec) -> np.ndarray:
-    """S for one field phi[C][n...]: S_ij^(l)(r) = (1/N_l) sum_x phi_i(x) phi_j(x + r)."""
+    """Descriptor of one field phi[C][n...], every level and pair in order:
+    s2:     S_ij^(l)(r) = (1/N_l) sum_x phi_i(x) phi_j(x + r);
+    sbar:   (1/N_l) sum_x f((phi_i(x) + phi_j(x + r)) / 2)^2;
+    stilde: sbar mapped back by Appendix A (correct_sbar)."""
     lv = pyramid(phi, spec.n_levels)
     out = np.zeros(spec.K, np.float64)
     for (l, (i, j), off, k) in spec.layout():
-        out[off:off + k] = _native.corr(lv[l][i], lv[l][j], spec.disp(l, (i, j)))
+        out[off:off + k] = _pair_corr(lv[l][i], lv[l][j], spec.disp(l, (i, j)), spec)
+    if spec.descriptor == "stilde":
+        out = correct_sbar(out, spec)
+    return out
+
+
+def _f_half_sq(spec: Spec) -> float:
+    return float(soft_threshold(0.5, spec.alpha)) ** 2
+
+
+def _level_vf(S: np.ndarray, spec: Spec, l: int):
+    """Sbar_cc(0) of every channel c at level l (r = 0 is the first entry of a half box)."""
+    return {i: S[off] for (ll, (i, j), off, k) in spec.layout() if ll == l and i == j}
+
+
+def correct_sbar(Sbar: np.ndarray, spec: Spec) -> np.ndarray:
+    """Appendix A, eq. (s2rfroms2rbar), per level and pair, with F = f(1/2)^2:
+    S(r) = (Sbar(r) - F (Sbar_ii(0) + Sbar_jj(0))) / (1 - 2F).  For an auto pair
+    at r != 0 this is the paper's map; at r = 0 it returns Sbar(0)."""
+    F = _f_half_sq(spec)
+    out = np.array(Sbar, np.float64, copy=True)
+    for l in range(spec.n_levels):
+        vf = _level_vf(Sbar, spec, l)
+        for (ll, (i, j), off, k) in spec.layout():
+            if ll == l:
+                out[off:off + k] = (Sbar[off:off + k] - F * (vf[i] + vf[j])) / (1.0 - 2.0 * F)
+    return out
+
+
+def correct_sbar_adjoint(G: np.ndarray, spec: Spec) -> np.ndarray:
+    """Transpose of correct_sbar (it is linear in Sbar): every entry is scaled by
+    1/(1 - 2F), and each channel's r = 0 auto entry also collects
+    -F/(1 - 2F) times the cotangent of every entry whose map reads it."""
+    F = _f_half_sq(spec)
+    G = np.asarray(G, np.float64)
+    out = G / (1.0 - 2.0 * F)
+    for l in range(spec.n_levels):
+        lay = [e for e in spec.layout() if e[0] == l]
+        auto_off = {i: off for (_, (i, j), off, k) in lay if i == j}
+        for (_, (i, j), off, k) in lay:
+            t = float(np.sum(G[off:off + k]))
+            out[auto_off[i]] -= F / (1.0 - 2.0 * F) * t
+            out[auto_off[j]] -= F / (1.0 - 2.0 * F) * t
     return out
 
 
@@ -179,12 +274,20 @@ def loss(S: np.ndarray, S_des: np.ndarray, spec: Spec):
     return E, G
 
 
+def _pair_adjoint(a, b, r, G, spec: Spec):
+    if spec.descriptor == "s2":
+        return _native.corr_adjoint(a, b, r, G)
+    return _native.sbar_adjoint(a, b, r, spec.alpha, soft_threshold_constants(spec.alpha), G)
+
+
 def adjoint(phi: np.ndarray, G: np.ndarray, spec: Spec) -> np.ndarray:
     """d/dphi of sum_k G[k] S[k] (all levels, all pairs), shape of phi."""
+    if spec.descriptor == "stilde":
+        G = correct_sbar_adjoint(G, spec)
     lv = pyramid(phi, spec.n_levels)
     grads = [np.zeros_like(f) for f in lv]
     for (l, (i, j), off, k) in spec.layout():
-        ga, gb = _native.corr_adjoint(lv[l][i], lv[l][j], spec.disp(l, (i, j)), G[off:off + k])
+        ga, gb = _pair_adjoint(lv[l][i], lv[l][j], spec.disp(l, (i, j)), G[off:off + k], spec)
         grads[l][i] += ga
         grads[l][j] += gb
     acc = grads[-1]
@@ -200,18 +303,24 @@ def loss_grad(phi: np.ndarray, S_des: np.ndarray, spec: Spec):
 
 
 def descriptor_at(phi: np.ndarray, spec: Spec, level: int, pair, r: np.ndarray) -> np.ndarray:
-    """S at an arbitrary list of displacements of one (level, pair)."""
+    """S2 or Sbar (no Appendix A map) at a list of displacements of one (level, pair)."""
     lv = pyramid(phi, level + 1)
-    return _native.corr(lv[level][pair[0]], lv[level][pair[1]], np.asarray(r))
+    return _pair_corr(lv[level][pair[0]], lv[level][pair[1]], np.asarray(r), spec)
 
 
 def adjoint_at_single_level(phi: np.ndarray, G: np.ndarray, spec: Spec, vox: np.ndarray) -> np.ndarray:
     """Gradient at listed finest-level voxels for a single-level spec: [C][nv]."""
     if spec.n_levels != 1:
         raise ValueError("sampled adjoint is defined here for one level only")
+    if spec.descriptor == "stilde":
+        G = correct_sbar_adjoint(G, spec)
     out = np.zeros((spec.n_channels, len(vox)), np.float64)
     for (l, (i, j), off, k) in spec.layout():
-        ga, gb = _native.corr_adjoint_at(phi[i], phi[j], spec.disp(l, (i, j)), G[off:off + k], vox)
+        if spec.descriptor == "s2":
+            ga, gb = _native.corr_adjoint_at(phi[i], phi[j], spec.disp(l, (i, j)), G[off:off + k], vox)
+        else:
+            ga, gb = _native.sbar_adjoint_at(phi[i], phi[j], spec.disp(l, (i, j)), spec.alpha,
+                                             soft_threshold_constants(spec.alpha), G[off:off + k], vox)
         out[i] += ga
         out[j] += gb
     return out

@@ -36,11 +36,29 @@ WORKLOADS = {
                      shape=(512, 512), C=1, L=3, P=64, recompute=False, batch=64),
     "3d128": dict(desc="3D 128^3 three-phase (C=2), P=32, 3-level multigrid (128/64/32)",
                   shape=(128, 128, 128), C=2, L=3, P=32, recompute=False, batch=1),
+    "2d256sbar": dict(desc="2D 256^2 two-phase, soft-threshold descriptor Sbar (alpha=10), P=31, "
+                           "3 levels (256/128/64), direct path",
+                      shape=(256, 256), C=1, L=3, P=31, recompute=False, batch=1, descriptor=1),
 }
+
+# Soft-threshold pair terms are bound by FP32 vector issue, not HBM.  A wave64
+# FP32 instruction takes 4 cycles of one 16-lane SIMD (packed FP32 is not used),
+# the exp and reciprocal 4 times that.  Issue slots (lane-cycles) per term, from
+# the compiled loop bodies: forward 7 plain + 2 quarter-rate = 15, adjoint
+# 11 + 2 quarter-rate = 19.  Peak terms/s = 256 CUs * 4 SIMDs * 16 lanes * 2.4 GHz / slots.
+VALU_LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+SOFT_SLOTS = {"direct_fwd_soft": 15, "direct_adj_soft": 19}
 
 
 # the sources the FFT-path kernels (the dominant kernels of every workload) compile from
 KERNEL_SOURCES = ("dmcr_internal.h", "fft_path.hip", "fft_reg.h")
+
+
+def K_level(spec, l):
+    """Descriptor entries of level l (every pair): half box for autos, full box for crosses."""
+    d = len(spec.shape)
+    vol = (2 * spec.max_disp[l] + 1) ** d
+    return sum((vol + 1) // 2 if i == j else vol for (i, j) in spec.pairs)
 
 
 def source_hash():
@@ -183,8 +201,16 @@ def cpu_baseline(phi64, spec_kw, target_seconds):
     shape, P, L = spec_kw["shape"], spec_kw["P"], spec_kw["L"]
     d = len(shape)
     C = phi64.shape[0]
-    ospec = oracle.Spec(shape=shape, n_channels=C, n_levels=L,
+    kind = ["s2", "sbar", "stilde"][spec_kw.get("descriptor", 0)]
+    ospec = oracle.Spec(shape=shape, n_channels=C, n_levels=L, descriptor=kind,
                         max_disp=tuple(min(P, min(s >> l for s in shape) // 2 - 1) for l in range(L)))
+    if kind == "s2":
+        fwd = oracle._native.corr
+        adj_at = oracle._native.corr_adjoint_at
+    else:
+        c = oracle.soft_threshold_constants(ospec.alpha)
+        fwd = lambda a, b, r: oracle._native.sbar(a, b, r, ospec.alpha, c)
+        adj_at = lambda a, b, r, G, v: oracle._native.sbar_adjoint_at(a, b, r, ospec.alpha, c, G, v)
     lv = oracle.pyramid(phi64, L)
     rng = np.random.default_rng(0)
     # finest level, first pair: cost per displacement = N MACs, per voxel = K MACs (x2 in the adjoint)
@@ -194,22 +220,22 @@ def cpu_baseline(phi64, spec_kw, target_seconds):
     N = int(np.prod(shape))
     # calibrate with a tiny sample, then size the real one
     t0 = time.perf_counter()
-    oracle._native.corr(lv[0][pair[0]], lv[0][pair[1]], rs[:4])
+    fwd(lv[0][pair[0]], lv[0][pair[1]], rs[:4])
     t_per_r = max((time.perf_counter() - t0) / 4, 1e-6)
     k_s = int(max(8, min(len(rs), 0.5 * target_seconds / t_per_r)))
     sel = rng.choice(len(rs), k_s, replace=False)
     t0 = time.perf_counter()
-    oracle._native.corr(lv[0][pair[0]], lv[0][pair[1]], rs[sel])
+    fwd(lv[0][pair[0]], lv[0][pair[1]], rs[sel])
     t_fwd = time.perf_counter() - t0
     G = rng.standard_normal(k)
     vox = rng.integers(0, min(shape), size=(64, d))
     t0 = time.perf_counter()
-    oracle._native.corr_adjoint_at(lv[0][pair[0]], lv[0][pair[1]], rs, G, vox)
+    adj_at(lv[0][pair[0]], lv[0][pair[1]], rs, G, vox)
     t_per_v = max((time.perf_counter() - t0) / 64, 1e-9)
     n_s = int(max(64, min(N, 0.5 * target_seconds / t_per_v)))
     vox = rng.integers(0, min(shape), size=(n_s, d))
     t0 = time.perf_counter()
-    oracle._native.corr_adjoint_at(lv[0][pair[0]], lv[0][pair[1]], rs, G, vox)
+    adj_at(lv[0][pair[0]], lv[0][pair[1]], rs, G, vox)
     t_adj = time.perf_counter() - t0
     # whole evaluation: every (level, pair) block, forward over its displacements and
     # adjoint over its voxels, scaled by the measured per-unit times (cost ~ N_l * K_lp)
@@ -244,7 +270,8 @@ def main():
     wl = WORKLOADS[args.workload]
     shape, C, L, P, B = wl["shape"], wl["C"], wl["L"], wl["P"], wl["batch"]
     flags = dmcr.FLAG_RECOMPUTE if wl["recompute"] else 0
-    spec = dmcr.make_spec(shape, C, L, P, flags=flags)
+    desc = wl.get("descriptor", dmcr.DESC_S2)
+    spec = dmcr.make_spec(shape, C, L, P, flags=flags, descriptor=desc)
     K = dmcr.dmcr_descriptor_size(spec)
     N = int(np.prod(shape))
 
@@ -309,29 +336,52 @@ def main():
               file=sys.stderr, flush=True)
     dom = kern[0]
     prof_ms = sum(r["total_ms"] for r in kern) / args.steps
-    roofline = dict(bound="hbm", kernel=dom["name"], achieved=round(dom["GBps"], 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(dom["GBps"] / HBM_PEAK_GBS, 4),
-                    traffic=stored_traffic(args.workload, dom["name"]),
-                    avg_us=round(dom["avg_us"], 2), bytes_per_launch=dom["bytes_per_launch"],
-                    source_hash=source_hash())
+    if dom["name"] in SOFT_SLOTS:
+        # pair terms per step: forward N_l * K_l (every pair), adjoint N_l * C^2 * box_l^d
+        d = len(shape)
+        terms = {"direct_fwd_soft": 0.0, "direct_adj_soft": 0.0}
+        for l in range(L):
+            Nl = N >> (d * l)
+            box = 2 * spec.max_disp[l] + 1
+            terms["direct_fwd_soft"] += B * Nl * K_level(spec, l)
+            terms["direct_adj_soft"] += B * Nl * C * C * box ** d
+        per_launch = terms[dom["name"]] / L
+        achieved = per_launch / (dom["avg_us"] * 1e-6) / 1e9
+        peak = VALU_LANE_SLOTS_PER_S / SOFT_SLOTS[dom["name"]] / 1e9
+        roofline = dict(bound="alu", kernel=dom["name"], achieved=round(achieved, 1), peak=round(peak, 1),
+                        unit="Gterm/s", frac=round(achieved / peak, 4), traffic=None,
+                        avg_us=round(dom["avg_us"], 2), terms_per_launch=per_launch)
+    else:
+        roofline = dict(bound="hbm", kernel=dom["name"], achieved=round(dom["GBps"], 1), peak=HBM_PEAK_GBS,
+                        unit="GB/s", frac=round(dom["GBps"] / HBM_PEAK_GBS, 4),
+                        traffic=stored_traffic(args.workload, dom["name"]),
+                        avg_us=round(dom["avg_us"], 2), bytes_per_launch=dom["bytes_per_launch"],
+                        source_hash=source_hash())
     total_bytes = sum(r["bytes_per_launch"] * r["launches"] for r in kern) / args.steps
     step_roofline = dict(bytes_per_step=total_bytes, bytes_per_voxel=total_bytes / (N * B),
                          achieved_GBps=round(total_bytes / (ms * 1e-3) / 1e9, 1),
                          frac=round(total_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                          kernel_ms_sum=round(prof_ms, 4))
+    if roofline["bound"] == "alu":
+        # the whole step against FP32 issue: every soft term at its slot cost
+        slots = sum(terms[k] * SOFT_SLOTS[k] for k in terms)
+        step_roofline = dict(bound="alu", terms_per_step=sum(terms.values()), issue_slots_per_step=slots,
+                             frac=round(slots / (ms * 1e-3) / VALU_LANE_SLOTS_PER_S, 4),
+                             kernel_ms_sum=round(prof_ms, 4))
 
     out = dict(metric=METRIC, value=value, unit="voxel·it/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload=wl["desc"], shape=list(shape), channels=C, levels=L,
-                           max_disp=list(spec.max_disp), K=K, batch=B, path="fft",
+                           max_disp=list(spec.max_disp), K=K, batch=B, path="direct" if desc else "fft",
+                           descriptor=["s2", "sbar", "stilde"][desc],
                            recompute=wl["recompute"], parallelism="single GPU"),
                roofline=roofline, step_roofline=step_roofline)
     if not args.no_serve and args.workload == "3d256":
         out["serving"] = serving(args.requests, args.rate, args.compare)
     if not args.no_cpu_baseline:
         phi64 = phi_h[0].astype(np.float64)
-        cb = cpu_baseline(phi64, dict(shape=shape, P=P, L=L), args.cpu_seconds)
+        cb = cpu_baseline(phi64, dict(shape=shape, P=P, L=L, descriptor=desc), args.cpu_seconds)
         out["cpu_baseline"] = dict(value=cb["value"], unit=cb["unit"], cores=cb["cores"], kind=cb["kind"],
                                    sample=cb["sample"])
     print(json.dumps(out), flush=True)

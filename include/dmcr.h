@@ -72,6 +72,22 @@ enum { DMCR_MAX_LEVELS = 8, DMCR_MAX_CHANNELS = 4, DMCR_MAX_PAIRS = 10 };
  * tile with a halo of P (the paper's own convolve-and-reduce, Sec. 3.2.3). */
 enum { DMCR_PATH_AUTO = 0, DMCR_PATH_FFT = 1, DMCR_PATH_DIRECT = 2 };
 
+/* spec.descriptor: which two-point statistic each (level, pair) block holds.
+ *   S2     the product form (1/N) sum_x phi_i(x) phi_j(x + r): the Appendix A
+ *          corrected descriptor of the identity threshold (Sec. 5.1).
+ *   SBAR   the paper's soft-threshold descriptor (Sec. 3.2.4, eq. softthreshold,
+ *          and eq. s3 with r_a = r_b): (1/N) sum_x f((phi_i(x) + phi_j(x + r)) / 2)^2
+ *          with the logistic f(u) = c1 / (1 + exp(-alpha (u + c2))) + c3 fixed by
+ *          f(0) = 0, f(1) = 1, f''(0.75) = 0.  The r = 0 mask of an auto pair
+ *          gives f(phi_i(x)), the same expression.
+ *   STILDE SBAR mapped back by Appendix A, eq. (s2rfroms2rbar): with F = f(1/2)^2,
+ *          (SBAR_ij(r) - F (SBAR_ii(0) + SBAR_jj(0))) / (1 - 2F); equals S2 on
+ *          binary fields.  Every channel of a listed pair needs its auto pair.
+ * SBAR and STILDE are evaluated on the DIRECT path only (AUTO selects it; FFT
+ * returns DMCR_EUNSUPPORTED): the soft threshold is not a product, so the
+ * convolution theorem does not apply. */
+enum { DMCR_DESC_S2 = 0, DMCR_DESC_SBAR = 1, DMCR_DESC_STILDE = 2 };
+
 /* spec.flags */
 enum {
     DMCR_FLAG_RECOMPUTE = 1  /* dmcr_loss_grad recomputes the forward spectra in the
@@ -90,6 +106,10 @@ typedef struct {
     int32_t pairs[2 * 16];                 /* (i, j) with i <= j, used if n_pairs > 0 */
     int32_t path;                          /* DMCR_PATH_*                             */
     int32_t flags;                         /* DMCR_FLAG_*                             */
+    int32_t descriptor;                    /* DMCR_DESC_*                             */
+    int32_t reserved;                      /* must be 0                               */
+    double  alpha;                         /* soft-threshold slope (SBAR, STILDE);
+                                              0 selects the paper's 10                */
 } dmcr_spec;
 
 /* Box handling for dmcr_reconstruct (Sec. 3.1). */

@@ -1,6 +1,9 @@
 // Direct (shifted-product) path for short correlation ranges: the paper's own
 // convolve-and-reduce of Sec. 3.2.3 (eq. convdef) with the sparse two-point
 // masks written as explicit shifts instead of dense mask convolutions.
+// The pair term is either the product a b (S2) or, for the soft-threshold
+// descriptor of Sec. 3.2.4, f((a + b) / 2)^2 with the logistic f; its
+// derivative with respect to either end is b, or f f' at (a + b) / 2.
 //
 // Forward: one block per (spatial tile, chunk of displacements, batch x pair).
 // The tile of phi_i and the tile of phi_j with a halo of P (periodic) sit in
@@ -36,11 +39,12 @@ __device__ __forceinline__ int wrapi(int i, int n)
 
 // Load the halo tile of `f` (one channel, [n0][n1][n2]) whose origin is the
 // tile origin minus P, into H[h0][h1][h2].
+template <int NT = kT>
 __device__ __forceinline__ void load_halo(const Geo &g, const float *__restrict__ f, int o0, int o1,
                                           int o2, float *H)
 {
     const int vol = g.h0 * g.h1 * g.h2;
-    for (int idx = threadIdx.x; idx < vol; idx += kT) {
+    for (int idx = threadIdx.x; idx < vol; idx += NT) {
         const int z = idx % g.h2;
         const int r = idx / g.h2;
         const int y = r % g.h1;
@@ -52,7 +56,33 @@ __device__ __forceinline__ void load_halo(const Geo &g, const float *__restrict_
     }
 }
 
+// logistic soft threshold f(u) = c1 / (1 + exp(-alpha (u + c2))) + c3
+struct Soft {
+    float alpha, c1, c2, c3;
+};
+
+__device__ __forceinline__ float soft_sigma(float u, const Soft &s)
+{
+    return __builtin_amdgcn_rcpf(1.f + __expf(-s.alpha * (u + s.c2)));
+}
+
+// f(u)^2: the quadratic reduction of one soft realisation
+__device__ __forceinline__ float soft_sq(float u, const Soft &s)
+{
+    const float f = fmaf(s.c1, soft_sigma(u, s), s.c3);
+    return f * f;
+}
+
+// f(u) f'(u): d f((a + b)/2)^2 / da (and / db)
+__device__ __forceinline__ float soft_ffp(float u, const Soft &s)
+{
+    const float sg = soft_sigma(u, s);
+    const float f = fmaf(s.c1, sg, s.c3);
+    return f * (s.c1 * s.alpha) * sg * (1.f - sg);
+}
+
 struct DirFwdArgs {
+    Soft soft;
     Geo g;
     const float *phi;   // level field [B][C][n..]
     float *part;        // [B*npairs][ntiles][kmax]
@@ -63,6 +93,19 @@ struct DirFwdArgs {
     int64_t cnt[kMaxPairs];
 };
 
+// pair term of the forward sum
+template <bool SOFT>
+__device__ __forceinline__ float pair_term(float a, float b, const Soft &s)
+{
+    if constexpr (SOFT)
+        return soft_sq(0.5f * (a + b), s);
+    else
+        return a * b;
+}
+
+// TX, TY, TZ: the tile edge when it is the full tile (16 x 16 or 4 x 8 x 8), so the
+// tile loops unroll and the LDS reads batch; 0 for grids smaller than one tile.
+template <bool SOFT, int TX, int TY, int TZ>
 __global__ __launch_bounds__(kT) void k_direct_fwd(DirFwdArgs a)
 {
     extern __shared__ float sm[];
@@ -102,12 +145,25 @@ __global__ __launch_bounds__(kT) void k_direct_fwd(DirFwdArgs a)
     }
     const int pz = (g.ndim == 3) ? r2 + g.P : 0;
     float acc = 0.f;
-    for (int x = 0; x < g.t0; ++x)
-        for (int y = 0; y < g.t1; ++y) {
-            const float *arow = Ta + (x * g.t1 + y) * g.t2;
-            const float *brow = Hb + ((x + r0 + g.P) * g.h1 + (y + r1 + g.P)) * g.h2 + pz;
-            for (int z = 0; z < g.t2; ++z) acc += arow[z] * brow[z];
-        }
+    const float *hb = Hb + ((r0 + g.P) * g.h1 + (r1 + g.P)) * g.h2 + pz;
+    if constexpr (TX > 0) {
+#pragma unroll
+        for (int x = 0; x < TX; ++x)
+#pragma unroll
+            for (int y = 0; y < TY; ++y) {
+                const float *arow = Ta + (x * TY + y) * TZ;
+                const float *brow = hb + (x * g.h1 + y) * g.h2;
+#pragma unroll
+                for (int z = 0; z < TZ; ++z) acc += pair_term<SOFT>(arow[z], brow[z], a.soft);
+            }
+    } else {
+        for (int x = 0; x < g.t0; ++x)
+            for (int y = 0; y < g.t1; ++y) {
+                const float *arow = Ta + (x * g.t1 + y) * g.t2;
+                const float *brow = hb + (x * g.h1 + y) * g.h2;
+                for (int z = 0; z < g.t2; ++z) acc += pair_term<SOFT>(arow[z], brow[z], a.soft);
+            }
+    }
     a.part[((int64_t)bp * a.ntiles + tile) * a.kmax + k] = acc;
 }
 
@@ -120,20 +176,35 @@ struct DirRedArgs {
     double invN;
 };
 
+// One block per (32 consecutive displacements, batch x pair): lane group q of
+// 8 sums tiles q, q + 8, ... in order (coalesced: the 32 displacements of a tile
+// are contiguous), then the 8 group sums are added in group order.
+constexpr int kRedK = 32, kRedG = kT / kRedK;
+
 __global__ __launch_bounds__(kT) void k_direct_reduce(DirRedArgs a)
 {
-    const int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x;
+    __shared__ double part[kRedG][kRedK];
+    const int kk = threadIdx.x % kRedK, grp = threadIdx.x / kRedK;
+    const int64_t k = (int64_t)blockIdx.x * kRedK + kk;
     const int bp = blockIdx.y;
     const int p = bp % a.npairs;
     const int64_t b = bp / a.npairs;
-    if (k >= a.cnt[p]) return;
-    const float *src = a.part + (int64_t)bp * a.ntiles * a.kmax + k;
     double s = 0.0;
-    for (int64_t t = 0; t < a.ntiles; ++t) s += (double)src[t * a.kmax];
-    a.S[b * a.K + a.off[p] + k] = (float)(s * a.invN);
+    if (k < a.cnt[p]) {
+        const float *src = a.part + (int64_t)bp * a.ntiles * a.kmax + k;
+        for (int64_t t = grp; t < a.ntiles; t += kRedG) s += (double)src[t * a.kmax];
+    }
+    part[grp][kk] = s;
+    __syncthreads();
+    if (grp == 0 && k < a.cnt[p]) {
+        double tot = part[0][kk];
+        for (int q = 1; q < kRedG; ++q) tot += part[q][kk];
+        a.S[b * a.K + a.off[p] + k] = (float)(tot * a.invN);
+    }
 }
 
 struct DirAdjArgs {
+    Soft soft;
     Geo g;
     const float *phi;
     const float *KB0;   // [B][C][C][box^d]
@@ -143,7 +214,24 @@ struct DirAdjArgs {
     float invN;
 };
 
-__global__ __launch_bounds__(kT) void k_direct_adj(DirAdjArgs a)
+// derivative of the pair term with respect to the thread's own end value
+template <bool SOFT>
+__device__ __forceinline__ float adj_term(float own, float other, const Soft &s)
+{
+    if constexpr (SOFT)
+        return soft_ffp(0.5f * (own + other), s);
+    else
+        return other;
+}
+
+// The adjoint has one output per voxel but |box| terms each: kAdjSplit threads
+// share a voxel, each taking every kAdjSplit-th box row r0, so a tile of 256
+// voxels keeps 16 waves busy; the partial sums are added in split order.
+constexpr int kAdjSplit = 4;
+constexpr int kAdjT = kT * kAdjSplit;
+
+template <bool SOFT>
+__global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
 {
     extern __shared__ float sm[];
     const Geo &g = a.g;
@@ -153,36 +241,55 @@ __global__ __launch_bounds__(kT) void k_direct_adj(DirAdjArgs a)
     const int tz = tile % g.nt2, ty = (tile / g.nt2) % g.nt1, tx = tile / (g.nt2 * g.nt1);
     const int o0 = tx * g.t0, o1 = ty * g.t1, o2 = tz * g.t2;
     const int tvol = g.t0 * g.t1 * g.t2;
-    // this thread's output voxel
-    const int vz = threadIdx.x % g.t2;
-    const int vy = (threadIdx.x / g.t2) % g.t1;
-    const int vx = threadIdx.x / (g.t2 * g.t1);
+    const int hvol = g.h0 * g.h1 * g.h2;
+    float *red = sm + hvol;            // [kAdjSplit][kT] partial sums
+    // this thread's output voxel and its share of the box rows
+    const int v = threadIdx.x % kT, split = threadIdx.x / kT;
+    const int vz = v % g.t2;
+    const int vy = (v / g.t2) % g.t1;
+    const int vx = v / (g.t2 * g.t1);
+    const bool active = v < tvol;
+    const int64_t vox = ((int64_t)(o0 + vx) * g.n1 + (o1 + vy)) * g.n2 + (o2 + vz);
+    // own value phi_c(x), needed by the soft pair term
+    const float own = (SOFT && active) ? a.phi[(b * a.C + c) * a.N + vox] : 0.f;
     float acc = 0.f;
     for (int j = 0; j < a.C; ++j) {
-        load_halo(g, a.phi + (b * a.C + j) * a.N, o0, o1, o2, sm);
+        load_halo<kAdjT>(g, a.phi + (b * a.C + j) * a.N, o0, o1, o2, sm);
         __syncthreads();
-        if ((int)threadIdx.x < tvol) {
+        if (active) {
             const float *Kc = a.KB0 + ((b * a.C + c) * a.C + j) * a.vol;
             if (g.ndim == 2) {
-                for (int r0 = 0; r0 < g.box; ++r0) {
+                for (int r0 = split; r0 < g.box; r0 += kAdjSplit) {
                     const float *hrow = sm + (vx + r0) * g.h1 + vy;
                     const float *krow = Kc + r0 * g.box;
-                    for (int r1 = 0; r1 < g.box; ++r1) acc += krow[r1] * hrow[r1];
+#pragma unroll 8
+                    for (int r1 = 0; r1 < g.box; ++r1) acc += krow[r1] * adj_term<SOFT>(own, hrow[r1], a.soft);
                 }
             } else {
-                for (int r0 = 0; r0 < g.box; ++r0)
+                for (int r0 = split; r0 < g.box; r0 += kAdjSplit)
                     for (int r1 = 0; r1 < g.box; ++r1) {
                         const float *hrow = sm + ((vx + r0) * g.h1 + (vy + r1)) * g.h2 + vz;
                         const float *krow = Kc + (r0 * g.box + r1) * g.box;
-                        for (int r2 = 0; r2 < g.box; ++r2) acc += krow[r2] * hrow[r2];
+#pragma unroll 8
+                        for (int r2 = 0; r2 < g.box; ++r2) acc += krow[r2] * adj_term<SOFT>(own, hrow[r2], a.soft);
                     }
             }
         }
         __syncthreads();
     }
-    if ((int)threadIdx.x < tvol)
-        a.grad[(b * a.C + c) * a.N + ((int64_t)(o0 + vx) * g.n1 + (o1 + vy)) * g.n2 + (o2 + vz)] =
-            acc * a.invN;
+    red[split * kT + v] = acc;
+    __syncthreads();
+    if (split == 0 && active) {
+        float t = red[v];
+#pragma unroll
+        for (int q = 1; q < kAdjSplit; ++q) t += red[q * kT + v];
+        a.grad[(b * a.C + c) * a.N + vox] = t * a.invN;
+    }
+}
+
+Soft make_soft(const Plan &p)
+{
+    return Soft{(float)p.alpha, (float)p.c1, (float)p.c2, (float)p.c3};
 }
 
 Geo make_geo(const Plan &p, int l)
@@ -226,7 +333,9 @@ bool direct_supported(const Plan &p, int l, int tile[3])
     const int64_t tvol = (int64_t)t[0] * t[1] * t[2];
     int64_t hvol = (int64_t)(t[0] + 2 * L.P) * (t[1] + 2 * L.P);
     if (p.ndim == 3) hvol *= (t[2] + 2 * L.P);
-    if ((size_t)(tvol + hvol) * sizeof(float) > kDirectLds) return false;
+    // forward: tile + halo; adjoint: halo + the kAdjSplit x 256 partial sums
+    const int64_t extra = tvol > (int64_t)kAdjSplit * kT ? tvol : (int64_t)kAdjSplit * kT;
+    if ((size_t)(extra + hvol) * sizeof(float) > kDirectLds) return false;
     if (tile) {
         tile[0] = t[0];
         tile[1] = t[1];
@@ -240,6 +349,7 @@ hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S
 {
     const LevelPlan &L = p.lv[l];
     DirFwdArgs a{};
+    a.soft = make_soft(p);
     a.g = make_geo(p, l);
     a.phi = phi;
     a.part = ws.at<float>(L.part);
@@ -261,8 +371,21 @@ hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S
     const int tvol = a.g.t0 * a.g.t1 * a.g.t2;
     const size_t lds = (size_t)(tvol + a.g.h0 * a.g.h1 * a.g.h2) * sizeof(float);
     dim3 grid((unsigned)a.ntiles, (unsigned)((kmax + kT - 1) / kT), (unsigned)(p.B * p.npairs));
-    hipError_t e = launch("direct_fwd", (double)p.B * p.C * L.N * 4 + (double)p.B * p.npairs * a.ntiles * kmax * 4,
-                          k_direct_fwd, grid, dim3(kT), lds, st, a);
+    const double fbytes = (double)p.B * p.C * L.N * 4 + (double)p.B * p.npairs * a.ntiles * kmax * 4;
+    const bool full2 = p.ndim == 2 && a.g.t0 == 16 && a.g.t1 == 16;
+    const bool full3 = p.ndim == 3 && a.g.t0 == 4 && a.g.t1 == 8 && a.g.t2 == 8;
+    const bool soft = p.desc != DMCR_DESC_S2;
+    const char *name = soft ? "direct_fwd_soft" : "direct_fwd";
+    hipError_t e;
+    if (full2)
+        e = soft ? launch(name, fbytes, k_direct_fwd<true, 16, 16, 1>, grid, dim3(kT), lds, st, a)
+                 : launch(name, fbytes, k_direct_fwd<false, 16, 16, 1>, grid, dim3(kT), lds, st, a);
+    else if (full3)
+        e = soft ? launch(name, fbytes, k_direct_fwd<true, 4, 8, 8>, grid, dim3(kT), lds, st, a)
+                 : launch(name, fbytes, k_direct_fwd<false, 4, 8, 8>, grid, dim3(kT), lds, st, a);
+    else
+        e = soft ? launch(name, fbytes, k_direct_fwd<true, 0, 0, 0>, grid, dim3(kT), lds, st, a)
+                 : launch(name, fbytes, k_direct_fwd<false, 0, 0, 0>, grid, dim3(kT), lds, st, a);
     if (e != hipSuccess) return e;
     DirRedArgs r{};
     r.part = a.part;
@@ -276,7 +399,7 @@ hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S
         r.off[q] = L.off[q];
     }
     r.invN = 1.0 / (double)L.N;
-    dim3 rg((unsigned)((kmax + kT - 1) / kT), (unsigned)(p.B * p.npairs));
+    dim3 rg((unsigned)((kmax + kRedK - 1) / kRedK), (unsigned)(p.B * p.npairs));
     return launch("direct_reduce", (double)p.B * p.npairs * a.ntiles * kmax * 4, k_direct_reduce, rg, dim3(kT), 0,
                   st, r);
 }
@@ -289,6 +412,7 @@ hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const fl
     hipError_t e = launch_build_kernels(p, l, G, KB0, st);
     if (e != hipSuccess) return e;
     DirAdjArgs a{};
+    a.soft = make_soft(p);
     a.g = make_geo(p, l);
     a.phi = phi;
     a.KB0 = KB0;
@@ -298,10 +422,11 @@ hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const fl
     a.vol = 1;
     for (int d = 0; d < p.ndim; ++d) a.vol *= L.box;
     a.invN = (float)(1.0 / (double)L.N);
-    const size_t lds = (size_t)(a.g.h0 * a.g.h1 * a.g.h2) * sizeof(float);
+    const size_t lds = (size_t)(a.g.h0 * a.g.h1 * a.g.h2 + kAdjSplit * kT) * sizeof(float);
     dim3 grid((unsigned)L.n_tiles, (unsigned)p.C, (unsigned)p.B);
     const double bytes = 2.0 * p.B * p.C * L.N * 4 + (double)p.B * p.C * p.C * a.vol * 4;
-    return launch("direct_adj", bytes, k_direct_adj, grid, dim3(kT), lds, st, a);
+    if (p.desc == DMCR_DESC_S2) return launch("direct_adj", bytes, k_direct_adj<false>, grid, dim3(kAdjT), lds, st, a);
+    return launch("direct_adj_soft", bytes, k_direct_adj<true>, grid, dim3(kAdjT), lds, st, a);
 }
 
 }  // namespace dmcr

@@ -72,6 +72,22 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
     if (p.ndim == 2) p.shape[2] = 1;
     p.flags = s->flags;
     if (s->path < DMCR_PATH_AUTO || s->path > DMCR_PATH_DIRECT) return DMCR_EINVAL;
+    // descriptor kind and soft-threshold constants (Sec. 3.2.4): the inflection
+    // condition f''(0.75) = 0 gives c2 = -0.75, then f(0) = 0 and f(1) = 1 fix c1, c3
+    if (s->descriptor < DMCR_DESC_S2 || s->descriptor > DMCR_DESC_STILDE || s->reserved != 0) return DMCR_EINVAL;
+    p.desc = s->descriptor;
+    if (p.desc != DMCR_DESC_S2) {
+        p.alpha = (s->alpha == 0.0) ? 10.0 : s->alpha;
+        if (!(p.alpha > 0.0) || !std::isfinite(p.alpha)) return DMCR_EINVAL;
+        if (s->path == DMCR_PATH_FFT) return DMCR_EUNSUPPORTED;
+        auto sig = [](double z) { return 1.0 / (1.0 + std::exp(-z)); };
+        p.c2 = -0.75;
+        const double lo = sig(p.alpha * p.c2), hi = sig(p.alpha * (1.0 + p.c2));
+        p.c1 = 1.0 / (hi - lo);
+        p.c3 = -p.c1 * lo;
+        const double fh = p.c1 * sig(p.alpha * (0.5 + p.c2)) + p.c3;
+        p.F = fh * fh;
+    }
     // pairs
     if (s->n_pairs <= 0) {
         for (int i = 0; i < p.C; ++i)
@@ -91,6 +107,15 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
             p.pi[q] = i;
             p.pj[q] = j;
         }
+    }
+    if (p.desc == DMCR_DESC_STILDE) {
+        // the map of pair (i, j) reads the r = 0 entries of the auto pairs (i, i) and (j, j)
+        for (int q = 0; q < p.npairs; ++q)
+            for (int c : {p.pi[q], p.pj[q]}) {
+                bool found = false;
+                for (int r = 0; r < p.npairs; ++r) found |= (p.pi[r] == c && p.pj[r] == c);
+                if (!found) return DMCR_EINVAL;
+            }
     }
     // levels
     int64_t off = 0;
@@ -131,7 +156,7 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
         int tile[3];
         const bool dok = direct_supported(p, l, tile);
         const bool fok = fft_supported(p, l);
-        if (s->path == DMCR_PATH_DIRECT) {
+        if (s->path == DMCR_PATH_DIRECT || p.desc != DMCR_DESC_S2) {
             if (!dok) return DMCR_EUNSUPPORTED;
             L.path = DMCR_PATH_DIRECT;
         } else if (s->path == DMCR_PATH_FFT) {
@@ -282,11 +307,13 @@ struct Sched {
 // Side lanes pay off only when the passes are long enough to hide the extra
 // event waits; small fields stay on the caller's stream (measured: a 512^2
 // three-level evaluation is slower with lanes, 256^3 and 64 x 512^2 faster).
+// The soft-threshold levels are long ALU-bound kernels whose coarse levels fill
+// only part of the chip, so their levels always run side by side.
 constexpr int64_t kLaneMinVoxels = int64_t(1) << 22;
 
 hipError_t make_sched(const Plan &p, hipStream_t st, Sched *s)
 {
-    const bool multi = (int64_t)p.B * p.C * p.lv[0].N >= kLaneMinVoxels;
+    const bool multi = (int64_t)p.B * p.C * p.lv[0].N >= kLaneMinVoxels || (p.desc != DMCR_DESC_S2 && p.L > 1);
     if (multi) {
         hipError_t e = tl_lanes.init();
         if (e != hipSuccess) return e;
@@ -314,6 +341,7 @@ hipError_t run_forward(const Plan &p, const float *phi, float *S, const Ws &ws, 
     }
     for (int l = 1; l < p.L; ++l)
         if ((e = sc.join(sc.main, sc.lane(l))) != hipSuccess) return e;
+    if (p.desc == DMCR_DESC_STILDE) return launch_stilde(p, S, sc.main);
     return hipSuccess;
 }
 
@@ -373,6 +401,7 @@ dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St
     // recompute uses side lane 0), so the final error sum runs there
     hipStream_t fin = (sc.multi && p.L == 1) ? sc.ln->side[1] : st;
     DMCR_TRY(launch_error(p, S, St, E, G, w, st, fin, fin != st ? sc.ln->event() : nullptr));
+    if (p.desc == DMCR_DESC_STILDE) DMCR_TRY(launch_stilde_adjoint(p, G, G, st));
     DMCR_TRY(run_adjoint(p, phi, G, grad, keep, w, sc, xf));
     return dev(sc.join(st, fin));
 }
@@ -456,6 +485,11 @@ dmcr_status dmcr_descriptor_adjoint(const dmcr_spec *spec, int32_t batch, const 
     Sched sc;
     DMCR_TRY(make_sched(p, stream, &sc));
     DMCR_TRY(run_pyramid(p, phi, w, stream));
+    if (p.desc == DMCR_DESC_STILDE) {
+        float *G = w.at<float>(p.G);
+        DMCR_TRY(launch_stilde_adjoint(p, dS, G, stream));
+        dS = G;
+    }
     return dev(run_adjoint(p, phi, dS, grad, false, w, sc));
 }
 

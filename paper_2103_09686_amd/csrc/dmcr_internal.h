@@ -49,6 +49,9 @@ struct LevelPlan {
 };
 
 struct Plan {
+    int desc;          // DMCR_DESC_*
+    double alpha, c1, c2, c3;   // soft threshold f(u) = c1 / (1 + exp(-alpha (u + c2))) + c3
+    double F;          // f(1/2)^2 (Appendix A)
     int ndim;
     int shape[3];
     int C;
@@ -117,6 +120,11 @@ hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const fl
                                 const Ws &ws, hipStream_t st);
 
 hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0, hipStream_t st);
+
+// Appendix A map of the soft-threshold descriptor (DMCR_DESC_STILDE), in place
+// on S [B][K], and its transpose from G_in to G_out (may be the same array).
+hipError_t launch_stilde(const Plan &p, float *S, hipStream_t st);
+hipError_t launch_stilde_adjoint(const Plan &p, const float *G_in, float *G_out, hipStream_t st);
 
 // E and the cotangent G from S.  G is ready on st; with st_final (and the
 // event parts_done) the final sum into E runs on st_final instead, off the

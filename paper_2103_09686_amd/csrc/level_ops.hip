@@ -172,9 +172,118 @@ __global__ __launch_bounds__(kThreads) void k_error_final(const double *part, in
     if (threadIdx.x == 0) E[b] = red[0] * invZ;
 }
 
+// Appendix A map of the soft-threshold descriptor, one block per (level, field).
+// With F = f(1/2)^2 and vf_c = Sbar_cc(0) (the first entry of the auto pair's
+// half box): S(r) = (Sbar(r) - F (vf_i + vf_j)) / (1 - 2F) for every entry of
+// pair (i, j) except the r = 0 entry of an auto pair, which the map leaves as it
+// is (the formula returns it unchanged).
+struct StildeArgs {
+    const float *in;
+    float *out;
+    int64_t K;
+    int npairs;
+    int pi[kMaxPairs], pj[kMaxPairs];
+    int auto_q[kMaxChannels];                 // pair index of (c, c)
+    int64_t off[kMaxLevels][kMaxPairs], cnt[kMaxLevels][kMaxPairs];
+    double F;
+};
+
+__global__ __launch_bounds__(kThreads) void k_stilde(StildeArgs a)
+{
+    const int l = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    float *S = a.out + b * a.K;
+    double vf[kMaxChannels];
+    for (int c = 0; c < kMaxChannels; ++c) vf[c] = a.auto_q[c] >= 0 ? (double)S[a.off[l][a.auto_q[c]]] : 0.0;
+    __syncthreads();   // every vf is read before any entry is rewritten
+    const double inv = 1.0 / (1.0 - 2.0 * a.F);
+    for (int q = 0; q < a.npairs; ++q) {
+        const double shift = a.F * (vf[a.pi[q]] + vf[a.pj[q]]);
+        const int64_t first = (a.pi[q] == a.pj[q]) ? 1 : 0;
+        float *Sq = S + a.off[l][q];
+        for (int64_t k = first + threadIdx.x; k < a.cnt[l][q]; k += kThreads)
+            Sq[k] = (float)(((double)Sq[k] - shift) * inv);
+    }
+}
+
+// Transpose of k_stilde (the map is linear in Sbar): every entry scales by
+// 1/(1 - 2F); the r = 0 entry of auto pair (c, c) also collects
+// -F/(1 - 2F) T_c, T_c = sum over pairs (i, j) of ([i = c] + [j = c]) sum_r G_ij(r).
+__global__ __launch_bounds__(kThreads) void k_stilde_adj(StildeArgs a)
+{
+    __shared__ double red[kThreads];
+    __shared__ double tot[kMaxPairs];
+    const int l = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    const float *Gi = a.in + b * a.K;
+    float *Go = a.out + b * a.K;
+    for (int q = 0; q < a.npairs; ++q) {
+        double acc = 0.0;
+        for (int64_t k = threadIdx.x; k < a.cnt[l][q]; k += kThreads) acc += (double)Gi[a.off[l][q] + k];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = kThreads / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) tot[q] = red[0];
+        __syncthreads();
+    }
+    const double inv = 1.0 / (1.0 - 2.0 * a.F);
+    for (int q = 0; q < a.npairs; ++q) {
+        const bool aut = a.pi[q] == a.pj[q];
+        for (int64_t k = threadIdx.x; k < a.cnt[l][q]; k += kThreads) {
+            double g = (double)Gi[a.off[l][q] + k] * inv;
+            if (aut && k == 0) {
+                const int c = a.pi[q];
+                double T = 0.0;
+                for (int r = 0; r < a.npairs; ++r) T += ((a.pi[r] == c) + (a.pj[r] == c)) * tot[r];
+                g -= a.F * inv * T;
+            }
+            Go[a.off[l][q] + k] = (float)g;
+        }
+    }
+}
+
+StildeArgs stilde_args(const Plan &p, const float *in, float *out)
+{
+    StildeArgs a{};
+    a.in = in;
+    a.out = out;
+    a.K = p.K;
+    a.npairs = p.npairs;
+    for (int c = 0; c < kMaxChannels; ++c) a.auto_q[c] = -1;
+    for (int q = 0; q < p.npairs; ++q) {
+        a.pi[q] = p.pi[q];
+        a.pj[q] = p.pj[q];
+        if (p.pi[q] == p.pj[q]) a.auto_q[p.pi[q]] = q;
+    }
+    for (int l = 0; l < p.L; ++l)
+        for (int q = 0; q < p.npairs; ++q) {
+            a.off[l][q] = p.lv[l].off[q];
+            a.cnt[l][q] = p.lv[l].cnt[q];
+        }
+    a.F = p.F;
+    return a;
+}
+
 unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
+
+hipError_t launch_stilde(const Plan &p, float *S, hipStream_t st)
+{
+    const StildeArgs a = stilde_args(p, S, S);
+    return launch("stilde", (double)p.B * p.K * 8, k_stilde, dim3((unsigned)p.L, (unsigned)p.B), dim3(kThreads), 0,
+                  st, a);
+}
+
+hipError_t launch_stilde_adjoint(const Plan &p, const float *G_in, float *G_out, hipStream_t st)
+{
+    const StildeArgs a = stilde_args(p, G_in, G_out);
+    return launch("stilde_adj", (double)p.B * p.K * 12, k_stilde_adj, dim3((unsigned)p.L, (unsigned)p.B),
+                  dim3(kThreads), 0, st, a);
+}
 
 hipError_t launch_restrict(const Plan &p, int l, const float *fine, float *coarse, hipStream_t st)
 {

@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmcr.so")
 
 PATH_AUTO, PATH_FFT, PATH_DIRECT = 0, 1, 2
+DESC_S2, DESC_SBAR, DESC_STILDE = 0, 1, 2
 FLAG_RECOMPUTE = 1
 BOUNDS_NONE, BOUNDS_PROJECT, BOUNDS_PENALTY = 0, 1, 2
 MAX_LEVELS, MAX_CHANNELS, MAX_PAIRS = 8, 4, 10
@@ -37,7 +38,8 @@ class c_spec(ctypes.Structure):
                 ("max_disp", ctypes.c_int32 * MAX_LEVELS),
                 ("level_weight", ctypes.c_double * MAX_LEVELS),
                 ("n_pairs", ctypes.c_int32), ("pairs", ctypes.c_int32 * 32),
-                ("path", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("path", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("descriptor", ctypes.c_int32), ("reserved", ctypes.c_int32), ("alpha", ctypes.c_double)]
 
 
 class c_bounds(ctypes.Structure):
@@ -68,7 +70,8 @@ class c_result(ctypes.Structure):
 @dataclass
 class Spec:
     """One multigrid descriptor: shape of the finest level, channels, levels,
-    per-level maximum displacement P_l, level weights, pairs, path, flags."""
+    per-level maximum displacement P_l, level weights, pairs, path, flags,
+    descriptor kind (DESC_*) and soft-threshold slope alpha (0: the paper's 10)."""
     shape: Tuple[int, ...]
     n_channels: int = 1
     n_levels: int = 1
@@ -77,6 +80,8 @@ class Spec:
     pairs: Tuple[Tuple[int, int], ...] = ()
     path: int = PATH_AUTO
     flags: int = 0
+    descriptor: int = DESC_S2
+    alpha: float = 0.0
 
     def __post_init__(self):
         self.shape = tuple(int(s) for s in self.shape)
@@ -109,6 +114,9 @@ class Spec:
             s.pairs[2 * q + 1] = j
         s.path = self.path
         s.flags = self.flags
+        s.descriptor = self.descriptor
+        s.reserved = 0
+        s.alpha = self.alpha
         return s
 
 

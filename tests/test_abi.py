@@ -37,8 +37,9 @@ def test_exports_every_declared_symbol(dm):
 
 
 def test_struct_sizes_match_header(dm):
-    # dmcr_spec: 4 + 12 + 4 + 4 + 32 + (pad 4?) + 64 + 4 + 128 + 4 + 4
-    assert ctypes.sizeof(dm.c_spec) == 264
+    # dmcr_spec: 4 + 12 + 4 + 4 + 32 + 64 + 4 + 128 + 4 + 4 + 4 (descriptor) + 4 + 8 (alpha)
+    assert ctypes.sizeof(dm.c_spec) == 280
+    assert dm.c_spec.alpha.offset == 272
     assert ctypes.sizeof(dm.c_result) == 32
 
 
@@ -94,3 +95,18 @@ def test_status_strings(dm):
     L = dm.lib()
     for code in (0, -1, -2, -3, -4, -5, 1):
         assert L.dmcr_status_string(code)
+
+
+def test_soft_descriptor_validation(dm):
+    """Soft-threshold descriptors run on the direct path only; S~ needs the auto pairs."""
+    base = dict(shape=(64, 64), n_channels=2, max_disp=(8,))
+    assert dm.dmcr_descriptor_size(dm.Spec(descriptor=dm.DESC_SBAR, **base)) > 0
+    assert dm.dmcr_descriptor_size(dm.Spec(descriptor=dm.DESC_STILDE, **base)) > 0
+    bad = [(dict(descriptor=dm.DESC_SBAR, path=dm.PATH_FFT), -3),
+           (dict(descriptor=dm.DESC_STILDE, pairs=((0, 1), (1, 1))), -1),
+           (dict(descriptor=3), -1),
+           (dict(descriptor=dm.DESC_SBAR, alpha=-1.0), -1)]
+    for kw, code in bad:
+        with pytest.raises(dm.DmcrError) as ei:
+            dm.dmcr_descriptor_size(dm.Spec(**kw, **base))
+        assert ei.value.code == code

@@ -7,10 +7,10 @@ Parity of functions listed as "parity unpinned" in their docstrings is not
 claimed.
 """
 from . import _native
-from .s2 import (DESCRIPTORS, Spec, adjoint, adjoint_at_single_level, all_pairs, box,
+from .s2 import (DESCRIPTORS, Spec, adam_step, adjoint, adjoint_at_single_level, all_pairs, box,
                  correct_sbar, correct_sbar_adjoint, descriptor, descriptor_at, error_Z, half_box,
                  in_half, lbfgs_direction, loss, loss_grad, penalised_loss_grad, penalty, pool,
-                 pool_adjoint, pyramid, reconstruct_lbfgsb, soft_threshold,
+                 pool_adjoint, pyramid, reconstruct_adam, reconstruct_lbfgsb, soft_threshold,
                  soft_threshold_constants)
 
 build = _native.build

@@ -376,6 +376,37 @@ def lbfgs_direction(g: np.ndarray, s_hist: Sequence[np.ndarray], y_hist: Sequenc
     return -q.reshape(np.shape(g))
 
 
+def adam_step(x, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-7, lo=None, hi=None):
+    """One Adam update (Kingma & Ba, Alg. 1; the paper's optimizer, Appendix B) in FP64:
+    biased moments m, v, their bias corrections at step t >= 1, the step
+    lr * m_hat / (sqrt(v_hat) + eps), then projection onto [lo, hi] if given.
+    Returns (x, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    x = x - lr * m_hat / (np.sqrt(v_hat) + eps)
+    if lo is not None:
+        x = np.clip(x, lo, hi)
+    return x, m, v
+
+
+def reconstruct_adam(S_des, spec: Spec, phi0, iters, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-7,
+                     lo=0.0, hi=1.0, tol=0.0):
+    """Projected Adam on the oracle's (E, dE/dphi): start from clip(phi0), take up to
+    `iters` steps, stop once E <= tol.  Returns (phi, E_final, steps taken)."""
+    x = np.clip(np.asarray(phi0, np.float64), lo, hi)
+    m = np.zeros_like(x)
+    v = np.zeros_like(x)
+    E, g, _ = loss_grad(x, S_des, spec)
+    t = 0
+    while t < iters and E > tol:
+        t += 1
+        x, m, v = adam_step(x, g, m, v, t, lr, beta1, beta2, eps, lo, hi)
+        E, g, _ = loss_grad(x, S_des, spec)
+    return x, float(E), t
+
+
 def reconstruct_lbfgsb(S_des, spec: Spec, phi0, maxiter=100, maxcor=10, lo=0.0, hi=1.0):
     """Reference reconstruction: SciPy L-BFGS-B on the oracle's (E, dE/dphi) in FP64,
     bounds [lo, hi] on every voxel.  Returns (phi, E_final, n_iter, n_eval)."""

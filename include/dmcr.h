@@ -123,12 +123,23 @@ typedef struct {
     double kappa;
 } dmcr_bounds;
 
+/* Optimizer of dmcr_reconstruct and the solver slots.  LBFGS: batched projected
+ * L-BFGS with backtracking.  ADAM: the paper's optimizer (Appendix B; Kingma &
+ * Ba, Alg. 1) with projection onto the box after each step; one evaluation per
+ * iteration, no line search. */
+enum { DMCR_OPT_LBFGS = 0, DMCR_OPT_ADAM = 1 };
+
 typedef struct {
-    int32_t m;          /* L-BFGS history length (1..32)                       */
+    int32_t m;          /* L-BFGS history length (1..32; ignored by ADAM)      */
     int32_t max_iter;   /* iteration budget                                    */
-    int32_t max_ls;     /* evaluations per line search                        */
+    int32_t max_ls;     /* evaluations per line search (ignored by ADAM)       */
     double  tol_derr;   /* stop when E <= tol_derr                             */
     double  c1, c2;     /* Wolfe constants (sufficient decrease, curvature)    */
+    int32_t method;     /* DMCR_OPT_*                                          */
+    double  lr;         /* ADAM: step size (the paper: 1e-3), > 0              */
+    double  beta1;      /* ADAM: first-moment decay (0.9), in [0, 1)           */
+    double  beta2;      /* ADAM: second-moment decay (0.999), in [0, 1)        */
+    double  eps;        /* ADAM: denominator guard (1e-7), > 0                 */
 } dmcr_opt;
 
 typedef struct {

@@ -18,6 +18,11 @@
 // history); a pair (s, y) enters the history only if s'y > eps y'y.  A failed
 // line search clears that element's history; a failure that started from
 // steepest descent stops the element.
+//
+// Adam (the paper's optimizer, Appendix B; Kingma & Ba, Alg. 1): per element the
+// biased moments m, v (in the first history slot), bias corrections 1 - beta^t
+// at the element's own step count t, the step lr m_hat / (sqrt(v_hat) + eps),
+// then projection onto the box; one evaluation per iteration.
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -196,6 +201,34 @@ __global__ __launch_bounds__(kV) void k_accept(const int *acc, float *x, const f
     }
 }
 
+// Adam step of active elements: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// x -= lr (m / bc1) / (sqrt(v / bc2) + eps), clipped to [lo, hi] with projection;
+// bc1[b] = 1 - b1^t, bc2[b] = 1 - b2^t at the element's step t
+__global__ __launch_bounds__(kV) void k_adam(float *x, const float *g, float *mm, float *vv, const double *bc1,
+                                             const double *bc2, const int *active, int64_t n, float lr, float b1,
+                                             float b2, float eps, int project, float lo, float hi)
+{
+    const int64_t b = blockIdx.y;
+    if (!active[b]) return;
+    const float ic1 = (float)(1.0 / bc1[b]), ic2 = (float)(1.0 / bc2[b]);
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV) {
+        const int64_t j = b * n + i;
+        const float gi = g[j];
+        const float m = b1 * mm[j] + (1.f - b1) * gi;
+        const float v = b2 * vv[j] + (1.f - b2) * gi * gi;
+        mm[j] = m;
+        vv[j] = v;
+        float xv = x[j] - lr * (m * ic1) / (sqrtf(v * ic2) + eps);
+        if (project) xv = fminf(fmaxf(xv, lo), hi);
+        x[j] = xv;
+    }
+}
+
+__global__ __launch_bounds__(kV) void k_zero(float *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV) p[i] = 0.f;
+}
+
 // E^bc = sum_i t_i^2 with t = (x-hi)H(x-hi)/N + (lo-x)H(lo-x)/N, H(0) = 0 (per channel N)
 __global__ __launch_bounds__(kV) void k_pen_part(const float *x, int64_t n, double invN, float lo, float hi,
                                                  double *part, int nblk)
@@ -254,8 +287,9 @@ RLayout r_layout(const Plan &p, const dmcr_opt &o)
     r.g = take(Bn * 4);
     r.gt = take(Bn * 4);
     r.d = take(Bn * 4);
-    r.s = take((size_t)o.m * Bn * 4);
-    r.y = take((size_t)o.m * Bn * 4);
+    const int hist = (o.method == DMCR_OPT_ADAM) ? 1 : o.m;   // Adam keeps m, v in slot 0
+    r.s = take((size_t)hist * Bn * 4);
+    r.y = take((size_t)hist * Bn * 4);
     r.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 4 * kV - 1) / (4 * kV)));
     r.part = take((size_t)p.B * r.nblk * 8);
     r.dot1 = take(B8);
@@ -277,8 +311,11 @@ RLayout r_layout(const Plan &p, const dmcr_opt &o)
 
 bool opt_ok(const dmcr_opt *o)
 {
-    return o && o->m >= 1 && o->m <= 32 && o->max_iter >= 0 && o->max_ls >= 1 && o->c1 > 0 && o->c1 < 1 &&
-           std::isfinite(o->tol_derr);
+    if (!o || o->max_iter < 0 || !std::isfinite(o->tol_derr)) return false;
+    if (o->method == DMCR_OPT_ADAM)
+        return o->lr > 0 && std::isfinite(o->lr) && o->beta1 >= 0 && o->beta1 < 1 && o->beta2 >= 0 &&
+               o->beta2 < 1 && o->eps > 0 && std::isfinite(o->eps) && o->m >= 1 && o->m <= 32;
+    return o->method == DMCR_OPT_LBFGS && o->m >= 1 && o->m <= 32 && o->max_ls >= 1 && o->c1 > 0 && o->c1 < 1;
 }
 
 #define RT(expr)                                               \
@@ -354,6 +391,7 @@ struct Solver {
 
     dmcr_status start(float *x, const int *which, int nwhich, dmcr_slot *slots);
     dmcr_status iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int iterations);
+    dmcr_status iterate_adam(float *x, dmcr_slot *slots, int iterations);
 };
 
 // (Re)start the listed slots: clip (PROJECT), evaluate loss and gradient of each
@@ -383,6 +421,10 @@ dmcr_status Solver::start(float *x, const int *which, int nwhich, dmcr_slot *slo
                                hi);
         }
         hipLaunchKernelGGL(k_reset_one, dim3(1), dim3(64), 0, st, rho, gamma, m, B, b);
+        if (o.method == DMCR_OPT_ADAM) {   // fresh moments
+            hipLaunchKernelGGL(k_zero, dim3(vblocks(n)), dim3(kV), 0, st, S(0) + (int64_t)b * n, n);
+            hipLaunchKernelGGL(k_zero, dim3(vblocks(n)), dim3(kV), 0, st, Y(0) + (int64_t)b * n, n);
+        }
         RT(hipGetLastError());
         RT(hipMemcpyAsync(hE.data(), Ed + b, 8, hipMemcpyDeviceToHost, st));
         if (penalty) RT(hipMemcpyAsync(hEbc.data(), Ebcd + b, 8, hipMemcpyDeviceToHost, st));
@@ -403,9 +445,59 @@ dmcr_status Solver::start(float *x, const int *which, int nwhich, dmcr_slot *slo
     return DMCR_OK;
 }
 
+// Up to `iterations` Adam steps of every running slot.
+dmcr_status Solver::iterate_adam(float *x, dmcr_slot *slots, int iterations)
+{
+    float *g = at<float>(r.g);
+    double *Ed = at<double>(r.E), *Ebcd = at<double>(r.Ebc);
+    double *bc1 = at<double>(r.dot1), *bc2 = at<double>(r.dot2);
+    int *active = at<int>(r.active);
+    std::vector<double> hE(B), hEbc(B, 0.0), h1(B, 1.0), h2(B, 1.0);
+    std::vector<int> act(B);
+    auto running = [&](int b) { return slots[b].active && slots[b].status == DMCR_RUNNING; };
+    for (int it = 0; it < iterations; ++it) {
+        bool any = false;
+        for (int b = 0; b < B; ++b) {
+            act[b] = running(b);
+            any |= act[b] != 0;
+            const int t = slots[b].iters + 1;
+            h1[b] = 1.0 - std::pow(o.beta1, t);
+            h2[b] = 1.0 - std::pow(o.beta2, t);
+        }
+        if (!any) break;
+        RS(put(active, act));
+        RS(put(bc1, h1));
+        RS(put(bc2, h2));
+        hipLaunchKernelGGL(k_adam, vg, dim3(kV), 0, st, x, g, S(0), Y(0), bc1, bc2, active, n, (float)o.lr,
+                           (float)o.beta1, (float)o.beta2, (float)o.eps, (int)project, lo, hi);
+        RT(hipGetLastError());
+        RS(evaluate(x, Ed, g));
+        RS(fetch(Ed, hE));
+        if (penalty) RS(fetch(Ebcd, hEbc));
+        RT(hipStreamSynchronize(st));
+        for (int b = 0; b < B; ++b) {
+            if (!act[b]) continue;
+            dmcr_slot &sl = slots[b];
+            ++sl.iters;
+            ++sl.evals;
+            sl.E = hE[b];
+            sl.f = hE[b] + (penalty ? bd.kappa * hE[b] * hEbc[b] : 0.0);
+            if (!std::isfinite(sl.f))
+                sl.status = DMCR_ENONFINITE;
+            else if (sl.E <= o.tol_derr)
+                sl.status = DMCR_OK;
+            else if (sl.iters >= o.max_iter)
+                sl.status = DMCR_NOT_CONVERGED;
+        }
+    }
+    RT(hipStreamSynchronize(st));
+    return DMCR_OK;
+}
+
 // Up to `iterations` L-BFGS iterations of every running slot.
 dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int iterations)
 {
+    if (o.method == DMCR_OPT_ADAM) return iterate_adam(x, slots, iterations);
     float *xt = at<float>(r.xt), *g = at<float>(r.g), *gt = at<float>(r.gt), *d = at<float>(r.d);
     double *rho = at<double>(r.rho), *alpha = at<double>(r.alpha), *gamma = at<double>(r.gamma);
     double *coef = at<double>(r.coef), *dot1 = at<double>(r.dot1), *dot2 = at<double>(r.dot2);
@@ -601,7 +693,7 @@ dmcr_status dmcr_solver_iterate(const dmcr_spec *spec, int32_t batch, const doub
                                 const dmcr_bounds *bounds, const dmcr_opt *opt, float *phi, dmcr_slot *slots,
                                 dmcr_ring *ring, int32_t iterations, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    if (!slots || !ring || iterations < 0 || ring->count < 0 || ring->count > opt->m || ring->head < 0 ||
+    if (!slots || !ring || !opt || iterations < 0 || ring->count < 0 || ring->count > opt->m || ring->head < 0 ||
         ring->head >= opt->m)
         return DMCR_EINVAL;
     Plan p;

@@ -19,6 +19,7 @@ PATH_AUTO, PATH_FFT, PATH_DIRECT = 0, 1, 2
 DESC_S2, DESC_SBAR, DESC_STILDE = 0, 1, 2
 FLAG_RECOMPUTE = 1
 BOUNDS_NONE, BOUNDS_PROJECT, BOUNDS_PENALTY = 0, 1, 2
+OPT_LBFGS, OPT_ADAM = 0, 1
 MAX_LEVELS, MAX_CHANNELS, MAX_PAIRS = 8, 4, 10
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSUPPORTED", -4: "EDEVICE",
@@ -49,7 +50,9 @@ class c_bounds(ctypes.Structure):
 
 class c_opt(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("max_ls", ctypes.c_int32),
-                ("tol_derr", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double)]
+                ("tol_derr", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
+                ("method", ctypes.c_int32), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
 
 
 class c_slot(ctypes.Structure):
@@ -328,15 +331,23 @@ class Bounds:
 
 @dataclass
 class Opt:
+    """Optimizer settings (dmcr_opt): L-BFGS by default; method=OPT_ADAM selects Adam
+    with the paper's TensorFlow defaults lr 1e-3, betas 0.9 / 0.999, eps 1e-7."""
     m: int = 10
     max_iter: int = 100
     max_ls: int = 20
     tol_derr: float = 1e-4
     c1: float = 1e-4
     c2: float = 0.9
+    method: int = 0
+    lr: float = 1e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-7
 
     def c(self):
-        return c_opt(self.m, self.max_iter, self.max_ls, self.tol_derr, self.c1, self.c2)
+        return c_opt(self.m, self.max_iter, self.max_ls, self.tol_derr, self.c1, self.c2, self.method,
+                     self.lr, self.beta1, self.beta2, self.eps)
 
 
 def dmcr_reconstruct_workspace_size(spec: Spec, batch: int, opt: Opt) -> int:

@@ -41,6 +41,21 @@ def test_struct_sizes_match_header(dm):
     assert ctypes.sizeof(dm.c_spec) == 280
     assert dm.c_spec.alpha.offset == 272
     assert ctypes.sizeof(dm.c_result) == 32
+    # dmcr_opt: 3 x 4 + pad + 3 x 8 + method 4 + pad + 4 x 8 (lr, beta1, beta2, eps)
+    assert ctypes.sizeof(dm.c_opt) == 80
+    assert dm.c_opt.lr.offset == 48
+
+
+def test_adam_options_validated(dm):
+    spec = dm.Spec(shape=(32, 32), max_disp=(4,))
+    lb = dm.dmcr_reconstruct_workspace_size(spec, 2, dm.Opt(m=10))
+    ad = dm.dmcr_reconstruct_workspace_size(spec, 2, dm.Opt(m=10, method=dm.OPT_ADAM))
+    assert ad < lb   # Adam keeps two vectors per element, L-BFGS 2m
+    for kw in [dict(lr=0.0), dict(lr=float("nan")), dict(beta1=1.0), dict(beta2=-0.1), dict(eps=0.0)]:
+        with pytest.raises(dm.DmcrError):
+            dm.dmcr_reconstruct_workspace_size(spec, 1, dm.Opt(method=dm.OPT_ADAM, **kw))
+    with pytest.raises(dm.DmcrError):
+        dm.dmcr_reconstruct_workspace_size(spec, 1, dm.Opt(method=2))
 
 
 @pytest.mark.parametrize("shape,C,L,P,pairs", [

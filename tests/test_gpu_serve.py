@@ -16,13 +16,17 @@ def sv():
     return serve
 
 
-def test_alone_equals_in_the_mix(sv):
+@pytest.mark.parametrize("method", ["lbfgs", "adam"])
+def test_alone_equals_in_the_mix(sv, method):
     from paper_2103_09686_amd import dmcr
     cache = sv.TargetCache()
     shape = (128, 128)
     stream = [(0.0, shape, 2, "boolean", 11), (0.0, shape, 2, "grf", 12), (0.0, shape, 2, "boolean", 13),
               (0.0, shape, 2, "grf", 14)]
-    opt = dmcr.Opt(max_iter=60, tol_derr=1e-6)
+    if method == "lbfgs":
+        opt = dmcr.Opt(max_iter=60, tol_derr=1e-6)
+    else:
+        opt = dmcr.Opt(method=dmcr.OPT_ADAM, lr=1e-2, max_iter=60, tol_derr=1e-6)
     # alone: a group of one slot, one request
     ex1 = sv.GpuExecutor(opt=opt, max_slots=1, keep_fields=True)
     srv1 = sv.Server(ex1, budget_bytes=1 << 34, iters_per_tick=3, threads=1)

@@ -53,6 +53,11 @@ def lib():
         L.ora_sbar_adjoint_at.argtypes = ([ctypes.c_int] * 3 + [_dp, _dp, ctypes.c_int, _ip, _dp, _dp,
                                           ctypes.c_int, _ip, _dp, _dp])
         L.ora_sbar_adjoint_at.restype = None
+        L.ora_s3.argtypes = [ctypes.c_int] * 3 + [_dp, _ip, ctypes.c_int, _ip, _ip, ctypes.c_int, _dp, _dp]
+        L.ora_s3.restype = None
+        L.ora_s3_adjoint.argtypes = ([ctypes.c_int] * 3 + [_dp, _ip, ctypes.c_int, _ip, _ip, ctypes.c_int, _dp,
+                                     _dp, _dp])
+        L.ora_s3_adjoint.restype = None
         L.ora_num_threads.restype = ctypes.c_int
         L.ora_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -164,6 +169,35 @@ def sbar_adjoint_at(a, b, r, alpha, c, G, vox):
     lib().ora_sbar_adjoint_at(A.shape[0], A.shape[1], A.shape[2], _d(A), _d(B), R.shape[0], _i(R),
                               _d(co), _d(Gk), V.shape[0], _i(V), _d(ga), _d(gb))
     return ga, gb
+
+
+def s3(f, vecs, pa, pb, mode, alpha=10.0, c=(0.0, 0.0, 0.0)):
+    """Three-point correlation of one field over index pairs (pa[k], pb[k]) into the
+    displacement list vecs: mode 0 product form, mode 1 soft threshold."""
+    ndim = np.ndim(f)
+    F = _as3(f)
+    V = _r3(vecs, ndim)
+    A = np.ascontiguousarray(pa, dtype=np.int32)
+    Bi = np.ascontiguousarray(pb, dtype=np.int32)
+    S = np.zeros(len(A), np.float64)
+    co = _coef(alpha, c)
+    lib().ora_s3(F.shape[0], F.shape[1], F.shape[2], _d(F), _i(V), len(A), _i(A), _i(Bi), int(mode), _d(co), _d(S))
+    return S
+
+
+def s3_adjoint(f, vecs, pa, pb, mode, G, alpha=10.0, c=(0.0, 0.0, 0.0)):
+    """Gradient of sum_k G[k] S3_k with respect to the field."""
+    ndim = np.ndim(f)
+    F = _as3(f)
+    V = _r3(vecs, ndim)
+    A = np.ascontiguousarray(pa, dtype=np.int32)
+    Bi = np.ascontiguousarray(pb, dtype=np.int32)
+    Gk = np.ascontiguousarray(G, dtype=np.float64)
+    co = _coef(alpha, c)
+    g = np.zeros_like(F)
+    lib().ora_s3_adjoint(F.shape[0], F.shape[1], F.shape[2], _d(F), _i(V), len(A), _i(A), _i(Bi), int(mode),
+                         _d(co), _d(Gk), _d(g))
+    return g.reshape(np.shape(f))
 
 
 def num_threads():

@@ -245,3 +245,87 @@ void ora_sbar_adjoint_at(int n0, int n1, int n2, const double *a, const double *
         gb_v[m] = sb / (double)N;
     }
 }
+
+/*
+ * Three-point correlation of one phase (Sec. 3.2.2, eq. s3): the quadratic
+ * reduction of two realisations of the same start point x,
+ *     S3(r_a, r_b) = (1/N) sum_x e_a(x) e_b(x).
+ * mode 0 (product form, the exact three-point probability on binary fields):
+ *     e_a(x) e_b(x) is replaced by phi(x) phi(x + r_a) phi(x + r_b);
+ * mode 1 (soft threshold, Sec. 3.2.4): e_c(x) = f((phi(x) + phi(x + r_c)) / 2)
+ *     with the logistic f (coef = {alpha, c1, c2, c3}); e_0(x) = f(phi(x)).
+ * `vec` holds M displacement triples, `pa`/`pb` the K3 index pairs (a, b).
+ */
+static inline double s3_term(const double *f, int64_t x, int64_t xa, int64_t xb, int mode, const double *coef)
+{
+    if (mode == 0) return f[x] * f[xa] * f[xb];
+    return soft_f(0.5 * (f[x] + f[xa]), coef) * soft_f(0.5 * (f[x] + f[xb]), coef);
+}
+
+void ora_s3(int n0, int n1, int n2, const double *f, const int *vec, int K3, const int *pa, const int *pb,
+            int mode, const double *coef, double *S)
+{
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    int k;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (k = 0; k < K3; ++k) {
+        const int *a = vec + 3 * pa[k], *b = vec + 3 * pb[k];
+        double acc = 0.0;
+        for (int64_t i0 = 0; i0 < n0; ++i0)
+            for (int64_t i1 = 0; i1 < n1; ++i1)
+                for (int64_t i2 = 0; i2 < n2; ++i2) {
+                    const int64_t x = lin(i0, i1, i2, n1, n2);
+                    const int64_t xa = lin(wrap(i0 + a[0], n0), wrap(i1 + a[1], n1), wrap(i2 + a[2], n2), n1, n2);
+                    const int64_t xb = lin(wrap(i0 + b[0], n0), wrap(i1 + b[1], n1), wrap(i2 + b[2], n2), n1, n2);
+                    acc += s3_term(f, x, xa, xb, mode, coef);
+                }
+        S[k] = acc / (double)N;
+    }
+}
+
+/* Gradient of sum_k G[k] S3_k with respect to f, accumulated into g: every
+ * voxel y collects the derivative of each term in which it appears as the start
+ * x, as x + r_a or as x + r_b (terms where two roles coincide collect both). */
+void ora_s3_adjoint(int n0, int n1, int n2, const double *f, const int *vec, int K3, const int *pa,
+                    const int *pb, int mode, const double *coef, const double *G, double *g)
+{
+    const int64_t N = (int64_t)n0 * n1 * n2;
+    int64_t y;
+#pragma omp parallel for schedule(static)
+    for (y = 0; y < N; ++y) {
+        const int64_t i0 = y / ((int64_t)n1 * n2), i1 = (y / n2) % n1, i2 = y % n2;
+        double acc = 0.0;
+        for (int k = 0; k < K3; ++k) {
+            const int *a = vec + 3 * pa[k], *b = vec + 3 * pb[k];
+            /* the three start points x whose term reads f(y): x = y, y - r_a, y - r_b */
+            for (int role = 0; role < 3; ++role) {
+                const int *s = role == 0 ? NULL : (role == 1 ? a : b);
+                const int64_t j0 = s ? wrap(i0 - s[0], n0) : i0;
+                const int64_t j1 = s ? wrap(i1 - s[1], n1) : i1;
+                const int64_t j2 = s ? wrap(i2 - s[2], n2) : i2;
+                const int64_t x = lin(j0, j1, j2, n1, n2);
+                const int64_t xa = lin(wrap(j0 + a[0], n0), wrap(j1 + a[1], n1), wrap(j2 + a[2], n2), n1, n2);
+                const int64_t xb = lin(wrap(j0 + b[0], n0), wrap(j1 + b[1], n1), wrap(j2 + b[2], n2), n1, n2);
+                /* derivative of the term at x with respect to the factor(s) at position `role` */
+                double d = 0.0;
+                if (mode == 0) {
+                    if (role == 0) d = f[xa] * f[xb];
+                    if (role == 1) d = f[x] * f[xb];
+                    if (role == 2) d = f[x] * f[xa];
+                } else {
+                    const double ua = 0.5 * (f[x] + f[xa]), ub = 0.5 * (f[x] + f[xb]);
+                    const double ea = soft_f(ua, coef), eb = soft_f(ub, coef);
+                    const double sa = 1.0 / (1.0 + exp(-coef[0] * (ua + coef[2])));
+                    const double sb = 1.0 / (1.0 + exp(-coef[0] * (ub + coef[2])));
+                    const double da = 0.5 * coef[1] * coef[0] * sa * (1.0 - sa);   /* d e_a / d f(x) = d e_a / d f(x + r_a) */
+                    const double db = 0.5 * coef[1] * coef[0] * sb * (1.0 - sb);
+                    if (role == 0) d = da * eb + ea * db;
+                    if (role == 1) d = da * eb;
+                    if (role == 2) d = ea * db;
+                }
+                acc += G[k] * d;
+            }
+        }
+        g[y] += acc / (double)N;
+    }
+}

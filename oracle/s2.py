@@ -110,6 +110,7 @@ class Spec:
     pairs: Tuple[Tuple[int, int], ...] = ()
     descriptor: str = "s2"            # one of DESCRIPTORS
     alpha: float = 10.0               # soft-threshold slope (sbar, stilde)
+    s3_max_disp: int = 0              # > 0: three-point block of every channel, vectors in [-P3, P3]^d
 
     def __post_init__(self):
         self.shape = tuple(int(s) for s in self.shape)
@@ -129,6 +130,13 @@ class Spec:
                 if i not in autos or j not in autos:
                     raise ValueError("the Appendix A map of pair %s needs the auto pairs of both channels"
                                      % ((i, j),))
+            if self.s3_max_disp > 0:
+                for c in range(self.n_channels):
+                    if c not in autos:
+                        raise ValueError("the Appendix A map of S3 needs the auto pair of channel %d" % c)
+                for l in range(self.n_levels):
+                    if 2 * self.s3_P(l) > self.max_disp[l]:
+                        raise ValueError("the Appendix A map of S3 reads S2(r_a - r_b): needs 2 P3 <= P")
 
     @property
     def ndim(self):
@@ -141,19 +149,46 @@ class Spec:
         P = self.max_disp[l]
         return half_box(self.ndim, P) if pair[0] == pair[1] else box(self.ndim, P)
 
-    def layout(self):
-        """List of (level, pair, offset, count) in descriptor order."""
+    def s3_P(self, l: int) -> int:
+        return min(self.s3_max_disp, self.max_disp[l])
+
+    def s3_vecs(self, l: int) -> np.ndarray:
+        """The M displacements of the three-point block of level l (full box, lexicographic)."""
+        return box(self.ndim, self.s3_P(l))
+
+    def s3_index_pairs(self, l: int):
+        """(ia, ib) with ia <= ib, ia-major: the unordered vector pairs (S3 is symmetric)."""
+        M = len(self.s3_vecs(l))
+        return np.triu_indices(M)
+
+    def blocks(self):
+        """Every block in descriptor order: ('s2', level, pair, offset, count) for the
+        pairs, then ('s3', level, channel, offset, count) for the three-point blocks."""
         out, off = [], 0
         for l in range(self.n_levels):
             for p in self.pairs:
                 k = len(self.disp(l, p))
-                out.append((l, p, off, k))
+                out.append(("s2", l, p, off, k))
                 off += k
+            if self.s3_max_disp > 0:
+                M = len(self.s3_vecs(l))
+                for c in range(self.n_channels):
+                    k = M * (M + 1) // 2
+                    out.append(("s3", l, c, off, k))
+                    off += k
         return out
+
+    def layout(self):
+        """List of (level, pair, offset, count) of the two-point blocks, in descriptor order."""
+        return [(l, p, off, k) for (kind, l, p, off, k) in self.blocks() if kind == "s2"]
+
+    def s3_layout(self):
+        """List of (level, channel, offset, count) of the three-point blocks."""
+        return [(l, c, off, k) for (kind, l, c, off, k) in self.blocks() if kind == "s3"]
 
     @property
     def K(self) -> int:
-        return sum(e[3] for e in self.layout())
+        return sum(e[4] for e in self.blocks())
 
 
 # ----------------------------------------------------------------------------
@@ -206,8 +241,79 @@ def descriptor(phi: np.ndarray, spec: Spec) -> np.ndarray:
     out = np.zeros(spec.K, np.float64)
     for (l, (i, j), off, k) in spec.layout():
         out[off:off + k] = _pair_corr(lv[l][i], lv[l][j], spec.disp(l, (i, j)), spec)
+    for (l, c, off, k) in spec.s3_layout():
+        ia, ib = spec.s3_index_pairs(l)
+        out[off:off + k] = _native.s3(lv[l][c], spec.s3_vecs(l), ia, ib, *_s3_mode(spec))
     if spec.descriptor == "stilde":
         out = correct_sbar(out, spec)
+        out = correct_s3(out, spec)
+    return out
+
+
+def _s3_mode(spec: Spec):
+    """(mode, alpha, (c1, c2, c3)) of the three-point blocks: the product form with the
+    S2 descriptor, the soft-threshold realisations otherwise."""
+    if spec.descriptor == "s2":
+        return 0, 0.0, (0.0, 0.0, 0.0)
+    return 1, spec.alpha, soft_threshold_constants(spec.alpha)
+
+
+def _s2_index(spec: Spec, l: int, c: int, r) -> int:
+    """Descriptor index of S2_cc(r) at level l for any r with |r_i| <= P_l (point
+    symmetry maps r outside the half box to -r)."""
+    r = tuple(int(v) for v in r)
+    if not in_half(r):
+        r = tuple(-v for v in r)
+    (_, _, off, _) = [e for e in spec.layout() if e[0] == l and e[1] == (c, c)][0]
+    hb = half_box(spec.ndim, spec.max_disp[l])
+    return off + int(np.flatnonzero((hb == np.array(r)).all(axis=1))[0])
+
+
+def _s3_map_terms(spec: Spec, l: int, c: int):
+    """For each entry k of the (l, c) three-point block: a list of (coefficient, index)
+    such that S3~_k = coef_bar * Sbar3_k + sum coefficient * S2~[index], following
+    Appendix A eq. (s3rfroms3rbar) with h = f(1/2):
+      r_a = r_b, or one of them 0:  S2~ of the other (coef_bar = 0);
+      otherwise: (Sbar3 - h (S2(r_a) + S2(r_b)) - h^2 (S2(0) - S2(r_a) - S2(r_b) + S2(r_a - r_b))) / (1 - 2h)."""
+    h = float(soft_threshold(0.5, spec.alpha))
+    vecs = spec.s3_vecs(l)
+    ia, ib = spec.s3_index_pairs(l)
+    out = []
+    for a_i, b_i in zip(ia, ib):
+        a, b = vecs[a_i], vecs[b_i]
+        if a_i == b_i or not b.any():
+            out.append((0.0, [(1.0, _s2_index(spec, l, c, a))]))
+        elif not a.any():
+            out.append((0.0, [(1.0, _s2_index(spec, l, c, b))]))
+        else:
+            q = 1.0 / (1.0 - 2.0 * h)
+            out.append((q, [((-h + h * h) * q, _s2_index(spec, l, c, a)),
+                            ((-h + h * h) * q, _s2_index(spec, l, c, b)),
+                            (-h * h * q, _s2_index(spec, l, c, np.zeros_like(a))),
+                            (-h * h * q, _s2_index(spec, l, c, a - b))]))
+    return out
+
+
+def correct_s3(S: np.ndarray, spec: Spec) -> np.ndarray:
+    """Appendix A eq. (s3rfroms3rbar) on every three-point block; S holds the corrected
+    two-point blocks (correct_sbar) and the raw Sbar3 blocks."""
+    out = np.array(S, np.float64, copy=True)
+    for (l, c, off, k) in spec.s3_layout():
+        for e, (cb, terms) in enumerate(_s3_map_terms(spec, l, c)):
+            out[off + e] = cb * S[off + e] + sum(w * S[i] for (w, i) in terms)
+    return out
+
+
+def correct_s3_adjoint(G: np.ndarray, spec: Spec) -> np.ndarray:
+    """Transpose of correct_s3 (linear in S): the three-point cotangent scales by the
+    Sbar3 coefficient, and each S2~ entry a map reads collects coefficient x cotangent."""
+    G = np.asarray(G, np.float64)
+    out = np.array(G, copy=True)
+    for (l, c, off, k) in spec.s3_layout():
+        for e, (cb, terms) in enumerate(_s3_map_terms(spec, l, c)):
+            out[off + e] = cb * G[off + e]
+            for (w, i) in terms:
+                out[i] += w * G[off + e]
     return out
 
 
@@ -235,12 +341,15 @@ def correct_sbar(Sbar: np.ndarray, spec: Spec) -> np.ndarray:
 
 
 def correct_sbar_adjoint(G: np.ndarray, spec: Spec) -> np.ndarray:
-    """Transpose of correct_sbar (it is linear in Sbar): every entry is scaled by
-    1/(1 - 2F), and each channel's r = 0 auto entry also collects
-    -F/(1 - 2F) times the cotangent of every entry whose map reads it."""
+    """Transpose of correct_sbar (it is linear in Sbar): every two-point entry is
+    scaled by 1/(1 - 2F), and each channel's r = 0 auto entry also collects
+    -F/(1 - 2F) times the cotangent of every entry whose map reads it; three-point
+    entries pass through unchanged."""
     F = _f_half_sq(spec)
     G = np.asarray(G, np.float64)
-    out = G / (1.0 - 2.0 * F)
+    out = np.array(G, copy=True)
+    for (_, _, off, k) in spec.layout():
+        out[off:off + k] = G[off:off + k] / (1.0 - 2.0 * F)
     for l in range(spec.n_levels):
         lay = [e for e in spec.layout() if e[0] == l]
         auto_off = {i: off for (_, (i, j), off, k) in lay if i == j}
@@ -253,7 +362,7 @@ def correct_sbar_adjoint(G: np.ndarray, spec: Spec) -> np.ndarray:
 
 def level_weights_per_entry(spec: Spec) -> np.ndarray:
     w = np.zeros(spec.K, np.float64)
-    for (l, _, off, k) in spec.layout():
+    for (_, l, _, off, k) in spec.blocks():
         w[off:off + k] = spec.level_weight[l]
     return w
 
@@ -283,13 +392,17 @@ def _pair_adjoint(a, b, r, G, spec: Spec):
 def adjoint(phi: np.ndarray, G: np.ndarray, spec: Spec) -> np.ndarray:
     """d/dphi of sum_k G[k] S[k] (all levels, all pairs), shape of phi."""
     if spec.descriptor == "stilde":
-        G = correct_sbar_adjoint(G, spec)
+        G = correct_sbar_adjoint(correct_s3_adjoint(G, spec), spec)
     lv = pyramid(phi, spec.n_levels)
     grads = [np.zeros_like(f) for f in lv]
     for (l, (i, j), off, k) in spec.layout():
         ga, gb = _pair_adjoint(lv[l][i], lv[l][j], spec.disp(l, (i, j)), G[off:off + k], spec)
         grads[l][i] += ga
         grads[l][j] += gb
+    for (l, c, off, k) in spec.s3_layout():
+        ia, ib = spec.s3_index_pairs(l)
+        mode, alpha, cc = _s3_mode(spec)
+        grads[l][c] += _native.s3_adjoint(lv[l][c], spec.s3_vecs(l), ia, ib, mode, G[off:off + k], alpha, cc)
     acc = grads[-1]
     for l in range(spec.n_levels - 2, -1, -1):
         acc = grads[l] + pool_adjoint(acc)
@@ -310,8 +423,8 @@ def descriptor_at(phi: np.ndarray, spec: Spec, level: int, pair, r: np.ndarray) 
 
 def adjoint_at_single_level(phi: np.ndarray, G: np.ndarray, spec: Spec, vox: np.ndarray) -> np.ndarray:
     """Gradient at listed finest-level voxels for a single-level spec: [C][nv]."""
-    if spec.n_levels != 1:
-        raise ValueError("sampled adjoint is defined here for one level only")
+    if spec.n_levels != 1 or spec.s3_max_disp > 0:
+        raise ValueError("sampled adjoint is defined here for one level of two-point blocks only")
     if spec.descriptor == "stilde":
         G = correct_sbar_adjoint(G, spec)
     out = np.zeros((spec.n_channels, len(vox)), np.float64)

@@ -39,7 +39,16 @@ WORKLOADS = {
     "2d256sbar": dict(desc="2D 256^2 two-phase, soft-threshold descriptor Sbar (alpha=10), P=31, "
                            "3 levels (256/128/64), direct path",
                       shape=(256, 256), C=1, L=3, P=31, recompute=False, batch=1, descriptor=1),
+    "2d256s3": dict(desc="2D 256^2 two-phase, S2 (P=31, FFT) + three-point S3 (P3=4: 81 vectors, 3321 pairs), "
+                         "3 levels (256/128/64), batch 8",
+                    shape=(256, 256), C=1, L=3, P=31, recompute=False, batch=8, s3=4),
 }
+
+# Three-point blocks are dense FP32 contractions done with FMA instructions:
+# the Gram product of the forward (N K3 multiply-adds, product form one more
+# multiply) and the M x M cotangent product of the adjoint (N M^2 multiply-adds).
+# Peak: 256 CUs * 4 SIMDs * 16 lanes * 2 flops * 2.4 GHz = 78.6 TFLOP/s (no packed FP32).
+FMA_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 # Soft-threshold pair terms are bound by FP32 vector issue, not HBM.  A wave64
 # FP32 instruction takes 4 cycles of one 16-lane SIMD (packed FP32 is not used),
@@ -244,11 +253,33 @@ def cpu_baseline(phi64, spec_kw, target_seconds):
         Nl = N >> (d * l)
         frac = (Nl / N)
         t_full += (t_fwd / k_s) * k2 * frac + (t_adj / n_s) * Nl * (k2 / k)
+    sample = ("%d of %d displacements (all %d voxels) forward + %d voxels (all %d displacements) "
+              "adjoint of level 0, pair %s; scaled to all levels and pairs by N_l*K_lp"
+              % (k_s, len(rs), N, n_s, len(rs), pair))
+    P3 = spec_kw.get("s3", 0)
+    if P3 > 0:
+        # three-point blocks: forward and adjoint over all voxels for a sample of
+        # the vector pairs, scaled by pairs and by N_l
+        mode, alpha, cc = (0, 0.0, (0.0, 0.0, 0.0)) if kind == "s2" else \
+            (1, ospec.alpha, oracle.soft_threshold_constants(ospec.alpha))
+        vecs = oracle.box(d, min(P3, ospec.max_disp[0]))
+        ia, ib = np.triu_indices(len(vecs))
+        ks = min(len(ia), 64)
+        sel = rng.choice(len(ia), ks, replace=False)
+        t0 = time.perf_counter()
+        oracle._native.s3(lv[0][0], vecs, ia[sel], ib[sel], mode, alpha, cc)
+        t3f = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle._native.s3_adjoint(lv[0][0], vecs, ia[sel], ib[sel], mode, np.ones(ks), alpha, cc)
+        t3a = time.perf_counter() - t0
+        for l in range(L):
+            Nl = N >> (d * l)
+            M3 = (2 * min(P3, ospec.max_disp[l]) + 1) ** d
+            t_full += C * (t3f + t3a) / ks * (M3 * (M3 + 1) // 2) * (Nl / N)
+        sample += "; three-point: %d of %d pairs forward and adjoint over all voxels, scaled by pairs and N_l" % (
+            ks, len(ia))
     return dict(value=N / t_full, unit="voxel·it/s", cores=oracle._native.num_threads(), kind="oracle",
-                sample="%d of %d displacements (all %d voxels) forward + %d voxels (all %d displacements) "
-                       "adjoint of level 0, pair %s; scaled to all levels and pairs by N_l*K_lp"
-                       % (k_s, len(rs), N, n_s, len(rs), pair),
-                seconds=t_fwd + t_adj)
+                sample=sample, seconds=t_fwd + t_adj)
 
 
 def main():
@@ -271,7 +302,7 @@ def main():
     shape, C, L, P, B = wl["shape"], wl["C"], wl["L"], wl["P"], wl["batch"]
     flags = dmcr.FLAG_RECOMPUTE if wl["recompute"] else 0
     desc = wl.get("descriptor", dmcr.DESC_S2)
-    spec = dmcr.make_spec(shape, C, L, P, flags=flags, descriptor=desc)
+    spec = dmcr.make_spec(shape, C, L, P, flags=flags, descriptor=desc, s3_max_disp=wl.get("s3", 0))
     K = dmcr.dmcr_descriptor_size(spec)
     N = int(np.prod(shape))
 
@@ -351,6 +382,22 @@ def main():
         roofline = dict(bound="alu", kernel=dom["name"], achieved=round(achieved, 1), peak=round(peak, 1),
                         unit="Gterm/s", frac=round(achieved / peak, 4), traffic=None,
                         avg_us=round(dom["avg_us"], 2), terms_per_launch=per_launch)
+    elif dom["name"].startswith(("s3_fwd", "s3_adj_terms")):
+        d = len(shape)
+        flops = 0.0
+        for l in range(L):
+            Nl = N >> (d * l)
+            P3 = min(spec.s3_max_disp, spec.max_disp[l])
+            M = (2 * P3 + 1) ** d
+            if dom["name"].startswith("s3_fwd"):
+                flops += B * C * Nl * (M * (M + 1) // 2) * (2 if desc else 3)
+            else:
+                flops += B * C * Nl * M * M * 2
+        per_launch = flops / L
+        achieved = per_launch / (dom["avg_us"] * 1e-6) / 1e12
+        roofline = dict(bound="alu", kernel=dom["name"], achieved=round(achieved, 2), peak=round(FMA_PEAK_TFLOPS, 1),
+                        unit="TFLOP/s", frac=round(achieved / FMA_PEAK_TFLOPS, 4), traffic=None,
+                        avg_us=round(dom["avg_us"], 2), flops_per_launch=per_launch)
     else:
         roofline = dict(bound="hbm", kernel=dom["name"], achieved=round(dom["GBps"], 1), peak=HBM_PEAK_GBS,
                         unit="GB/s", frac=round(dom["GBps"] / HBM_PEAK_GBS, 4),
@@ -362,7 +409,7 @@ def main():
                          achieved_GBps=round(total_bytes / (ms * 1e-3) / 1e9, 1),
                          frac=round(total_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                          kernel_ms_sum=round(prof_ms, 4))
-    if roofline["bound"] == "alu":
+    if roofline["bound"] == "alu" and roofline["unit"] == "Gterm/s":
         # the whole step against FP32 issue: every soft term at its slot cost
         slots = sum(terms[k] * SOFT_SLOTS[k] for k in terms)
         step_roofline = dict(bound="alu", terms_per_step=sum(terms.values()), issue_slots_per_step=slots,
@@ -374,14 +421,14 @@ def main():
                vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload=wl["desc"], shape=list(shape), channels=C, levels=L,
                            max_disp=list(spec.max_disp), K=K, batch=B, path="direct" if desc else "fft",
-                           descriptor=["s2", "sbar", "stilde"][desc],
+                           descriptor=["s2", "sbar", "stilde"][desc], s3_max_disp=spec.s3_max_disp,
                            recompute=wl["recompute"], parallelism="single GPU"),
                roofline=roofline, step_roofline=step_roofline)
     if not args.no_serve and args.workload == "3d256":
         out["serving"] = serving(args.requests, args.rate, args.compare)
     if not args.no_cpu_baseline:
         phi64 = phi_h[0].astype(np.float64)
-        cb = cpu_baseline(phi64, dict(shape=shape, P=P, L=L, descriptor=desc), args.cpu_seconds)
+        cb = cpu_baseline(phi64, dict(shape=shape, P=P, L=L, descriptor=desc, s3=wl.get("s3", 0)), args.cpu_seconds)
         out["cpu_baseline"] = dict(value=cb["value"], unit=cb["unit"], cores=cb["cores"], kind=cb["kind"],
                                    sample=cb["sample"])
     print(json.dumps(out), flush=True)

@@ -88,6 +88,20 @@ enum { DMCR_PATH_AUTO = 0, DMCR_PATH_FFT = 1, DMCR_PATH_DIRECT = 2 };
  * convolution theorem does not apply. */
 enum { DMCR_DESC_S2 = 0, DMCR_DESC_SBAR = 1, DMCR_DESC_STILDE = 2 };
 
+/* Three-point correlations (Sec. 3.2.2, eq. s3), spec.s3_max_disp = P3 > 0.  Each
+ * level l appends, after its two-point blocks, one block per channel c holding
+ *     S3_c(r_a, r_b) = (1/N) sum_x e_a(x) e_b(x)
+ * for every unordered pair r_a <= r_b (index order) of the M = (2 P3_l + 1)^d
+ * vectors of [-P3_l, P3_l]^d in lexicographic order (axis 0 slowest), P3_l =
+ * min(P3, P_l); the block has M (M + 1) / 2 entries, r_a-major.  The realisation
+ * product e_a e_b is phi(x) phi(x + r_a) phi(x + r_b) with DMCR_DESC_S2 (the exact
+ * three-point probability on binary fields) and f(u_a) f(u_b), u_c = (phi(x) +
+ * phi(x + r_c)) / 2, with the soft-threshold descriptors; STILDE maps it back
+ * by Appendix A, eq. (s3rfroms3rbar), from the mapped two-point values, which
+ * needs 2 P3_l <= P_l and the auto pair of every channel.  Evaluated by
+ * dedicated kernels on every path; larger vector sets (M > 361: 2-D P3 > 9,
+ * 3-D P3 > 3) return DMCR_EUNSUPPORTED. */
+
 /* spec.flags */
 enum {
     DMCR_FLAG_RECOMPUTE = 1  /* dmcr_loss_grad recomputes the forward spectra in the
@@ -107,7 +121,8 @@ typedef struct {
     int32_t path;                          /* DMCR_PATH_*                             */
     int32_t flags;                         /* DMCR_FLAG_*                             */
     int32_t descriptor;                    /* DMCR_DESC_*                             */
-    int32_t reserved;                      /* must be 0                               */
+    int32_t s3_max_disp;                   /* P3 > 0 appends a three-point block per
+                                              channel and level (see below); 0 = none */
     double  alpha;                         /* soft-threshold slope (SBAR, STILDE);
                                               0 selects the paper's 10                */
 } dmcr_spec;
@@ -153,8 +168,10 @@ typedef struct {
 /* Number of descriptor entries K (all levels and pairs); < 0: dmcr_status. */
 int64_t dmcr_descriptor_size(const dmcr_spec *spec);
 
-/* Offsets of each (level, pair) block in descriptor order: writes
- * n_levels * n_pairs + 1 values (the last one is K) to host array `offsets`. */
+/* Offsets of every block in descriptor order: per level, each pair's two-point
+ * block, then (s3_max_disp > 0) each channel's three-point block; writes
+ * n_levels * (n_pairs + (s3_max_disp > 0 ? n_channels : 0)) + 1 values (the last
+ * one is K) to host array `offsets`. */
 dmcr_status dmcr_descriptor_offsets(const dmcr_spec *spec, int64_t *offsets);
 
 /* Workspace bytes needed by every call below for this spec and batch size. */

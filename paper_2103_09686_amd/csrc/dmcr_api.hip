@@ -74,8 +74,9 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
     if (s->path < DMCR_PATH_AUTO || s->path > DMCR_PATH_DIRECT) return DMCR_EINVAL;
     // descriptor kind and soft-threshold constants (Sec. 3.2.4): the inflection
     // condition f''(0.75) = 0 gives c2 = -0.75, then f(0) = 0 and f(1) = 1 fix c1, c3
-    if (s->descriptor < DMCR_DESC_S2 || s->descriptor > DMCR_DESC_STILDE || s->reserved != 0) return DMCR_EINVAL;
+    if (s->descriptor < DMCR_DESC_S2 || s->descriptor > DMCR_DESC_STILDE || s->s3_max_disp < 0) return DMCR_EINVAL;
     p.desc = s->descriptor;
+    p.s3 = s->s3_max_disp > 0;
     if (p.desc != DMCR_DESC_S2) {
         p.alpha = (s->alpha == 0.0) ? 10.0 : s->alpha;
         if (!(p.alpha > 0.0) || !std::isfinite(p.alpha)) return DMCR_EINVAL;
@@ -86,6 +87,7 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
         p.c1 = 1.0 / (hi - lo);
         p.c3 = -p.c1 * lo;
         const double fh = p.c1 * sig(p.alpha * (0.5 + p.c2)) + p.c3;
+        p.fh = fh;
         p.F = fh * fh;
     }
     // pairs
@@ -109,13 +111,18 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
         }
     }
     if (p.desc == DMCR_DESC_STILDE) {
-        // the map of pair (i, j) reads the r = 0 entries of the auto pairs (i, i) and (j, j)
+        // the map of pair (i, j) reads the r = 0 entries of the auto pairs (i, i) and
+        // (j, j); the three-point map reads the auto pair of every channel
+        auto has_auto = [&](int c) {
+            for (int r = 0; r < p.npairs; ++r)
+                if (p.pi[r] == c && p.pj[r] == c) return true;
+            return false;
+        };
         for (int q = 0; q < p.npairs; ++q)
-            for (int c : {p.pi[q], p.pj[q]}) {
-                bool found = false;
-                for (int r = 0; r < p.npairs; ++r) found |= (p.pi[r] == c && p.pj[r] == c);
-                if (!found) return DMCR_EINVAL;
-            }
+            if (!has_auto(p.pi[q]) || !has_auto(p.pj[q])) return DMCR_EINVAL;
+        if (p.s3)
+            for (int c = 0; c < p.C; ++c)
+                if (!has_auto(c)) return DMCR_EINVAL;
     }
     // levels
     int64_t off = 0;
@@ -146,6 +153,16 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
             off += L.cnt[q];
             lvlK += L.cnt[q];
         }
+        if (p.s3) {
+            L.s3P = std::min(s->s3_max_disp, L.P);
+            if (p.desc == DMCR_DESC_STILDE && 2 * L.s3P > L.P) return DMCR_EINVAL;  // map reads S2(r_a - r_b)
+            L.s3M = 1;
+            for (int a = 0; a < p.ndim; ++a) L.s3M *= 2 * L.s3P + 1;
+            L.s3K = (int64_t)L.s3M * (L.s3M + 1) / 2;
+            L.s3off = off;
+            off += p.C * L.s3K;
+            lvlK += p.C * L.s3K;
+        }
         p.Z += p.w[l] * p.w[l] * (double)lvlK;
     }
     p.lvl_off[p.L] = off;
@@ -173,6 +190,12 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
             L.n_tiles = (L.N / ((int64_t)tile[0] * tile[1] * tile[2]));
         }
     }
+    if (p.s3)
+        for (int l = 0; l < p.L; ++l) {
+            LevelPlan &L = p.lv[l];
+            if (!s3_supported(p, l, &L.s3VB, &L.s3VBa)) return DMCR_EUNSUPPORTED;
+            L.s3chunks = L.N / L.s3VB;
+        }
     // workspace
     Carver cv;
     const int C = p.C;
@@ -205,6 +228,14 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
             L.part = cv.take((size_t)B * p.npairs * L.n_tiles * kmax * sizeof(float));
         }
     }
+    if (p.s3)
+        for (int l = 0; l < p.L; ++l) {
+            LevelPlan &L = p.lv[l];
+            L.s3part = cv.take((size_t)B * C * L.s3chunks * L.s3K * sizeof(float));
+            L.s3Q = cv.take((size_t)B * C * L.s3M * L.N * sizeof(float));
+            L.s3G = cv.take((size_t)B * C * L.s3M * ((L.s3M + 3) / 4 * 4) * sizeof(float));
+            if (p.desc == DMCR_DESC_S2) L.s3R = cv.take((size_t)B * C * L.s3M * L.N * sizeof(float));
+        }
     p.S = cv.take((size_t)B * p.K * sizeof(float));
     p.G = cv.take((size_t)B * p.K * sizeof(float));
     p.err_chunks = std::max<int64_t>(1, std::min<int64_t>(8192, (p.K + 511) / 512));
@@ -338,10 +369,14 @@ hipError_t run_forward(const Plan &p, const float *phi, float *S, const Ws &ws, 
                 ? fft_forward_level(p, l, f, S, ws, sc.lane(l), x_free ? x_free[l] : nullptr)
                 : direct_forward_level(p, l, f, S, ws, sc.lane(l));
         if (e != hipSuccess) return e;
+        if (p.s3 && (e = s3_forward_level(p, l, f, S, ws, sc.lane(l))) != hipSuccess) return e;
     }
     for (int l = 1; l < p.L; ++l)
         if ((e = sc.join(sc.main, sc.lane(l))) != hipSuccess) return e;
-    if (p.desc == DMCR_DESC_STILDE) return launch_stilde(p, S, sc.main);
+    if (p.desc == DMCR_DESC_STILDE) {
+        if ((e = launch_stilde(p, S, sc.main)) != hipSuccess) return e;
+        if (p.s3) return launch_s3_map(p, S, sc.main);
+    }
     return hipSuccess;
 }
 
@@ -368,6 +403,7 @@ hipError_t run_adjoint(const Plan &p, const float *phi, const float *G, float *g
             e = direct_adjoint_level(p, l, f, G, g, ws, sc.lane(l));
         }
         if (e != hipSuccess) return e;
+        if (p.s3 && (e = s3_adjoint_level(p, l, f, G, g, ws, sc.lane(l))) != hipSuccess) return e;
     }
     for (int l = p.L - 1; l >= 0; --l) {
         if ((e = sc.join(sc.main, sc.lane(l))) != hipSuccess) return e;
@@ -401,7 +437,10 @@ dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St
     // recompute uses side lane 0), so the final error sum runs there
     hipStream_t fin = (sc.multi && p.L == 1) ? sc.ln->side[1] : st;
     DMCR_TRY(launch_error(p, S, St, E, G, w, st, fin, fin != st ? sc.ln->event() : nullptr));
-    if (p.desc == DMCR_DESC_STILDE) DMCR_TRY(launch_stilde_adjoint(p, G, G, st));
+    if (p.desc == DMCR_DESC_STILDE) {
+        if (p.s3) DMCR_TRY(launch_s3_map_adjoint(p, G, st));
+        DMCR_TRY(launch_stilde_adjoint(p, G, G, st));
+    }
     DMCR_TRY(run_adjoint(p, phi, G, grad, keep, w, sc, xf));
     return dev(sc.join(st, fin));
 }
@@ -426,8 +465,11 @@ dmcr_status dmcr_descriptor_offsets(const dmcr_spec *spec, int64_t *offsets)
     const dmcr_status s = make_plan(spec, 1, &p);
     if (s != DMCR_OK) return s;
     int i = 0;
-    for (int l = 0; l < p.L; ++l)
+    for (int l = 0; l < p.L; ++l) {
         for (int q = 0; q < p.npairs; ++q) offsets[i++] = p.lv[l].off[q];
+        if (p.s3)
+            for (int c = 0; c < p.C; ++c) offsets[i++] = p.lv[l].s3off + c * p.lv[l].s3K;
+    }
     offsets[i] = p.K;
     return DMCR_OK;
 }
@@ -487,7 +529,13 @@ dmcr_status dmcr_descriptor_adjoint(const dmcr_spec *spec, int32_t batch, const 
     DMCR_TRY(run_pyramid(p, phi, w, stream));
     if (p.desc == DMCR_DESC_STILDE) {
         float *G = w.at<float>(p.G);
-        DMCR_TRY(launch_stilde_adjoint(p, dS, G, stream));
+        if (p.s3) {
+            DMCR_TRY(hipMemcpyAsync(G, dS, (size_t)p.B * p.K * sizeof(float), hipMemcpyDeviceToDevice, stream));
+            DMCR_TRY(launch_s3_map_adjoint(p, G, stream));
+            DMCR_TRY(launch_stilde_adjoint(p, G, G, stream));
+        } else {
+            DMCR_TRY(launch_stilde_adjoint(p, dS, G, stream));
+        }
         dS = G;
     }
     return dev(run_adjoint(p, phi, dS, grad, false, w, sc));

@@ -46,12 +46,24 @@ struct LevelPlan {
     size_t part;       // DIRECT: per-tile partial sums
     int64_t n_tiles;   // DIRECT: tiles per field
     int tile[3];       // DIRECT: tile edge per axis
+    // three-point blocks (spec.s3_max_disp > 0)
+    int s3P;           // P3 of this level (0: no block)
+    int s3M;           // vectors (2 P3 + 1)^d
+    int64_t s3K;       // entries per channel block, M (M + 1) / 2
+    int64_t s3off;     // descriptor offset of channel 0's block (channel c at s3off + c s3K)
+    int s3VB, s3VBa;   // voxels per block of the forward and of the adjoint
+    int64_t s3chunks;  // forward blocks per field and channel (N / s3VB)
+    size_t s3part;     // [B][C][s3chunks][s3K] float partial sums
+    size_t s3Q, s3R;   // adjoint: [B][C][M][N] float per-vector terms (R: product form only)
+    size_t s3G;        // adjoint: [B][C][M][Mp] full symmetric cotangent (Mp = M rounded up to 4)
 };
 
 struct Plan {
     int desc;          // DMCR_DESC_*
     double alpha, c1, c2, c3;   // soft threshold f(u) = c1 / (1 + exp(-alpha (u + c2))) + c3
     double F;          // f(1/2)^2 (Appendix A)
+    double fh;         // f(1/2)
+    int s3;            // three-point blocks present
     int ndim;
     int shape[3];
     int C;
@@ -125,6 +137,17 @@ hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0
 // on S [B][K], and its transpose from G_in to G_out (may be the same array).
 hipError_t launch_stilde(const Plan &p, float *S, hipStream_t st);
 hipError_t launch_stilde_adjoint(const Plan &p, const float *G_in, float *G_out, hipStream_t st);
+
+// Three-point blocks of level l: forward into S, adjoint added into grad (the
+// level gradient written by the two-point adjoint).  The Appendix A map of the
+// three-point blocks (STILDE) in place on S, and its transpose in place on G
+// (run before launch_stilde_adjoint; it adds into the two-point cotangents).
+bool s3_supported(const Plan &p, int l, int *VB, int *VBa);
+hipError_t s3_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws, hipStream_t st);
+hipError_t s3_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad, const Ws &ws,
+                            hipStream_t st);
+hipError_t launch_s3_map(const Plan &p, float *S, hipStream_t st);
+hipError_t launch_s3_map_adjoint(const Plan &p, float *G, hipStream_t st);
 
 // E and the cotangent G from S.  G is ready on st; with st_final (and the
 // event parts_done) the final sum into E runs on st_final instead, off the

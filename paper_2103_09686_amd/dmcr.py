@@ -40,7 +40,7 @@ class c_spec(ctypes.Structure):
                 ("level_weight", ctypes.c_double * MAX_LEVELS),
                 ("n_pairs", ctypes.c_int32), ("pairs", ctypes.c_int32 * 32),
                 ("path", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("descriptor", ctypes.c_int32), ("reserved", ctypes.c_int32), ("alpha", ctypes.c_double)]
+                ("descriptor", ctypes.c_int32), ("s3_max_disp", ctypes.c_int32), ("alpha", ctypes.c_double)]
 
 
 class c_bounds(ctypes.Structure):
@@ -74,7 +74,8 @@ class c_result(ctypes.Structure):
 class Spec:
     """One multigrid descriptor: shape of the finest level, channels, levels,
     per-level maximum displacement P_l, level weights, pairs, path, flags,
-    descriptor kind (DESC_*) and soft-threshold slope alpha (0: the paper's 10)."""
+    descriptor kind (DESC_*), soft-threshold slope alpha (0: the paper's 10) and
+    the three-point range P3 (0: no three-point blocks)."""
     shape: Tuple[int, ...]
     n_channels: int = 1
     n_levels: int = 1
@@ -85,6 +86,7 @@ class Spec:
     flags: int = 0
     descriptor: int = DESC_S2
     alpha: float = 0.0
+    s3_max_disp: int = 0
 
     def __post_init__(self):
         self.shape = tuple(int(s) for s in self.shape)
@@ -118,7 +120,7 @@ class Spec:
         s.path = self.path
         s.flags = self.flags
         s.descriptor = self.descriptor
-        s.reserved = 0
+        s.s3_max_disp = self.s3_max_disp
         s.alpha = self.alpha
         return s
 
@@ -206,7 +208,7 @@ def dmcr_descriptor_size(spec: Spec) -> int:
 
 def dmcr_descriptor_offsets(spec: Spec):
     s = spec.c()
-    n = spec.n_levels * len(spec.pairs) + 1
+    n = spec.n_levels * (len(spec.pairs) + (spec.n_channels if spec.s3_max_disp > 0 else 0)) + 1
     out = (ctypes.c_int64 * n)()
     _check("dmcr_descriptor_offsets", lib().dmcr_descriptor_offsets(ctypes.byref(s), out))
     return list(out)

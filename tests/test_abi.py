@@ -125,3 +125,16 @@ def test_soft_descriptor_validation(dm):
         with pytest.raises(dm.DmcrError) as ei:
             dm.dmcr_descriptor_size(dm.Spec(**kw, **base))
         assert ei.value.code == code
+
+
+def test_three_point_validation(dm, ora):
+    ok = dm.Spec(shape=(64, 64), max_disp=(8,), s3_max_disp=4)
+    assert dm.dmcr_descriptor_size(ok) == ora.Spec(shape=(64, 64), max_disp=(8,), s3_max_disp=4).K
+    bad = [(dict(shape=(64, 64), max_disp=(12,), s3_max_disp=10), -3),       # more than 361 vectors
+           (dict(shape=(32, 32, 32), max_disp=(4,), s3_max_disp=4), -3),
+           (dict(shape=(64, 64), max_disp=(5,), s3_max_disp=3, descriptor=2), -1),   # S~3 needs 2 P3 <= P
+           (dict(shape=(64, 64), max_disp=(8,), s3_max_disp=-1), -1)]
+    for kw, code in bad:
+        with pytest.raises(dm.DmcrError) as ei:
+            dm.dmcr_descriptor_size(dm.Spec(**kw))
+        assert ei.value.code == code, kw

@@ -221,6 +221,23 @@ dmcr_status dmcr_reconstruct(const dmcr_spec *spec, int32_t batch, const double 
                              const dmcr_bounds *bounds, const dmcr_opt *opt, float *phi_inout,
                              dmcr_result *results, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Sequential coarse-to-fine reconstruction: the level-by-level multigrid
+ * practice that Sec. 3.3 contrasts with its simultaneous scheme, for comparison.
+ * The start field is mean-pooled to the coarsest level; each level l, coarsest
+ * first, is reconstructed alone (the single-level spec of level l, weight 1)
+ * against the level-l slice of the multigrid target S_target ([B][K], device),
+ * with up to opt->max_iter iterations; its result, upsampled by nearest
+ * neighbour, starts level l - 1.  phi_inout receives the finest result.
+ * results[b]: final_E is the multigrid error of the result against the whole
+ * target, iters and evals are summed over the levels (evals includes the final
+ * evaluation); why is DMCR_OK if final_E <= tol_derr.  Workspace:
+ * dmcr_reconstruct_c2f_workspace_size.  Blocking, like dmcr_reconstruct. */
+dmcr_status dmcr_reconstruct_c2f_workspace_size(const dmcr_spec *spec, int32_t batch, const dmcr_opt *opt,
+                                                size_t *bytes);
+dmcr_status dmcr_reconstruct_coarse_to_fine(const dmcr_spec *spec, int32_t batch, const double *S_target,
+                                            const dmcr_bounds *bounds, const dmcr_opt *opt, float *phi_inout,
+                                            dmcr_result *results, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Kernel timing (diagnostics).  dmcr_profile_start() clears the table and
  * makes every later launch record a HIP event pair on its own stream, with
  * the launch's algorithmic bytes (inputs read once plus outputs written

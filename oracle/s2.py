@@ -520,6 +520,44 @@ def reconstruct_adam(S_des, spec: Spec, phi0, iters, lr=1e-3, beta1=0.9, beta2=0
     return x, float(E), t
 
 
+def level_spec(spec: Spec, l: int) -> Spec:
+    """The single-level spec of level l (its grid, P_l, the same pairs and kinds)."""
+    return Spec(shape=spec.level_shape(l), n_channels=spec.n_channels, n_levels=1,
+                max_disp=(spec.max_disp[l],), level_weight=(1.0,), pairs=spec.pairs,
+                descriptor=spec.descriptor, alpha=spec.alpha, s3_max_disp=spec.s3_max_disp)
+
+
+def level_slice(spec: Spec, l: int) -> slice:
+    """Entries of level l in the multigrid descriptor (level-major order)."""
+    offs = [off for (_, ll, _, off, _) in spec.blocks() if ll == l]
+    ends = [off + k for (_, ll, _, off, k) in spec.blocks() if ll == l]
+    return slice(min(offs), max(ends))
+
+
+def upsample(g: np.ndarray) -> np.ndarray:
+    """Nearest-neighbour upsampling of a [C][n...] field by 2 along every axis."""
+    out = g
+    for a in range(g.ndim - 1):
+        out = np.repeat(out, 2, axis=1 + a)
+    return out
+
+
+def reconstruct_coarse_to_fine(S_des, spec: Spec, phi0, maxiter=100, maxcor=10, lo=0.0, hi=1.0):
+    """Sequential coarse-to-fine reference: the start field pooled to the coarsest
+    level, each level reconstructed alone (SciPy L-BFGS-B on its single-level loss
+    against its slice of the target), the result upsampled to start the next finer
+    level.  Returns (phi, multigrid E of the result)."""
+    lv = pyramid(np.asarray(phi0, np.float64), spec.n_levels)
+    x = lv[-1]
+    for l in range(spec.n_levels - 1, -1, -1):
+        if l < spec.n_levels - 1:
+            x = upsample(x)
+        ls = level_spec(spec, l)
+        x, _, _, _ = reconstruct_lbfgsb(np.asarray(S_des)[level_slice(spec, l)], ls, x, maxiter, maxcor, lo, hi)
+    E = loss(descriptor(x, spec), S_des, spec)[0]
+    return x, float(E)
+
+
 def reconstruct_lbfgsb(S_des, spec: Spec, phi0, maxiter=100, maxcor=10, lo=0.0, hi=1.0):
     """Reference reconstruction: SciPy L-BFGS-B on the oracle's (E, dE/dphi) in FP64,
     bounds [lo, hi] on every voxel.  Returns (phi, E_final, n_iter, n_eval)."""

@@ -418,6 +418,11 @@ hipError_t run_adjoint(const Plan &p, const float *phi, const float *G, float *g
 
 }  // namespace
 
+hipError_t run_pyramid_levels(const Plan &p, const float *phi, const Ws &ws, hipStream_t st)
+{
+    return run_pyramid(p, phi, ws, st);
+}
+
 // forward, error, adjoint with one plan (shared by dmcr_loss_grad and the
 // reconstruction loop)
 dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St, double *E, float *grad,

@@ -114,6 +114,9 @@ struct Ws {
 hipError_t launch_restrict(const Plan &p, int l, const float *fine, float *coarse, hipStream_t st);
 hipError_t launch_prolong_add(const Plan &p, int l, const float *coarse_grad, float *fine_grad,
                               hipStream_t st);
+// fine (level l) = nearest-neighbour upsampling of coarse (level l + 1)
+hipError_t launch_upsample(const Plan &p, int l, const float *coarse, float *fine, hipStream_t st);
+hipError_t run_pyramid_levels(const Plan &p, const float *phi, const Ws &ws, hipStream_t st);
 
 // x_free (optional) is recorded on st once the partial spectrum X of the level
 // has been consumed, so that a recompute of X on another stream may start.

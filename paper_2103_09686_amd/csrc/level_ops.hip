@@ -42,10 +42,11 @@ __global__ __launch_bounds__(kThreads) void k_restrict(const float *__restrict__
     }
 }
 
-// fine(x) += 2^-d coarse(floor(x/2))   (transpose of the mean pool)
+// fine(x) += w coarse(floor(x/2)); w = 2^-d is the transpose of the mean pool.
+// With assign, fine(x) = w coarse(floor(x/2)) (w = 1: nearest-neighbour upsampling).
 __global__ __launch_bounds__(kThreads) void k_prolong_add(const float *__restrict__ coarse,
                                                           float *__restrict__ fine, int64_t total,
-                                                          int ndim, int f0, int f1, int f2, float w)
+                                                          int ndim, int f0, int f1, int f2, float w, int assign)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= total) return;
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(const float *__restric
         const int64_t bc = r / f0;
         ci = ((bc * (f0 / 2) + x0 / 2) * (f1 / 2) + x1 / 2) * (f2 / 2) + x2 / 2;
     }
-    fine[i] += w * coarse[ci];
+    fine[i] = (assign ? 0.f : fine[i]) + w * coarse[ci];
 }
 
 struct KernArgs {
@@ -303,7 +304,17 @@ hipError_t launch_prolong_add(const Plan &p, int l, const float *coarse_grad, fl
     const float w = p.ndim == 2 ? 0.25f : 0.125f;
     const double bytes = (double)total * 8 + (double)total * 4 / (1 << p.ndim);
     return launch("prolong_add", bytes, k_prolong_add, dim3(blocks_for(total)), dim3(kThreads), 0, st,
-                  coarse_grad, fine_grad, total, p.ndim, f.n[0], f.n[1], f.n[2], w);
+                  coarse_grad, fine_grad, total, p.ndim, f.n[0], f.n[1], f.n[2], w, 0);
+}
+
+hipError_t launch_upsample(const Plan &p, int l, const float *coarse, float *fine, hipStream_t st)
+{
+    const LevelPlan &f = p.lv[l];
+    const int64_t total = (int64_t)p.B * p.C * f.N;
+    if (total == 0) return hipSuccess;
+    const double bytes = (double)total * 4 + (double)total * 4 / (1 << p.ndim);
+    return launch("upsample", bytes, k_prolong_add, dim3(blocks_for(total)), dim3(kThreads), 0, st, coarse, fine,
+                  total, p.ndim, f.n[0], f.n[1], f.n[2], 1.f, 1);
 }
 
 hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0, hipStream_t st)

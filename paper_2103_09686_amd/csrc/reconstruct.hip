@@ -657,9 +657,134 @@ dmcr_status make_solver(const dmcr_spec *spec, int32_t batch, const double *S_ta
     return DMCR_OK;
 }
 
+// Sequential coarse-to-fine schedule (the earlier multigrid practice that
+// Sec. 3.3 contrasts with): reconstruct the coarsest level alone against its own
+// part of the target, upsample the result (nearest neighbour) as the start of
+// the next finer level, and so on down to the finest field.  Stage s uses the
+// single-level spec of level s; its target is the level-s slice of the
+// multigrid target (the descriptor is level-major).
+struct C2FLayout {
+    size_t tgt;        // [B][max K_s] double
+    size_t stage_ws;   // workspace of the stage solvers
+    size_t E;          // [B] double (final multigrid error)
+    size_t grad;       // [B][C][N] float (final evaluation)
+    size_t bytes;
+};
+
+dmcr_spec stage_spec(const dmcr_spec &s, const Plan &p, int l)
+{
+    dmcr_spec t = s;
+    for (int a = 0; a < p.ndim; ++a) t.shape[a] = s.shape[a] >> l;
+    t.n_levels = 1;
+    t.max_disp[0] = s.max_disp[l];
+    t.level_weight[0] = 1.0;
+    return t;
+}
+
+dmcr_status c2f_layout(const dmcr_spec *spec, int B, const dmcr_opt &o, const Plan &p, C2FLayout *out)
+{
+    C2FLayout c{};
+    size_t top = align_up_bytes(p.bytes);
+    int64_t kmax = 0;
+    size_t wsmax = 0;
+    for (int l = 0; l < p.L; ++l) {
+        kmax = std::max<int64_t>(kmax, p.lvl_off[l + 1] - p.lvl_off[l]);
+        const dmcr_spec t = stage_spec(*spec, p, l);
+        Plan ps;
+        dmcr_status st = make_plan(&t, B, &ps);
+        if (st != DMCR_OK) return st;
+        wsmax = std::max(wsmax, r_layout(ps, o).bytes);
+    }
+    c.tgt = top;
+    top = align_up_bytes(top + (size_t)B * kmax * 8);
+    c.stage_ws = top;
+    top = align_up_bytes(top + wsmax);
+    c.E = top;
+    top = align_up_bytes(top + (size_t)B * 8);
+    c.grad = top;
+    top = align_up_bytes(top + (size_t)B * p.C * p.lv[0].N * 4);
+    c.bytes = top;
+    *out = c;
+    return DMCR_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+dmcr_status dmcr_reconstruct_c2f_workspace_size(const dmcr_spec *spec, int32_t batch, const dmcr_opt *opt,
+                                                size_t *bytes)
+{
+    if (!bytes || !opt_ok(opt)) return DMCR_EINVAL;
+    Plan p;
+    dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    C2FLayout c;
+    if ((s = c2f_layout(spec, batch, *opt, p, &c)) != DMCR_OK) return s;
+    *bytes = c.bytes;
+    return DMCR_OK;
+}
+
+dmcr_status dmcr_reconstruct_coarse_to_fine(const dmcr_spec *spec, int32_t batch, const double *S_target,
+                                            const dmcr_bounds *bounds, const dmcr_opt *opt, float *phi,
+                                            dmcr_result *results, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    if (!results || batch < 1 || !S_target || !phi || !bounds || !opt_ok(opt)) return DMCR_EINVAL;
+    Plan p;
+    dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    C2FLayout c;
+    if ((s = c2f_layout(spec, batch, *opt, p, &c)) != DMCR_OK) return s;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign)) return DMCR_EINVAL;
+    if (ws_bytes < c.bytes) return DMCR_ENOMEM;
+    char *base = static_cast<char *>(ws);
+    const Ws w{base};
+    // the pyramid of the start field: level l's start is the l-fold mean pool
+    RT(run_pyramid_levels(p, phi, w, st));
+    std::vector<int> iters(batch, 0), evals(batch, 0);
+    std::vector<int32_t> all(batch);
+    for (int b = 0; b < batch; ++b) all[b] = b;
+    for (int l = p.L - 1; l >= 0; --l) {
+        float *x = (l == 0) ? phi : w.at<float>(p.lv[l].field);
+        if (l + 1 < p.L) RT(launch_upsample(p, l, w.at<float>(p.lv[l + 1].field), x, st));
+        const int64_t Kl = p.lvl_off[l + 1] - p.lvl_off[l];
+        double *tgt = w.at<double>(c.tgt);
+        RT(hipMemcpy2DAsync(tgt, Kl * 8, S_target + p.lvl_off[l], p.K * 8, Kl * 8, batch, hipMemcpyDeviceToDevice,
+                            st));
+        const dmcr_spec t = stage_spec(*spec, p, l);
+        Plan ps;
+        Solver *sv = nullptr;
+        std::vector<char> mem;
+        s = make_solver(&t, batch, tgt, bounds, opt, x, base + c.stage_ws, c.grad - c.stage_ws, st, ps, &sv, mem);
+        if (s != DMCR_OK) return s;
+        std::vector<dmcr_slot> slots(batch);
+        dmcr_ring ring{opt->m - 1, 0};
+        s = sv->start(x, all.data(), batch, slots.data());
+        if (s == DMCR_OK) s = sv->iterate(x, slots.data(), &ring, opt->max_iter);
+        sv->~Solver();
+        if (s != DMCR_OK) return s;
+        for (int b = 0; b < batch; ++b) {
+            iters[b] += slots[b].iters;
+            evals[b] += slots[b].evals;
+        }
+    }
+    // the finest field against the whole multigrid target
+    double *Ed = w.at<double>(c.E);
+    RS(loss_grad_internal(p, phi, S_target, Ed, w.at<float>(c.grad), w, st));
+    std::vector<double> hE(batch);
+    RT(hipMemcpyAsync(hE.data(), Ed, batch * sizeof(double), hipMemcpyDeviceToHost, st));
+    RT(hipStreamSynchronize(st));
+    bool all_ok = true;
+    for (int b = 0; b < batch; ++b) {
+        results[b].final_E = hE[b];
+        results[b].final_derr = hE[b];
+        results[b].iters = iters[b];
+        results[b].evals = evals[b] + 1;
+        results[b].why = !std::isfinite(hE[b]) ? DMCR_ENONFINITE : (hE[b] <= opt->tol_derr ? DMCR_OK : DMCR_NOT_CONVERGED);
+        all_ok &= results[b].why == DMCR_OK;
+    }
+    return all_ok ? DMCR_OK : DMCR_NOT_CONVERGED;
+}
 
 dmcr_status dmcr_reconstruct_workspace_size(const dmcr_spec *spec, int32_t batch, const dmcr_opt *opt,
                                             size_t *bytes)

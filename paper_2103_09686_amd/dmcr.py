@@ -163,6 +163,11 @@ def lib():
         L.dmcr_reconstruct.argtypes = [sp, ctypes.c_int32, _vp, ctypes.POINTER(c_bounds),
                                        ctypes.POINTER(c_opt), _vp, ctypes.POINTER(c_result), _vp,
                                        ctypes.c_size_t, _vp]
+        L.dmcr_reconstruct_c2f_workspace_size.argtypes = [sp, ctypes.c_int32, ctypes.POINTER(c_opt),
+                                                          ctypes.POINTER(ctypes.c_size_t)]
+        L.dmcr_reconstruct_coarse_to_fine.argtypes = [sp, ctypes.c_int32, _vp, ctypes.POINTER(c_bounds),
+                                                      ctypes.POINTER(c_opt), _vp, ctypes.POINTER(c_result), _vp,
+                                                      ctypes.c_size_t, _vp]
         L.dmcr_solver_start.argtypes = [sp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _vp,
                                         ctypes.POINTER(c_bounds), ctypes.POINTER(c_opt), _vp,
                                         ctypes.POINTER(c_slot), _vp, ctypes.c_size_t, _vp]
@@ -174,6 +179,7 @@ def lib():
         for fn in ("dmcr_descriptor_offsets", "dmcr_workspace_size", "dmcr_pyramid",
                    "dmcr_descriptor_forward", "dmcr_descriptor_adjoint", "dmcr_error_cotangent",
                    "dmcr_loss_grad", "dmcr_reconstruct_workspace_size", "dmcr_reconstruct",
+                   "dmcr_reconstruct_c2f_workspace_size", "dmcr_reconstruct_coarse_to_fine",
                    "dmcr_solver_start", "dmcr_solver_iterate"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
@@ -375,6 +381,35 @@ def dmcr_reconstruct(spec: Spec, S_target: torch.Tensor, phi: torch.Tensor, boun
                                   ctypes.byref(bo), ctypes.byref(o), _ptr(phi, torch.float32, "phi"), res,
                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
     _check("dmcr_reconstruct", code)
+    return code, [dict(final_E=r.final_E, final_derr=r.final_derr, iters=r.iters, evals=r.evals, why=r.why)
+                  for r in res]
+
+
+def dmcr_reconstruct_c2f_workspace_size(spec: Spec, batch: int, opt: Opt) -> int:
+    s, o = spec.c(), opt.c()
+    b = ctypes.c_size_t()
+    _check("dmcr_reconstruct_c2f_workspace_size",
+           lib().dmcr_reconstruct_c2f_workspace_size(ctypes.byref(s), batch, ctypes.byref(o), ctypes.byref(b)))
+    return b.value
+
+
+def dmcr_reconstruct_coarse_to_fine(spec: Spec, S_target: torch.Tensor, phi: torch.Tensor, bounds: Bounds = None,
+                                    opt: Opt = None, ws=None, stream=None):
+    """Sequential coarse-to-fine reconstruction in place on phi (level by level,
+    coarsest first, each started from the upsampled result of the coarser level);
+    returns (code, list of result dicts) with the multigrid error of the result."""
+    bounds = bounds or Bounds()
+    opt = opt or Opt()
+    B = _batch(spec, phi)
+    need = dmcr_reconstruct_c2f_workspace_size(spec, B, opt)
+    if ws is None:
+        ws = workspace(need, phi.device)
+    s, bo, o = spec.c(), bounds.c(), opt.c()
+    res = (c_result * B)()
+    code = lib().dmcr_reconstruct_coarse_to_fine(ctypes.byref(s), B, _ptr(S_target, torch.float64, "S_target"),
+                                                 ctypes.byref(bo), ctypes.byref(o), _ptr(phi, torch.float32, "phi"),
+                                                 res, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+    _check("dmcr_reconstruct_coarse_to_fine", code)
     return code, [dict(final_E=r.final_E, final_derr=r.final_derr, iters=r.iters, evals=r.evals, why=r.why)
                   for r in res]
 

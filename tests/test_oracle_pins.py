@@ -316,3 +316,20 @@ def test_lbfgs_two_loop_equals_dense_bfgs(ora):
         V = np.eye(n) - rho * np.outer(y, s)
         H = V.T @ H @ V + rho * np.outer(s, s)
     np.testing.assert_allclose(ora.lbfgs_direction(g, s_hist, y_hist), -H @ g, rtol=1e-10, atol=1e-12)
+
+
+def test_level_slices_and_upsampling(ora):
+    """The level-l slice of the multigrid descriptor is the single-level descriptor of
+    the l-fold pooled field (what the coarse-to-fine stages reconstruct against), and
+    nearest-neighbour upsampling is 2^d times the transpose of the mean pool."""
+    rng = np.random.default_rng(61)
+    spec = ora.Spec(shape=(16, 32), n_channels=2, n_levels=3, max_disp=(3, 2, 1), s3_max_disp=1)
+    phi = rng.random((2, 16, 32))
+    S = ora.descriptor(phi, spec)
+    lv = ora.pyramid(phi, 3)
+    for l in range(3):
+        np.testing.assert_allclose(S[ora.level_slice(spec, l)], ora.descriptor(lv[l], ora.level_spec(spec, l)),
+                                   rtol=0, atol=1e-15)
+    g = rng.random((2, 8, 16))
+    np.testing.assert_allclose(ora.upsample(g), 4 * ora.pool_adjoint(g), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(ora.pool(ora.upsample(g)), g, rtol=0, atol=1e-15)

@@ -755,7 +755,7 @@ dmcr_status dmcr_reconstruct_coarse_to_fine(const dmcr_spec *spec, int32_t batch
         Plan ps;
         Solver *sv = nullptr;
         std::vector<char> mem;
-        s = make_solver(&t, batch, tgt, bounds, opt, x, base + c.stage_ws, c.grad - c.stage_ws, st, ps, &sv, mem);
+        s = make_solver(&t, batch, tgt, bounds, opt, x, base + c.stage_ws, c.E - c.stage_ws, st, ps, &sv, mem);
         if (s != DMCR_OK) return s;
         std::vector<dmcr_slot> slots(batch);
         dmcr_ring ring{opt->m - 1, 0};

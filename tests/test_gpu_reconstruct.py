@@ -108,3 +108,31 @@ def test_3d_128_three_phase_reaches_tolerance(dm, ora):
     code, res = dm.dmcr_reconstruct(spec, St, x, dm.Bounds(), dm.Opt(max_iter=400, tol_derr=1e-4))
     print("3d128", res[0], flush=True)
     assert code == 0 and res[0]["final_E"] <= 1e-4
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("where", ["field", "target"])
+def test_nonfinite_element_fails_alone(dm, ora, method, where):
+    """A NaN in one element's start field (no bounds: projection would clip it away) or
+    in its target stops that element with ENONFINITE; the other elements of the batch
+    return exactly what they return when run alone."""
+    shape = (64, 64)
+    ospec, S_des = target(ora, shape, (16,))
+    spec = dm.Spec(shape=shape, max_disp=(16,))
+    opt = dm.Opt(method=method, lr=1e-2, max_iter=20, tol_derr=0.0)
+    bounds = dm.Bounds(0.0, 1.0, dm.BOUNDS_NONE)
+    starts = np.stack([synth.uniform(shape, 20 + b) for b in range(3)]).astype(np.float32)
+    tg = np.stack([S_des] * 3)
+    if where == "field":
+        starts[1, 0, 5, 7] = np.nan
+    else:
+        tg[1, 3] = np.nan
+    x = torch.from_numpy(starts).cuda()
+    St = torch.from_numpy(tg).cuda()
+    code, res = dm.dmcr_reconstruct(spec, St, x, bounds, opt)
+    assert res[1]["why"] == dm.ENONFINITE
+    for b in (0, 2):
+        xb = torch.from_numpy(starts[b:b + 1].copy()).cuda()
+        _, rb = dm.dmcr_reconstruct(spec, St[b:b + 1].contiguous(), xb, bounds, opt)
+        assert rb[0]["final_E"] == res[b]["final_E"] and rb[0]["iters"] == res[b]["iters"]
+        assert torch.equal(xb[0], x[b])

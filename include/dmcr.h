@@ -22,7 +22,9 @@
  *       S_ij^(l)(r) = (1/N_l) sum_x phi_i^(l)(x) phi_j^(l)((x + r) mod n_l)
  *   (Sec. 3.2.1-3.2.2 with the periodic shift of eq. convdef; for soft
  *   fields this is the Appendix A corrected descriptor with the identity
- *   threshold used in Sec. 5.1).  Auto pairs (i == j) use the half box H_P
+ *   threshold used in Sec. 5.1).  spec.descriptor selects the paper's
+ *   soft-threshold form instead (see DMCR_DESC_*), and spec.s3_max_disp adds
+ *   three-point blocks (eq. s3).  Auto pairs (i == j) use the half box H_P
  *   (r = 0 or first non-zero component > 0; point symmetry, Appendix B),
  *   cross pairs the full box [-P, P]^d.
  * Descriptor order.  Level-major (finest first), then pair in the order of
@@ -35,9 +37,10 @@
  *   device memory of the current HIP device; the library never allocates on
  *   these calls: scratch comes from the caller's workspace `ws` of at least
  *   dmcr_workspace_size() bytes (256-byte aligned).
- * Streams.  Every call except dmcr_reconstruct is asynchronous on `stream`
- *   and returns before the work finishes; device faults surface on a later
- *   call or synchronisation.  Calls that share a workspace must not overlap.
+ * Streams.  Every call except the reconstruction and solver-slot calls is
+ *   asynchronous on `stream` and returns before the work finishes; device
+ *   faults surface on a later call or synchronisation.  Calls that share a
+ *   workspace must not overlap.
  * Errors.  Arguments are validated before any launch; on error nothing is
  *   launched and a negative dmcr_status is returned.  No call aborts.
  */
@@ -213,7 +216,7 @@ dmcr_status dmcr_reconstruct_workspace_size(const dmcr_spec *spec, int32_t batch
                                             const dmcr_opt *opt, size_t *bytes);
 
 /* Reconstruction (Sec. 3, Fig. 1 loop): minimise E (+ penalty) over phi with
- * L-BFGS, starting from phi_inout (device [B][C][n...], overwritten with the
+ * L-BFGS or Adam (opt->method), starting from phi_inout (device [B][C][n...], overwritten with the
  * result).  S_target: device float64 [B][K].  results: host array of B.
  * Blocking: synchronises `stream` before returning.  Returns DMCR_OK if every
  * element reached tol_derr, DMCR_NOT_CONVERGED if some did not, or an error. */
@@ -262,12 +265,13 @@ int32_t dmcr_profile_stop(dmcr_kernel_stat *out, int32_t max);
  * dmcr_ring (initialise head = opt->m - 1, count = 0).  Slots are independent:
  * each slot's iterates are bitwise the same whatever the other slots hold.
  *   dmcr_solver_start   (re)starts the listed slots from their current phi:
- *                       projection, one evaluation, empty history; sets
- *                       active = 1 and status = RUNNING (or OK / ENONFINITE).
- *   dmcr_solver_iterate runs up to `iterations` L-BFGS iterations of every
- *                       slot with active = 1 and status = RUNNING; a slot
- *                       stops with OK (E <= tol_derr) or NOT_CONVERGED
- *                       (iters >= max_iter or a stalled line search).
+ *                       projection, one evaluation, empty history (Adam: zero
+ *                       moments); sets active = 1 and status = RUNNING (or OK /
+ *                       ENONFINITE).
+ *   dmcr_solver_iterate runs up to `iterations` L-BFGS or Adam iterations of
+ *                       every slot with active = 1 and status = RUNNING; a slot
+ *                       stops with OK (E <= tol_derr), NOT_CONVERGED (iters >=
+ *                       max_iter or a stalled line search) or ENONFINITE.
  * Both synchronise `stream` before returning.  The caller clears `active` of a
  * slot it retires and may then start a new request in it. */
 typedef struct {

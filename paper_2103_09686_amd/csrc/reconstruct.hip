@@ -201,16 +201,19 @@ __global__ __launch_bounds__(kV) void k_accept(const int *acc, float *x, const f
     }
 }
 
-// Adam step of active elements: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
-// x -= lr (m / bc1) / (sqrt(v / bc2) + eps), clipped to [lo, hi] with projection;
-// bc1[b] = 1 - b1^t, bc2[b] = 1 - b2^t at the element's step t
-__global__ __launch_bounds__(kV) void k_adam(float *x, const float *g, float *mm, float *vv, const double *bc1,
-                                             const double *bc2, const int *active, int64_t n, float lr, float b1,
-                                             float b2, float eps, int project, float lo, float hi)
+// Adam step of running elements (status RUNNING, step t = iters + 1):
+// m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// x -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), clipped to [lo, hi] with projection
+__global__ __launch_bounds__(kV) void k_adam(float *x, const float *g, float *mm, float *vv, const int *status,
+                                             const int *iters, int64_t n, float lr, double beta1, double beta2,
+                                             float eps, int project, float lo, float hi)
 {
     const int64_t b = blockIdx.y;
-    if (!active[b]) return;
-    const float ic1 = (float)(1.0 / bc1[b]), ic2 = (float)(1.0 / bc2[b]);
+    if (status[b] != DMCR_RUNNING) return;
+    const int t = iters[b] + 1;
+    const float b1 = (float)beta1, b2 = (float)beta2;
+    const float ic1 = (float)(1.0 / (1.0 - pow(beta1, (double)t)));
+    const float ic2 = (float)(1.0 / (1.0 - pow(beta2, (double)t)));
     for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV) {
         const int64_t j = b * n + i;
         const float gi = g[j];
@@ -222,6 +225,24 @@ __global__ __launch_bounds__(kV) void k_adam(float *x, const float *g, float *mm
         if (project) xv = fminf(fmaxf(xv, lo), hi);
         x[j] = xv;
     }
+}
+
+// after an Adam step's evaluation: count it and decide each running element's status
+__global__ void k_adam_check(const double *E, const double *Ebc, double kappa, int penalty, double tol, int max_iter,
+                             double *f, int *iters, int *evals, int *status, int B)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B || status[b] != DMCR_RUNNING) return;
+    ++iters[b];
+    ++evals[b];
+    const double fb = E[b] + (penalty ? kappa * E[b] * Ebc[b] : 0.0);
+    f[b] = fb;
+    if (!isfinite(fb))
+        status[b] = DMCR_ENONFINITE;
+    else if (E[b] <= tol)
+        status[b] = DMCR_OK;
+    else if (iters[b] >= max_iter)
+        status[b] = DMCR_NOT_CONVERGED;
 }
 
 __global__ __launch_bounds__(kV) void k_zero(float *p, int64_t n)
@@ -267,6 +288,7 @@ __global__ __launch_bounds__(kV) void k_pen_grad(const float *x, float *g, const
 struct RLayout {
     size_t xt, g, gt, d, s, y;
     size_t part, dot1, dot2, rho, alpha, gamma, coef, E, Et, Ebc, als, active, acc, flag;
+    size_t sl_f, sl_iters, sl_evals, sl_status;   // Adam: per-slot state kept on the device
     int nblk;
     size_t bytes;
 };
@@ -305,6 +327,10 @@ RLayout r_layout(const Plan &p, const dmcr_opt &o)
     r.active = take((size_t)p.B * 4);
     r.acc = take((size_t)p.B * 4);
     r.flag = take((size_t)p.B * 4);
+    r.sl_f = take(B8);
+    r.sl_iters = take((size_t)p.B * 4);
+    r.sl_evals = take((size_t)p.B * 4);
+    r.sl_status = take((size_t)p.B * 4);
     r.bytes = top;
     return r;
 }
@@ -371,6 +397,12 @@ struct Solver {
     dmcr_status fetch(const double *src, std::vector<double> &dst) const
     {
         RT(hipMemcpyAsync(dst.data(), src, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        return DMCR_OK;
+    }
+
+    dmcr_status fetch_int(const int *src, std::vector<int> &dst) const
+    {
+        RT(hipMemcpyAsync(dst.data(), src, B * sizeof(int), hipMemcpyDeviceToHost, st));
         return DMCR_OK;
     }
 
@@ -445,52 +477,59 @@ dmcr_status Solver::start(float *x, const int *which, int nwhich, dmcr_slot *slo
     return DMCR_OK;
 }
 
-// Up to `iterations` Adam steps of every running slot.
+// Up to `iterations` Adam steps of every running slot.  The per-slot counters
+// and the stopping decisions live on the device, so steps are queued without a
+// host round trip; the host checks every kCheck steps whether any slot still runs.
 dmcr_status Solver::iterate_adam(float *x, dmcr_slot *slots, int iterations)
 {
+    constexpr int kCheck = 16;
     float *g = at<float>(r.g);
-    double *Ed = at<double>(r.E), *Ebcd = at<double>(r.Ebc);
-    double *bc1 = at<double>(r.dot1), *bc2 = at<double>(r.dot2);
-    int *active = at<int>(r.active);
-    std::vector<double> hE(B), hEbc(B, 0.0), h1(B, 1.0), h2(B, 1.0);
-    std::vector<int> act(B);
-    auto running = [&](int b) { return slots[b].active && slots[b].status == DMCR_RUNNING; };
+    double *Ed = at<double>(r.E), *Ebcd = at<double>(r.Ebc), *fd = at<double>(r.sl_f);
+    int *itd = at<int>(r.sl_iters), *evd = at<int>(r.sl_evals), *std_ = at<int>(r.sl_status);
+    std::vector<int> hit(B), hev(B), hst(B);
+    std::vector<double> hf(B), hE(B);
+    for (int b = 0; b < B; ++b) {
+        hit[b] = slots[b].iters;
+        hev[b] = slots[b].evals;
+        hst[b] = (slots[b].active && slots[b].status == DMCR_RUNNING) ? DMCR_RUNNING : DMCR_OK;
+        hf[b] = slots[b].f;
+    }
+    RS(put(itd, hit));
+    RS(put(evd, hev));
+    RS(put(std_, hst));
+    RS(put(fd, hf));
     for (int it = 0; it < iterations; ++it) {
-        bool any = false;
-        for (int b = 0; b < B; ++b) {
-            act[b] = running(b);
-            any |= act[b] != 0;
-            const int t = slots[b].iters + 1;
-            h1[b] = 1.0 - std::pow(o.beta1, t);
-            h2[b] = 1.0 - std::pow(o.beta2, t);
+        if (it % kCheck == 0) {
+            RS(fetch_int(std_, hst));
+            RT(hipStreamSynchronize(st));
+            bool any = false;
+            for (int b = 0; b < B; ++b) any |= hst[b] == DMCR_RUNNING;
+            if (!any) break;
         }
-        if (!any) break;
-        RS(put(active, act));
-        RS(put(bc1, h1));
-        RS(put(bc2, h2));
-        hipLaunchKernelGGL(k_adam, vg, dim3(kV), 0, st, x, g, S(0), Y(0), bc1, bc2, active, n, (float)o.lr,
-                           (float)o.beta1, (float)o.beta2, (float)o.eps, (int)project, lo, hi);
+        hipLaunchKernelGGL(k_adam, vg, dim3(kV), 0, st, x, g, S(0), Y(0), std_, itd, n, (float)o.lr, o.beta1, o.beta2,
+                           (float)o.eps, (int)project, lo, hi);
         RT(hipGetLastError());
         RS(evaluate(x, Ed, g));
-        RS(fetch(Ed, hE));
-        if (penalty) RS(fetch(Ebcd, hEbc));
-        RT(hipStreamSynchronize(st));
-        for (int b = 0; b < B; ++b) {
-            if (!act[b]) continue;
-            dmcr_slot &sl = slots[b];
-            ++sl.iters;
-            ++sl.evals;
-            sl.E = hE[b];
-            sl.f = hE[b] + (penalty ? bd.kappa * hE[b] * hEbc[b] : 0.0);
-            if (!std::isfinite(sl.f))
-                sl.status = DMCR_ENONFINITE;
-            else if (sl.E <= o.tol_derr)
-                sl.status = DMCR_OK;
-            else if (sl.iters >= o.max_iter)
-                sl.status = DMCR_NOT_CONVERGED;
-        }
+        hipLaunchKernelGGL(k_adam_check, sg, dim3(64), 0, st, Ed, Ebcd, bd.kappa, (int)penalty, o.tol_derr,
+                           o.max_iter, fd, itd, evd, std_, B);
+        RT(hipGetLastError());
     }
+    RS(fetch_int(itd, hit));
+    RS(fetch_int(evd, hev));
+    RS(fetch_int(std_, hst));
+    RS(fetch(fd, hf));
+    RS(fetch(Ed, hE));
     RT(hipStreamSynchronize(st));
+    for (int b = 0; b < B; ++b) {
+        if (!(slots[b].active && slots[b].status == DMCR_RUNNING)) continue;
+        dmcr_slot &sl = slots[b];
+        if (hit[b] == sl.iters) continue;   // took no step
+        sl.iters = hit[b];
+        sl.evals = hev[b];
+        sl.status = hst[b];
+        sl.f = hf[b];
+        sl.E = hE[b];
+    }
     return DMCR_OK;
 }
 

@@ -60,7 +60,7 @@ SOFT_SLOTS = {"direct_fwd_soft": 15, "direct_adj_soft": 19}
 
 
 # the sources the FFT-path kernels (the dominant kernels of every workload) compile from
-KERNEL_SOURCES = ("dmcr_internal.h", "fft_path.hip", "fft_reg.h")
+KERNEL_SOURCES = ("dmcr_internal.h", "fft_path.hip", "fft_plane.hip", "fft_reg.h")
 
 
 def K_level(spec, l):
@@ -321,23 +321,6 @@ def main():
     def step():
         dmcr.dmcr_loss_grad(spec, phi, S_target, E, grad, ws)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    t0.record(stream)
-    for _ in range(args.steps):
-        step()
-    t1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = t0.elapsed_time(t1) / args.steps
-    value = N * B / (ms * 1e-3)
-    print("timed %d steps: %.4f ms/step (wall %.3f s)" % (args.steps, ms, wall), file=sys.stderr, flush=True)
-
-    # second pass: per-kernel HIP events on the launch stream
     import ctypes
     lib = dmcr.lib()
     lib.dmcr_profile_start.restype = ctypes.c_int
@@ -348,23 +331,49 @@ def main():
                     ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
     lib.dmcr_profile_stop.argtypes = [ctypes.POINTER(KStat), ctypes.c_int32]
-    lib.dmcr_profile_start()
-    for _ in range(args.steps):
-        step()
-    stats = (KStat * 64)()
-    nk = lib.dmcr_profile_stop(stats, 64)
-    torch.cuda.synchronize()
-    kern = []
-    for i in range(min(nk, 64)):
-        s = stats[i]
-        kern.append(dict(name=s.name.decode(), launches=s.launches, avg_us=1e3 * s.total_ms / s.launches,
-                         total_ms=s.total_ms, bytes_per_launch=s.bytes / s.launches,
-                         GBps=(s.bytes / s.launches) / (s.total_ms / s.launches * 1e-3) / 1e9))
-    kern.sort(key=lambda r: -r["total_ms"])
-    for r in kern:
-        print("  %-16s n=%-5d avg %9.2f us  %8.1f GB/s  (%.1f MB/launch)" %
-              (r["name"], r["launches"], r["avg_us"], r["GBps"], r["bytes_per_launch"] / 1e6),
+
+    def timed(fn):
+        """Warm-up, then args.steps steps between two events on the launch stream: ms per step."""
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        t0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / args.steps
+        print("timed %d steps: %.4f ms/step (wall %.3f s)" % (args.steps, ms, time.perf_counter() - wall0),
               file=sys.stderr, flush=True)
+        return ms
+
+    def kernel_table(fn):
+        """Second pass of the same steps with HIP events around every launch, on its stream."""
+        lib.dmcr_profile_start()
+        for _ in range(args.steps):
+            fn()
+        stats = (KStat * 64)()
+        nk = lib.dmcr_profile_stop(stats, 64)
+        torch.cuda.synchronize()
+        kern = []
+        for i in range(min(nk, 64)):
+            s = stats[i]
+            kern.append(dict(name=s.name.decode(), launches=s.launches, avg_us=1e3 * s.total_ms / s.launches,
+                             total_ms=s.total_ms, bytes_per_launch=s.bytes / s.launches,
+                             GBps=(s.bytes / s.launches) / (s.total_ms / s.launches * 1e-3) / 1e9))
+        kern.sort(key=lambda r: -r["total_ms"])
+        for r in kern:
+            print("  %-16s n=%-5d avg %9.2f us  %8.1f GB/s  (%.1f MB/launch)" %
+                  (r["name"], r["launches"], r["avg_us"], r["GBps"], r["bytes_per_launch"] / 1e6),
+                  file=sys.stderr, flush=True)
+        return kern
+
+    ms = timed(step)
+    value = N * B / (ms * 1e-3)
+    kern = kernel_table(step)
     dom = kern[0]
     prof_ms = sum(r["total_ms"] for r in kern) / args.steps
     if dom["name"] in SOFT_SLOTS:
@@ -424,6 +433,25 @@ def main():
                            descriptor=["s2", "sbar", "stilde"][desc], s3_max_disp=spec.s3_max_disp,
                            recompute=wl["recompute"], parallelism="single GPU"),
                roofline=roofline, step_roofline=step_roofline)
+    if len(shape) == 3 and shape[1] == shape[2] == 256 and not desc:
+        # the same step with the fused one-pass plane transforms of 256 x 256 planes (opt-in)
+        spec_f = dmcr.make_spec(shape, C, L, P, flags=flags | dmcr.FLAG_FUSED_PLANES, descriptor=desc,
+                                s3_max_disp=wl.get("s3", 0))
+        ws_f = dmcr.workspace(dmcr.dmcr_workspace_size(spec_f, B))
+
+        def step_f():
+            dmcr.dmcr_loss_grad(spec_f, phi, S_target, E, grad, ws_f)
+
+        print("alternative: fused 256 x 256 plane transforms", file=sys.stderr, flush=True)
+        ms_f = timed(step_f)
+        kern_f = kernel_table(step_f)
+        bytes_f = sum(r["bytes_per_launch"] * r["launches"] for r in kern_f) / args.steps
+        out["alternatives"] = [dict(
+            flags="FUSED_PLANES", ms_per_step=ms_f, value=N * B / (ms_f * 1e-3),
+            dominant_kernel=kern_f[0]["name"], dominant_avg_us=round(kern_f[0]["avg_us"], 2),
+            dominant_frac=round(kern_f[0]["GBps"] / HBM_PEAK_GBS, 4), bytes_per_step=bytes_f,
+            step_frac=round(bytes_f / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))]
+        del ws_f
     if not args.no_serve and args.workload == "3d256":
         out["serving"] = serving(args.requests, args.rate, args.compare)
     if not args.no_cpu_baseline:

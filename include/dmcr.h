@@ -107,8 +107,14 @@ enum { DMCR_DESC_S2 = 0, DMCR_DESC_SBAR = 1, DMCR_DESC_STILDE = 2 };
 
 /* spec.flags */
 enum {
-    DMCR_FLAG_RECOMPUTE = 1  /* dmcr_loss_grad recomputes the forward spectra in the
-                                adjoint instead of keeping them between the two halves */
+    DMCR_FLAG_RECOMPUTE = 1,    /* dmcr_loss_grad recomputes the forward spectra in the
+                                   adjoint instead of keeping them between the two halves */
+    DMCR_FLAG_FUSED_PLANES = 2  /* FFT path, 3-D levels with 256 x 256 planes: transform the
+                                   contiguous axis and axis 1 in one pass (one plane per
+                                   workgroup) instead of two.  Levels with square planes of
+                                   side 32..128 always do.  Fewer HBM bytes; at 256 the fused
+                                   pass holds a whole compute unit per plane and cannot
+                                   overlap its loads with its stores */
 };
 
 typedef struct {

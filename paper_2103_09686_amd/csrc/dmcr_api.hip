@@ -70,6 +70,7 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
         p.shape[a] = s->shape[a];
     }
     if (p.ndim == 2) p.shape[2] = 1;
+    if (s->flags & ~(DMCR_FLAG_RECOMPUTE | DMCR_FLAG_FUSED_PLANES)) return DMCR_EINVAL;
     p.flags = s->flags;
     if (s->path < DMCR_PATH_AUTO || s->path > DMCR_PATH_DIRECT) return DMCR_EINVAL;
     // descriptor kind and soft-threshold constants (Sec. 3.2.4): the inflection

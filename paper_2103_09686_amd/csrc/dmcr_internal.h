@@ -122,12 +122,22 @@ hipError_t run_pyramid_levels(const Plan &p, const float *phi, const Ws &ws, hip
 // has been consumed, so that a recompute of X on another stream may start.
 hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
                              hipStream_t st, hipEvent_t x_free = nullptr);
-hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &ws, hipStream_t st);
+// fused = false keeps the two-pass transforms of 3-D levels (for a spectrum
+// computed while other kernels of the same step run on other streams).
+hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &ws, hipStream_t st,
+                              bool fused = true);
 // Without have_spectrum the spectrum is recomputed: on st_spec after x_free when
 // st_spec is given (overlapping the cotangent transforms on st), else on st.
 hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
                              bool have_spectrum, const Ws &ws, hipStream_t st, hipStream_t st_spec = nullptr,
                              hipEvent_t x_free = nullptr, hipEvent_t spec_done = nullptr);
+
+// 3-D levels with square planes of side 32..256: the contiguous axis and axis 1
+// transformed in one pass (fft_plane.hip).  Forward: real field [B][C][n0][n][n]
+// -> half spectra X [B][C][n0][n][hp]; inverse: X -> real field (unnormalised).
+bool plane_supported(const Plan &p, int l);
+hipError_t plane_forward(const Plan &p, int l, const float *phi, float2 *X, hipStream_t st);
+hipError_t plane_inverse(const Plan &p, int l, const float2 *X, float *grad, hipStream_t st);
 
 hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
                                 hipStream_t st);

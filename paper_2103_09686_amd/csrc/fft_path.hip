@@ -258,8 +258,11 @@ __global__ __launch_bounds__(256) void k_r2c(RowArgs a)
     const float2 wp = tw_n<false>(p, L);
     float2 u[S][R2];
     pencil_fwd<LH, false, LANE_P>(v, u, ex, p, t, T);
-    // Z in natural order for the split (pencil_fwd ended with a barrier)
-    constexpr int pitch = nh + 1;
+    // Z in natural order for the split (pencil_fwd ended with a barrier); the row
+    // pitch of R2 mod 32 float2 puts the rows that a wave touches at once (R2
+    // lanes of 8 bytes each) R2 * 8 bytes apart in the 64 four-byte banks
+    constexpr int pitch = nh + R2;
+    static_assert(T * pitch <= ex_size<LH>(T), "natural-order rows exceed the exchange");
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -733,11 +736,12 @@ bool fft_supported(const Plan &p, int l)
 
 // Half spectrum of every channel, transformed along every axis except 0:
 // X = DFT_{1..d-1}(phi) (the contiguous axis real-to-half-complex).
-hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &ws, hipStream_t st)
+hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &ws, hipStream_t st, bool fused)
 {
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C;
     float2 *X = ws.at<float2>(L.X);
+    if (fused && plane_supported(p, l)) return plane_forward(p, l, phi, X, st);   // both axes in one pass
     const int nl = L.n[p.ndim - 1];
     const int64_t rows = (p.ndim == 2) ? (int64_t)B * C * L.n[0] : (int64_t)B * C * L.n[0] * L.n[1];
     RowArgs r = row_args(phi, X, rows, IO_FULL, nl, IO_HALF, L.hp, 0, true, false, 1.f);
@@ -853,7 +857,9 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
     if (!have_spectrum) {
         if (st_spec) {
             if (x_free) TRY_HIP(hipStreamWaitEvent(st_spec, x_free, 0));
-            TRY_HIP(fft_spectrum_level(p, l, phi, ws, st_spec));
+            // a plane workgroup takes a whole CU's LDS, so the fused pass would
+            // not share the CUs with the cotangent transforms it overlaps
+            TRY_HIP(fft_spectrum_level(p, l, phi, ws, st_spec, false));
             TRY_HIP(hipEventRecord(spec_done, st_spec));
             TRY_HIP(hipStreamWaitEvent(st, spec_done, 0));
         } else {
@@ -877,6 +883,7 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
     a.scale = (float)(invN * invN);
     const double bytes0 = 2.0 * B * C * n0 * inner_valid * 8 + (double)B * CC * L.box * inner_valid * 8;
     TRY_HIP(axis0_launch(C, true, ilog2(n0), a, bytes0, st));
+    if (plane_supported(p, l)) return plane_inverse(p, l, X, grad, st);   // both axes in one pass
     if (p.ndim == 3) {
         ColArgs c = col_args(X, X, (int64_t)B * C * n0 * L.hp, L.hp, IO_FULL, L.n[1], IO_FULL, L.n[1], 0);
         c.h = L.h;

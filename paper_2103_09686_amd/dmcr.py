@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdmcr.so")
 PATH_AUTO, PATH_FFT, PATH_DIRECT = 0, 1, 2
 DESC_S2, DESC_SBAR, DESC_STILDE = 0, 1, 2
 FLAG_RECOMPUTE = 1
+FLAG_FUSED_PLANES = 2
 BOUNDS_NONE, BOUNDS_PROJECT, BOUNDS_PENALTY = 0, 1, 2
 OPT_LBFGS, OPT_ADAM = 0, 1
 MAX_LEVELS, MAX_CHANNELS, MAX_PAIRS = 8, 4, 10

@@ -89,6 +89,7 @@ def test_config_sizes_quoted_in_the_workloads(dm):
     (dict(shape=(64, 64), level_weight=(0.0,)), -1),
     (dict(shape=(64, 64), n_channels=2, pairs=((1, 0),)), -1),
     (dict(shape=(64, 64, 64), max_disp=(20,), path=2), -3),  # DIRECT halo does not fit LDS
+    (dict(shape=(64, 64), flags=4), -1),                       # unknown flag bit
 ])
 def test_validation(dm, kw, code):
     spec = dm.Spec(**kw)

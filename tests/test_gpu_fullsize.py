@@ -21,9 +21,11 @@ def dm():
     return dmcr
 
 
-def test_3d_256_sampled(dm, ora):
+@pytest.mark.parametrize("fused", [False, True])
+def test_3d_256_sampled(dm, ora, fused):
     shape = (256, 256, 256)
-    spec = dm.Spec(shape=shape, n_channels=1, n_levels=1, max_disp=(32,), path=1, flags=dm.FLAG_RECOMPUTE)
+    flags = dm.FLAG_RECOMPUTE | (dm.FLAG_FUSED_PLANES if fused else 0)
+    spec = dm.Spec(shape=shape, n_channels=1, n_levels=1, max_disp=(32,), path=1, flags=flags)
     ospec = ora.Spec(shape=shape, n_channels=1, n_levels=1, max_disp=(32,))
     phi32 = synth.uniform(shape, 0).astype(np.float32)
     phi = phi32.astype(np.float64)

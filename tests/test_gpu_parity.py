@@ -70,7 +70,28 @@ CASES = [
     ((128, 128), 1, 2, (31, 31), (), 1),
     ((2, 2), 1, 1, (0,), (), 1),
     ((4, 4, 4), 1, 2, (1, 0), (), 0),
+    # square planes: the contiguous axis and axis 1 in one fused pass (n = 32..256)
+    ((8, 32, 32), 2, 1, (3,), (), 1),
+    ((4, 64, 64), 1, 2, (1, 0), (), 1),
+    ((8, 128, 128), 1, 1, (3,), (), 1),
+    ((4, 256, 256), 2, 1, (1,), (), 1),
 ]
+
+
+@pytest.mark.parametrize("C", [1, 2])
+def test_fused_256_planes_parity(dm, ora, C):
+    """256 x 256 planes through the fused one-pass plane transforms (opt-in flag)."""
+    shape, P = (4, 256, 256), (1,)
+    spec, ospec = specs(dm, ora, shape, C, 1, P, path=1, flags=dm.FLAG_FUSED_PLANES)
+    B = 2
+    phi = f32(np.stack([synth.uniform(shape, 200 + b, channels=C) for b in range(B)]))
+    dphi = to_dev(phi)
+    S = dm.dmcr_descriptor_forward(spec, dphi).cpu().numpy().astype(np.float64)
+    dS = f32(np.random.default_rng(3).standard_normal((B, ospec.K)))
+    g = dm.dmcr_descriptor_adjoint(spec, dphi, to_dev(dS)).cpu().numpy().astype(np.float64)
+    for b in range(B):
+        check_S(S[b], ora.descriptor(phi[b], ospec), ospec, "fwd b=%d" % b)
+        check_grad(g[b], ora.adjoint(phi[b], dS[b], ospec), "adj b=%d" % b)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[str(i) for i in range(len(CASES))])

@@ -135,6 +135,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle sample time")
     ap.add_argument("--calibrate-copy", action="store_true", help="time plain copies of 64/256/1024 MiB and exit")
+    ap.add_argument("--fused-planes", action="store_true",
+                    help="3-D levels with 256 x 256 planes take the fused one-pass plane transforms")
+    ap.add_argument("--no-alternatives", action="store_true",
+                    help="skip the second measurement of the step with the fused 256 x 256 plane transforms")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the continuous-batching serving workload (latency percentiles)")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests in the Poisson stream")
@@ -301,6 +305,8 @@ def main():
     wl = WORKLOADS[args.workload]
     shape, C, L, P, B = wl["shape"], wl["C"], wl["L"], wl["P"], wl["batch"]
     flags = dmcr.FLAG_RECOMPUTE if wl["recompute"] else 0
+    if args.fused_planes:
+        flags |= dmcr.FLAG_FUSED_PLANES
     desc = wl.get("descriptor", dmcr.DESC_S2)
     spec = dmcr.make_spec(shape, C, L, P, flags=flags, descriptor=desc, s3_max_disp=wl.get("s3", 0))
     K = dmcr.dmcr_descriptor_size(spec)
@@ -410,7 +416,7 @@ def main():
     else:
         roofline = dict(bound="hbm", kernel=dom["name"], achieved=round(dom["GBps"], 1), peak=HBM_PEAK_GBS,
                         unit="GB/s", frac=round(dom["GBps"] / HBM_PEAK_GBS, 4),
-                        traffic=stored_traffic(args.workload, dom["name"]),
+                        traffic=stored_traffic(args.workload + ("fused" if args.fused_planes else ""), dom["name"]),
                         avg_us=round(dom["avg_us"], 2), bytes_per_launch=dom["bytes_per_launch"],
                         source_hash=source_hash())
     total_bytes = sum(r["bytes_per_launch"] * r["launches"] for r in kern) / args.steps
@@ -431,9 +437,11 @@ def main():
                config=dict(workload=wl["desc"], shape=list(shape), channels=C, levels=L,
                            max_disp=list(spec.max_disp), K=K, batch=B, path="direct" if desc else "fft",
                            descriptor=["s2", "sbar", "stilde"][desc], s3_max_disp=spec.s3_max_disp,
-                           recompute=wl["recompute"], parallelism="single GPU"),
+                           recompute=wl["recompute"], fused_planes_256=bool(args.fused_planes),
+                           parallelism="single GPU"),
                roofline=roofline, step_roofline=step_roofline)
-    if len(shape) == 3 and shape[1] == shape[2] == 256 and not desc:
+    if len(shape) == 3 and shape[1] == shape[2] == 256 and not desc and not (args.fused_planes or
+                                                                              args.no_alternatives):
         # the same step with the fused one-pass plane transforms of 256 x 256 planes (opt-in)
         spec_f = dmcr.make_spec(shape, C, L, P, flags=flags | dmcr.FLAG_FUSED_PLANES, descriptor=desc,
                                 s3_max_disp=wl.get("s3", 0))

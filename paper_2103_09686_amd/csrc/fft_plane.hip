@@ -50,6 +50,10 @@ struct Plane {
     static constexpr int rpitch = nh + R2;   // inverse staging and the natural-order rows
     static constexpr int region = cmax(cmax(ex_size<LH>(nb), nh * cpitch), nb * rpitch);
     static constexpr int lds_len = NB * region + nh;
+    // the staging index maps use R2 | nb and R1 | nb (a lane set's column or row
+    // range starts on a multiple of R2 or R1); the launch uses one block per plane
+    static_assert(nb % R2 == 0 && nb % R1 == 0, "lane set must hold whole R1 and R2 groups");
+    static_assert(threads <= 1024 && lds_len * 8 <= 160 * 1024, "one plane per workgroup must fit a CU");
 };
 
 // threadIdx.x behind an optimisation barrier: the index arithmetic of a phase is

@@ -166,7 +166,8 @@ def serving(n_requests, rate, n_compare):
     print("serving: %d requests prepared in %.1f s" % (len(reqs), prep), file=sys.stderr, flush=True)
     opt = dmcr.Opt(max_iter=2000, tol_derr=1e-4)
     budget = int(0.6 * torch.cuda.mem_get_info()[0])
-    srv = serve.Server(serve.GpuExecutor(opt=opt), budget_bytes=budget, iters_per_tick=4, threads=8)
+    srv = serve.Server(serve.GpuExecutor(opt=opt), budget_bytes=budget, iters_per_tick=4, threads=8,
+                       asynchronous=True)
     done = srv.run(reqs)
     srv.close()
     live = serve.summary(done)
@@ -176,7 +177,8 @@ def serving(n_requests, rate, n_compare):
     for r in base:
         r.arrival = 0.0
     batched = copy.copy(base)
-    srv = serve.Server(serve.GpuExecutor(opt=opt), budget_bytes=budget, iters_per_tick=4, threads=8)
+    srv = serve.Server(serve.GpuExecutor(opt=opt), budget_bytes=budget, iters_per_tick=4, threads=8,
+                       asynchronous=True)
     torch.cuda.synchronize()
     tb = time.perf_counter()
     bdone = srv.run([copy.copy(r) for r in batched])

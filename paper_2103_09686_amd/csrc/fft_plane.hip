@@ -14,6 +14,10 @@
 // and are separated after the column transform with the Hermitian symmetry of
 // the DFT of a real sequence (the inverse takes Re and Im of the packed result).
 //
+// Planes of side 32..128 always take this path; 256 only with
+// DMCR_FLAG_FUSED_PLANES (one plane then holds a whole compute unit, so its loads
+// and stores cannot overlap: fewer bytes, but a lower bandwidth than two passes).
+//
 // Pencil DFTs are those of fft_reg.h: the contiguous-axis rows use the packed
 // real transform of length n/2 with lanes along a row; the columns use lanes
 // across columns, so every LDS gather and every global store of the column
@@ -43,7 +47,7 @@ struct Plane {
     static constexpr int threads = R2 * nb;
     // LDS: one region per lane set, holding its pencil exchange or its share of
     // a staged half plane (columns h nb.. of every row for the forward column
-    // phase, rows h nb.. for the inverse row phase), then the packed column
+    // phase, rows h nb.. for the inverse row phase), then the packed column.
     // Row pitches of R2 mod 32 float2: the rows that a wave touches at once (R2
     // lanes of 8 bytes each) start R2 * 8 bytes apart in the 64 four-byte banks.
     static constexpr int cpitch = nb + R2;   // forward staging: row pitch within a column set

@@ -14,6 +14,12 @@ stay resident in HBM.  Each scheduler tick
   3. retires slots that reached the error tolerance or the iteration cap and
      records latency from arrival to result.
 
+With asynchronous=True the groups do not wait for each other: a group is
+advanced again as soon as its own iterations finish, and requests are admitted
+into a group only between its advances.  A group of small fields then keeps
+iterating while a group of 256^3 fields works through its slower iterations,
+instead of idling to the end of a common tick.
+
 A slot's iterates do not depend on the other slots (see dmcr_solver_iterate),
 so a request's result is the same alone and in the mix.  The scheduler is
 written against a small executor interface so that its policy can be tested
@@ -65,7 +71,9 @@ class Executor:
 
 
 class Server:
-    def __init__(self, executor: Executor, budget_bytes: int, iters_per_tick: int = 4, threads: int = 8):
+    def __init__(self, executor: Executor, budget_bytes: int, iters_per_tick: int = 4, threads: int = 8,
+                 asynchronous: bool = False):
+        self.asynchronous = asynchronous
         self.ex = executor
         self.budget = budget_bytes
         self.iters_per_tick = iters_per_tick
@@ -114,9 +122,14 @@ class Server:
     def submit(self, req: Request):
         self.queue.append(req)
 
-    def _admit(self):
+    def _admit(self, busy=()):
+        """Admit queued requests into free slots; groups in `busy` are being advanced
+        and take no requests until they return."""
         waiting = []
         for req in self.queue:
+            if req.key in busy:
+                waiting.append(req)
+                continue
             g = self._group_for(req.key)
             if g is None and not self.groups and self.ex.footprint(req.key, 1) > self.budget:
                 # can never fit, even alone: fail it instead of waiting forever
@@ -132,18 +145,20 @@ class Server:
             self.owner[req.key][slot] = req
         self.queue = waiting
 
+    def _retire(self, k, finished):
+        for slot, status, E, iters in finished:
+            req = self.owner[k].pop(slot)
+            req.t_done = self.ex.now()
+            req.final_E, req.iters, req.status = E, iters, status
+            self.done.append(req)
+            self.free[k].append(slot)
+
     def tick(self):
         self._admit()
         busy = [k for k in self.groups if self.owner[k]]
         futs = {self.pool.submit(self.groups[k].step, self.iters_per_tick): k for k in busy}
         for f in cf.as_completed(futs):
-            k = futs[f]
-            for slot, status, E, iters in f.result():
-                req = self.owner[k].pop(slot)
-                req.t_done = self.ex.now()
-                req.final_E, req.iters, req.status = E, iters, status
-                self.done.append(req)
-                self.free[k].append(slot)
+            self._retire(futs[f], f.result())
         self.ticks += 1
         hook = getattr(self.ex, "after_tick", None)
         if hook:
@@ -154,6 +169,8 @@ class Server:
 
     def run(self, requests: List[Request], wait=None):
         """Release requests at their arrival times (executor clock) and serve until all finish."""
+        if self.asynchronous:
+            return self._run_async(requests, wait)
         pending = sorted(requests, key=lambda r: r.arrival)
         i = 0
         t0 = self.ex.now()
@@ -168,6 +185,38 @@ class Server:
                 (wait or self.ex.wait_until)(t0 + pending[i].arrival)
                 continue
             self.tick()
+        return self.done
+
+    def _run_async(self, requests: List[Request], wait=None):
+        pending = sorted(requests, key=lambda r: r.arrival)
+        i = 0
+        t0 = self.ex.now()
+        running: Dict[Tuple, cf.Future] = {}
+        while i < len(pending) or self.queue or running or any(self.owner[k] for k in self.groups):
+            now = self.ex.now() - t0
+            while i < len(pending) and pending[i].arrival <= now:
+                r = pending[i]
+                r.arrival += t0
+                self.submit(r)
+                i += 1
+            self._admit(busy=running)
+            for k in self.groups:
+                if self.owner[k] and k not in running:
+                    running[k] = self.pool.submit(self.groups[k].step, self.iters_per_tick)
+            if not running:
+                if i < len(pending):
+                    (wait or self.ex.wait_until)(t0 + pending[i].arrival)
+                    continue
+                if self.queue:
+                    raise RuntimeError("%d requests can be neither admitted nor failed" % len(self.queue))
+                break
+            timeout = None
+            if i < len(pending):
+                timeout = max(0.0, t0 + pending[i].arrival - self.ex.now())
+            finished, _ = cf.wait(list(running.values()), timeout=timeout, return_when=cf.FIRST_COMPLETED)
+            for k in [k for k, f in running.items() if f in finished]:
+                self._retire(k, running.pop(k).result())
+                self.ticks += 1
         return self.done
 
     def close(self):

@@ -56,14 +56,15 @@ def test_alone_equals_in_the_mix(sv, method):
     srv4.close()
 
 
-def test_short_mixed_stream_converges(sv):
+@pytest.mark.parametrize("asynchronous", [False, True])
+def test_short_mixed_stream_converges(sv, asynchronous):
     from paper_2103_09686_amd import dmcr
     cache = sv.TargetCache(variants=1)
     sizes = [(128, 128), (256, 256), (64, 64, 64)]
     stream = sv.request_stream(24, 40.0, seed=5, sizes=sizes)
     reqs = sv.gpu_requests(stream, cache)
     ex = sv.GpuExecutor(opt=dmcr.Opt(max_iter=2000, tol_derr=1e-4))
-    srv = sv.Server(ex, budget_bytes=8 << 30, iters_per_tick=4, threads=4)
+    srv = sv.Server(ex, budget_bytes=8 << 30, iters_per_tick=4, threads=4, asynchronous=asynchronous)
     done = srv.run(reqs)
     srv.close()
     s = sv.summary(done)

@@ -1,6 +1,8 @@
 """The continuous-batching scheduler on a simulated executor (virtual clock, fake HBM
 budget, fixed per-request iteration needs): admission by footprint, slot reuse,
 release of idle groups, latency accounting, no deadlock on requests that cannot fit."""
+import time
+
 import numpy as np
 import pytest
 
@@ -138,3 +140,62 @@ def test_request_stream_and_level_rule():
     assert serve.levels_for(64, 31) == 1 and serve.levels_for(128, 31) == 2 and serve.levels_for(256, 31) == 3
     key = serve.make_key((128, 128, 128), 3)
     assert key[1] == 2 and key[2] == serve.levels_for(128, 16)
+
+
+# -- asynchronous groups (real clock: each group's advance sleeps in proportion to
+# its field size, so groups of different sizes finish their advances at different times)
+class TimedGroup(FakeGroup):
+    def __init__(self, ex, key, capacity):
+        super().__init__(ex, key, capacity)
+        self.in_step = False
+
+    def admit(self, slot, req):
+        assert not self.in_step, "request admitted while the group is being advanced"
+        super().admit(slot, req)
+
+    def step(self, iterations):
+        self.in_step = True
+        time.sleep(2e-5 * self.key[0] * iterations)
+        out = super().step(iterations)
+        self.in_step = False
+        return out
+
+
+class TimedExecutor(FakeExecutor):
+    def make_group(self, key, capacity):
+        return TimedGroup(self, key, capacity)
+
+    def now(self):
+        return time.perf_counter()
+
+    def wait_until(self, t):
+        d = t - time.perf_counter()
+        if d > 0:
+            time.sleep(min(d, 0.005))
+
+
+def test_asynchronous_groups_finish_every_request():
+    ex = TimedExecutor(caps={(1,): 3, (20,): 2})
+    srv = serve.Server(ex, budget_bytes=10 ** 9, iters_per_tick=4, threads=4, asynchronous=True)
+    rs = reqs(40, [(1,), (20,)], seed=5, rate=400.0)
+    need = {r.rid: r.payload for r in rs}
+    done = srv.run(rs)
+    srv.close()
+    assert sorted(r.rid for r in done) == list(range(40))
+    for r in done:
+        assert r.iters == need[r.rid] and r.status == 0
+        assert r.t_done >= r.t_admit >= r.arrival
+    assert ex.max_active[(1,)] <= 3 and ex.max_active[(20,)] <= 2
+
+
+def test_asynchronous_budget_and_unfit_requests():
+    ex = TimedExecutor()
+    srv = serve.Server(ex, budget_bytes=450, iters_per_tick=4, threads=2, asynchronous=True)
+    rs = reqs(20, [(1,), (2,)], seed=3, rate=400.0)
+    done = srv.run(rs)
+    srv.close()
+    assert len(done) == 20 and all(r.status == 0 for r in done) and srv.peak_bytes <= 450
+    srv = serve.Server(TimedExecutor(), budget_bytes=50, iters_per_tick=4, threads=1, asynchronous=True)
+    done = srv.run([serve.Request(rid=0, arrival=0.0, key=(1,), voxels=1, payload=5)])
+    srv.close()
+    assert len(done) == 1 and done[0].status == -2

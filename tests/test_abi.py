@@ -90,6 +90,7 @@ def test_config_sizes_quoted_in_the_workloads(dm):
     (dict(shape=(64, 64), n_channels=2, pairs=((1, 0),)), -1),
     (dict(shape=(64, 64, 64), max_disp=(20,), path=2), -3),  # DIRECT halo does not fit LDS
     (dict(shape=(64, 64), flags=4), -1),                       # unknown flag bit
+    (dict(shape=(2048, 8), max_disp=(3,), path=1), -3),         # FFT axis above 1024
 ])
 def test_validation(dm, kw, code):
     spec = dm.Spec(**kw)
@@ -139,3 +140,10 @@ def test_three_point_validation(dm, ora):
         with pytest.raises(dm.DmcrError) as ei:
             dm.dmcr_descriptor_size(dm.Spec(**kw))
         assert ei.value.code == code, kw
+
+
+def test_empty_batch_rejected(dm):
+    spec = dm.Spec(shape=(64, 64))
+    with pytest.raises(dm.DmcrError) as e:
+        dm.dmcr_workspace_size(spec, 0)
+    assert e.value.code == -1

@@ -70,6 +70,9 @@ CASES = [
     ((128, 128), 1, 2, (31, 31), (), 1),
     ((2, 2), 1, 1, (0,), (), 1),
     ((4, 4, 4), 1, 2, (1, 0), (), 0),
+    # the longest axis the LDS transforms take (1024), on each axis
+    ((1024, 16), 1, 1, (7,), (), 1),
+    ((16, 1024), 2, 1, (7,), (), 1),
     # square planes: the contiguous axis and axis 1 in one fused pass (n = 32..256)
     ((8, 32, 32), 2, 1, (3,), (), 1),
     ((4, 64, 64), 1, 2, (1, 0), (), 1),

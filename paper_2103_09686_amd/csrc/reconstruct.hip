@@ -8,8 +8,16 @@
 // covers the whole batch.  The host reads back only the per-element scalars
 // each decision needs (loss, penalty, directional derivatives).
 //
-// Direction: two-loop recursion (Nocedal & Wright, Alg. 7.4) with initial
-// scaling gamma = s'y / y'y of the newest accepted pair.  Box handling
+// Direction: the compact representation of the L-BFGS inverse Hessian (Byrd,
+// Nocedal & Schnabel, Math. Prog. 63, 1994, Thm. 2.2) with H0 = gamma I, gamma =
+// s'y / y'y of the newest accepted pair:
+//   H g = gamma g + S p - gamma Y q,  q = R^-1 S'g,  p = R^-T ((D + gamma Y'Y) q - gamma Y'g),
+// R the upper triangle of S'Y over the element's valid pairs in age order, D its
+// diagonal.  It equals the two-loop recursion (Nocedal & Wright, Alg. 7.4) in
+// exact arithmetic, but needs only one pass of dot products over the history,
+// an O(m^2) float64 solve per element and one pass of linear combination,
+// instead of 2m dependent dot/update passes.  S'Y and Y'Y are kept per element
+// and extended by one row and column per accepted pair.  Box handling
 // (Sec. 3.1): PROJECT clips trial points to [lo, hi] and zeroes direction
 // components that push an active bound outward; PENALTY adds lambda E^bc with
 // E^bc as printed in Sec. 3.1 and lambda = kappa * E held constant in the
@@ -64,13 +72,28 @@ __global__ __launch_bounds__(kV) void k_dot_part(const float *a, const float *bv
     if (threadIdx.x == 0) part[b * nblk + blockIdx.x] = red[0];
 }
 
-__global__ void k_sum_parts(const double *part, int nblk, double *out, int B)
+// Deterministic sum of one element's block partials: thread t adds partials
+// t, t + kV, ... in order, then a fixed tree.  One block per element.
+__device__ __forceinline__ double block_sum(const double *p, int cnt, int64_t stride, double *red)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
     double s = 0.0;
-    for (int i = 0; i < nblk; ++i) s += part[(int64_t)b * nblk + i];
-    out[b] = s;
+    for (int i = threadIdx.x; i < cnt; i += kV) s += p[i * stride];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kV / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// out[b] = sum of part[b][0 .. nblk)   (grid: one block of kV threads per element)
+__global__ __launch_bounds__(kV) void k_sum_parts(const double *part, int nblk, double *out, int B)
+{
+    __shared__ double red[kV];
+    const int64_t b = blockIdx.x;
+    const double s = block_sum(part + b * nblk, nblk, 1, red);
+    if (threadIdx.x == 0) out[b] = s;
 }
 
 __global__ void k_fill(double *p, double v, int n)
@@ -79,47 +102,175 @@ __global__ void k_fill(double *p, double v, int n)
     if (i < n) p[i] = v;
 }
 
-// y[b] += sgn * coef[b] * x[b]   (coefficient read on the device; a zero
-// coefficient leaves y untouched without reading x, whose history slot may
-// hold nothing valid)
-__global__ __launch_bounds__(kV) void k_axpy(float *y, const float *x, const double *coef, double sgn, int64_t n)
+// Dot products of one vector x with a list of vectors, all per element b:
+// out index ds.out[k] receives x[b] . v_k[b].  Up to kMaxDots of them (the g
+// pass has 2m + 1, the new-pair pass 3m, m <= 32).
+constexpr int kMaxDots = 100;
+struct DotSet {
+    const float *v[kMaxDots];
+    int out[kMaxDots];
+    int count;
+};
+
+// part[(b nblk + blk) kMaxDots + out_k] = block blk's share of x[b] . v_k[b]
+// (fixed order: strided element loop, then wave shuffles, then waves in order)
+__global__ __launch_bounds__(kV) void k_dots_part(const float *x, DotSet ds, int64_t n, double *part, int nblk)
 {
+    __shared__ double red[kV / 64][8];
     const int64_t b = blockIdx.y;
-    if (coef[b] == 0.0) return;
-    const float c = (float)(sgn * coef[b]);
-    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV)
-        y[b * n + i] += c * x[b * n + i];
+    const float *X = x + b * n;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int c0 = 0; c0 < ds.count; c0 += 8) {
+        const int cn = min(8, ds.count - c0);
+        double acc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+#pragma unroll 2
+        for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)nblk * kV) {
+            const double xv = X[i];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k < cn) acc[k] += xv * (double)ds.v[c0 + k][b * n + i];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_down(acc[k], off);
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) red[wave][k] = acc[k];
+        __syncthreads();
+        if (threadIdx.x < cn) {
+            double sum = 0.0;
+            for (int w = 0; w < kV / 64; ++w) sum += red[w][threadIdx.x];
+            part[((int64_t)b * nblk + blockIdx.x) * kMaxDots + ds.out[c0 + threadIdx.x]] = sum;
+        }
+        __syncthreads();
+    }
 }
 
-// y[b] *= sgn * coef[b]
-__global__ __launch_bounds__(kV) void k_scale(float *y, const double *coef, double sgn, int64_t n)
+// dots[b kMaxDots + out_k] = sum over the blocks' partials (grid: element b x dot k)
+__global__ __launch_bounds__(kV) void k_dots_sum(const double *part, int nblk, DotSet ds, double *dots)
 {
-    const int64_t b = blockIdx.y;
-    const float c = (float)(sgn * coef[b]);
-    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV)
-        y[b * n + i] *= c;
+    __shared__ double red[kV];
+    const int64_t b = blockIdx.x;
+    const int o = ds.out[blockIdx.y];
+    const double s = block_sum(part + b * nblk * kMaxDots + o, nblk, kMaxDots, red);
+    if (threadIdx.x == 0) dots[b * kMaxDots + o] = s;
 }
 
-__global__ void k_alpha(const double *dot, const double *rho, double *alpha, int B)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) alpha[b] = rho[b] != 0.0 ? rho[b] * dot[b] : 0.0;  // empty slot: no contribution
-}
-
-__global__ void k_beta(const double *dot, const double *rho, const double *alpha, double *coef, int B)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) coef[b] = rho[b] != 0.0 ? alpha[b] - rho[b] * dot[b] : 0.0;
-}
-
-// new pair in ring slot `slot`: rho = 1/s'y if accepted and s'y > eps y'y, else 0; gamma follows
-__global__ void k_pair(const double *sy, const double *yy, const int *acc, double *rho_slot, double *gamma, int B)
+// Compact-representation coefficients of element b (one thread each):
+// dots[j] = S_j.g, dots[m + j] = Y_j.g (ring slot j), dots[2m] = g.g;
+// SY[b][i][j] = s_i.y_j, YY[b][i][j] = y_i.y_j.  Valid pairs (rho != 0) in age
+// order from the oldest; H g = cg g + sum_j cS_j S_j + cY_j Y_j.
+__global__ void k_lbfgs_coef(const double *dots, const double *rho, const double *gamma, const double *SY,
+                             const double *YY, int head, int count, int m, int B, double *cS, double *cY, double *cg,
+                             double *gg)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
-    const bool ok = acc[b] && sy[b] > 2.220446049250313e-16 * yy[b] && yy[b] > 0.0;
-    rho_slot[b] = ok ? 1.0 / sy[b] : 0.0;
-    if (ok) gamma[b] = sy[b] / yy[b];
+    const double *db = dots + (int64_t)b * kMaxDots;
+    const double *sy = SY + (int64_t)b * m * m, *yy = YY + (int64_t)b * m * m;
+    int idx[32];
+    int k = 0;
+    for (int t = count - 1; t >= 0; --t) {
+        const int i = (head - t + m) % m;
+        if (rho[(int64_t)i * B + b] != 0.0) idx[k++] = i;
+    }
+    const double gam = gamma[b];
+    double q[32], pc[32];
+    for (int u = k - 1; u >= 0; --u) {            // R q = S'g (back substitution)
+        double acc = db[idx[u]];
+        for (int v = u + 1; v < k; ++v) acc -= sy[idx[u] * m + idx[v]] * q[v];
+        q[u] = acc / sy[idx[u] * m + idx[u]];
+    }
+    for (int u = 0; u < k; ++u) {                 // R' p = D q + gamma Y'Y q - gamma Y'g
+        double acc = sy[idx[u] * m + idx[u]] * q[u] - gam * db[m + idx[u]];
+        for (int v = 0; v < k; ++v) acc += gam * yy[idx[u] * m + idx[v]] * q[v];
+        for (int v = 0; v < u; ++v) acc -= sy[idx[v] * m + idx[u]] * pc[v];
+        pc[u] = acc / sy[idx[u] * m + idx[u]];
+    }
+    for (int i = 0; i < m; ++i) {
+        cS[(int64_t)b * m + i] = 0.0;
+        cY[(int64_t)b * m + i] = 0.0;
+    }
+    for (int u = 0; u < k; ++u) {
+        cS[(int64_t)b * m + idx[u]] = pc[u];
+        cY[(int64_t)b * m + idx[u]] = -gam * q[u];
+    }
+    cg[b] = gam;
+    gg[b] = db[2 * m];
+}
+
+// d = -(cg g + sum_j cS_j S_j + cY_j Y_j) over the ring slots in use, oldest
+// first (so that an element's sum runs in the same order wherever its pairs sit
+// in the shared ring), with projection: components that push an active bound
+// outward are zeroed.  A zero coefficient skips its history vector (which may
+// hold nothing valid).  part = block partials of g . d.
+__global__ __launch_bounds__(kV) void k_combine_dir(const float *x, const float *g, float *d, const float *Sb,
+                                                    const float *Yb, const double *cS, const double *cY,
+                                                    const double *cg, int m, int head, int count, int B, int64_t n,
+                                                    int project, float lo, float hi, double *part, int nblk)
+{
+    __shared__ float cs[32], cy[32];
+    __shared__ double red[kV];
+    const int64_t b = blockIdx.y;
+    if (threadIdx.x < count) {
+        cs[threadIdx.x] = (float)cS[b * m + threadIdx.x];
+        cy[threadIdx.x] = (float)cY[b * m + threadIdx.x];
+    }
+    __syncthreads();
+    const float c0 = (float)cg[b];
+    const int64_t stride = (int64_t)B * n;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)nblk * kV) {
+        const int64_t j = b * n + i;
+        const float gv = g[j];
+        float h = c0 * gv;
+        for (int t = count - 1; t >= 0; --t) {
+            const int k = (head - t + m) % m;
+            if (cs[k] != 0.f) h += cs[k] * Sb[k * stride + j];
+            if (cy[k] != 0.f) h += cy[k] * Yb[k * stride + j];
+        }
+        const float xv = x[j];
+        float dv = -h;
+        if (project && ((xv <= lo && dv < 0.f) || (xv >= hi && dv > 0.f))) dv = 0.f;
+        d[j] = dv;
+        acc += (double)gv * (double)dv;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kV / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[b * nblk + blockIdx.x] = red[0];
+}
+
+// New pair in ring slot `slot` (written by k_accept for accepted elements):
+// dots[j] = s_j.y_new, dots[m + j] = y_j.y_new, dots[2m + j] = s_new.y_j (j < count).
+// rho = 1/s'y if accepted and s'y > eps y'y, else 0; gamma follows; the slot's
+// row and column of S'Y and Y'Y are refreshed.
+__global__ void k_pair_update(const double *dots, const int *acc, int slot, int count, int m, int B, double *rho,
+                              double *gamma, double *SY, double *YY)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    if (!acc[b]) {
+        rho[(int64_t)slot * B + b] = 0.0;
+        return;
+    }
+    const double *db = dots + (int64_t)b * kMaxDots;
+    const double sy = db[2 * m + slot], yy = db[m + slot];
+    const bool ok = sy > 2.220446049250313e-16 * yy && yy > 0.0;
+    rho[(int64_t)slot * B + b] = ok ? 1.0 / sy : 0.0;
+    if (ok) gamma[b] = sy / yy;
+    double *syb = SY + (int64_t)b * m * m, *yyb = YY + (int64_t)b * m * m;
+    for (int j = 0; j < count; ++j) {
+        syb[slot * m + j] = db[2 * m + j];
+        syb[j * m + slot] = db[j];
+        yyb[slot * m + j] = db[m + j];
+        yyb[j * m + slot] = db[m + j];
+    }
 }
 
 // clear the history of one element
@@ -287,7 +438,9 @@ __global__ __launch_bounds__(kV) void k_pen_grad(const float *x, float *g, const
 
 struct RLayout {
     size_t xt, g, gt, d, s, y;
-    size_t part, dot1, dot2, rho, alpha, gamma, coef, E, Et, Ebc, als, active, acc, flag;
+    size_t part, dot1, dot2, rho, gamma, E, Et, Ebc, als, active, acc, flag;
+    size_t SY, YY, cS, cY, cg, mdots, mpart;   // L-BFGS compact representation
+    int nblkG;                                 // blocks per element of the history dot passes
     size_t sl_f, sl_iters, sl_evals, sl_status;   // Adam: per-slot state kept on the device
     int nblk;
     size_t bytes;
@@ -317,9 +470,17 @@ RLayout r_layout(const Plan &p, const dmcr_opt &o)
     r.dot1 = take(B8);
     r.dot2 = take(B8);
     r.rho = take((size_t)o.m * B8);
-    r.alpha = take((size_t)o.m * B8);
     r.gamma = take(B8);
-    r.coef = take(B8);
+    r.SY = take((size_t)o.m * o.m * B8);
+    r.YY = take((size_t)o.m * o.m * B8);
+    r.cS = take((size_t)o.m * B8);
+    r.cY = take((size_t)o.m * B8);
+    r.cg = take(B8);
+    r.mdots = take((size_t)kMaxDots * B8);
+    // history passes read up to 2m + 1 vectors per element: enough blocks to keep
+    // the loads of a large field in flight
+    r.nblkG = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (n + 4 * kV - 1) / (4 * kV)));
+    r.mpart = take((size_t)r.nblkG * kMaxDots * B8);
     r.E = take(B8);
     r.Et = take(B8);
     r.Ebc = take(B8);
@@ -377,8 +538,50 @@ struct Solver {
     hipError_t dot(const float *a, const float *bv, const float *cv, double *out) const
     {
         hipLaunchKernelGGL(k_dot_part, dim3(r.nblk, B), dim3(kV), 0, st, a, bv, cv, n, at<double>(r.part), r.nblk);
-        hipLaunchKernelGGL(k_sum_parts, sg, dim3(64), 0, st, at<double>(r.part), r.nblk, out, B);
+        hipLaunchKernelGGL(k_sum_parts, dim3(B), dim3(kV), 0, st, at<double>(r.part), r.nblk, out, B);
         return hipGetLastError();
+    }
+
+    // dots of x with the listed vectors (DotSet), summed into mdots
+    hipError_t dots(const float *x, const DotSet &ds) const
+    {
+        hipLaunchKernelGGL(k_dots_part, dim3(r.nblkG, B), dim3(kV), 0, st, x, ds, n, at<double>(r.mpart), r.nblkG);
+        hipLaunchKernelGGL(k_dots_sum, dim3(B, ds.count), dim3(kV), 0, st, at<double>(r.mpart), r.nblkG, ds,
+                           at<double>(r.mdots));
+        return hipGetLastError();
+    }
+
+    // S_j.g -> [j], Y_j.g -> [m + j] (ring slots j < count), g.g -> [2m]
+    hipError_t dots_g(const float *g, int count) const
+    {
+        DotSet ds{};
+        for (int j = 0; j < count; ++j) {
+            ds.v[ds.count] = S(j);
+            ds.out[ds.count++] = j;
+            ds.v[ds.count] = Y(j);
+            ds.out[ds.count++] = m + j;
+        }
+        ds.v[ds.count] = g;
+        ds.out[ds.count++] = 2 * m;
+        return dots(g, ds);
+    }
+
+    // new pair in ring slot `slot`: s_j.y_new -> [j], y_j.y_new -> [m + j],
+    // s_new.y_j -> [2m + j] (j < count, the ring slots in use including `slot`)
+    hipError_t dots_pair(int slot, int count) const
+    {
+        DotSet a{}, c{};
+        for (int j = 0; j < count; ++j) {
+            a.v[a.count] = S(j);
+            a.out[a.count++] = j;
+            a.v[a.count] = Y(j);
+            a.out[a.count++] = m + j;
+            c.v[c.count] = Y(j);
+            c.out[c.count++] = 2 * m + j;
+        }
+        hipError_t e = dots(Y(slot), a);
+        if (e != hipSuccess) return e;
+        return dots(S(slot), c);
     }
 
     dmcr_status evaluate(const float *pt, double *Ed, float *grad) const
@@ -387,7 +590,7 @@ struct Solver {
         if (penalty) {
             hipLaunchKernelGGL(k_pen_part, dim3(r.nblk, B), dim3(kV), 0, st, pt, n, invN, lo, hi, at<double>(r.part),
                                r.nblk);
-            hipLaunchKernelGGL(k_sum_parts, sg, dim3(64), 0, st, at<double>(r.part), r.nblk, at<double>(r.Ebc), B);
+            hipLaunchKernelGGL(k_sum_parts, dim3(B), dim3(kV), 0, st, at<double>(r.part), r.nblk, at<double>(r.Ebc), B);
             hipLaunchKernelGGL(k_pen_grad, vg, dim3(kV), 0, st, pt, grad, Ed, bd.kappa, n, invN, lo, hi);
             RT(hipGetLastError());
         }
@@ -448,7 +651,7 @@ dmcr_status Solver::start(float *x, const int *which, int nwhich, dmcr_slot *slo
         if (penalty) {
             hipLaunchKernelGGL(k_pen_part, dim3(r.nblk, 1), dim3(kV), 0, st, xb, n, invN, lo, hi, at<double>(r.part),
                                r.nblk);
-            hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, at<double>(r.part), r.nblk, Ebcd + b, 1);
+            hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kV), 0, st, at<double>(r.part), r.nblk, Ebcd + b, 1);
             hipLaunchKernelGGL(k_pen_grad, dim3(vblocks(n), 1), dim3(kV), 0, st, xb, gb, Ed + b, bd.kappa, n, invN, lo,
                                hi);
         }
@@ -538,9 +741,11 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
 {
     if (o.method == DMCR_OPT_ADAM) return iterate_adam(x, slots, iterations);
     float *xt = at<float>(r.xt), *g = at<float>(r.g), *gt = at<float>(r.gt), *d = at<float>(r.d);
-    double *rho = at<double>(r.rho), *alpha = at<double>(r.alpha), *gamma = at<double>(r.gamma);
-    double *coef = at<double>(r.coef), *dot1 = at<double>(r.dot1), *dot2 = at<double>(r.dot2);
+    double *rho = at<double>(r.rho), *gamma = at<double>(r.gamma);
+    double *dot1 = at<double>(r.dot1), *dot2 = at<double>(r.dot2);
     double *Etd = at<double>(r.Et), *Ebcd = at<double>(r.Ebc), *als = at<double>(r.als);
+    double *SY = at<double>(r.SY), *YY = at<double>(r.YY), *cS = at<double>(r.cS), *cY = at<double>(r.cY);
+    double *cg = at<double>(r.cg), *mdots = at<double>(r.mdots);
     int *active = at<int>(r.active), *accd = at<int>(r.acc), *flagd = at<int>(r.flag);
 
     std::vector<double> hE(B), hEbc(B, 0.0), hd(B), hd2(B), step(B);
@@ -553,24 +758,14 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
         for (int b = 0; b < B; ++b) any |= running(b);
         if (!any) break;
 
-        // ---- direction d = -H g over the ring (newest first), then projection ----
-        RT(hipMemcpyAsync(d, g, (size_t)B * n * 4, hipMemcpyDeviceToDevice, st));
-        for (int k = 0; k < count; ++k) {
-            const int i = (head - k + m) % m;
-            RT(dot(S(i), d, nullptr, dot1));
-            hipLaunchKernelGGL(k_alpha, sg, dim3(64), 0, st, dot1, rho + i * B, alpha + i * B, B);
-            hipLaunchKernelGGL(k_axpy, vg, dim3(kV), 0, st, d, Y(i), alpha + i * B, -1.0, n);
-        }
-        hipLaunchKernelGGL(k_scale, vg, dim3(kV), 0, st, d, gamma, 1.0, n);
-        for (int k = count - 1; k >= 0; --k) {
-            const int i = (head - k + m) % m;
-            RT(dot(Y(i), d, nullptr, dot1));
-            hipLaunchKernelGGL(k_beta, sg, dim3(64), 0, st, dot1, rho + i * B, alpha + i * B, coef, B);
-            hipLaunchKernelGGL(k_axpy, vg, dim3(kV), 0, st, d, S(i), coef, 1.0, n);
-        }
-        hipLaunchKernelGGL(k_finish_dir, vg, dim3(kV), 0, st, x, d, n, (int)project, lo, hi);
-        RT(dot(g, d, nullptr, dot1));
-        RT(dot(g, g, nullptr, dot2));
+        // ---- direction d = -H g (compact representation), then projection ----
+        RT(dots_g(g, count));
+        hipLaunchKernelGGL(k_lbfgs_coef, sg, dim3(64), 0, st, mdots, rho, gamma, SY, YY, head, count, m, B, cS, cY,
+                           cg, dot2);
+        hipLaunchKernelGGL(k_combine_dir, dim3(r.nblkG, B), dim3(kV), 0, st, x, g, d, S(0), Y(0), cS, cY, cg, m, head,
+                           count, B, n, (int)project, lo, hi, at<double>(r.mpart), r.nblkG);
+        hipLaunchKernelGGL(k_sum_parts, dim3(B), dim3(kV), 0, st, at<double>(r.mpart), r.nblkG, dot1, B);
+        RT(hipGetLastError());
         RS(fetch(dot1, hd));
         RS(fetch(dot2, hd2));
         RT(hipStreamSynchronize(st));
@@ -626,12 +821,12 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
         const int slot = (head + 1) % m;
         RS(put(accd, acc));
         hipLaunchKernelGGL(k_accept, vg, dim3(kV), 0, st, accd, x, xt, g, gt, S(slot), Y(slot), n);
-        RT(dot(S(slot), Y(slot), nullptr, dot1));
-        RT(dot(Y(slot), Y(slot), nullptr, dot2));
-        hipLaunchKernelGGL(k_pair, sg, dim3(64), 0, st, dot1, dot2, accd, rho + slot * B, gamma, B);
+        const int cnew = std::min(count + 1, m);   // ring slots in use: 0 .. cnew - 1
+        RT(dots_pair(slot, cnew));
+        hipLaunchKernelGGL(k_pair_update, sg, dim3(64), 0, st, mdots, accd, slot, cnew, m, B, rho, gamma, SY, YY);
         RT(hipGetLastError());
         head = slot;
-        count = std::min(count + 1, m);
+        count = cnew;
         bool any_fail = false;
         for (int b = 0; b < B; ++b) {
             flag[b] = 0;

@@ -102,58 +102,95 @@ __global__ void k_fill(double *p, double v, int n)
     if (i < n) p[i] = v;
 }
 
-// Dot products of one vector x with a list of vectors, all per element b:
-// out index ds.out[k] receives x[b] . v_k[b].  Up to kMaxDots of them (the g
-// pass has 2m + 1, the new-pair pass 3m, m <= 32).
-constexpr int kMaxDots = 100;
-struct DotSet {
-    const float *v[kMaxDots];
-    int out[kMaxDots];
-    int count;
-};
+// History dot products, one pass over the ring slots j < cnt in use, per element b:
+//   [j] = S_j.g, [m + j] = Y_j.g, [2m] = g.g
+// and, with a new pair (s_new, y_new) just written to a ring slot,
+//   [2m + 1 + j] = s_j.y_new, [3m + 1 + j] = y_j.y_new, [4m + 1 + j] = s_new.y_j.
+// Fixed order throughout: strided element loop, wave shuffles, waves in order.
+constexpr int kMaxDots = 5 * 32 + 1;
+constexpr int kHistJ = 4;   // ring slots per chunk (5 kHistJ + 1 accumulators)
 
-// part[(b nblk + blk) kMaxDots + out_k] = block blk's share of x[b] . v_k[b]
-// (fixed order: strided element loop, then wave shuffles, then waves in order)
-__global__ __launch_bounds__(kV) void k_dots_part(const float *x, DotSet ds, int64_t n, double *part, int nblk)
+__device__ __forceinline__ int hist_count(int cnt, bool pair) { return 2 * cnt + 1 + (pair ? 3 * cnt : 0); }
+
+__device__ __forceinline__ int hist_out(int k, int cnt, int m)
 {
-    __shared__ double red[kV / 64][8];
+    if (k < cnt) return k;
+    if (k < 2 * cnt) return m + (k - cnt);
+    if (k == 2 * cnt) return 2 * m;
+    k -= 2 * cnt + 1;
+    if (k < cnt) return 2 * m + 1 + k;
+    if (k < 2 * cnt) return 3 * m + 1 + (k - cnt);
+    return 4 * m + 1 + (k - 2 * cnt);
+}
+
+__global__ __launch_bounds__(kV) void k_hist_dots(const float *Sb, const float *Yb, int cnt, const float *g,
+                                                  const float *ynew, const float *snew, int m, int B, int64_t n,
+                                                  double *part, int nblk)
+{
+    constexpr int NA = 5 * kHistJ + 1;
+    __shared__ double red[kV / 64][NA];
     const int64_t b = blockIdx.y;
-    const float *X = x + b * n;
+    const int64_t stride = (int64_t)B * n;
+    const bool pair = ynew != nullptr;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int c0 = 0; c0 < ds.count; c0 += 8) {
-        const int cn = min(8, ds.count - c0);
-        double acc[8];
+    double *pb = part + ((int64_t)b * nblk + blockIdx.x) * kMaxDots;
+    for (int c0 = 0; c0 < cnt || c0 == 0; c0 += kHistJ) {
+        const int cj = min(kHistJ, cnt - c0);
+        double acc[NA];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] = 0.0;
-#pragma unroll 2
+        for (int k = 0; k < NA; ++k) acc[k] = 0.0;
         for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)nblk * kV) {
-            const double xv = X[i];
+            const int64_t e = b * n + i;
+            const double gv = g[e];
+            const double yn = pair ? (double)ynew[e] : 0.0, sn = pair ? (double)snew[e] : 0.0;
+            if (c0 == 0) acc[NA - 1] += gv * gv;
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (k < cn) acc[k] += xv * (double)ds.v[c0 + k][b * n + i];
+            for (int jj = 0; jj < kHistJ; ++jj) {
+                if (jj < cj) {
+                    const int64_t o = (int64_t)(c0 + jj) * stride + e;
+                    const double sv = Sb[o], yv = Yb[o];
+                    acc[5 * jj + 0] += sv * gv;
+                    acc[5 * jj + 1] += yv * gv;
+                    if (pair) {
+                        acc[5 * jj + 2] += sv * yn;
+                        acc[5 * jj + 3] += yv * yn;
+                        acc[5 * jj + 4] += sn * yv;
+                    }
+                }
+            }
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
+        for (int k = 0; k < NA; ++k)
             for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_down(acc[k], off);
         if (lane == 0)
 #pragma unroll
-            for (int k = 0; k < 8; ++k) red[wave][k] = acc[k];
+            for (int k = 0; k < NA; ++k) red[wave][k] = acc[k];
         __syncthreads();
-        if (threadIdx.x < cn) {
+        if (threadIdx.x < NA) {
+            const int k = threadIdx.x;
             double sum = 0.0;
-            for (int w = 0; w < kV / 64; ++w) sum += red[w][threadIdx.x];
-            part[((int64_t)b * nblk + blockIdx.x) * kMaxDots + ds.out[c0 + threadIdx.x]] = sum;
+            for (int w = 0; w < kV / 64; ++w) sum += red[w][k];
+            if (k == NA - 1) {
+                if (c0 == 0) pb[2 * m] = sum;
+            } else {
+                const int jj = k / 5, r = k % 5, j = c0 + jj;
+                if (jj < cj && (r < 2 || pair)) {
+                    const int o = r == 0 ? j : r == 1 ? m + j : r == 2 ? 2 * m + 1 + j : r == 3 ? 3 * m + 1 + j
+                                                                                          : 4 * m + 1 + j;
+                    pb[o] = sum;
+                }
+            }
         }
         __syncthreads();
     }
 }
 
-// dots[b kMaxDots + out_k] = sum over the blocks' partials (grid: element b x dot k)
-__global__ __launch_bounds__(kV) void k_dots_sum(const double *part, int nblk, DotSet ds, double *dots)
+// dots[b kMaxDots + o] = sum over the blocks' partials (grid: element b x dot k)
+__global__ __launch_bounds__(kV) void k_hist_sum(const double *part, int nblk, int cnt, int m, double *dots)
 {
     __shared__ double red[kV];
     const int64_t b = blockIdx.x;
-    const int o = ds.out[blockIdx.y];
+    const int o = hist_out(blockIdx.y, cnt, m);
     const double s = block_sum(part + b * nblk * kMaxDots + o, nblk, kMaxDots, red);
     if (threadIdx.x == 0) dots[b * kMaxDots + o] = s;
 }
@@ -247,7 +284,7 @@ __global__ __launch_bounds__(kV) void k_combine_dir(const float *x, const float 
 }
 
 // New pair in ring slot `slot` (written by k_accept for accepted elements):
-// dots[j] = s_j.y_new, dots[m + j] = y_j.y_new, dots[2m + j] = s_new.y_j (j < count).
+// dots[2m + 1 + j] = s_j.y_new, [3m + 1 + j] = y_j.y_new, [4m + 1 + j] = s_new.y_j (j < count).
 // rho = 1/s'y if accepted and s'y > eps y'y, else 0; gamma follows; the slot's
 // row and column of S'Y and Y'Y are refreshed.
 __global__ void k_pair_update(const double *dots, const int *acc, int slot, int count, int m, int B, double *rho,
@@ -260,16 +297,17 @@ __global__ void k_pair_update(const double *dots, const int *acc, int slot, int 
         return;
     }
     const double *db = dots + (int64_t)b * kMaxDots;
-    const double sy = db[2 * m + slot], yy = db[m + slot];
+    const double *sjy = db + 2 * m + 1, *yjy = db + 3 * m + 1, *sny = db + 4 * m + 1;
+    const double sy = sny[slot], yy = yjy[slot];
     const bool ok = sy > 2.220446049250313e-16 * yy && yy > 0.0;
     rho[(int64_t)slot * B + b] = ok ? 1.0 / sy : 0.0;
     if (ok) gamma[b] = sy / yy;
     double *syb = SY + (int64_t)b * m * m, *yyb = YY + (int64_t)b * m * m;
     for (int j = 0; j < count; ++j) {
-        syb[slot * m + j] = db[2 * m + j];
-        syb[j * m + slot] = db[j];
-        yyb[slot * m + j] = db[m + j];
-        yyb[j * m + slot] = db[m + j];
+        syb[slot * m + j] = sny[j];
+        syb[j * m + slot] = sjy[j];
+        yyb[slot * m + j] = yjy[j];
+        yyb[j * m + slot] = yjy[j];
     }
 }
 
@@ -440,7 +478,6 @@ struct RLayout {
     size_t xt, g, gt, d, s, y;
     size_t part, dot1, dot2, rho, gamma, E, Et, Ebc, als, active, acc, flag;
     size_t SY, YY, cS, cY, cg, mdots, mpart;   // L-BFGS compact representation
-    int nblkG;                                 // blocks per element of the history dot passes
     size_t sl_f, sl_iters, sl_evals, sl_status;   // Adam: per-slot state kept on the device
     int nblk;
     size_t bytes;
@@ -465,7 +502,8 @@ RLayout r_layout(const Plan &p, const dmcr_opt &o)
     const int hist = (o.method == DMCR_OPT_ADAM) ? 1 : o.m;   // Adam keeps m, v in slot 0
     r.s = take((size_t)hist * Bn * 4);
     r.y = take((size_t)hist * Bn * 4);
-    r.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 4 * kV - 1) / (4 * kV)));
+    // enough blocks per element to keep the loads of a large field in flight
+    r.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (n + 4 * kV - 1) / (4 * kV)));
     r.part = take((size_t)p.B * r.nblk * 8);
     r.dot1 = take(B8);
     r.dot2 = take(B8);
@@ -477,10 +515,7 @@ RLayout r_layout(const Plan &p, const dmcr_opt &o)
     r.cY = take((size_t)o.m * B8);
     r.cg = take(B8);
     r.mdots = take((size_t)kMaxDots * B8);
-    // history passes read up to 2m + 1 vectors per element: enough blocks to keep
-    // the loads of a large field in flight
-    r.nblkG = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (n + 4 * kV - 1) / (4 * kV)));
-    r.mpart = take((size_t)r.nblkG * kMaxDots * B8);
+    r.mpart = take((size_t)r.nblk * kMaxDots * B8);
     r.E = take(B8);
     r.Et = take(B8);
     r.Ebc = take(B8);
@@ -542,46 +577,17 @@ struct Solver {
         return hipGetLastError();
     }
 
-    // dots of x with the listed vectors (DotSet), summed into mdots
-    hipError_t dots(const float *x, const DotSet &ds) const
+    // history dot products of the ring slots 0 .. cnt - 1 against g and, with
+    // slot >= 0, against the new pair in that slot; summed into mdots
+    hipError_t hist_dots(const float *g, int cnt, int slot) const
     {
-        hipLaunchKernelGGL(k_dots_part, dim3(r.nblkG, B), dim3(kV), 0, st, x, ds, n, at<double>(r.mpart), r.nblkG);
-        hipLaunchKernelGGL(k_dots_sum, dim3(B, ds.count), dim3(kV), 0, st, at<double>(r.mpart), r.nblkG, ds,
+        const float *yn = slot >= 0 ? Y(slot) : nullptr, *sn = slot >= 0 ? S(slot) : nullptr;
+        hipLaunchKernelGGL(k_hist_dots, dim3(r.nblk, B), dim3(kV), 0, st, S(0), Y(0), cnt, g, yn, sn, m, B, n,
+                           at<double>(r.mpart), r.nblk);
+        const int nout = 2 * cnt + 1 + (slot >= 0 ? 3 * cnt : 0);
+        hipLaunchKernelGGL(k_hist_sum, dim3(B, nout), dim3(kV), 0, st, at<double>(r.mpart), r.nblk, cnt, m,
                            at<double>(r.mdots));
         return hipGetLastError();
-    }
-
-    // S_j.g -> [j], Y_j.g -> [m + j] (ring slots j < count), g.g -> [2m]
-    hipError_t dots_g(const float *g, int count) const
-    {
-        DotSet ds{};
-        for (int j = 0; j < count; ++j) {
-            ds.v[ds.count] = S(j);
-            ds.out[ds.count++] = j;
-            ds.v[ds.count] = Y(j);
-            ds.out[ds.count++] = m + j;
-        }
-        ds.v[ds.count] = g;
-        ds.out[ds.count++] = 2 * m;
-        return dots(g, ds);
-    }
-
-    // new pair in ring slot `slot`: s_j.y_new -> [j], y_j.y_new -> [m + j],
-    // s_new.y_j -> [2m + j] (j < count, the ring slots in use including `slot`)
-    hipError_t dots_pair(int slot, int count) const
-    {
-        DotSet a{}, c{};
-        for (int j = 0; j < count; ++j) {
-            a.v[a.count] = S(j);
-            a.out[a.count++] = j;
-            a.v[a.count] = Y(j);
-            a.out[a.count++] = m + j;
-            c.v[c.count] = Y(j);
-            c.out[c.count++] = 2 * m + j;
-        }
-        hipError_t e = dots(Y(slot), a);
-        if (e != hipSuccess) return e;
-        return dots(S(slot), c);
     }
 
     dmcr_status evaluate(const float *pt, double *Ed, float *grad) const
@@ -752,6 +758,7 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
     std::vector<int> act(B), acc(B), flag(B);
     auto running = [&](int b) { return slots[b].active && slots[b].status == DMCR_RUNNING; };
     int head = ring->head, count = ring->count;
+    bool gdots = false;   // mdots holds S'g, Y'g, g'g of the current g and history
 
     for (int it = 0; it < iterations; ++it) {
         bool any = false;
@@ -759,12 +766,12 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
         if (!any) break;
 
         // ---- direction d = -H g (compact representation), then projection ----
-        RT(dots_g(g, count));
+        if (!gdots) RT(hist_dots(g, count, -1));
         hipLaunchKernelGGL(k_lbfgs_coef, sg, dim3(64), 0, st, mdots, rho, gamma, SY, YY, head, count, m, B, cS, cY,
                            cg, dot2);
-        hipLaunchKernelGGL(k_combine_dir, dim3(r.nblkG, B), dim3(kV), 0, st, x, g, d, S(0), Y(0), cS, cY, cg, m, head,
-                           count, B, n, (int)project, lo, hi, at<double>(r.mpart), r.nblkG);
-        hipLaunchKernelGGL(k_sum_parts, dim3(B), dim3(kV), 0, st, at<double>(r.mpart), r.nblkG, dot1, B);
+        hipLaunchKernelGGL(k_combine_dir, dim3(r.nblk, B), dim3(kV), 0, st, x, g, d, S(0), Y(0), cS, cY, cg, m, head,
+                           count, B, n, (int)project, lo, hi, at<double>(r.part), r.nblk);
+        hipLaunchKernelGGL(k_sum_parts, dim3(B), dim3(kV), 0, st, at<double>(r.part), r.nblk, dot1, B);
         RT(hipGetLastError());
         RS(fetch(dot1, hd));
         RS(fetch(dot2, hd2));
@@ -822,7 +829,8 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
         RS(put(accd, acc));
         hipLaunchKernelGGL(k_accept, vg, dim3(kV), 0, st, accd, x, xt, g, gt, S(slot), Y(slot), n);
         const int cnew = std::min(count + 1, m);   // ring slots in use: 0 .. cnew - 1
-        RT(dots_pair(slot, cnew));
+        RT(hist_dots(g, cnew, slot));   // the new pair's dots and the next direction's
+        gdots = true;
         hipLaunchKernelGGL(k_pair_update, sg, dim3(64), 0, st, mdots, accd, slot, cnew, m, B, rho, gamma, SY, YY);
         RT(hipGetLastError());
         head = slot;

@@ -329,6 +329,24 @@ __global__ void k_reset(const int *flag, double *rho, double *gamma, int m, int 
     gamma[b] = 1.0;
 }
 
+// After the direction, per element: one whose d is not a descent direction
+// (g.d >= 0) falls back to projected steepest descent (flag) with a cleared
+// history; the first trial step is 1/|g| without history, else 1.
+__global__ void k_dir_check(const double *gd, const double *gg, const int *active, const int *hist, int *flag,
+                            double *rho, double *gamma, double *step, int m, int B)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int f = active[b] && !(gd[b] < 0.0);
+    flag[b] = f;
+    if (f) {
+        for (int i = 0; i < m; ++i) rho[(int64_t)i * B + b] = 0.0;
+        gamma[b] = 1.0;
+    }
+    const double gn = sqrt(gg[b]);
+    step[b] = ((f || hist[b] == 0) && gn > 0.0) ? 1.0 / gn : 1.0;
+}
+
 // x_t = clip(x + alpha d) for elements with active[b]
 __global__ __launch_bounds__(kV) void k_trial(const float *x, const float *d, const double *alpha, const int *active,
                                               float *xt, int64_t n, int project, float lo, float hi)
@@ -479,6 +497,7 @@ struct RLayout {
     size_t part, dot1, dot2, rho, gamma, E, Et, Ebc, als, active, acc, flag;
     size_t SY, YY, cS, cY, cg, mdots, mpart;   // L-BFGS compact representation
     size_t sl_f, sl_iters, sl_evals, sl_status;   // Adam: per-slot state kept on the device
+    size_t histd;                                 // L-BFGS: each element's history length
     int nblk;
     size_t bytes;
 };
@@ -527,6 +546,7 @@ RLayout r_layout(const Plan &p, const dmcr_opt &o)
     r.sl_iters = take((size_t)p.B * 4);
     r.sl_evals = take((size_t)p.B * 4);
     r.sl_status = take((size_t)p.B * 4);
+    r.histd = take((size_t)p.B * 4);
     r.bytes = top;
     return r;
 }
@@ -754,8 +774,9 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
     double *cg = at<double>(r.cg), *mdots = at<double>(r.mdots);
     int *active = at<int>(r.active), *accd = at<int>(r.acc), *flagd = at<int>(r.flag);
 
-    std::vector<double> hE(B), hEbc(B, 0.0), hd(B), hd2(B), step(B);
-    std::vector<int> act(B), acc(B), flag(B);
+    std::vector<double> hE(B), hEbc(B, 0.0), hd(B), step(B);
+    std::vector<int> act(B), acc(B), flag(B), hist(B);
+    int *histd = at<int>(r.histd);
     auto running = [&](int b) { return slots[b].active && slots[b].status == DMCR_RUNNING; };
     int head = ring->head, count = ring->count;
     bool gdots = false;   // mdots holds S'g, Y'g, g'g of the current g and history
@@ -765,6 +786,14 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
         for (int b = 0; b < B; ++b) any |= running(b);
         if (!any) break;
 
+        for (int b = 0; b < B; ++b) {
+            act[b] = running(b);
+            acc[b] = 0;
+            hist[b] = slots[b].hist;
+        }
+        RS(put(active, act));
+        RS(put(histd, hist));
+
         // ---- direction d = -H g (compact representation), then projection ----
         if (!gdots) RT(hist_dots(g, count, -1));
         hipLaunchKernelGGL(k_lbfgs_coef, sg, dim3(64), 0, st, mdots, rho, gamma, SY, YY, head, count, m, B, cS, cY,
@@ -772,43 +801,34 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
         hipLaunchKernelGGL(k_combine_dir, dim3(r.nblk, B), dim3(kV), 0, st, x, g, d, S(0), Y(0), cS, cY, cg, m, head,
                            count, B, n, (int)project, lo, hi, at<double>(r.part), r.nblk);
         hipLaunchKernelGGL(k_sum_parts, dim3(B), dim3(kV), 0, st, at<double>(r.part), r.nblk, dot1, B);
+        // not a descent direction: (projected) steepest descent; first step, on the device
+        hipLaunchKernelGGL(k_dir_check, sg, dim3(64), 0, st, dot1, dot2, active, histd, flagd, rho, gamma, als, m, B);
+        hipLaunchKernelGGL(k_steepest, vg, dim3(kV), 0, st, flagd, x, g, d, n, (int)project, lo, hi);
         RT(hipGetLastError());
-        RS(fetch(dot1, hd));
-        RS(fetch(dot2, hd2));
-        RT(hipStreamSynchronize(st));
-        // not a descent direction: fall back to (projected) steepest descent
-        bool any_flag = false;
-        for (int b = 0; b < B; ++b) {
-            flag[b] = running(b) && !(hd[b] < 0.0);
-            if (flag[b]) slots[b].hist = 0;
-            any_flag |= flag[b] != 0;
-        }
-        if (any_flag) {
-            RS(put(flagd, flag));
-            hipLaunchKernelGGL(k_reset, sg, dim3(64), 0, st, flagd, rho, gamma, m, B);
-            hipLaunchKernelGGL(k_steepest, vg, dim3(kV), 0, st, flagd, x, g, d, n, (int)project, lo, hi);
-        }
 
         // ---- backtracking line search along the projected path ----
-        for (int b = 0; b < B; ++b) {
-            act[b] = running(b);
-            acc[b] = 0;
-            const double gn = std::sqrt(hd2[b]);
-            step[b] = (slots[b].hist == 0 && gn > 0.0) ? 1.0 / gn : 1.0;
-        }
         for (int ls = 0; ls < o.max_ls; ++ls) {
             bool anyact = false;
             for (int b = 0; b < B; ++b) anyact |= act[b] != 0;
             if (!anyact) break;
-            RS(put(active, act));
-            RS(put(als, step));
+            if (ls > 0) {
+                RS(put(active, act));
+                RS(put(als, step));
+            }
             hipLaunchKernelGGL(k_trial, vg, dim3(kV), 0, st, x, d, als, active, xt, n, (int)project, lo, hi);
             RS(evaluate(xt, Etd, gt));
             RT(dot(g, xt, x, dot1));
             RS(fetch(Etd, hE));
             if (penalty) RS(fetch(Ebcd, hEbc));
             RS(fetch(dot1, hd));
+            if (ls == 0) {
+                RS(fetch(als, step));
+                RS(fetch_int(flagd, flag));
+            }
             RT(hipStreamSynchronize(st));
+            if (ls == 0)
+                for (int b = 0; b < B; ++b)
+                    if (flag[b]) slots[b].hist = 0;   // the device cleared its history
             for (int b = 0; b < B; ++b) {
                 if (!act[b]) continue;
                 ++slots[b].evals;

@@ -187,13 +187,14 @@ def test_batched_equals_single_bitwise_and_repeatable(dm):
 
 
 def test_autograd_function_fd(dm, ora):
-    """S2Descriptor backward vs central differences of the oracle loss (h = 1e-3, FP64)
-    at sampled voxels, and vs the oracle gradient (differentiation check, 2-D 256^2)."""
+    """Differentiation check on a batch of 64 2-D 256^2 U(0,1) fields: S2Descriptor
+    backward against central differences (h = 1e-3, FP64) of the oracle loss at 256
+    voxels (4 per field), and against the oracle gradient of four whole fields."""
     shape = (256, 256)
     spec, ospec = specs(dm, ora, shape, 1, 1, (31,))
     tgt, _ = synth.boolean_spheres(shape, 4, 0.30, seed=0)
     S_des = ora.descriptor(tgt, ospec)
-    B = 4
+    B = 64
     phi = f32(np.stack([synth.uniform(shape, s) for s in range(B)]))
     x = to_dev(phi).requires_grad_(True)
     S = dm.s2_descriptor(x, spec)
@@ -201,17 +202,40 @@ def test_autograd_function_fd(dm, ora):
     loss = (((S.double() - torch.from_numpy(S_des).cuda()) ** 2).sum(dim=1) / Z).sum()
     loss.backward()
     g = x.grad.cpu().numpy().astype(np.float64)
-    rng = np.random.default_rng(0)
-    vox = rng.integers(0, 256, size=(16, 2))
-    h = 1e-3
-    for b in range(B):
+    for b in (0, 21, 42, 63):
         E, g_ora, _ = ora.loss_grad(phi[b], S_des, ospec)
         check_grad(g[b], g_ora, "autograd b=%d" % b)
-        if b == 0:
-            for (i, j) in vox[:4]:
-                p, m = phi[b].copy(), phi[b].copy()
-                p[0, i, j] += h
-                m[0, i, j] -= h
-                fd = (ora.loss(ora.descriptor(p, ospec), S_des, ospec)[0]
-                      - ora.loss(ora.descriptor(m, ospec), S_des, ospec)[0]) / (2 * h)
-                assert abs(fd - g[b, 0, i, j]) <= 1e-4 * np.max(np.abs(g_ora)), (i, j, fd, g[b, 0, i, j])
+    # central differences.  S is quadratic in phi, so a change h at voxel v moves
+    # S(r) by exactly (h (phi(v + r) + phi(v - r)) + h^2 [r = 0]) / N (periodic),
+    # checked below against a full recomputation; E(phi +- h e_v) then follows from
+    # the oracle's loss on S +- that change.
+    (_, pair, off, k) = ospec.layout()[0]
+    R = ospec.disp(0, pair)
+    n0, n1 = shape
+    N = float(n0 * n1)
+    is0 = np.all(R == 0, axis=1)
+    rng = np.random.default_rng(0)
+    h = 1e-3
+
+    def dS(f, v, hh):
+        a = f[(v[0] + R[:, 0]) % n0, (v[1] + R[:, 1]) % n1] + f[(v[0] - R[:, 0]) % n0, (v[1] - R[:, 1]) % n1]
+        return (hh * a + hh * hh * is0) / N
+
+    f0 = phi[0, 0].astype(np.float64)
+    S0 = ora.descriptor(phi[0], ospec)
+    v = (17, 200)
+    p = phi[0].astype(np.float64).copy()
+    p[0, v[0], v[1]] += h
+    assert np.max(np.abs(ora.descriptor(p, ospec) - (S0 + dS(f0, v, h)))) <= 1e-15
+    checked = 0
+    for b in range(B):
+        fb = phi[b, 0].astype(np.float64)
+        Sb = S0 if b == 0 else ora.descriptor(phi[b], ospec)
+        scale = np.max(np.abs(g[b]))
+        for v in rng.integers(0, 256, size=(4, 2)):
+            Ep = ora.loss(Sb + dS(fb, v, h), S_des, ospec)[0]
+            Em = ora.loss(Sb + dS(fb, v, -h), S_des, ospec)[0]
+            fd = (Ep - Em) / (2 * h)
+            assert abs(fd - g[b, 0, v[0], v[1]]) <= 1e-4 * scale, (b, tuple(v), fd, g[b, 0, v[0], v[1]])
+            checked += 1
+    assert checked == 256

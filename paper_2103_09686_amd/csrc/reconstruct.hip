@@ -347,6 +347,24 @@ __global__ void k_dir_check(const double *gd, const double *gg, const int *activ
     step[b] = ((f || hist[b] == 0) && gn > 0.0) ? 1.0 / gn : 1.0;
 }
 
+// dst[k] = src[idx[k]] (rows of len elements), k < gridDim.y
+template <class T>
+__global__ __launch_bounds__(kV) void k_gather(const int *idx, const T *src, T *dst, int64_t len)
+{
+    const int64_t k = blockIdx.y, b = idx[k];
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < len; i += (int64_t)gridDim.x * kV)
+        dst[k * len + i] = src[b * len + i];
+}
+
+// dst[idx[k]] = src[k]
+template <class T>
+__global__ __launch_bounds__(kV) void k_scatter(const int *idx, const T *src, T *dst, int64_t len)
+{
+    const int64_t k = blockIdx.y, b = idx[k];
+    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < len; i += (int64_t)gridDim.x * kV)
+        dst[b * len + i] = src[k * len + i];
+}
+
 // x_t = clip(x + alpha d) for elements with active[b]
 __global__ __launch_bounds__(kV) void k_trial(const float *x, const float *d, const double *alpha, const int *active,
                                               float *xt, int64_t n, int project, float lo, float hi)
@@ -498,6 +516,7 @@ struct RLayout {
     size_t SY, YY, cS, cY, cg, mdots, mpart;   // L-BFGS compact representation
     size_t sl_f, sl_iters, sl_evals, sl_status;   // Adam: per-slot state kept on the device
     size_t histd;                                 // L-BFGS: each element's history length
+    size_t pk_idx, pk_x, pk_g, pk_St, pk_E, pk_Ebc;   // packed evaluation of B' < B elements
     int nblk;
     size_t bytes;
 };
@@ -547,6 +566,13 @@ RLayout r_layout(const Plan &p, const dmcr_opt &o)
     r.sl_evals = take((size_t)p.B * 4);
     r.sl_status = take((size_t)p.B * 4);
     r.histd = take((size_t)p.B * 4);
+    const size_t Bp = (size_t)std::max(0, p.B - 1);   // at most B - 1 elements are packed
+    r.pk_idx = take((size_t)p.B * 4);
+    r.pk_x = take(Bp * n * 4);
+    r.pk_g = take(Bp * n * 4);
+    r.pk_St = take(Bp * p.K * 8);
+    r.pk_E = take(B8);
+    r.pk_Ebc = take(B8);
     r.bytes = top;
     return r;
 }
@@ -649,6 +675,45 @@ struct Solver {
 
     dmcr_spec spec1;  // the spec, for batch-1 plans of single-slot evaluations
     Ws w1;            // same workspace base (a batch-1 plan fits inside the batch-B one)
+
+    // Loss and gradient of the trial points of the elements with act[b] only,
+    // when they are fewer than B: gathered into a batch of B' = count elements
+    // (the evaluation of an element does not depend on the batch it is in),
+    // evaluated, and scattered back into Ed, grad (and the penalty's E^bc).
+    mutable std::vector<int> pk_host;   // the packed indices, alive until the next call
+
+    dmcr_status evaluate_packed(const std::vector<int> &act, const float *pt, double *Ed, float *grad) const
+    {
+        std::vector<int> &idx = pk_host;
+        idx.clear();
+        for (int b = 0; b < B; ++b)
+            if (act[b]) idx.push_back(b);
+        const int bp = (int)idx.size();
+        idx.resize(B, 0);
+        int *idxd = at<int>(r.pk_idx);
+        float *px = at<float>(r.pk_x), *pg = at<float>(r.pk_g);
+        double *pS = at<double>(r.pk_St), *pE = at<double>(r.pk_E), *pEbc = at<double>(r.pk_Ebc);
+        RS(put(idxd, idx));
+        const dim3 gv(vblocks(n), bp), gk(vblocks(p.K), bp), g1(1, bp);
+        hipLaunchKernelGGL(k_gather<float>, gv, dim3(kV), 0, st, idxd, pt, px, n);
+        hipLaunchKernelGGL(k_gather<double>, gk, dim3(kV), 0, st, idxd, St, pS, p.K);
+        RT(hipGetLastError());
+        Plan pb;
+        dmcr_spec sb = spec1;
+        RS(make_plan(&sb, bp, &pb));
+        RS(loss_grad_internal(pb, px, pS, pE, pg, w1, st));
+        if (penalty) {
+            hipLaunchKernelGGL(k_pen_part, dim3(r.nblk, bp), dim3(kV), 0, st, px, n, invN, lo, hi, at<double>(r.part),
+                               r.nblk);
+            hipLaunchKernelGGL(k_sum_parts, dim3(bp), dim3(kV), 0, st, at<double>(r.part), r.nblk, pEbc, bp);
+            hipLaunchKernelGGL(k_pen_grad, gv, dim3(kV), 0, st, px, pg, pE, bd.kappa, n, invN, lo, hi);
+            hipLaunchKernelGGL(k_scatter<double>, g1, dim3(kV), 0, st, idxd, pEbc, at<double>(r.Ebc), (int64_t)1);
+        }
+        hipLaunchKernelGGL(k_scatter<float>, gv, dim3(kV), 0, st, idxd, pg, grad, n);
+        hipLaunchKernelGGL(k_scatter<double>, g1, dim3(kV), 0, st, idxd, pE, Ed, (int64_t)1);
+        RT(hipGetLastError());
+        return DMCR_OK;
+    }
 
     dmcr_status start(float *x, const int *which, int nwhich, dmcr_slot *slots);
     dmcr_status iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int iterations);
@@ -816,7 +881,12 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
                 RS(put(als, step));
             }
             hipLaunchKernelGGL(k_trial, vg, dim3(kV), 0, st, x, d, als, active, xt, n, (int)project, lo, hi);
-            RS(evaluate(xt, Etd, gt));
+            int nact = 0;
+            for (int b = 0; b < B; ++b) nact += act[b] != 0;
+            if (nact < B)
+                RS(evaluate_packed(act, xt, Etd, gt));   // backtracking elements only, or a partly idle batch
+            else
+                RS(evaluate(xt, Etd, gt));
             RT(dot(g, xt, x, dot1));
             RS(fetch(Etd, hE));
             if (penalty) RS(fetch(Ebcd, hEbc));

@@ -465,11 +465,11 @@ def penalised_loss_grad(phi, S_des, spec, kappa=1.0, lo=0.0, hi=1.0):
 # ----------------------------------------------------------------------------
 # optimiser references
 # ----------------------------------------------------------------------------
-def lbfgs_direction(g: np.ndarray, s_hist: Sequence[np.ndarray], y_hist: Sequence[np.ndarray]):
+def lbfgs_direction(g: np.ndarray, s_hist: Sequence[np.ndarray], y_hist: Sequence[np.ndarray], gamma=None):
     """Two-loop recursion (Nocedal & Wright, Alg. 7.4), FP64: returns -H g.
 
-    s_hist / y_hist are ordered oldest first.  Initial scaling
-    gamma = s'y / y'y of the newest pair (identity if the history is empty)."""
+    s_hist / y_hist are ordered oldest first.  Initial scaling gamma as given, else
+    s'y / y'y of the newest pair (identity if the history is empty)."""
     q = np.array(g, np.float64, copy=True).reshape(-1)
     m = len(s_hist)
     alpha = np.zeros(m)
@@ -479,7 +479,9 @@ def lbfgs_direction(g: np.ndarray, s_hist: Sequence[np.ndarray], y_hist: Sequenc
         rho[i] = 1.0 / float(np.dot(y, s))
         alpha[i] = rho[i] * float(np.dot(s, q))
         q -= alpha[i] * y
-    if m:
+    if gamma is not None:
+        q *= gamma
+    elif m:
         s, y = s_hist[-1].reshape(-1), y_hist[-1].reshape(-1)
         q *= float(np.dot(s, y)) / float(np.dot(y, y))
     for i in range(m):
@@ -487,6 +489,67 @@ def lbfgs_direction(g: np.ndarray, s_hist: Sequence[np.ndarray], y_hist: Sequenc
         beta = rho[i] * float(np.dot(y, q))
         q += (alpha[i] - beta) * s
     return -q.reshape(np.shape(g))
+
+
+def reconstruct_lbfgs_projected(S_des, spec: Spec, phi0, iters, m=10, c1=1e-4, max_ls=20, lo=0.0, hi=1.0):
+    """Projected L-BFGS on the relaxed problem of Sec. 3 (box lo <= phi <= hi), FP64,
+    with the same rules as the GPU driver; returns (phi, [E after each iteration],
+    [evaluations of each iteration]).
+
+    Each iteration: d = -H g by the two-loop recursion over the valid pairs among
+    the last m iterations' pairs, initial scaling gamma = s'y / y'y of the newest
+    valid pair (1 after a reset); components of d that push an active bound outward
+    are zeroed; if g'd >= 0 the history is cleared and d = -g (projected).
+    Backtracking along the projected path x_t = clip(x + a d), halving a, with the
+    Armijo test f(x_t) <= f(x) + c1 g'(x_t - x) (Nocedal & Wright, Alg. 3.1 on the
+    projected path); the first trial is a = 1/|g| while no step has been accepted
+    since the last reset, else 1.  An accepted step records the pair s = x_t - x,
+    y = g_t - g, valid if s'y > eps y'y and y'y > 0; a failed search records no
+    pair and clears the history."""
+    x = np.clip(np.asarray(phi0, np.float64), lo, hi)
+    E, g, _ = loss_grad(x, S_des, spec)
+    f = E
+    ring = []           # pairs of the last m iterations, None where none was recorded
+    gamma, hist = 1.0, 0
+    Es, evals = [], []
+    eps = np.finfo(np.float64).eps
+    for _ in range(iters):
+        valid = [p for p in ring if p is not None]
+        d = lbfgs_direction(g, [p[0] for p in valid], [p[1] for p in valid], gamma=gamma)
+        d[((x <= lo) & (d < 0)) | ((x >= hi) & (d > 0))] = 0.0
+        if not float(np.sum(g * d)) < 0.0:
+            ring = [None] * len(ring)
+            gamma, hist = 1.0, 0
+            d = -g.copy()
+            d[((x <= lo) & (d < 0)) | ((x >= hi) & (d > 0))] = 0.0
+        gn = float(np.sqrt(np.sum(g * g)))
+        a = 1.0 / gn if (hist == 0 and gn > 0.0) else 1.0
+        accepted, n_ev = False, 0
+        for _ls in range(max_ls):
+            xt = np.clip(x + a * d, lo, hi)
+            Et, gt, _ = loss_grad(xt, S_des, spec)
+            n_ev += 1
+            dd = float(np.sum(g * (xt - x)))
+            if np.isfinite(Et) and dd < 0.0 and Et <= f + c1 * dd:
+                accepted = True
+                break
+            a *= 0.5
+        pair = None
+        if accepted:
+            s_, y_ = xt - x, gt - g
+            sy, yy = float(np.sum(s_ * y_)), float(np.sum(y_ * y_))
+            if sy > eps * yy and yy > 0.0:
+                pair = (s_, y_)
+                gamma = sy / yy
+            x, g, f = xt, gt, Et
+            hist = min(hist + 1, m)
+        ring = (ring + [pair])[-m:]
+        if not accepted:
+            ring = [None] * len(ring)
+            gamma, hist = 1.0, 0
+        Es.append(f)
+        evals.append(n_ev)
+    return x, Es, evals
 
 
 def adam_step(x, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-7, lo=None, hi=None):

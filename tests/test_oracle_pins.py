@@ -318,6 +318,35 @@ def test_lbfgs_two_loop_equals_dense_bfgs(ora):
     np.testing.assert_allclose(ora.lbfgs_direction(g, s_hist, y_hist), -H @ g, rtol=1e-10, atol=1e-12)
 
 
+def test_projected_lbfgs_first_step_and_armijo(ora):
+    """The oracle's projected L-BFGS: its first iteration is the projected steepest
+    step x1 = clip(x0 - a g) with a = 2^-k / |g| for the smallest k that passes the
+    Armijo test (brute force), every iteration keeps f non-increasing and passes
+    Armijo against a fresh evaluation, and the gamma argument of the two-loop
+    scales an empty history's direction."""
+    rng = np.random.default_rng(62)
+    spec = ora.Spec(shape=(8, 8), max_disp=(2,))
+    tgt = (rng.random((1, 8, 8)) < 0.4).astype(np.float64)
+    S_des = ora.descriptor(tgt, spec)
+    x0 = rng.random((1, 8, 8))
+    x1, Es, ev = ora.reconstruct_lbfgs_projected(S_des, spec, x0, 1)
+    E0, g0, _ = ora.loss_grad(x0, S_des, spec)
+    a = 1.0 / np.sqrt(np.sum(g0 * g0))
+    for k in range(20):
+        xt = np.clip(x0 - a * g0, 0.0, 1.0)
+        Et = ora.loss(ora.descriptor(xt, spec), S_des, spec)[0]
+        if Et <= E0 + 1e-4 * np.sum(g0 * (xt - x0)):
+            break
+        a *= 0.5
+    np.testing.assert_allclose(x1, xt, rtol=0, atol=1e-15)
+    assert ev == [k + 1] and Es[0] == pytest.approx(Et, rel=1e-14)
+    x, Es, ev = ora.reconstruct_lbfgs_projected(S_des, spec, x0, 12)
+    assert all(b <= a_ for a_, b in zip([E0] + Es[:-1], Es)) and Es[-1] < 0.5 * E0
+    assert np.all((x >= 0.0) & (x <= 1.0))
+    g = rng.standard_normal(5)
+    np.testing.assert_allclose(ora.lbfgs_direction(g, [], [], gamma=0.25), -0.25 * g, rtol=0, atol=0)
+
+
 def test_level_slices_and_upsampling(ora):
     """The level-l slice of the multigrid descriptor is the single-level descriptor of
     the l-fold pooled field (what the coarse-to-fine stages reconstruct against), and

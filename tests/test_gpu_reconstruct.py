@@ -164,3 +164,54 @@ def test_lbfgs_trajectory_matches_oracle(dm, ora):
     print("E gpu", E_gpu, "\nE ora", E_ora, "\nevals", ev_gpu, ev_ora, flush=True)
     assert ev_gpu == ev_ora
     np.testing.assert_allclose(E_gpu, E_ora, rtol=1e-4)
+
+
+@pytest.mark.parametrize("m", [1, 32])
+def test_history_length_extremes(dm, ora, m):
+    """History of one pair and of the largest ring (32): a batch of three converges,
+    and each slot's result equals the slot run alone (bitwise), which exercises the
+    packed evaluation of partly active batches with the ring wrapping around."""
+    shape = (64, 64)
+    ospec, S_des = target(ora, shape, (16,))
+    spec = dm.Spec(shape=shape, max_disp=(16,))
+    opt = dm.Opt(m=m, max_iter=120, tol_derr=1e-4)
+    starts = [synth.uniform(shape, 30 + b).astype(np.float32) for b in range(3)]
+    sv = dm.Solver(spec, 3, dm.Bounds(), opt)
+    for b in range(3):
+        sv.phi[b].copy_(torch.from_numpy(starts[b]))
+        sv.St[b].copy_(torch.from_numpy(S_des))
+    sv.start([0, 1, 2])
+    sv.iterate(120)
+    for b in range(3):
+        one = dm.Solver(spec, 1, dm.Bounds(), opt)
+        one.phi[0].copy_(torch.from_numpy(starts[b]))
+        one.St[0].copy_(torch.from_numpy(S_des))
+        one.start([0])
+        one.iterate(120)
+        assert sv.slots[b].iters == one.slots[0].iters and sv.slots[b].E == one.slots[0].E, (m, b)
+        assert torch.equal(sv.phi[b], one.phi[0]), (m, b)
+        assert sv.slots[b].E <= 1e-4 or sv.slots[b].iters == 120, (m, b, sv.slots[b].E)
+
+
+def test_penalty_mode_packed_batch(dm, ora):
+    """Penalty mode in a batch whose elements stop at different times (packed
+    evaluations carry the penalty term): each element equals its run alone."""
+    shape = (32, 32)
+    ospec, S_des = target(ora, shape, (8,))
+    spec = dm.Spec(shape=shape, max_disp=(8,))
+    bounds = dm.Bounds(0.0, 1.0, dm.BOUNDS_PENALTY, 1.0)
+    opt = dm.Opt(max_iter=40, tol_derr=0.0)
+    starts = [synth.uniform(shape, 50 + b).astype(np.float32) for b in range(3)]
+    sv = dm.Solver(spec, 3, bounds, opt)
+    for b in range(3):
+        sv.phi[b].copy_(torch.from_numpy(starts[b]))
+        sv.St[b].copy_(torch.from_numpy(S_des))
+    sv.start([0, 1, 2])
+    sv.iterate(40)
+    for b in range(3):
+        one = dm.Solver(spec, 1, bounds, opt)
+        one.phi[0].copy_(torch.from_numpy(starts[b]))
+        one.St[0].copy_(torch.from_numpy(S_des))
+        one.start([0])
+        one.iterate(40)
+        assert sv.slots[b].E == one.slots[0].E and torch.equal(sv.phi[b], one.phi[0]), b

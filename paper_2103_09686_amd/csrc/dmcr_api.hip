@@ -318,6 +318,7 @@ struct Sched {
     Lanes *ln;
     hipStream_t main;
     bool multi;  // false: everything on the caller's stream
+    bool side_recompute;  // a recomputed spectrum is built on a spare lane
     hipStream_t lane(int l) const { return (l == 0 || !multi) ? main : ln->side[(l - 1) % Lanes::kSide]; }
     // a stream that is not lane(l) of a level in use, for level l's recompute
     hipStream_t spare(int l, int L) const
@@ -337,21 +338,35 @@ struct Sched {
 };
 
 // Side lanes pay off only when the passes are long enough to hide the extra
-// event waits; small fields stay on the caller's stream (measured: a 512^2
-// three-level evaluation is slower with lanes, 256^3 and 64 x 512^2 faster).
-// The soft-threshold levels are long ALU-bound kernels whose coarse levels fill
-// only part of the chip, so their levels always run side by side.
-constexpr int64_t kLaneMinVoxels = int64_t(1) << 22;
+// event waits; smaller batches stay on the caller's stream (measured: a 512^2
+// three-level evaluation and a two-channel 128^3 three-level one (4.2M voxels)
+// are faster on one stream, 256^3 and 64 x 512^2 (16.8M) with lanes).  The
+// soft-threshold levels are long ALU-bound kernels whose coarse levels fill only
+// part of the chip, so their levels always run side by side.  Under stream
+// capture the event waits become graph edges that cost no host time, so a
+// captured call also runs its levels side by side (measured on replay: the
+// two-channel 128^3 three-level evaluation 0.156 ms with lanes, 0.212 ms on one
+// stream).  A recompute moves to a spare lane only by the size rule: there it
+// takes the two-pass spectrum, and results must not depend on capture.
+constexpr int64_t kLaneMinVoxels = int64_t(1) << 24;
 
 hipError_t make_sched(const Plan &p, hipStream_t st, Sched *s)
 {
-    const bool multi = (int64_t)p.B * p.C * p.lv[0].N >= kLaneMinVoxels || (p.desc != DMCR_DESC_S2 && p.L > 1);
+    // the null stream cannot be captured
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (st != nullptr) {
+        hipError_t e = hipStreamIsCapturing(st, &cs);
+        if (e != hipSuccess) return e;
+    }
+    const bool eager_multi =
+        (int64_t)p.B * p.C * p.lv[0].N >= kLaneMinVoxels || (p.desc != DMCR_DESC_S2 && p.L > 1);
+    const bool multi = eager_multi || (cs == hipStreamCaptureStatusActive && p.L > 1);
     if (multi) {
         hipError_t e = tl_lanes.init();
         if (e != hipSuccess) return e;
         tl_lanes.next = 0;
     }
-    *s = Sched{&tl_lanes, st, multi};
+    *s = Sched{&tl_lanes, st, multi, eager_multi};
     return hipSuccess;
 }
 
@@ -435,9 +450,9 @@ dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St
     DMCR_TRY(make_sched(p, st, &sc));
     const bool keep = (p.flags & DMCR_FLAG_RECOMPUTE) == 0;
     hipEvent_t x_free[kMaxLevels] = {};
-    if (!keep && sc.multi)
+    if (!keep && sc.side_recompute)
         for (int l = 0; l < p.L; ++l) x_free[l] = sc.ln->event();
-    hipEvent_t *xf = (!keep && sc.multi) ? x_free : nullptr;
+    hipEvent_t *xf = (!keep && sc.side_recompute) ? x_free : nullptr;
     DMCR_TRY(run_forward(p, phi, S, w, sc, xf));
     // one level: side lane 1 is idle (lane 0 is the caller's stream, the
     // recompute uses side lane 0), so the final error sum runs there

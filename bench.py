@@ -7,8 +7,9 @@ A step is one dmcr_loss_grad over one batch with the field, the target
 descriptor and the workspace already resident in HBM.  The default workload
 is a 3-D 256^3 two-phase U(0,1) field, P = 32, one level, spectra recomputed
 in the adjoint.  The script prints one JSON line with the throughput, the
-roofline figure of the dominant kernel (HIP events around every launch, on the
-launch stream, in a second pass of the same steps) and the FP64 oracle timed
+roofline figure of the dominant kernel (every launch carries a HIP event pair
+stamped with the dispatch's own begin and end, in a second pass of the same
+steps) and the FP64 oracle timed
 on a bounded sample on the host cores.  Unless --no-serve is given it also runs
 the continuous-batching serving workload (a Poisson stream of mixed 2-D/3-D,
 2-3 phase reconstruction requests) and adds its latency percentiles and its
@@ -359,7 +360,7 @@ def main():
         return ms
 
     def kernel_table(fn):
-        """Second pass of the same steps with HIP events around every launch, on its stream."""
+        """Second pass of the same steps, every launch timed by the event pair it carries."""
         lib.dmcr_profile_start()
         for _ in range(args.steps):
             fn()

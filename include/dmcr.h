@@ -248,12 +248,14 @@ dmcr_status dmcr_reconstruct_coarse_to_fine(const dmcr_spec *spec, int32_t batch
                                             dmcr_result *results, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Kernel timing (diagnostics).  dmcr_profile_start() clears the table and
- * makes every later launch record a HIP event pair on its own stream, with
- * the launch's algorithmic bytes (inputs read once plus outputs written
- * once).  dmcr_profile_stop() synchronises on the recorded events, writes
- * at most `max` per-kernel totals to `out` (host) and returns the number of
- * distinct kernels (or a negative dmcr_status).  Process-global and not
- * thread-safe; recording adds a small gap between launches. */
+ * makes every later launch of the evaluation kernels carry a HIP event pair
+ * that the runtime stamps with the dispatch's own begin and end
+ * (hipExtLaunchKernel), with the launch's algorithmic bytes (inputs read once
+ * plus outputs written once).  dmcr_profile_stop() synchronises on the
+ * recorded events, writes at most `max` per-kernel totals to `out` (host) and
+ * returns the number of distinct kernels (or a negative dmcr_status).
+ * Process-global and not thread-safe; do not record while a stream is being
+ * captured. */
 typedef struct {
     char name[48];
     int32_t launches;

@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "../../include/dmcr.h"
@@ -89,20 +90,24 @@ dmcr_status make_plan(const dmcr_spec *spec, int B, Plan *plan);
 
 // ---- kernel timing (dmcr_profile_start / dmcr_profile_stop) ---------------
 bool prof_on();
-void prof_begin(const char *name, double bytes, hipStream_t st);
-void prof_end(hipStream_t st);
+// A start/stop event pair for one launch of `name` (both null if none is left).
+void prof_pair(const char *name, double bytes, hipEvent_t *start, hipEvent_t *stop);
 
-// Launch `kernel` on `st`, bracketed by profiling events when enabled.
+// Launch `kernel` on `st`.  While timing is on, the launch carries a start/stop
+// event pair that the runtime stamps from the dispatch itself (the kernel's own
+// begin and end, as a kernel trace reports them), so the timing adds no stream
+// commands between kernels.
 template <typename Kern, typename... Args>
 hipError_t launch(const char *name, double bytes, Kern kernel, dim3 grid, dim3 block, size_t lds,
                   hipStream_t st, Args... args)
 {
-    const bool on = prof_on();
-    if (on) prof_begin(name, bytes, st);
-    hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
-    hipError_t e = hipGetLastError();
-    if (on) prof_end(st);
-    return e;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (prof_on()) prof_pair(name, bytes, &a, &b);
+    if (a && b)
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, st, a, b, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+    return hipGetLastError();
 }
 
 // ---- launchers (all asynchronous on `st`) ---------------------------------

@@ -1,6 +1,7 @@
 // Per-kernel timing with HIP events (dmcr_profile_start / dmcr_profile_stop).
-// Each recorded launch gets an event pair on its own stream; totals are
-// aggregated by kernel name when recording stops.
+// Each recorded launch carries an event pair that the runtime stamps with the
+// dispatch's begin and end; totals are aggregated by kernel name when recording
+// stops.
 #include <string.h>
 
 #include <map>
@@ -38,19 +39,12 @@ hipEvent_t take_event()
 
 bool prof_on() { return g_on; }
 
-void prof_begin(const char *name, double bytes, hipStream_t st)
+void prof_pair(const char *name, double bytes, hipEvent_t *start, hipEvent_t *stop)
 {
-    Rec r{name, bytes, take_event(), nullptr};
-    if (r.a) hipEventRecord(r.a, st);
+    Rec r{name, bytes, take_event(), take_event()};
+    *start = r.a;
+    *stop = r.b;
     g_recs.push_back(r);
-}
-
-void prof_end(hipStream_t st)
-{
-    if (g_recs.empty()) return;
-    Rec &r = g_recs.back();
-    r.b = take_event();
-    if (r.b) hipEventRecord(r.b, st);
 }
 
 }  // namespace dmcr

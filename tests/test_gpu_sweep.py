@@ -1,0 +1,105 @@
+"""Seeded random parity sweep: 60 valid configurations drawn once from a fixed
+seed (2-D and 3-D, square and elongated axes, 1-3 channels with all or a subset
+of the pairs, 1-3 levels with a random P per level, every path, spectra kept or
+recomputed, batches of 1-3), each compared with the FP64 oracle:
+
+  * descriptor, per (level, pair): max |S_gpu - S_oracle| <= 1e-5 max |S_oracle|;
+  * adjoint of a random cotangent: ||g_gpu - g_oracle|| <= 1e-4 ||g_oracle||;
+  * dmcr_loss_grad against the oracle's loss and gradient (1e-4 relative), with a
+    target whose mean differs from the field's, so that S - S* does not cancel
+    (the cotangent would otherwise inherit the relative rounding of S amplified
+    by the cancellation).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2103_09686_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _draw_cases(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        nd = int(rng.integers(2, 4))
+        if nd == 2:
+            shape = tuple(int(2 ** rng.integers(2, 9)) for _ in range(2))
+        elif rng.random() < 0.4:
+            m = int(2 ** rng.integers(5, 7))                  # square planes: fused transforms
+            shape = (int(2 ** rng.integers(2, 5)), m, m)
+        else:
+            shape = tuple(int(2 ** rng.integers(1, 6)) for _ in range(3))
+        C = int(rng.integers(1, 4))
+        mn = min(shape)
+        L = int(rng.integers(1, max(1, min(3, int(math.log2(mn)))) + 1))
+        # P_l <= n_l / 2 - 1 on the shortest axis; half of the levels take the largest
+        pmax = [max(0, (mn >> l) // 2 - 1) for l in range(L)]
+        P = tuple(pm if rng.random() < 0.5 else int(rng.integers(0, pm + 1)) for pm in pmax)
+        path = int(rng.integers(0, 3))
+        recompute = bool(rng.random() < 0.5)
+        B = int(rng.integers(1, 4))
+        pairs = ()
+        if C > 1 and rng.random() < 0.3:
+            allp = [(i, j) for i in range(C) for j in range(i, C)]
+            k = int(rng.integers(1, len(allp) + 1))
+            pairs = tuple(allp[i] for i in sorted(rng.choice(len(allp), k, replace=False)))
+        # bound the oracle's direct sums (voxels x displacements, all levels)
+        box = lambda p: (2 * p + 1) ** nd
+        cost = sum((int(np.prod(shape)) >> (nd * l)) * box(P[l]) * C * C for l in range(L))
+        if cost > 3e8:
+            continue
+        out.append((shape, C, L, P, pairs, path, recompute, B))
+    return out
+
+
+CASES = _draw_cases(60, 20260101)
+
+
+@pytest.fixture(scope="module")
+def dm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_09686_amd import dmcr
+    dmcr.lib()
+    return dmcr
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("case", CASES, ids=["%d-%s" % (i, "x".join(map(str, c[0]))) for i, c in enumerate(CASES)])
+def test_random_config_parity(dm, ora, case):
+    shape, C, L, P, pairs, path, recompute, B = case
+    print("sweep case", case, flush=True)
+    flags = dm.FLAG_RECOMPUTE if recompute else 0
+    spec = dm.Spec(shape=shape, n_channels=C, n_levels=L, max_disp=P, pairs=pairs, path=path, flags=flags)
+    ospec = ora.Spec(shape=shape, n_channels=C, n_levels=L, max_disp=P, pairs=pairs)
+    K = dm.dmcr_descriptor_size(spec)
+    assert K == ospec.K
+    seed = abs(hash(case)) % 100000
+    phi = f32(np.stack([synth.uniform(shape, seed + b, channels=C) for b in range(B)]))
+    dphi = torch.from_numpy(phi.astype(np.float32)).cuda()
+    S = dm.dmcr_descriptor_forward(spec, dphi).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(seed)
+    dS = f32(rng.standard_normal((B, K)))
+    g = dm.dmcr_descriptor_adjoint(spec, dphi, torch.from_numpy(dS.astype(np.float32)).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    St = np.stack([ora.descriptor(phi[b] ** 2, ospec) for b in range(B)])
+    E, gl = dm.dmcr_loss_grad(spec, dphi, torch.from_numpy(St).cuda())
+    E = E.cpu().numpy()
+    gl = gl.cpu().numpy().astype(np.float64)
+    for b in range(B):
+        So = ora.descriptor(phi[b], ospec)
+        for (l, pair, off, k) in ospec.layout():
+            err = np.max(np.abs(S[b, off:off + k] - So[off:off + k]))
+            assert err <= 1e-5 * np.max(np.abs(So[off:off + k])) + 1e-30, ("S", b, l, pair, err)
+        go = ora.adjoint(phi[b], dS[b], ospec)
+        assert np.linalg.norm(g[b] - go) <= 1e-4 * np.linalg.norm(go), ("adjoint", b)
+        Eo, gO, _ = ora.loss_grad(phi[b], St[b], ospec)
+        assert abs(E[b] - Eo) <= 1e-4 * abs(Eo), ("E", b, E[b], Eo)
+        assert np.linalg.norm(gl[b] - gO) <= 1e-4 * np.linalg.norm(gO), ("loss gradient", b)

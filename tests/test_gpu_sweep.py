@@ -1,4 +1,6 @@
-"""Seeded random parity sweep: 60 valid configurations drawn once from a fixed
+"""Seeded random parity sweeps against the FP64 oracle.
+
+Two-point product form: 60 valid configurations drawn once from a fixed
 seed (2-D and 3-D, square and elongated axes, 1-3 channels with all or a subset
 of the pairs, 1-3 levels with a random P per level, every path, spectra kept or
 recomputed, batches of 1-3), each compared with the FP64 oracle:
@@ -9,6 +11,12 @@ recomputed, batches of 1-3), each compared with the FP64 oracle:
     target whose mean differs from the field's, so that S - S* does not cancel
     (the cotangent would otherwise inherit the relative rounding of S amplified
     by the cancellation).
+
+Descriptor variants: 40 configurations of the soft-threshold descriptor S-bar,
+its Appendix A map S-tilde and the three-point blocks (any of the three with or
+without them), with random slopes alpha, on the paths that evaluate them (the
+soft descriptors only on the direct path); descriptor and adjoint parity per
+block.
 """
 import math
 
@@ -103,3 +111,79 @@ def test_random_config_parity(dm, ora, case):
         Eo, gO, _ = ora.loss_grad(phi[b], St[b], ospec)
         assert abs(E[b] - Eo) <= 1e-4 * abs(Eo), ("E", b, E[b], Eo)
         assert np.linalg.norm(gl[b] - gO) <= 1e-4 * np.linalg.norm(gO), ("loss gradient", b)
+
+
+KINDS = {0: "s2", 1: "sbar", 2: "stilde"}
+
+
+def _draw_variants(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        nd = int(rng.integers(2, 4))
+        if nd == 2:
+            shape = tuple(int(2 ** rng.integers(3, 8)) for _ in range(2))
+        else:
+            shape = tuple(int(2 ** rng.integers(2, 5)) for _ in range(3))
+        C = int(rng.integers(1, 4))
+        mn = min(shape)
+        L = int(rng.integers(1, max(1, min(3, int(math.log2(mn)) - 1)) + 1))
+        desc = int(rng.integers(0, 3))
+        P3 = int(rng.integers(1, (4 if nd == 2 else 2) + 1)) if rng.random() < 0.4 else 0
+        pmax = [max(0, (mn >> l) // 2 - 1) for l in range(L)]
+        P = tuple(pm if rng.random() < 0.5 else int(rng.integers(0, pm + 1)) for pm in pmax)
+        if P3 and desc == 2:
+            # the map of the three-point blocks needs 2 P3 <= P_l on every level
+            P = tuple(max(p, 2 * P3) for p in P)
+            if any(p > pm for p, pm in zip(P, pmax)):
+                P3 = 0
+                P = tuple(min(p, pm) for p, pm in zip(P, pmax))
+        pairs = ()
+        if C > 1 and rng.random() < 0.3:
+            allp = [(i, j) for i in range(C) for j in range(i, C)]
+            k = int(rng.integers(1, len(allp) + 1))
+            pairs = {allp[i] for i in rng.choice(len(allp), k, replace=False)}
+            if desc == 2 or P3:
+                pairs |= {(c, c) for c in range(C)}     # S-tilde needs every auto pair
+            pairs = tuple(sorted(pairs))
+        alpha = 0.0 if rng.random() < 0.5 else float(np.round(rng.uniform(3, 20), 2))
+        path = int(rng.choice([0, 2])) if desc else int(rng.integers(0, 3))
+        B = int(rng.integers(1, 3))
+        cost = sum((int(np.prod(shape)) >> (nd * l)) * (2 * P[l] + 1) ** nd * C * C for l in range(L))
+        if P3:
+            cost += int(np.prod(shape)) * ((2 * P3 + 1) ** nd) ** 2 * C
+        if cost > 2e8:
+            continue
+        out.append((shape, C, L, P, pairs, desc, alpha, P3, path, B))
+    return out
+
+
+VARIANTS = _draw_variants(40, 20260102)
+
+
+@pytest.mark.parametrize("case", VARIANTS,
+                         ids=["%d-%s-%s%s" % (i, "x".join(map(str, c[0])), KINDS[c[5]], "-s3" if c[7] else "")
+                              for i, c in enumerate(VARIANTS)])
+def test_random_variant_parity(dm, ora, case):
+    shape, C, L, P, pairs, desc, alpha, P3, path, B = case
+    print("variant case", case, flush=True)
+    spec = dm.Spec(shape=shape, n_channels=C, n_levels=L, max_disp=P, pairs=pairs, path=path,
+                   descriptor=desc, alpha=alpha, s3_max_disp=P3)
+    ospec = ora.Spec(shape=shape, n_channels=C, n_levels=L, max_disp=P, pairs=pairs, descriptor=KINDS[desc],
+                     alpha=alpha if alpha else 10.0, s3_max_disp=P3)
+    K = dm.dmcr_descriptor_size(spec)
+    assert K == ospec.K
+    seed = abs(hash(case)) % 100000
+    phi = f32(np.stack([synth.uniform(shape, seed + b, channels=C) for b in range(B)]))
+    dphi = torch.from_numpy(phi.astype(np.float32)).cuda()
+    S = dm.dmcr_descriptor_forward(spec, dphi).cpu().numpy().astype(np.float64)
+    dS = f32(np.random.default_rng(seed).standard_normal((B, K)))
+    g = dm.dmcr_descriptor_adjoint(spec, dphi, torch.from_numpy(dS.astype(np.float32)).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    for b in range(B):
+        So = ora.descriptor(phi[b], ospec)
+        for (kind, l, q, off, k) in ospec.blocks():
+            err = np.max(np.abs(S[b, off:off + k] - So[off:off + k]))
+            assert err <= 1e-5 * np.max(np.abs(So[off:off + k])) + 1e-30, (kind, b, l, q, err)
+        go = ora.adjoint(phi[b], dS[b], ospec)
+        assert np.linalg.norm(g[b] - go) <= 1e-4 * np.linalg.norm(go), ("adjoint", b)

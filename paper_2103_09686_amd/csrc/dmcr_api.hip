@@ -401,7 +401,7 @@ hipError_t run_forward(const Plan &p, const float *phi, float *S, const Ws &ws, 
 // plus the prolongation of the next coarser total (Sec. 3.3: back-propagation
 // through all levels at once).
 hipError_t run_adjoint(const Plan &p, const float *phi, const float *G, float *grad, bool have_spectrum,
-                       const Ws &ws, Sched &sc, hipEvent_t *x_free = nullptr)
+                       const Ws &ws, Sched &sc, hipEvent_t *x_free = nullptr, const double *St = nullptr)
 {
     hipError_t e;
     for (int l = 1; l < p.L; ++l)
@@ -412,9 +412,9 @@ hipError_t run_adjoint(const Plan &p, const float *phi, const float *G, float *g
         if (p.lv[l].path == DMCR_PATH_FFT) {
             if (!have_spectrum && x_free)
                 e = fft_adjoint_level(p, l, f, G, g, false, ws, sc.lane(l), sc.spare(l, p.L), x_free[l],
-                                      sc.ln->event());
+                                      sc.ln->event(), St);
             else
-                e = fft_adjoint_level(p, l, f, G, g, have_spectrum, ws, sc.lane(l));
+                e = fft_adjoint_level(p, l, f, G, g, have_spectrum, ws, sc.lane(l), nullptr, nullptr, nullptr, St);
         } else {
             e = direct_adjoint_level(p, l, f, G, g, ws, sc.lane(l));
         }
@@ -457,6 +457,16 @@ dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St
     // one level: side lane 1 is idle (lane 0 is the caller's stream, the
     // recompute uses side lane 0), so the final error sum runs there
     hipStream_t fin = (sc.multi && p.L == 1) ? sc.ln->side[1] : st;
+    // One FFT level of the product form: the cotangent-kernel pass forms G from
+    // S and St itself, so the whole error reduction moves to that side lane and
+    // the adjoint starts right after the forward.
+    const bool g_inline = fin != st && p.lv[0].path == DMCR_PATH_FFT && p.desc == DMCR_DESC_S2 && !p.s3;
+    if (g_inline) {
+        DMCR_TRY(sc.join(fin, st));
+        DMCR_TRY(launch_error(p, S, St, E, G, w, fin, fin, nullptr));
+        DMCR_TRY(run_adjoint(p, phi, S, grad, keep, w, sc, xf, St));
+        return dev(sc.join(st, fin));
+    }
     DMCR_TRY(launch_error(p, S, St, E, G, w, st, fin, fin != st ? sc.ln->event() : nullptr));
     if (p.desc == DMCR_DESC_STILDE) {
         if (p.s3) DMCR_TRY(launch_s3_map_adjoint(p, G, st));

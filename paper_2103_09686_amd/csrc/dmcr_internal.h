@@ -133,9 +133,13 @@ hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &
                               bool fused = true);
 // Without have_spectrum the spectrum is recomputed: on st_spec after x_free when
 // st_spec is given (overlapping the cotangent transforms on st), else on st.
+// With St, G is the descriptor S and the cotangent 2 w_l^2 (S - St) / Z of the
+// loss is formed while loading (bitwise as the error kernel forms it), so the
+// adjoint need not wait for the error kernel.
 hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
                              bool have_spectrum, const Ws &ws, hipStream_t st, hipStream_t st_spec = nullptr,
-                             hipEvent_t x_free = nullptr, hipEvent_t spec_done = nullptr);
+                             hipEvent_t x_free = nullptr, hipEvent_t spec_done = nullptr,
+                             const double *St = nullptr);
 
 // 3-D levels with square planes of side 32..256: the contiguous axis and axis 1
 // transformed in one pass (fft_plane.hip).  Forward: real field [B][C][n0][n][n]

@@ -83,6 +83,10 @@ struct RowArgs {
     int64_t rows_per_pair, center, Kstride, vol;
     int64_t off[kMaxPairs];
     int pi[kMaxPairs], pj[kMaxPairs];
+    // IO_GBOX with St: `in` is the descriptor S and the cotangent is formed while
+    // loading, G = 2 w2 (S - St) / Z, exactly as the error kernel forms it
+    const double *St;
+    double w2, invZ;
 };
 
 // Box row m of the adjoint kernel K_cj (see k_build_kernels):
@@ -91,6 +95,7 @@ struct RowArgs {
 // Pairs are distinct, so at most one of them feeds a given (c, j).
 struct GboxRow {
     const float *G;   // descriptor slice of the feeding pair, or null
+    const double *Gt; // the same slice of the target when G is formed from S
     int kind;         // 1 auto, 2 direct, 3 mirrored
     int bi0;          // box index of the row's first entry
 };
@@ -103,15 +108,14 @@ __device__ __forceinline__ GboxRow gbox_row(const RowArgs &a, uint32_t m)
     rest /= (uint32_t)a.C;
     const int c = (int)(rest % (uint32_t)a.C);
     const int64_t b = rest / (uint32_t)a.C;
-    GboxRow g{nullptr, 0, (int)row * a.in_len};
+    GboxRow g{nullptr, nullptr, 0, (int)row * a.in_len};
     const float *Gb = static_cast<const float *>(a.in) + b * a.Kstride;
     for (int q = 0; q < a.npairs; ++q) {
-        if (a.pi[q] == c && a.pj[q] == j) {
+        const bool direct = a.pi[q] == c && a.pj[q] == j, mirrored = a.pi[q] == j && a.pj[q] == c;
+        if (direct || mirrored) {
             g.G = Gb + a.off[q];
-            g.kind = (c == j) ? 1 : 2;
-        } else if (a.pi[q] == j && a.pj[q] == c) {
-            g.G = Gb + a.off[q];
-            g.kind = 3;
+            if (a.St) g.Gt = a.St + b * a.Kstride + a.off[q];
+            g.kind = direct ? ((c == j) ? 1 : 2) : 3;
         }
     }
     return g;
@@ -129,6 +133,7 @@ __device__ __forceinline__ float gbox_value(const RowArgs &a, const GboxRow &g, 
         idx = (bi >= center ? bi : mirror) - center;
         f = (bi == center) ? 2.f : 1.f;
     }
+    if (g.Gt) return f * (float)(2.0 * a.w2 * ((double)g.G[idx] - g.Gt[idx]) * a.invZ);
     return f * g.G[idx];
 }
 
@@ -821,7 +826,7 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
 
 hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
                              bool have_spectrum, const Ws &ws, hipStream_t st, hipStream_t st_spec, hipEvent_t x_free,
-                             hipEvent_t spec_done)
+                             hipEvent_t spec_done, const double *St)
 {
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C, CC = C * C;
@@ -843,7 +848,13 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
         r.pi[q] = p.pi[q];
         r.pj[q] = p.pj[q];
     }
-    const double kb_bytes = (double)B * (p.lvl_off[l + 1] - p.lvl_off[l]) * 4 + (double)r.nrows * L.h * 8;
+    if (St) {
+        r.St = St;
+        r.w2 = p.w[l] * p.w[l];
+        r.invZ = 1.0 / p.Z;
+    }
+    const double kb_bytes =
+        (double)B * (p.lvl_off[l + 1] - p.lvl_off[l]) * (St ? 12 : 4) + (double)r.nrows * L.h * 8;
     TRY_HIP((rows_launch<T_KB_LAST, false>(ilog2(nl), r, kb_bytes, st)));
     if (p.ndim == 2) {
         KBaxis0 = KB1;

@@ -396,39 +396,51 @@ hipError_t run_forward(const Plan &p, const float *phi, float *S, const Ws &ws, 
     return hipSuccess;
 }
 
-// Adjoint of every level on its lane, then the prolongation chain on the
-// caller's stream, coarsest first: each level's total gradient is its own term
-// plus the prolongation of the next coarser total (Sec. 3.3: back-propagation
-// through all levels at once).
+// Adjoint of every level on its lane, coarsest first: each level's total
+// gradient is its own term plus the prolongation of the next coarser total
+// (Sec. 3.3: back-propagation through all levels at once), added on the level's
+// lane once the coarser total is complete; where the level ends in the
+// contiguous-axis inverse, that pass adds it while writing.
 hipError_t run_adjoint(const Plan &p, const float *phi, const float *G, float *grad, bool have_spectrum,
                        const Ws &ws, Sched &sc, hipEvent_t *x_free = nullptr, const double *St = nullptr)
 {
     hipError_t e;
     for (int l = 1; l < p.L; ++l)
         if ((e = sc.join(sc.lane(l), sc.main)) != hipSuccess) return e;
+    // ready[l]: level l's total gradient is complete on lane(l)
+    hipEvent_t ready[kMaxLevels] = {};
     for (int l = p.L - 1; l >= 0; --l) {
         const float *f = level_field(p, l, phi, ws);
         float *g = (l == 0) ? grad : ws.at<float>(p.lv[l].grad);
+        const float *cg = (l + 1 < p.L) ? ws.at<float>(p.lv[l + 1].grad) : nullptr;
+        hipEvent_t cready = (cg && sc.lane(l) != sc.lane(l + 1)) ? ready[l + 1] : nullptr;
+        // the prolongation of the coarser total rides on the level's last inverse pass
+        const bool fuse = cg && fft_fused_prolong(p, l);
         if (p.lv[l].path == DMCR_PATH_FFT) {
+            const float *fc = fuse ? cg : nullptr;
+            hipEvent_t fr = fuse ? cready : nullptr;
             if (!have_spectrum && x_free)
                 e = fft_adjoint_level(p, l, f, G, g, false, ws, sc.lane(l), sc.spare(l, p.L), x_free[l],
-                                      sc.ln->event(), St);
+                                      sc.ln->event(), St, fc, fr);
             else
-                e = fft_adjoint_level(p, l, f, G, g, have_spectrum, ws, sc.lane(l), nullptr, nullptr, nullptr, St);
+                e = fft_adjoint_level(p, l, f, G, g, have_spectrum, ws, sc.lane(l), nullptr, nullptr, nullptr, St,
+                                      fc, fr);
         } else {
             e = direct_adjoint_level(p, l, f, G, g, ws, sc.lane(l));
         }
         if (e != hipSuccess) return e;
         if (p.s3 && (e = s3_adjoint_level(p, l, f, G, g, ws, sc.lane(l))) != hipSuccess) return e;
-    }
-    for (int l = p.L - 1; l >= 0; --l) {
-        if ((e = sc.join(sc.main, sc.lane(l))) != hipSuccess) return e;
-        if (l + 1 < p.L) {
-            float *g = (l == 0) ? grad : ws.at<float>(p.lv[l].grad);
-            e = launch_prolong_add(p, l, ws.at<float>(p.lv[l + 1].grad), g, sc.main);
-            if (e != hipSuccess) return e;
+        if (cg && !fuse) {
+            if (cready && (e = hipStreamWaitEvent(sc.lane(l), cready, 0)) != hipSuccess) return e;
+            if ((e = launch_prolong_add(p, l, cg, g, sc.lane(l))) != hipSuccess) return e;
+        }
+        if (l > 0 && sc.multi) {
+            ready[l] = sc.ln->event();
+            if ((e = hipEventRecord(ready[l], sc.lane(l))) != hipSuccess) return e;
         }
     }
+    // lane(0) is the caller's stream; it waited for level 1's total, which waited
+    // for level 2's, and so on, so every lane has joined it
     return hipSuccess;
 }
 

@@ -136,10 +136,17 @@ hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &
 // With St, G is the descriptor S and the cotangent 2 w_l^2 (S - St) / Z of the
 // loss is formed while loading (bitwise as the error kernel forms it), so the
 // adjoint need not wait for the error kernel.
+// With coarse (only where fft_fused_prolong holds), the last inverse pass also
+// adds the prolongation of the next coarser level's total gradient, 2^-d times
+// each voxel's parent, after st waits for coarse_ready (if given).
 hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
                              bool have_spectrum, const Ws &ws, hipStream_t st, hipStream_t st_spec = nullptr,
                              hipEvent_t x_free = nullptr, hipEvent_t spec_done = nullptr,
-                             const double *St = nullptr);
+                             const double *St = nullptr, const float *coarse = nullptr,
+                             hipEvent_t coarse_ready = nullptr);
+// Whether level l's adjoint ends in the contiguous-axis inverse that can add the
+// prolongation (FFT path, no fused plane transform, rows of at least 4).
+bool fft_fused_prolong(const Plan &p, int l);
 
 // 3-D levels with square planes of side 32..256: the contiguous axis and axis 1
 // transformed in one pass (fft_plane.hip).  Forward: real field [B][C][n0][n][n]

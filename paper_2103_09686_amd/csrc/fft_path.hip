@@ -87,6 +87,12 @@ struct RowArgs {
     // loading, G = 2 w2 (S - St) / Z, exactly as the error kernel forms it
     const double *St;
     double w2, invZ;
+    // T_C2R_FULL with coarse: each real output also takes cw times its parent in
+    // the next coarser level's gradient (the prolongation of the multigrid
+    // adjoint); row m = (bc n0 + z) n1 + y of the fine rows, n1 = 1 in 2-D
+    const float *coarse;
+    float cw;
+    int64_t fn0, fn1;
 };
 
 // Box row m of the adjoint kernel K_cj (see k_build_kernels):
@@ -343,10 +349,27 @@ __global__ __launch_bounds__(256) void k_c2r(RowArgs a)
             }
     } else {
         float2 *dst = static_cast<float2 *>(a.out) + m * (a.out_len / 2);
+        if (TAG == T_C2R_FULL && a.coarse) {
+            // outputs 2 mm and 2 mm + 1 share the parent mm of the coarse row
+            const int64_t y = m % a.fn1, r = m / a.fn1;
+            const int64_t z = r % a.fn0, bc = r / a.fn0;
+            const int64_t h1 = a.fn1 > 1 ? a.fn1 / 2 : 1;
+            const float *cr = a.coarse + ((bc * (a.fn0 / 2) + z / 2) * h1 + y / 2) * nh;
 #pragma unroll
-        for (int s = 0; s < S; ++s)
+            for (int s = 0; s < S; ++s)
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) dst[(p + R2 * s) + R1 * k2] = c_scale(u[s][k2], a.scale);
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const int mm = (p + R2 * s) + R1 * k2;
+                    const float2 g = c_scale(u[s][k2], a.scale);
+                    const float c = cr[mm];
+                    dst[mm] = make_float2(fmaf(a.cw, c, g.x), fmaf(a.cw, c, g.y));
+                }
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) dst[(p + R2 * s) + R1 * k2] = c_scale(u[s][k2], a.scale);
+        }
     }
 }
 
@@ -824,10 +847,16 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
     return rows_launch<T_C2R_DESC, true>(ilog2(nl), d, dbytes, st);
 }
 
+bool fft_fused_prolong(const Plan &p, int l)
+{
+    return p.lv[l].path == DMCR_PATH_FFT && !plane_supported(p, l) && p.lv[l].n[p.ndim - 1] >= 4;
+}
+
 hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
                              bool have_spectrum, const Ws &ws, hipStream_t st, hipStream_t st_spec, hipEvent_t x_free,
-                             hipEvent_t spec_done, const double *St)
+                             hipEvent_t spec_done, const double *St, const float *coarse, hipEvent_t coarse_ready)
 {
+    if (coarse && !fft_fused_prolong(p, l)) return hipErrorInvalidValue;
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C, CC = C * C;
     float2 *KB1 = ws.at<float2>(L.KB1);
@@ -903,8 +932,17 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
     const int64_t rows = (p.ndim == 2) ? (int64_t)B * C * n0 : (int64_t)B * C * n0 * L.n[1];
     RowArgs o = row_args(X, grad, rows, IO_HALF, L.hp, IO_FULL, nl, 0, false, true, 1.f);
     o.in_valid = L.h;
-    if (nl >= 4) return real_launch<T_C2R_FULL, true>(ilog2(nl), o, row_bytes(o), st);
-    return rows_launch<T_C2R_FULL, true>(ilog2(nl), o, row_bytes(o), st);
+    double obytes = row_bytes(o);
+    if (coarse) {
+        if (coarse_ready) TRY_HIP(hipStreamWaitEvent(st, coarse_ready, 0));
+        o.coarse = coarse;
+        o.cw = p.ndim == 2 ? 0.25f : 0.125f;
+        o.fn0 = n0;
+        o.fn1 = (p.ndim == 2) ? 1 : L.n[1];
+        obytes += (double)rows * nl * 4 / (1 << p.ndim);   // the coarse level: 2^-d of the voxels
+    }
+    if (nl >= 4) return real_launch<T_C2R_FULL, true>(ilog2(nl), o, obytes, st);
+    return rows_launch<T_C2R_FULL, true>(ilog2(nl), o, obytes, st);
 }
 
 }  // namespace dmcr

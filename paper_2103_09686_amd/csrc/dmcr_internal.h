@@ -144,8 +144,9 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
                              hipEvent_t x_free = nullptr, hipEvent_t spec_done = nullptr,
                              const double *St = nullptr, const float *coarse = nullptr,
                              hipEvent_t coarse_ready = nullptr);
-// Whether level l's adjoint ends in the contiguous-axis inverse that can add the
-// prolongation (FFT path, no fused plane transform, rows of at least 4).
+// Whether level l's adjoint ends in an inverse pass that can add the
+// prolongation: the fused plane transform, or the contiguous-axis inverse with
+// rows of at least 4 (FFT path).
 bool fft_fused_prolong(const Plan &p, int l);
 
 // 3-D levels with square planes of side 32..256: the contiguous axis and axis 1
@@ -153,7 +154,10 @@ bool fft_fused_prolong(const Plan &p, int l);
 // -> half spectra X [B][C][n0][n][hp]; inverse: X -> real field (unnormalised).
 bool plane_supported(const Plan &p, int l);
 hipError_t plane_forward(const Plan &p, int l, const float *phi, float2 *X, hipStream_t st);
-hipError_t plane_inverse(const Plan &p, int l, const float2 *X, float *grad, hipStream_t st);
+// With coarse, the inverse also adds 1/8 of the coarser level's gradient at each
+// voxel's parent (the multigrid prolongation; needs an even n0).
+hipError_t plane_inverse(const Plan &p, int l, const float2 *X, float *grad, hipStream_t st,
+                         const float *coarse = nullptr);
 
 hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
                                 hipStream_t st);

@@ -849,7 +849,7 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
 
 bool fft_fused_prolong(const Plan &p, int l)
 {
-    return p.lv[l].path == DMCR_PATH_FFT && !plane_supported(p, l) && p.lv[l].n[p.ndim - 1] >= 4;
+    return p.lv[l].path == DMCR_PATH_FFT && (plane_supported(p, l) || p.lv[l].n[p.ndim - 1] >= 4);
 }
 
 hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
@@ -923,7 +923,8 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
     a.scale = (float)(invN * invN);
     const double bytes0 = 2.0 * B * C * n0 * inner_valid * 8 + (double)B * CC * L.box * inner_valid * 8;
     TRY_HIP(axis0_launch(C, true, ilog2(n0), a, bytes0, st));
-    if (plane_supported(p, l)) return plane_inverse(p, l, X, grad, st);   // both axes in one pass
+    if (coarse && coarse_ready) TRY_HIP(hipStreamWaitEvent(st, coarse_ready, 0));
+    if (plane_supported(p, l)) return plane_inverse(p, l, X, grad, st, coarse);   // both axes in one pass
     if (p.ndim == 3) {
         ColArgs c = col_args(X, X, (int64_t)B * C * n0 * L.hp, L.hp, IO_FULL, L.n[1], IO_FULL, L.n[1], 0);
         c.h = L.h;
@@ -934,7 +935,6 @@ hipError_t fft_adjoint_level(const Plan &p, int l, const float *phi, const float
     o.in_valid = L.h;
     double obytes = row_bytes(o);
     if (coarse) {
-        if (coarse_ready) TRY_HIP(hipStreamWaitEvent(st, coarse_ready, 0));
         o.coarse = coarse;
         o.cw = p.ndim == 2 ? 0.25f : 0.125f;
         o.fn0 = n0;

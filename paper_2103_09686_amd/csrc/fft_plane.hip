@@ -300,10 +300,13 @@ __global__ __launch_bounds__(Plane<L>::threads) void k_plane_fwd(const float *in
 
 // Contiguous-axis half-to-real transform of the half plane staged from the
 // column phase (val[h][s][k2] = row (q + R2 s) + R1 k2, column h nb + c; packed
-// column 0).  dst: the real rows as pairs, row r at dst + r nh.
-template <int L>
+// column 0).  dst: the real rows as pairs, row r at dst + r nh.  With PRO, each
+// output also takes cw times its parent in the coarser plane cplane (rows of nh
+// reals; fine row row0 + r has parent row (row0 + r) / 2, and the two reals of
+// pair j share the parent j).
+template <int L, bool PRO = false>
 __device__ __forceinline__ void row_c2r(const float2 (&val)[Plane<L>::NB][Plane<L>::S][Plane<L>::R2], float2 *lds,
-                                        float2 *dst)
+                                        float2 *dst, const float *cplane = nullptr, int row0 = 0, float cw = 0.f)
 {
     using G = Plane<L>;
     constexpr int nh = G::nh, nb = G::nb, NB = G::NB, LH = G::LH, R1 = G::R1, R2 = G::R2, S = G::S,
@@ -354,10 +357,22 @@ __device__ __forceinline__ void row_c2r(const float2 (&val)[Plane<L>::NB][Plane<
 #pragma unroll
     for (int h = 0; h < NB; ++h) {
         float2 *row = dst + (size_t)(h * nb + t) * nh;
+        if constexpr (PRO) {
+            const float *cr = cplane + (size_t)((row0 + h * nb + t) / 2) * nh;
 #pragma unroll
-        for (int s = 0; s < S; ++s)
+            for (int s = 0; s < S; ++s)
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) row[(p + R2 * s) + R1 * k2] = u[h][s][k2];
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const int j = (p + R2 * s) + R1 * k2;
+                    const float c = cr[j];
+                    row[j] = make_float2(fmaf(cw, c, u[h][s][k2].x), fmaf(cw, c, u[h][s][k2].y));
+                }
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) row[(p + R2 * s) + R1 * k2] = u[h][s][k2];
+        }
     }
 }
 
@@ -403,9 +418,11 @@ __device__ __forceinline__ void cols_inv(float2 (&v)[Plane<L>::NB][Plane<L>::R1]
 }
 
 // in: half spectra [nplanes][n][hp]; out: real planes [nplanes][n][n] (both
-// axes inverse, unnormalised)
-template <int L>
-__global__ __launch_bounds__(Plane<L>::threads) void k_plane_inv(const float2 *in, float *out, int hp)
+// axes inverse, unnormalised).  With PRO, plane pl = bc n0 + z also adds cw times
+// the coarser level's plane bc n0/2 + z/2 of `coarse` at each voxel's parent.
+template <int L, bool PRO>
+__global__ __launch_bounds__(Plane<L>::threads) void k_plane_inv(const float2 *in, float *out, int hp,
+                                                                 const float *coarse, float cw, int n0)
 {
     using G = Plane<L>;
     constexpr int n = G::n, nh = G::nh, nb = G::nb, NB = G::NB, R1 = G::R1, R2 = G::R2, S = G::S;
@@ -438,29 +455,47 @@ __global__ __launch_bounds__(Plane<L>::threads) void k_plane_inv(const float2 *i
             }
         });
     });
-    row_c2r<L>(se, lds, dst);
-    row_c2r<L>(so, lds, dst + (size_t)nh * nh);
+    if constexpr (PRO) {
+        const int64_t bc = pl / n0, z = pl % n0;
+        const float *cplane = coarse + (bc * (n0 / 2) + z / 2) * nh * nh;
+        row_c2r<L, true>(se, lds, dst, cplane, 0, cw);
+        row_c2r<L, true>(so, lds, dst + (size_t)nh * nh, cplane, nh, cw);
+    } else {
+        row_c2r<L>(se, lds, dst);
+        row_c2r<L>(so, lds, dst + (size_t)nh * nh);
+    }
 }
 
+// the prolongation of the inverse (coarse, cw, n0) is used when coarse is set
+struct PlanePro {
+    const float *coarse;
+    float cw;
+    int n0;
+};
+
 template <int L>
-hipError_t plane_launch(bool inv, const void *in, void *out, int64_t nplanes, int hp, double bytes, hipStream_t st)
+hipError_t plane_launch(bool inv, const void *in, void *out, int64_t nplanes, int hp, double bytes, hipStream_t st,
+                        PlanePro pro)
 {
     const dim3 g((unsigned)nplanes), b(Plane<L>::threads);
+    if (inv && pro.coarse)
+        return launch("plane_inv", bytes, k_plane_inv<L, true>, g, b, 0, st, static_cast<const float2 *>(in),
+                      static_cast<float *>(out), hp, pro.coarse, pro.cw, pro.n0);
     if (inv)
-        return launch("plane_inv", bytes, k_plane_inv<L>, g, b, 0, st, static_cast<const float2 *>(in),
-                      static_cast<float *>(out), hp);
+        return launch("plane_inv", bytes, k_plane_inv<L, false>, g, b, 0, st, static_cast<const float2 *>(in),
+                      static_cast<float *>(out), hp, (const float *)nullptr, 0.f, 1);
     return launch("plane_fwd", bytes, k_plane_fwd<L>, g, b, 0, st, static_cast<const float *>(in),
                   static_cast<float2 *>(out), hp);
 }
 
 hipError_t plane_dispatch(bool inv, int L, const void *in, void *out, int64_t nplanes, int hp, double bytes,
-                          hipStream_t st)
+                          hipStream_t st, PlanePro pro = PlanePro{nullptr, 0.f, 1})
 {
     switch (L) {
-    case 5: return plane_launch<5>(inv, in, out, nplanes, hp, bytes, st);
-    case 6: return plane_launch<6>(inv, in, out, nplanes, hp, bytes, st);
-    case 7: return plane_launch<7>(inv, in, out, nplanes, hp, bytes, st);
-    case 8: return plane_launch<8>(inv, in, out, nplanes, hp, bytes, st);
+    case 5: return plane_launch<5>(inv, in, out, nplanes, hp, bytes, st, pro);
+    case 6: return plane_launch<6>(inv, in, out, nplanes, hp, bytes, st, pro);
+    case 7: return plane_launch<7>(inv, in, out, nplanes, hp, bytes, st, pro);
+    case 8: return plane_launch<8>(inv, in, out, nplanes, hp, bytes, st, pro);
     }
     return hipErrorInvalidValue;
 }
@@ -494,14 +529,16 @@ hipError_t plane_forward(const Plan &p, int l, const float *phi, float2 *X, hipS
     return plane_dispatch(false, plane_log2(L), phi, X, nplanes, L.hp, bytes, st);
 }
 
-hipError_t plane_inverse(const Plan &p, int l, const float2 *X, float *grad, hipStream_t st)
+hipError_t plane_inverse(const Plan &p, int l, const float2 *X, float *grad, hipStream_t st, const float *coarse)
 {
     const LevelPlan &L = p.lv[l];
     if (!plane_supported(p, l)) return hipErrorInvalidValue;
     const int64_t nplanes = (int64_t)p.B * p.C * L.n[0];
     if (nplanes >= (int64_t(1) << 31)) return hipErrorInvalidValue;
-    const double bytes = (double)nplanes * L.n[1] * ((double)L.n[2] * 4 + (double)L.h * 8);
-    return plane_dispatch(true, plane_log2(L), X, grad, nplanes, L.hp, bytes, st);
+    if (coarse && L.n[0] % 2) return hipErrorInvalidValue;
+    double bytes = (double)nplanes * L.n[1] * ((double)L.n[2] * 4 + (double)L.h * 8);
+    if (coarse) bytes += (double)nplanes * L.n[1] * L.n[2] * 4 / 8;   // the coarse level: 1/8 of the voxels
+    return plane_dispatch(true, plane_log2(L), X, grad, nplanes, L.hp, bytes, st, PlanePro{coarse, 0.125f, L.n[0]});
 }
 
 }  // namespace dmcr

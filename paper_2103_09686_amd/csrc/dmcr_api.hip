@@ -269,13 +269,31 @@ const float *level_field(const Plan &p, int l, const float *phi, const Ws &ws)
     return l == 0 ? phi : ws.at<const float>(p.lv[l].field);
 }
 
-hipError_t run_pyramid(const Plan &p, const float *phi, const Ws &ws, hipStream_t st)
+// levels 1..L-1 of the pyramid of phi into out[1..L-1]
+hipError_t pyramid_into(const Plan &p, const float *phi, float *const *out, hipStream_t st)
 {
-    for (int l = 0; l + 1 < p.L; ++l) {
-        hipError_t e = launch_restrict(p, l, level_field(p, l, phi, ws), ws.at<float>(p.lv[l + 1].field), st);
+    for (int l = 0; l + 1 < p.L;) {
+        const float *f = (l == 0) ? phi : out[l];
+        hipError_t e;
+        // two levels per pass (its float4 loads need a 16-byte aligned field; the
+        // caller's field may be a view that is only 8-byte aligned)
+        if (l + 2 < p.L && reinterpret_cast<uintptr_t>(f) % 16 == 0) {
+            e = launch_restrict2(p, l, f, out[l + 1], out[l + 2], st);
+            l += 2;
+        } else {
+            e = launch_restrict(p, l, f, out[l + 1], st);
+            l += 1;
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t run_pyramid(const Plan &p, const float *phi, const Ws &ws, hipStream_t st)
+{
+    float *out[kMaxLevels] = {};
+    for (int l = 1; l < p.L; ++l) out[l] = ws.at<float>(p.lv[l].field);
+    return pyramid_into(p, phi, out, st);
 }
 
 // Internal streams that let independent work of one call overlap: the levels
@@ -534,14 +552,13 @@ dmcr_status dmcr_pyramid(const dmcr_spec *spec, int32_t batch, const float *phi,
     dmcr_status s = make_plan(spec, batch, &p);
     if (s != DMCR_OK) return s;
     if (!phi || (p.L > 1 && !levels)) return DMCR_EINVAL;
-    const float *prev = phi;
-    float *out = levels;
-    for (int l = 0; l + 1 < p.L; ++l) {
-        DMCR_TRY(launch_restrict(p, l, prev, out, stream));
-        prev = out;
-        out += (int64_t)p.B * p.C * p.lv[l + 1].N;
+    float *out[kMaxLevels] = {};
+    float *next = levels;
+    for (int l = 1; l < p.L; ++l) {
+        out[l] = next;
+        next += (int64_t)p.B * p.C * p.lv[l].N;
     }
-    return DMCR_OK;
+    return dev(pyramid_into(p, phi, out, stream));
 }
 
 dmcr_status dmcr_descriptor_forward(const dmcr_spec *spec, int32_t batch, const float *phi, float *S,

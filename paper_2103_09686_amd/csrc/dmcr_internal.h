@@ -117,6 +117,8 @@ struct Ws {
 };
 
 hipError_t launch_restrict(const Plan &p, int l, const float *fine, float *coarse, hipStream_t st);
+// levels l+1 and l+2 from level l in one pass (bitwise as two launch_restrict)
+hipError_t launch_restrict2(const Plan &p, int l, const float *fine, float *mid, float *coarse, hipStream_t st);
 hipError_t launch_prolong_add(const Plan &p, int l, const float *coarse_grad, float *fine_grad,
                               hipStream_t st);
 // fine (level l) = nearest-neighbour upsampling of coarse (level l + 1)

@@ -42,6 +42,64 @@ __global__ __launch_bounds__(kThreads) void k_restrict(const float *__restrict__
     }
 }
 
+// Two levels at once: level l+2 voxel y from the 4^d block of level l at 4y,
+// writing its 2^d level-(l+1) children on the way.  The sums are those of
+// k_restrict applied twice, in the same order, so both levels are bitwise the
+// same as two one-level passes.  c* are the level-(l+2) extents.
+__global__ __launch_bounds__(kThreads) void k_restrict2(const float *__restrict__ fine,
+                                                        float *__restrict__ mid, float *__restrict__ coarse,
+                                                        int64_t total, int ndim, int c0, int c1, int c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= total) return;
+    if (ndim == 2) {
+        const int64_t x1 = i % c1;
+        const int64_t r = i / c1;
+        const int64_t x0 = r % c0;
+        const int64_t bc = r / c0;
+        const int64_t m1 = 2 * (int64_t)c1, f1 = 4 * (int64_t)c1;
+        const float *f = fine + (bc * 4 * c0 + 4 * x0) * f1 + 4 * x1;
+        float v[2][2];
+#pragma unroll
+        for (int a0 = 0; a0 < 2; ++a0) {
+            const float4 a = *reinterpret_cast<const float4 *>(f + (2 * a0) * f1);
+            const float4 b = *reinterpret_cast<const float4 *>(f + (2 * a0 + 1) * f1);
+            v[a0][0] = 0.25f * ((a.x + a.y) + (b.x + b.y));
+            v[a0][1] = 0.25f * ((a.z + a.w) + (b.z + b.w));
+            *reinterpret_cast<float2 *>(mid + (bc * 2 * c0 + 2 * x0 + a0) * m1 + 2 * x1) =
+                make_float2(v[a0][0], v[a0][1]);
+        }
+        coarse[i] = 0.25f * ((v[0][0] + v[0][1]) + (v[1][0] + v[1][1]));
+    } else {
+        const int64_t x2 = i % c2;
+        int64_t r = i / c2;
+        const int64_t x1 = r % c1;
+        r /= c1;
+        const int64_t x0 = r % c0;
+        const int64_t bc = r / c0;
+        const int64_t m2 = 2 * (int64_t)c2, m1 = 2 * (int64_t)c1;
+        const int64_t f2 = 4 * (int64_t)c2, f1 = 4 * (int64_t)c1;
+        const float *f = fine + ((bc * 4 * c0 + 4 * x0) * f1 + 4 * x1) * f2 + 4 * x2;
+        float v[2][2][2];
+#pragma unroll
+        for (int a0 = 0; a0 < 2; ++a0)
+#pragma unroll
+            for (int a1 = 0; a1 < 2; ++a1) {
+                const float *q = f + (2 * a0) * f1 * f2 + (2 * a1) * f2;
+                const float4 a = *reinterpret_cast<const float4 *>(q);
+                const float4 b = *reinterpret_cast<const float4 *>(q + f2);
+                const float4 c = *reinterpret_cast<const float4 *>(q + f1 * f2);
+                const float4 d = *reinterpret_cast<const float4 *>(q + f1 * f2 + f2);
+                v[a0][a1][0] = 0.125f * (((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y)));
+                v[a0][a1][1] = 0.125f * (((a.z + a.w) + (b.z + b.w)) + ((c.z + c.w) + (d.z + d.w)));
+                *reinterpret_cast<float2 *>(mid + ((bc * 2 * c0 + 2 * x0 + a0) * m1 + 2 * x1 + a1) * m2 + 2 * x2) =
+                    make_float2(v[a0][a1][0], v[a0][a1][1]);
+            }
+        coarse[i] = 0.125f * (((v[0][0][0] + v[0][0][1]) + (v[0][1][0] + v[0][1][1])) +
+                              ((v[1][0][0] + v[1][0][1]) + (v[1][1][0] + v[1][1][1])));
+    }
+}
+
 // fine(x) += w coarse(floor(x/2)); w = 2^-d is the transpose of the mean pool.
 // With assign, fine(x) = w coarse(floor(x/2)) (w = 1: nearest-neighbour upsampling).
 __global__ __launch_bounds__(kThreads) void k_prolong_add(const float *__restrict__ coarse,
@@ -293,6 +351,16 @@ hipError_t launch_restrict(const Plan &p, int l, const float *fine, float *coars
     if (total == 0) return hipSuccess;
     return launch("restrict", (double)total * 4 * (1 + (1 << p.ndim)), k_restrict, dim3(blocks_for(total)),
                   dim3(kThreads), 0, st, fine, coarse, total, p.ndim, c.n[0], c.n[1], c.n[2]);
+}
+
+hipError_t launch_restrict2(const Plan &p, int l, const float *fine, float *mid, float *coarse, hipStream_t st)
+{
+    const LevelPlan &c = p.lv[l + 2];
+    const int64_t total = (int64_t)p.B * p.C * c.N;
+    if (total == 0) return hipSuccess;
+    const int64_t nmid = total << p.ndim, nfine = nmid << p.ndim;
+    return launch("restrict", (double)(nfine + nmid + total) * 4, k_restrict2, dim3(blocks_for(total)),
+                  dim3(kThreads), 0, st, fine, mid, coarse, total, p.ndim, c.n[0], c.n[1], c.n[2]);
 }
 
 hipError_t launch_prolong_add(const Plan &p, int l, const float *coarse_grad, float *fine_grad,

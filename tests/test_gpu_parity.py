@@ -169,6 +169,29 @@ def test_pyramid_parity(dm, ora):
         np.testing.assert_allclose(lv[l - 1].cpu().numpy()[0], ref[l], rtol=2e-7, atol=0)
 
 
+@pytest.mark.parametrize("shape,L", [((64, 32), 3), ((64, 32), 4), ((16, 32, 8), 3), ((32, 16, 16), 4)])
+def test_pyramid_two_levels_per_pass(dm, ora, shape, L):
+    """Levels l+1 and l+2 come from level l in one pass when the field is 16-byte
+    aligned; a view 8 bytes off takes two one-level passes.  Both must equal each
+    other bitwise and the oracle's mean pool."""
+    spec = dm.Spec(shape=shape, n_channels=2, n_levels=L, max_disp=(0,))
+    B = 2
+    phi = f32(np.stack([synth.uniform(shape, 60 + b, channels=2) for b in range(B)]))
+    a = to_dev(phi)
+    flat = torch.zeros(a.numel() + 2, device="cuda")
+    flat[2:] = a.reshape(-1)
+    b = flat[2:].view(a.shape)                  # 8-byte aligned, not 16
+    assert a.data_ptr() % 16 == 0 and b.data_ptr() % 16 == 8
+    la = dm.dmcr_pyramid(spec, a)
+    lb = dm.dmcr_pyramid(spec, b)
+    for l in range(1, L):
+        assert torch.equal(la[l - 1], lb[l - 1]), l
+    for i in range(B):
+        ref = ora.pyramid(phi[i], L)
+        for l in range(1, L):
+            np.testing.assert_allclose(la[l - 1].cpu().numpy()[i], ref[l], rtol=2e-7, atol=0)
+
+
 def test_batched_equals_single_bitwise_and_repeatable(dm):
     shape = (64, 64)
     for path in (1, 2):

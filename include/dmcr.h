@@ -36,7 +36,10 @@
  * Memory.  The caller owns every buffer.  Pointers marked "device" must be
  *   device memory of the current HIP device; the library never allocates on
  *   these calls: scratch comes from the caller's workspace `ws` of at least
- *   dmcr_workspace_size() bytes (256-byte aligned).
+ *   dmcr_workspace_size() bytes (256-byte aligned).  Fields, gradients,
+ *   pyramid levels and float64 buffers must be 8-byte aligned (fields move as
+ *   float pairs); a 16-byte aligned field lets the pyramid restrict two levels
+ *   per pass.  A misaligned pointer returns DMCR_EINVAL.
  * Streams.  Every call except the reconstruction and solver-slot calls is
  *   asynchronous on `stream` and returns before the work finishes; device
  *   faults surface on a later call or synchronisation.  Calls that share a

@@ -552,6 +552,7 @@ dmcr_status dmcr_pyramid(const dmcr_spec *spec, int32_t batch, const float *phi,
     dmcr_status s = make_plan(spec, batch, &p);
     if (s != DMCR_OK) return s;
     if (!phi || (p.L > 1 && !levels)) return DMCR_EINVAL;
+    if (!aligned8(phi) || !aligned8(levels)) return DMCR_EINVAL;
     float *out[kMaxLevels] = {};
     float *next = levels;
     for (int l = 1; l < p.L; ++l) {
@@ -567,7 +568,7 @@ dmcr_status dmcr_descriptor_forward(const dmcr_spec *spec, int32_t batch, const 
     Plan p;
     dmcr_status s = make_plan(spec, batch, &p);
     if (s != DMCR_OK) return s;
-    if (!phi || !S) return DMCR_EINVAL;
+    if (!phi || !S || !aligned8(phi)) return DMCR_EINVAL;
     if ((s = check_ws(p, ws, ws_bytes)) != DMCR_OK) return s;
     Ws w{static_cast<char *>(ws)};
     Sched sc;
@@ -581,7 +582,7 @@ dmcr_status dmcr_descriptor_adjoint(const dmcr_spec *spec, int32_t batch, const 
     Plan p;
     dmcr_status s = make_plan(spec, batch, &p);
     if (s != DMCR_OK) return s;
-    if (!phi || !dS || !grad) return DMCR_EINVAL;
+    if (!phi || !dS || !grad || !aligned8(phi) || !aligned8(grad)) return DMCR_EINVAL;
     if ((s = check_ws(p, ws, ws_bytes)) != DMCR_OK) return s;
     Ws w{static_cast<char *>(ws)};
     Sched sc;
@@ -607,7 +608,7 @@ dmcr_status dmcr_error_cotangent(const dmcr_spec *spec, int32_t batch, const flo
     Plan p;
     dmcr_status s = make_plan(spec, batch, &p);
     if (s != DMCR_OK) return s;
-    if (!S || !S_target || !E || !G) return DMCR_EINVAL;
+    if (!S || !S_target || !E || !G || !aligned8(S_target) || !aligned8(E)) return DMCR_EINVAL;
     if ((s = check_ws(p, ws, ws_bytes)) != DMCR_OK) return s;
     Ws w{static_cast<char *>(ws)};
     return dev(launch_error(p, S, S_target, E, G, w, stream));
@@ -620,6 +621,7 @@ dmcr_status dmcr_loss_grad(const dmcr_spec *spec, int32_t batch, const float *ph
     dmcr_status s = make_plan(spec, batch, &p);
     if (s != DMCR_OK) return s;
     if (!phi || !S_target || !E || !grad) return DMCR_EINVAL;
+    if (!aligned8(phi) || !aligned8(grad) || !aligned8(S_target) || !aligned8(E)) return DMCR_EINVAL;
     if ((s = check_ws(p, ws, ws_bytes)) != DMCR_OK) return s;
     Ws w{static_cast<char *>(ws)};
     return loss_grad_internal(p, phi, S_target, E, grad, w, stream);

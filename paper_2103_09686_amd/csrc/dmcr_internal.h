@@ -17,6 +17,8 @@ constexpr int kMaxChannels = DMCR_MAX_CHANNELS;
 constexpr int kMaxPairs = DMCR_MAX_PAIRS;
 constexpr int kMaxFft = 1024;          // longest axis handled by the LDS transforms
 constexpr size_t kAlign = 256;
+// field buffers move as float pairs: phi, gradients and pyramid levels need 8-byte alignment
+inline bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7) == 0; }
 
 // Rows stored along a transformed axis: all n (FULL), the first n/2+1 of a
 // Hermitian half spectrum (HALF), the 2P+1 rows |r| <= P in box order (BOX),

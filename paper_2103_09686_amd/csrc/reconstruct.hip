@@ -965,7 +965,7 @@ dmcr_status make_solver(const dmcr_spec *spec, int32_t batch, const double *S_ta
                         const dmcr_opt *opt, float *phi, void *ws, size_t ws_bytes, hipStream_t st, Plan &p,
                         Solver **out, std::vector<char> &mem)
 {
-    if (!opt_ok(opt) || !bounds || !S_target || !phi) return DMCR_EINVAL;
+    if (!opt_ok(opt) || !bounds || !S_target || !phi || !aligned8(phi) || !aligned8(S_target)) return DMCR_EINVAL;
     if (bounds->mode < DMCR_BOUNDS_NONE || bounds->mode > DMCR_BOUNDS_PENALTY) return DMCR_EINVAL;
     if (bounds->mode != DMCR_BOUNDS_NONE && !(bounds->lo < bounds->hi)) return DMCR_EINVAL;
     if (bounds->mode == DMCR_BOUNDS_PENALTY && !(bounds->kappa >= 0.0)) return DMCR_EINVAL;
@@ -1062,6 +1062,7 @@ dmcr_status dmcr_reconstruct_coarse_to_fine(const dmcr_spec *spec, int32_t batch
                                             dmcr_result *results, void *ws, size_t ws_bytes, hipStream_t st)
 {
     if (!results || batch < 1 || !S_target || !phi || !bounds || !opt_ok(opt)) return DMCR_EINVAL;
+    if (!aligned8(phi) || !aligned8(S_target)) return DMCR_EINVAL;
     Plan p;
     dmcr_status s = make_plan(spec, batch, &p);
     if (s != DMCR_OK) return s;

@@ -147,3 +147,26 @@ def test_empty_batch_rejected(dm):
     with pytest.raises(dm.DmcrError) as e:
         dm.dmcr_workspace_size(spec, 0)
     assert e.value.code == -1
+
+
+def test_misaligned_buffers_rejected_before_any_launch(dm):
+    """Fields and float64 buffers must be 8-byte aligned: a pointer 4 bytes off is
+    rejected with DMCR_EINVAL before anything is launched (host-side check only,
+    so fake device addresses are safe here)."""
+    spec = dm.Spec(shape=(64, 64), max_disp=(8,))
+    s = spec.c()
+    K = dm.dmcr_descriptor_size(spec)
+    ws_bytes = dm.dmcr_workspace_size(spec, 1)
+    L = dm.lib()
+    ws = ctypes.c_void_p(1 << 20)                        # 256-byte aligned fake address
+    ok, bad = ctypes.c_void_p(1 << 24), ctypes.c_void_p((1 << 24) + 4)
+    E = ctypes.c_void_p(1 << 25)
+    assert L.dmcr_loss_grad(ctypes.byref(s), 1, bad, ok, E, ok, ws, ws_bytes, None) == -1     # phi
+    assert L.dmcr_loss_grad(ctypes.byref(s), 1, ok, bad, E, ok, ws, ws_bytes, None) == -1     # target
+    assert L.dmcr_loss_grad(ctypes.byref(s), 1, ok, ok, E, bad, ws, ws_bytes, None) == -1     # grad
+    assert L.dmcr_descriptor_forward(ctypes.byref(s), 1, bad, ok, ws, ws_bytes, None) == -1
+    assert L.dmcr_descriptor_adjoint(ctypes.byref(s), 1, ok, ok, bad, ws, ws_bytes, None) == -1
+    s2 = dm.Spec(shape=(64, 64), n_levels=3, max_disp=(8,)).c()
+    assert L.dmcr_pyramid(ctypes.byref(s2), 1, bad, ok, None) == -1
+    assert L.dmcr_pyramid(ctypes.byref(s2), 1, ok, bad, None) == -1
+    assert K > 0

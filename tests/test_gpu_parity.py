@@ -192,6 +192,23 @@ def test_pyramid_two_levels_per_pass(dm, ora, shape, L):
             np.testing.assert_allclose(la[l - 1].cpu().numpy()[i], ref[l], rtol=2e-7, atol=0)
 
 
+@pytest.mark.parametrize("shape,C,B,P", [((512, 512), 1, 64, 32), ((64, 64, 64), 2, 32, 8)],
+                         ids=["2d512_b64", "3d64_c2_b32"])
+def test_side_lanes_equal_one_stream_bitwise(dm, shape, C, B, P):
+    """A three-level batch of B C N = 2^24 voxels runs its levels on side lanes,
+    chained by events (the coarser total gradient prolonged inside each level's
+    last inverse pass, two restrictions per pass).  Each field's loss and gradient
+    must equal, bitwise, the same field evaluated alone on one stream."""
+    spec = dm.make_spec(shape, C, 3, P)
+    print("lanes case", shape, C, B, flush=True)
+    phi = to_dev(np.stack([synth.uniform(shape, 500 + b, channels=C) for b in range(B)]))
+    S_t = dm.dmcr_descriptor_forward(spec, (phi * 0.5 + 0.1).contiguous()).double().contiguous()
+    E, g = dm.dmcr_loss_grad(spec, phi, S_t)
+    for b in (0, B // 2, B - 1):
+        E1, g1 = dm.dmcr_loss_grad(spec, phi[b:b + 1].contiguous(), S_t[b:b + 1].contiguous())
+        assert torch.equal(E1[0], E[b]) and torch.equal(g1[0], g[b]), b
+
+
 def test_batched_equals_single_bitwise_and_repeatable(dm):
     shape = (64, 64)
     for path in (1, 2):

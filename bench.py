@@ -382,8 +382,23 @@ def main():
                   file=sys.stderr, flush=True)
         return kern
 
+    def step_percentiles(fn, n=100):
+        """Per-step GPU time: an event pair around each of n back-to-back steps on the
+        launch stream (after the timed region, so the clock is steady)."""
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        t = sorted(a.elapsed_time(b) for a, b in evs)
+        return dict(steps=n, p50_ms=round(t[n // 2], 5), p99_ms=round(t[min(n - 1, int(0.99 * n))], 5),
+                    max_ms=round(t[-1], 5))
+
     ms = timed(step)
     value = N * B / (ms * 1e-3)
+    step_time = step_percentiles(step)
+    print("per-step GPU time: %s" % step_time, file=sys.stderr, flush=True)
     kern = kernel_table(step)
     dom = kern[0]
     prof_ms = sum(r["total_ms"] for r in kern) / args.steps
@@ -437,7 +452,7 @@ def main():
                              kernel_ms_sum=round(prof_ms, 4))
 
     out = dict(metric=METRIC, value=value, unit="voxel·it/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
+               warmup=args.warmup, ms_per_step=ms, step_time=step_time, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload=wl["desc"], shape=list(shape), channels=C, levels=L,
                            max_disp=list(spec.max_disp), K=K, batch=B, path="direct" if desc else "fft",

@@ -63,3 +63,59 @@ def test_2d_512_three_levels(dm, ora):
             sel = np.arange(k)
         ref = ora._native.corr(lv[l][0], lv[l][0], rs[sel])
         assert np.max(np.abs(S[off + sel] - ref)) <= 1e-5 * np.max(np.abs(ref)), l
+
+
+def test_3d_512_sampled(dm, ora):
+    """The largest cube whose every axis the transforms take (512^3, 134M voxels):
+    one level, P = 32, spectra recomputed; 256 sampled displacements of S and the
+    gradient at 64 sampled voxels for a seeded cotangent."""
+    shape = (512, 512, 512)
+    print("fullsize 512^3", flush=True)
+    spec = dm.Spec(shape=shape, n_channels=1, n_levels=1, max_disp=(32,), path=1, flags=dm.FLAG_RECOMPUTE)
+    ospec = ora.Spec(shape=shape, n_channels=1, n_levels=1, max_disp=(32,))
+    phi32 = synth.uniform(shape, 3).astype(np.float32)
+    d = torch.from_numpy(phi32[None]).cuda()
+    S = dm.dmcr_descriptor_forward(spec, d).cpu().numpy()[0].astype(np.float64)
+    rng = np.random.default_rng(2)
+    H = ora.half_box(3, 32)
+    idx = np.sort(rng.choice(len(H), 256, replace=False))
+    idx[0] = 0
+    phi = phi32.astype(np.float64)
+    S_ora = ora._native.corr(phi[0], phi[0], H[idx])
+    assert np.max(np.abs(S[idx] - S_ora)) <= 1e-5 * np.max(np.abs(S_ora))
+    u = rng.standard_normal(len(H)).astype(np.float32)
+    g = dm.dmcr_descriptor_adjoint(spec, d, torch.from_numpy(u[None]).cuda()).cpu().numpy()[0, 0]
+    vox = rng.integers(0, 512, size=(64, 3))
+    g_ora = ora.adjoint_at_single_level(phi, u.astype(np.float64), ospec, vox)[0]
+    g_s = g[tuple(vox.T)].astype(np.float64)
+    assert np.linalg.norm(g_s - g_ora) <= 1e-4 * np.linalg.norm(g_ora)
+
+
+def test_2d_1024_two_channels_three_levels(dm, ora):
+    """The largest 2-D field (1024^2), two channels (both autos and the cross pair),
+    three levels, P = 31: 256 sampled entries of every (level, pair) block; the
+    one-level gradient of both channels at 64 sampled pixels."""
+    shape = (1024, 1024)
+    print("fullsize 1024^2", flush=True)
+    spec = dm.make_spec(shape, 2, 3, 31)
+    ospec = ora.Spec(shape=shape, n_channels=2, n_levels=3, max_disp=spec.max_disp)
+    phi32 = synth.uniform(shape, 4, channels=2).astype(np.float32)
+    phi = phi32.astype(np.float64)
+    d = torch.from_numpy(phi32[None]).cuda()
+    S = dm.dmcr_descriptor_forward(spec, d).cpu().numpy()[0].astype(np.float64)
+    lv = ora.pyramid(phi, 3)
+    rng = np.random.default_rng(3)
+    for (l, (i, j), off, k) in ospec.layout():
+        rs = ospec.disp(l, (i, j))
+        sel = rng.choice(k, min(k, 256), replace=False)
+        ref = ora._native.corr(lv[l][i], lv[l][j], rs[sel])
+        assert np.max(np.abs(S[off + sel] - ref)) <= 1e-5 * np.max(np.abs(ref)), (l, i, j)
+    spec1 = dm.Spec(shape=shape, n_channels=2, n_levels=1, max_disp=(31,), path=1)
+    ospec1 = ora.Spec(shape=shape, n_channels=2, n_levels=1, max_disp=(31,))
+    u = rng.standard_normal(ospec1.K).astype(np.float32)
+    g = dm.dmcr_descriptor_adjoint(spec1, d, torch.from_numpy(u[None]).cuda()).cpu().numpy()[0]
+    vox = rng.integers(0, 1024, size=(64, 2))
+    g_ora = ora.adjoint_at_single_level(phi, u.astype(np.float64), ospec1, vox)
+    for c in range(2):
+        g_s = g[c][tuple(vox.T)].astype(np.float64)
+        assert np.linalg.norm(g_s - g_ora[c]) <= 1e-4 * np.linalg.norm(g_ora[c]), c

@@ -73,6 +73,10 @@ CASES = [
     # the longest axis the LDS transforms take (1024), on each axis
     ((1024, 16), 1, 1, (7,), (), 1),
     ((16, 1024), 2, 1, (7,), (), 1),
+    # the declared maxima: four channels (all ten pairs) and eight levels (down to 2 x 2)
+    ((32, 32), 4, 2, (5, 3), (), 1),
+    ((16, 8, 8), 4, 1, (2,), (), 2),
+    ((256, 256), 1, 8, (7, 7, 7, 7, 7, 3, 1, 0), (), 0),
     # square planes: the contiguous axis and axis 1 in one fused pass (n = 32..256)
     ((8, 32, 32), 2, 1, (3,), (), 1),
     ((4, 64, 64), 1, 2, (1, 0), (), 1),

@@ -362,9 +362,9 @@ struct Sched {
 // soft-threshold levels are long ALU-bound kernels whose coarse levels fill only
 // part of the chip, so their levels always run side by side.  Under stream
 // capture the event waits become graph edges that cost no host time, so a
-// captured call also runs its levels side by side (measured on replay: the
-// two-channel 128^3 three-level evaluation 0.156 ms with lanes, 0.212 ms on one
-// stream).  A recompute moves to a spare lane only by the size rule: there it
+// captured call also runs its levels side by side (measured: the two-channel
+// 128^3 three-level evaluation replays in 0.139 ms with lanes and takes
+// 0.193 ms eager on one stream).  A recompute moves to a spare lane only by the size rule: there it
 // takes the two-pass spectrum, and results must not depend on capture.
 constexpr int64_t kLaneMinVoxels = int64_t(1) << 24;
 

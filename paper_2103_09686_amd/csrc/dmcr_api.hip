@@ -364,8 +364,9 @@ struct Sched {
 // capture the event waits become graph edges that cost no host time, so a
 // captured call also runs its levels side by side (measured: the two-channel
 // 128^3 three-level evaluation replays in 0.139 ms with lanes and takes
-// 0.193 ms eager on one stream).  A recompute moves to a spare lane only by the size rule: there it
-// takes the two-pass spectrum, and results must not depend on capture.
+// 0.193 ms eager on one stream).  A recompute moves to a spare lane only by the
+// size rule: there it takes the two-pass spectrum, and results must not depend
+// on capture.
 constexpr int64_t kLaneMinVoxels = int64_t(1) << 24;
 
 hipError_t make_sched(const Plan &p, hipStream_t st, Sched *s)

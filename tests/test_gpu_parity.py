@@ -196,15 +196,18 @@ def test_pyramid_two_levels_per_pass(dm, ora, shape, L):
             np.testing.assert_allclose(la[l - 1].cpu().numpy()[i], ref[l], rtol=2e-7, atol=0)
 
 
-@pytest.mark.parametrize("shape,C,B,P", [((512, 512), 1, 64, 32), ((64, 64, 64), 2, 32, 8)],
-                         ids=["2d512_b64", "3d64_c2_b32"])
-def test_side_lanes_equal_one_stream_bitwise(dm, shape, C, B, P):
-    """A three-level batch of B C N = 2^24 voxels runs its levels on side lanes,
-    chained by events (the coarser total gradient prolonged inside each level's
-    last inverse pass, two restrictions per pass).  Each field's loss and gradient
-    must equal, bitwise, the same field evaluated alone on one stream."""
-    spec = dm.make_spec(shape, C, 3, P)
-    print("lanes case", shape, C, B, flush=True)
+@pytest.mark.parametrize("shape,C,B,L,P", [((512, 512), 1, 64, 3, 32), ((64, 64, 64), 2, 32, 3, 8),
+                                           ((1024, 1024), 1, 16, 1, 16)],
+                         ids=["2d512_b64_3lv", "3d64_c2_b32_3lv", "2d1024_b16_1lv"])
+def test_side_lanes_equal_one_stream_bitwise(dm, shape, C, B, L, P):
+    """A batch of B C N = 2^24 voxels runs on side lanes.  With three levels, the
+    levels are chained by events: the coarser total gradient is prolonged inside
+    each level's last inverse pass, and the pyramid takes two restrictions per
+    pass.  With one FFT level, the cotangent-kernel pass forms G from S and the
+    target itself, and the error reduction runs beside it.  Each field's loss and
+    gradient must equal, bitwise, the same field evaluated alone on one stream."""
+    spec = dm.make_spec(shape, C, L, P, path=1)
+    print("lanes case", shape, C, B, L, flush=True)
     phi = to_dev(np.stack([synth.uniform(shape, 500 + b, channels=C) for b in range(B)]))
     S_t = dm.dmcr_descriptor_forward(spec, (phi * 0.5 + 0.1).contiguous()).double().contiguous()
     E, g = dm.dmcr_loss_grad(spec, phi, S_t)

@@ -170,3 +170,26 @@ def test_misaligned_buffers_rejected_before_any_launch(dm):
     assert L.dmcr_pyramid(ctypes.byref(s2), 1, bad, ok, None) == -1
     assert L.dmcr_pyramid(ctypes.byref(s2), 1, ok, bad, None) == -1
     assert K > 0
+
+
+def test_no_cpu_fallback(dm):
+    """The binding computes nothing on the host: host tensors are refused before any
+    call, and a missing library is an error, not a slower path."""
+    import subprocess
+    import sys
+    import torch
+    spec = dm.Spec(shape=(16, 16), max_disp=(3,))
+    with pytest.raises(TypeError):
+        dm.dmcr_descriptor_forward(spec, torch.zeros(1, 1, 16, 16))
+    with pytest.raises(TypeError):
+        dm.dmcr_loss_grad(spec, torch.zeros(1, 1, 16, 16), torch.zeros(1, dm.dmcr_descriptor_size(spec),
+                                                                       dtype=torch.float64))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2103_09686_amd import dmcr\n"
+            "dmcr.LIB_PATH = '/nonexistent/libdmcr.so'\n"
+            "try:\n"
+            "    dmcr.dmcr_descriptor_size(dmcr.Spec(shape=(16, 16)))\n"
+            "except RuntimeError as e:\n"
+            "    print('refused:', e)\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "refused: libdmcr.so is not built" in r.stdout, r.stdout + r.stderr

@@ -166,6 +166,36 @@ def test_lbfgs_trajectory_matches_oracle(dm, ora):
     np.testing.assert_allclose(E_gpu, E_ora, rtol=1e-4)
 
 
+@pytest.mark.parametrize("shape,C,L,P", [((32, 32), 2, 2, (6, 3)), ((16, 16, 16), 1, 2, (4, 2)),
+                                         ((64, 32), 1, 3, (8, 4, 2))],
+                         ids=["2d32_c2_2lv", "3d16_2lv", "2d64x32_3lv"])
+def test_lbfgs_trajectory_other_configs(dm, ora, shape, C, L, P):
+    """The same trajectory check on several channels and levels: each of the first
+    six iterations takes the oracle's number of evaluations and reaches its E to
+    1e-4 relative."""
+    iters = 6
+    ospec = ora.Spec(shape=shape, n_channels=C, n_levels=L, max_disp=P)
+    r = 3 if len(shape) == 2 else 2
+    tgt = np.concatenate([synth.boolean_spheres(shape, r, 0.25 + 0.05 * c, seed=10 + c)[0] for c in range(C)])
+    S_des = ora.descriptor(tgt, ospec)
+    phi0 = synth.uniform(shape, 2, channels=C).astype(np.float32)
+    _, E_ora, ev_ora = ora.reconstruct_lbfgs_projected(S_des, ospec, phi0.astype(np.float64), iters)
+    sv = dm.Solver(dm.Spec(shape=shape, n_channels=C, n_levels=L, max_disp=P), 1, dm.Bounds(),
+                   dm.Opt(max_iter=10000, tol_derr=0.0))
+    sv.phi[0].copy_(torch.from_numpy(phi0))
+    sv.St[0].copy_(torch.from_numpy(S_des))
+    sv.start([0])
+    E_gpu, ev_gpu, last = [], [], sv.slots[0].evals
+    for _ in range(iters):
+        sv.iterate(1)
+        E_gpu.append(sv.slots[0].E)
+        ev_gpu.append(sv.slots[0].evals - last)
+        last = sv.slots[0].evals
+    print("E gpu", E_gpu, "\nE ora", E_ora, "\nevals", ev_gpu, ev_ora, flush=True)
+    assert ev_gpu == ev_ora
+    np.testing.assert_allclose(E_gpu, E_ora, rtol=1e-4)
+
+
 @pytest.mark.parametrize("m", [1, 32])
 def test_history_length_extremes(dm, ora, m):
     """History of one pair and of the largest ring (32): a batch of three converges,

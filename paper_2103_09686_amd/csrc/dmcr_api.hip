@@ -214,6 +214,9 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
             const int64_t nl = L.n[p.ndim - 1];
             const int64_t half = L.N / nl * L.hp;  // complex entries of one (padded) half spectrum
             L.X = cv.take((size_t)B * C * half * sizeof(float2));
+            L.mparts = fft_mean_parts(p, l);
+            L.msum = cv.take((size_t)B * C * L.mparts * sizeof(double));
+            L.mu = cv.take((size_t)B * C * sizeof(double));
             const int64_t inner = half / L.n[0];
             L.Y = cv.take((size_t)B * p.npairs * L.box * inner * sizeof(float2));
             if (p.ndim == 3) {

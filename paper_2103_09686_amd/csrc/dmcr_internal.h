@@ -46,6 +46,9 @@ struct LevelPlan {
     size_t KB0;        // adjoint kernels on the box, real [B][C*C][box^d]
     size_t KB1;        // after last-axis transform [B][C*C][box^(d-1)][h]
     size_t KB2;        // 3-D: after axis-1 transform [B][C*C][box][n1][h]
+    size_t msum;       // FFT: float64 partial sums of every field [B][C][mparts]
+    int64_t mparts;    // FFT: partial sums per field (fft_mean_parts)
+    size_t mu;         // FFT: float64 field means [B][C]
     size_t part;       // DIRECT: per-tile partial sums
     int64_t n_tiles;   // DIRECT: tiles per field
     int tile[3];       // DIRECT: tile edge per axis
@@ -132,9 +135,13 @@ hipError_t run_pyramid_levels(const Plan &p, const float *phi, const Ws &ws, hip
 hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
                              hipStream_t st, hipEvent_t x_free = nullptr);
 // fused = false keeps the two-pass transforms of 3-D levels (for a spectrum
-// computed while other kernels of the same step run on other streams).
+// computed while other kernels of the same step run on other streams).  With
+// msum, the first pass also writes float64 partial sums of every field
+// (fft_mean_parts per field, in field order).
 hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &ws, hipStream_t st,
-                              bool fused = true);
+                              bool fused = true, double *msum = nullptr);
+// partial sums per field that the first forward pass of level l writes
+int64_t fft_mean_parts(const Plan &p, int l);
 // Without have_spectrum the spectrum is recomputed: on st_spec after x_free when
 // st_spec is given (overlapping the cotangent transforms on st), else on st.
 // With St, G is the descriptor S and the cotangent 2 w_l^2 (S - St) / Z of the
@@ -157,7 +164,11 @@ bool fft_fused_prolong(const Plan &p, int l);
 // transformed in one pass (fft_plane.hip).  Forward: real field [B][C][n0][n][n]
 // -> half spectra X [B][C][n0][n][hp]; inverse: X -> real field (unnormalised).
 bool plane_supported(const Plan &p, int l);
-hipError_t plane_forward(const Plan &p, int l, const float *phi, float2 *X, hipStream_t st);
+// waves per plane workgroup (one partial sum of the mean each)
+int plane_waves(const Plan &p, int l);
+// With msum, also float64 sums of every wave's share of each plane, at
+// msum[plane * plane_waves + wave].
+hipError_t plane_forward(const Plan &p, int l, const float *phi, float2 *X, hipStream_t st, double *msum = nullptr);
 // With coarse, the inverse also adds 1/8 of the coarser level's gradient at each
 // voxel's parent (the multigrid prolongation; needs an even n0).
 hipError_t plane_inverse(const Plan &p, int l, const float2 *X, float *grad, hipStream_t st,

@@ -9,6 +9,15 @@
 // pruned: the inverse keeps only rows |r| <= P of each axis, and the transforms
 // of the cotangent boxes read only those rows.
 //
+// Fluctuation form.  The forward drops the zero-frequency product, so the
+// transforms correlate the fields minus their means (an exact identity: the
+// mean of a field lives in that one bin), and the gather adds mu_i mu_j back in
+// float64 before the single rounding to float32.  The means are float64 sums
+// of the float32 field taken while the first pass loads it.  Without this the
+// float32 rounding of the large zero-frequency term shifts every S(r) by the
+// same few 1e-8, an error that the loss gradient sums coherently over r once
+// S - S* is small (Sec. 3.1 loss near its minimum).
+//
 // Every kernel is one pass over HBM.  Pencils are transformed in two register
 // steps with one LDS exchange (fft_reg.h):
 //   k_rows       contiguous-axis transform of T rows; R2 adjacent lanes walk
@@ -19,6 +28,8 @@
 //                axis-0 inverse (the "reduce" step fused into the transform)
 //   k_axis0_adj  axis-0 forward DFT of fields and cotangent boxes, the adjoint
 //                product sum, full axis-0 inverse (in place)
+#include <algorithm>
+
 #include "dmcr_internal.h"
 #include "fft_reg.h"
 
@@ -93,6 +104,13 @@ struct RowArgs {
     const float *coarse;
     float cw;
     int64_t fn0, fn1;
+    // T_R2C_LAST with msum: float64 sums of the loaded field over groups of
+    // mlanes lanes (mlanes / R2 whole rows of one field), one partial per group,
+    // at msum[first row / (mlanes / R2)]
+    double *msum;
+    int mlanes;
+    // IO_DESC with mu: float64 channel means [B][C]; pair (i, j) adds mu_i mu_j
+    const double *mu;
 };
 
 // Box row m of the adjoint kernel K_cj (see k_build_kernels):
@@ -169,6 +187,15 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const int e = row_of(a.in_mode, R2 * i1 + p, n, a.P);
             v[i1] = make_float2((valid && e >= 0) ? src[e] : 0.f, 0.f);
         }
+        if constexpr (TAG == T_R2C_LAST) {
+            if (a.msum) {
+                double sm = 0.0;
+#pragma unroll
+                for (int i1 = 0; i1 < R1; ++i1) sm += (double)v[i1].x;
+                sm = group_sum(sm, a.mlanes);
+                if (valid && (threadIdx.x & (a.mlanes - 1)) == 0) a.msum[m / (a.mlanes / R2)] = sm;
+            }
+        }
     } else {
         const float2 *src = static_cast<const float2 *>(a.in) + m * a.in_len;
 #pragma unroll
@@ -208,12 +235,13 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
         const bool aut = (a.auto_mask >> q) & 1;
         const int64_t bi0 = (int64_t)row * a.out_len;
         float *dst = static_cast<float *>(a.out) + b * a.Kstride + a.off[q] + bi0 - (aut ? a.center : 0);
+        const double mm = a.mu ? a.mu[b * a.C + a.pi[q]] * a.mu[b * a.C + a.pj[q]] : 0.0;
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int k2 = 0; k2 < R2; ++k2) {
                 const int e = row_of(IO_BOX, (p + R2 * s) + R1 * k2, n, a.P);
-                if (e >= 0 && !(aut && bi0 + e < a.center)) dst[e] = u[s][k2].x * a.scale;
+                if (e >= 0 && !(aut && bi0 + e < a.center)) dst[e] = (float)((double)(u[s][k2].x * a.scale) + mm);
             }
     } else if (a.out_real) {
         float *dst = static_cast<float *>(a.out) + m * a.out_len;
@@ -266,6 +294,16 @@ __global__ __launch_bounds__(256) void k_r2c(RowArgs a)
     float2 v[R1];
 #pragma unroll
     for (int i1 = 0; i1 < R1; ++i1) v[i1] = src[R2 * i1 + p];
+    if (a.msum) {
+        double sm = 0.0;
+#pragma unroll
+        for (int i1 = 0; i1 < R1; ++i1) {
+            sm += (double)v[i1].x;
+            sm += (double)v[i1].y;
+        }
+        sm = group_sum(sm, a.mlanes);
+        if (valid && (threadIdx.x & (a.mlanes - 1)) == 0) a.msum[m / (a.mlanes / R2)] = sm;
+    }
     const float2 wp = tw_n<false>(p, L);
     float2 u[S][R2];
     pencil_fwd<LH, false, LANE_P>(v, u, ex, p, t, T);
@@ -336,6 +374,7 @@ __global__ __launch_bounds__(256) void k_c2r(RowArgs a)
         const int bi0 = (int)row * a.out_len;
         const int lo = aut ? (int)a.center - bi0 : 0;   // entries e < lo are not stored
         float *dst = static_cast<float *>(a.out) + b * a.Kstride + a.off[q] + bi0 - (aut ? a.center : 0);
+        const double mu2 = a.mu ? a.mu[b * a.C + a.pi[q]] * a.mu[b * a.C + a.pj[q]] : 0.0;
         const int n = 2 * nh;
 #pragma unroll
         for (int s = 0; s < S; ++s)
@@ -344,8 +383,8 @@ __global__ __launch_bounds__(256) void k_c2r(RowArgs a)
                 const int mm = (p + R2 * s) + R1 * k2;
                 const int e0 = row_of(IO_BOX, 2 * mm, n, a.P);
                 const int e1 = row_of(IO_BOX, 2 * mm + 1, n, a.P);
-                if (e0 >= 0 && e0 >= lo) dst[e0] = u[s][k2].x * a.scale;
-                if (e1 >= 0 && e1 >= lo) dst[e1] = u[s][k2].y * a.scale;
+                if (e0 >= 0 && e0 >= lo) dst[e0] = (float)((double)(u[s][k2].x * a.scale) + mu2);
+                if (e1 >= 0 && e1 >= lo) dst[e1] = (float)((double)(u[s][k2].y * a.scale) + mu2);
             }
     } else {
         float2 *dst = static_cast<float2 *>(a.out) + m * (a.out_len / 2);
@@ -503,6 +542,9 @@ __global__ __launch_bounds__(256) void k_axis0_fwd(Axis0Args a)
                 for (int s = 0; s < S; ++s)
 #pragma unroll
                     for (int k = 0; k < R2; ++k) w[s][k] = c_scale(c_cmul(X[ci][s][k], X[cj][s][k]), a.scale);
+                // the zero frequency of the field (column 0, row k0 = 0): the product of
+                // the means, added back in float64 by the gather
+                if (loc.i == 0 && p == 0) w[0][0] = make_float2(0.f, 0.f);
                 float2 out[R1];
                 pencil_mirror<L, true>(w, out, ex, p, t, T);
                 if (loc.valid) {
@@ -571,11 +613,39 @@ __global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
     });
 }
 
+// mu[f] = (sum of field f's np partial sums, in index order) / N, float64
+__global__ __launch_bounds__(256) void k_field_means(const double *part, int64_t np, double invN, double *mu)
+{
+    __shared__ double red[256];
+    const double *pf = part + (int64_t)blockIdx.x * np;
+    double sm = 0.0;
+    for (int64_t j = threadIdx.x; j < np; j += 256) sm += pf[j];
+    red[threadIdx.x] = sm;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) mu[blockIdx.x] = red[0] * invN;
+}
+
 int ilog2(int n)
 {
     int l = 0;
     while ((1 << l) < n) ++l;
     return l;
+}
+
+// lanes of the contiguous-axis forward that hold one partial sum of the mean:
+// R2 lanes per row, whole rows of one field, at most a wave
+int mean_lanes(const Plan &p, int l)
+{
+    const LevelPlan &L = p.lv[l];
+    const int nl = L.n[p.ndim - 1];
+    const int LL = nl >= 4 ? ilog2(nl) - 1 : ilog2(nl);   // packed real rows use the half length
+    const int R2 = 1 << (LL / 2);
+    const int64_t rpc = L.N / nl;                          // rows per field
+    return (int)std::min<int64_t>(64, rpc * R2);
 }
 
 
@@ -762,18 +832,33 @@ bool fft_supported(const Plan &p, int l)
     return p.C <= 4;
 }
 
+int64_t fft_mean_parts(const Plan &p, int l)
+{
+    const LevelPlan &L = p.lv[l];
+    if (plane_supported(p, l)) return (int64_t)L.n[0] * plane_waves(p, l);
+    const int nl = L.n[p.ndim - 1];
+    const int LL = nl >= 4 ? ilog2(nl) - 1 : ilog2(nl);
+    const int R2 = 1 << (LL / 2);
+    return L.N / nl / (mean_lanes(p, l) / R2);
+}
+
 // Half spectrum of every channel, transformed along every axis except 0:
 // X = DFT_{1..d-1}(phi) (the contiguous axis real-to-half-complex).
-hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &ws, hipStream_t st, bool fused)
+hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &ws, hipStream_t st, bool fused,
+                              double *msum)
 {
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C;
     float2 *X = ws.at<float2>(L.X);
-    if (fused && plane_supported(p, l)) return plane_forward(p, l, phi, X, st);   // both axes in one pass
+    if (fused && plane_supported(p, l)) return plane_forward(p, l, phi, X, st, msum);   // both axes in one pass
     const int nl = L.n[p.ndim - 1];
     const int64_t rows = (p.ndim == 2) ? (int64_t)B * C * L.n[0] : (int64_t)B * C * L.n[0] * L.n[1];
     RowArgs r = row_args(phi, X, rows, IO_FULL, nl, IO_HALF, L.hp, 0, true, false, 1.f);
     r.out_valid = L.h;
+    if (msum) {
+        r.msum = msum;
+        r.mlanes = mean_lanes(p, l);
+    }
     if (nl >= 4)
         TRY_HIP((real_launch<T_R2C_LAST, false>(ilog2(nl), r, row_bytes(r), st)));
     else
@@ -791,7 +876,11 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
 {
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C;
-    TRY_HIP(fft_spectrum_level(p, l, phi, ws, st));
+    double *msum = ws.at<double>(L.msum);
+    double *mu = ws.at<double>(L.mu);
+    TRY_HIP(fft_spectrum_level(p, l, phi, ws, st, true, msum));
+    TRY_HIP(launch("field_means", (double)B * C * L.mparts * 8, k_field_means, dim3((unsigned)(B * C)), dim3(256), 0,
+                   st, (const double *)msum, L.mparts, 1.0 / (double)L.N, mu));
     float2 *X = ws.at<float2>(L.X);
     float2 *Y = ws.at<float2>(L.Y);
     const int n0 = L.n[0];
@@ -838,8 +927,12 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
     for (int a2 = 0; a2 < p.ndim; ++a2) boxvol *= L.box;
     d.center = (boxvol - 1) / 2;
     d.auto_mask = 0;
+    d.mu = mu;
+    d.C = C;
     for (int q = 0; q < p.npairs; ++q) {
         d.off[q] = L.off[q];
+        d.pi[q] = p.pi[q];
+        d.pj[q] = p.pj[q];
         if (p.pi[q] == p.pj[q]) d.auto_mask |= 1 << q;
     }
     const double dbytes = (double)d.nrows * L.h * 8 + (double)d.nrows * L.box * 4;

@@ -265,9 +265,25 @@ __device__ __forceinline__ void col_fwd(const float2 (&val)[Plane<L>::NB][Plane<
     }
 }
 
-// in: real planes [nplanes][n][n]; out: half spectra [nplanes][n][hp]
+// float64 sum of a thread's loaded share of a half plane
 template <int L>
-__global__ __launch_bounds__(Plane<L>::threads) void k_plane_fwd(const float *in, float2 *out, int hp)
+__device__ __forceinline__ double rows_sum(const float2 (&v)[Plane<L>::NB][Plane<L>::R1])
+{
+    double sm = 0.0;
+#pragma unroll
+    for (int h = 0; h < Plane<L>::NB; ++h)
+#pragma unroll
+        for (int i1 = 0; i1 < Plane<L>::R1; ++i1) {
+            sm += (double)v[h][i1].x;
+            sm += (double)v[h][i1].y;
+        }
+    return sm;
+}
+
+// in: real planes [nplanes][n][n]; out: half spectra [nplanes][n][hp].  With
+// msum, msum[plane * waves + wave] = float64 sum of the wave's share of the plane.
+template <int L>
+__global__ __launch_bounds__(Plane<L>::threads) void k_plane_fwd(const float *in, float2 *out, int hp, double *msum)
 {
     using G = Plane<L>;
     constexpr int n = G::n, nh = G::nh, nb = G::nb, NB = G::NB, R1 = G::R1, R2 = G::R2;
@@ -280,7 +296,13 @@ __global__ __launch_bounds__(Plane<L>::threads) void k_plane_fwd(const float *in
         float2 v[NB][R1], vn[NB][R1];
         rows_load<L>(src, v);
         rows_load<L>(src + (size_t)nh * nh, vn);   // second half in flight during the first
+        double sm = msum ? rows_sum<L>(v) : 0.0;
         rows_r2c<L>(v, a, lds);
+        if (msum) {
+            sm = group_sum(sm + rows_sum<L>(vn), 64);
+            const int tid = phase_tid();
+            if ((tid & 63) == 0) msum[pl * (G::threads / 64) + tid / 64] = sm;
+        }
         rows_r2c<L>(vn, b, lds);
     }
     const int t = phase_tid() / R2;
@@ -466,11 +488,13 @@ __global__ __launch_bounds__(Plane<L>::threads) void k_plane_inv(const float2 *i
     }
 }
 
-// the prolongation of the inverse (coarse, cw, n0) is used when coarse is set
+// the prolongation of the inverse (coarse, cw, n0) is used when coarse is set;
+// msum: the forward's partial sums of the means (or null)
 struct PlanePro {
     const float *coarse;
     float cw;
     int n0;
+    double *msum;
 };
 
 template <int L>
@@ -485,11 +509,11 @@ hipError_t plane_launch(bool inv, const void *in, void *out, int64_t nplanes, in
         return launch("plane_inv", bytes, k_plane_inv<L, false>, g, b, 0, st, static_cast<const float2 *>(in),
                       static_cast<float *>(out), hp, (const float *)nullptr, 0.f, 1);
     return launch("plane_fwd", bytes, k_plane_fwd<L>, g, b, 0, st, static_cast<const float *>(in),
-                  static_cast<float2 *>(out), hp);
+                  static_cast<float2 *>(out), hp, pro.msum);
 }
 
 hipError_t plane_dispatch(bool inv, int L, const void *in, void *out, int64_t nplanes, int hp, double bytes,
-                          hipStream_t st, PlanePro pro = PlanePro{nullptr, 0.f, 1})
+                          hipStream_t st, PlanePro pro = PlanePro{nullptr, 0.f, 1, nullptr})
 {
     switch (L) {
     case 5: return plane_launch<5>(inv, in, out, nplanes, hp, bytes, st, pro);
@@ -519,14 +543,24 @@ bool plane_supported(const Plan &p, int l)
     return lg >= 5 && lg <= 8 && L.h == L.n[2] / 2 + 1;
 }
 
-hipError_t plane_forward(const Plan &p, int l, const float *phi, float2 *X, hipStream_t st)
+int plane_waves(const Plan &p, int l)
+{
+    switch (plane_log2(p.lv[l])) {
+    case 5: return Plane<5>::threads / 64;
+    case 6: return Plane<6>::threads / 64;
+    case 7: return Plane<7>::threads / 64;
+    default: return Plane<8>::threads / 64;
+    }
+}
+
+hipError_t plane_forward(const Plan &p, int l, const float *phi, float2 *X, hipStream_t st, double *msum)
 {
     const LevelPlan &L = p.lv[l];
     if (!plane_supported(p, l)) return hipErrorInvalidValue;
     const int64_t nplanes = (int64_t)p.B * p.C * L.n[0];
     if (nplanes >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     const double bytes = (double)nplanes * L.n[1] * ((double)L.n[2] * 4 + (double)L.h * 8);
-    return plane_dispatch(false, plane_log2(L), phi, X, nplanes, L.hp, bytes, st);
+    return plane_dispatch(false, plane_log2(L), phi, X, nplanes, L.hp, bytes, st, PlanePro{nullptr, 0.f, 1, msum});
 }
 
 hipError_t plane_inverse(const Plan &p, int l, const float2 *X, float *grad, hipStream_t st, const float *coarse)
@@ -538,7 +572,8 @@ hipError_t plane_inverse(const Plan &p, int l, const float2 *X, float *grad, hip
     if (coarse && L.n[0] % 2) return hipErrorInvalidValue;
     double bytes = (double)nplanes * L.n[1] * ((double)L.n[2] * 4 + (double)L.h * 8);
     if (coarse) bytes += (double)nplanes * L.n[1] * L.n[2] * 4 / 8;   // the coarse level: 1/8 of the voxels
-    return plane_dispatch(true, plane_log2(L), X, grad, nplanes, L.hp, bytes, st, PlanePro{coarse, 0.125f, L.n[0]});
+    return plane_dispatch(true, plane_log2(L), X, grad, nplanes, L.hp, bytes, st,
+                          PlanePro{coarse, 0.125f, L.n[0], nullptr});
 }
 
 }  // namespace dmcr

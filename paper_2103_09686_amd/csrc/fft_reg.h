@@ -193,6 +193,15 @@ __device__ __forceinline__ void dft_reg(float2 (&x)[R])
     }
 }
 
+// Sum of x over aligned groups of `lanes` adjacent lanes of a wave (a power of
+// two, at most 64) by a fixed xor butterfly.  Partners add the same two values,
+// so every lane of a group ends with the same bits, whatever the launch.
+__device__ __forceinline__ double group_sum(double x, int lanes)
+{
+    for (int o = 1; o < lanes; o <<= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
 // ---------------------------------------------------------------------------
 // the split of one pencil length
 // ---------------------------------------------------------------------------

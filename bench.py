@@ -64,10 +64,15 @@ SOFT_SLOTS = {"direct_fwd_soft": 15, "direct_adj_soft": 19}
 KERNEL_SOURCES = ("dmcr_internal.h", "fft_path.hip", "fft_plane.hip", "fft_reg.h")
 
 
+def level_P(spec, l):
+    """P of level l as the library applies it: min(P_l, n_l / 2 - 1)."""
+    return min(spec.max_disp[l], min(n >> l for n in spec.shape) // 2 - 1)
+
+
 def K_level(spec, l):
     """Descriptor entries of level l (every pair): half box for autos, full box for crosses."""
     d = len(spec.shape)
-    vol = (2 * spec.max_disp[l] + 1) ** d
+    vol = (2 * level_P(spec, l) + 1) ** d
     return sum((vol + 1) // 2 if i == j else vol for (i, j) in spec.pairs)
 
 
@@ -144,7 +149,7 @@ def parse():
                     help="skip the second measurement of the step with the fused 256 x 256 plane transforms")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the continuous-batching serving workload (latency percentiles)")
-    ap.add_argument("--requests", type=int, default=400, help="serving: requests in the Poisson stream")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests in the Poisson stream")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
     ap.add_argument("--compare", type=int, default=100,
                     help="serving: requests in the batched vs one-at-a-time throughput comparison")
@@ -158,6 +163,8 @@ def serving(n_requests, rate, n_compare):
     and the throughput of continuous batching against plain one-at-a-time GPU
     reconstruction on the same requests (all available at once)."""
     import copy
+
+    import numpy as np
     import torch
     from paper_2103_09686_amd import dmcr, serve
 
@@ -175,34 +182,59 @@ def serving(n_requests, rate, n_compare):
     srv.close()
     live = serve.summary(done)
     print("serving (Poisson %.0f/s): %s" % (rate, live), file=sys.stderr, flush=True)
-    # throughput comparison on the first n_compare requests, all available at t = 0
+    # throughput comparison on the first n_compare requests, all available at t = 0;
+    # both sides keep their result fields on the device for the rounded-field error
     base = serve.gpu_requests(stream[:n_compare], cache)
     for r in base:
         r.arrival = 0.0
     batched = copy.copy(base)
-    srv = serve.Server(serve.GpuExecutor(opt=opt), budget_bytes=budget, iters_per_tick=4, threads=8,
-                       asynchronous=True)
+    ex = serve.GpuExecutor(opt=opt, keep_fields=True)
+    srv = serve.Server(ex, budget_bytes=budget, iters_per_tick=4, threads=8, asynchronous=True)
     torch.cuda.synchronize()
     tb = time.perf_counter()
     bdone = srv.run([copy.copy(r) for r in batched])
     torch.cuda.synchronize()
     tb = time.perf_counter() - tb
+    bfields = {}
+    for g in srv.groups.values():
+        bfields.update(g.fields_by_rid)
+    brnd = serve.rounded_errors(bdone, bfields)
     srv.close()
+    del bfields
     seq = [copy.copy(r) for r in base]
+    bufs = serve.sequential_buffers(seq, opt)      # every class resident before the clock starts
     torch.cuda.synchronize()
     ts = time.perf_counter()
-    serve.run_sequential(seq, opt=opt)
+    _, sfields = serve.run_sequential(seq, opt=opt, bufs=bufs, keep_fields=True)
     torch.cuda.synchronize()
     ts = time.perf_counter() - ts
+    srnd = serve.rounded_errors(seq, sfields)
+    del sfields, bufs
+    bsum, ssum = serve.summary(bdone), serve.summary(seq)
+
+    def rnd_stats(rd):
+        e = [v[0] for v in rd.values()]
+        rel = [v[1] for v in rd.values()]
+        return dict(rounded_E_p50=float(np.percentile(e, 50)), rounded_E_max=float(max(e)),
+                    rounded_rel_err_p50=float(np.percentile(rel, 50)), rounded_rel_err_max=float(max(rel)))
+
     out = dict(requests=live["requests"], rate_per_s=rate, p50_s=round(live["p50_s"], 4),
                p99_s=round(live["p99_s"], 4), mean_s=round(live["mean_s"], 4),
                served_requests_per_s=round(live["requests_per_s"], 3),
                converged=live["converged"], max_final_E=live["max_final_E"],
+               iters_per_request=dict(mean=round(live["iters_mean"], 2), p50=live["iters_p50"],
+                                      p99=live["iters_p99"]),
+               rel_err_p50=live.get("rel_err_p50"), rel_err_max=live.get("rel_err_max"),
                compare=dict(requests=n_compare, batched_requests_per_s=round(n_compare / tb, 2),
                             one_at_a_time_requests_per_s=round(n_compare / ts, 2), speedup=round(ts / tb, 2),
                             batched_max_E=max(r.final_E for r in bdone), one_at_a_time_max_E=max(r.final_E for r in seq),
+                            batched_rel_err_max=bsum.get("rel_err_max"),
+                            one_at_a_time_rel_err_max=ssum.get("rel_err_max"),
+                            batched_iters_mean=round(bsum["iters_mean"], 2),
+                            one_at_a_time_iters_mean=round(ssum["iters_mean"], 2),
                             batched_voxel_it_per_s=sum(r.voxels * r.iters for r in bdone) / tb,
-                            one_at_a_time_voxel_it_per_s=sum(r.voxels * r.iters for r in seq) / ts),
+                            one_at_a_time_voxel_it_per_s=sum(r.voxels * r.iters for r in seq) / ts,
+                            batched_rounded=rnd_stats(brnd), one_at_a_time_rounded=rnd_stats(srnd)),
                prepare_s=round(prep, 1))
     print("serving compare: %s" % out["compare"], file=sys.stderr, flush=True)
     return out
@@ -408,7 +440,7 @@ def main():
         terms = {"direct_fwd_soft": 0.0, "direct_adj_soft": 0.0}
         for l in range(L):
             Nl = N >> (d * l)
-            box = 2 * spec.max_disp[l] + 1
+            box = 2 * level_P(spec, l) + 1
             terms["direct_fwd_soft"] += B * Nl * K_level(spec, l)
             terms["direct_adj_soft"] += B * Nl * C * C * box ** d
         per_launch = terms[dom["name"]] / L
@@ -422,7 +454,7 @@ def main():
         flops = 0.0
         for l in range(L):
             Nl = N >> (d * l)
-            P3 = min(spec.s3_max_disp, spec.max_disp[l])
+            P3 = min(spec.s3_max_disp, level_P(spec, l))
             M = (2 * P3 + 1) ** d
             if dom["name"].startswith("s3_fwd"):
                 flops += B * C * Nl * (M * (M + 1) // 2) * (2 if desc else 3)
@@ -455,7 +487,8 @@ def main():
                warmup=args.warmup, ms_per_step=ms, step_time=step_time, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload=wl["desc"], shape=list(shape), channels=C, levels=L,
-                           max_disp=list(spec.max_disp), K=K, batch=B, path="direct" if desc else "fft",
+                           max_disp=[level_P(spec, l) for l in range(L)], K=K, batch=B,
+                           path="direct" if desc else "fft",
                            descriptor=["s2", "sbar", "stilde"][desc], s3_max_disp=spec.s3_max_disp,
                            recompute=wl["recompute"], fused_planes_256=bool(args.fused_planes),
                            parallelism="single GPU"),

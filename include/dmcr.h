@@ -125,9 +125,19 @@ typedef struct {
     int32_t shape[3];                      /* finest level, powers of two, >= 2       */
     int32_t n_channels;                    /* C, 1..DMCR_MAX_CHANNELS                 */
     int32_t n_levels;                      /* 1..DMCR_MAX_LEVELS; every axis must be
-                                              divisible by 2^(n_levels-1)              */
-    int32_t max_disp[DMCR_MAX_LEVELS];     /* P_l, 0 <= P_l <= min_axis(n_l)/2 - 1     */
-    double  level_weight[DMCR_MAX_LEVELS]; /* w_l (eq. mg); must be > 0               */
+                                              divisible by 2^(n_levels-1).  0 selects
+                                              the level rule of Appendix B (P = 31:
+                                              1, 2, 3 levels at 64, 128, 256):
+                                              L = max(1, 1 + round(log2(min_axis /
+                                              (2 (P + 1))))), P = max_disp[0] on every
+                                              level, default weights               */
+    int32_t max_disp[DMCR_MAX_LEVELS];     /* P_l >= 0; clipped to min_axis(n_l)/2 - 1
+                                              (a longer displacement aliases)          */
+    double  level_weight[DMCR_MAX_LEVELS]; /* w_l (eq. mg), > 0; 0 selects the default
+                                              2^{d l / 2} (level 0 finest), the square
+                                              root of the voxels a coarse voxel
+                                              summarises (2^{l-1} of eq. mg's footnote,
+                                              1-based, in 2-D)                          */
     int32_t n_pairs;                       /* 0 = all pairs i <= j in lexicographic order */
     int32_t pairs[2 * 16];                 /* (i, j) with i <= j, used if n_pairs > 0 */
     int32_t path;                          /* DMCR_PATH_*                             */
@@ -146,7 +156,8 @@ typedef struct {
     int32_t mode;    /* PROJECT: iterates are clipped to [lo, hi] and the search direction
                         is restricted to free variables; PENALTY: L = E + lambda E^bc with
                         E^bc as printed in Sec. 3.1 and lambda = kappa E held constant in
-                        the gradient                                                       */
+                        the gradient and in the Armijo test of a line search started at
+                        that point (see dmcr_penalised_loss_grad)                          */
     double kappa;
 } dmcr_bounds;
 
@@ -161,7 +172,8 @@ typedef struct {
     int32_t max_iter;   /* iteration budget                                    */
     int32_t max_ls;     /* evaluations per line search (ignored by ADAM)       */
     double  tol_derr;   /* stop when E <= tol_derr                             */
-    double  c1, c2;     /* Wolfe constants (sufficient decrease, curvature)    */
+    double  c1;         /* Armijo sufficient-decrease constant, (0, 1); the
+                           backtracking search halves the step until it holds  */
     int32_t method;     /* DMCR_OPT_*                                          */
     double  lr;         /* ADAM: step size (the paper: 1e-3), > 0              */
     double  beta1;      /* ADAM: first-moment decay (0.9), in [0, 1)           */
@@ -177,13 +189,17 @@ typedef struct {
     int32_t why;         /* dmcr_status for this batch element                */
 } dmcr_result;
 
+/* Number of multigrid levels L of the spec (spec->n_levels, or the level rule
+ * when it is 0); < 0: dmcr_status. */
+int32_t dmcr_level_count(const dmcr_spec *spec);
+
 /* Number of descriptor entries K (all levels and pairs); < 0: dmcr_status. */
 int64_t dmcr_descriptor_size(const dmcr_spec *spec);
 
 /* Offsets of every block in descriptor order: per level, each pair's two-point
  * block, then (s3_max_disp > 0) each channel's three-point block; writes
- * n_levels * (n_pairs + (s3_max_disp > 0 ? n_channels : 0)) + 1 values (the last
- * one is K) to host array `offsets`. */
+ * L * (n_pairs + (s3_max_disp > 0 ? n_channels : 0)) + 1 values (L from
+ * dmcr_level_count; the last one is K) to host array `offsets`. */
 dmcr_status dmcr_descriptor_offsets(const dmcr_spec *spec, int64_t *offsets);
 
 /* Workspace bytes needed by every call below for this spec and batch size. */
@@ -219,6 +235,18 @@ dmcr_status dmcr_error_cotangent(const dmcr_spec *spec, int32_t batch, const flo
 dmcr_status dmcr_loss_grad(const dmcr_spec *spec, int32_t batch, const float *phi,
                            const double *S_target, double *E, float *grad, void *ws,
                            size_t ws_bytes, hipStream_t stream);
+
+/* The loss of the relaxed problem (Sec. 3.1, eq. L_func_dMCR) and its gradient:
+ * with bounds->mode == DMCR_BOUNDS_PENALTY, L[b] = E[b] + lambda E^bc[b], where
+ * E^bc = sum_c sum_x [ (phi - hi) H(phi - hi) / N + (lo - phi) H(lo - phi) / N ]^2
+ * (the printed penalty with the box [lo, hi], H(0) = 0, N voxels per channel)
+ * and lambda = kappa E[b], held constant in the gradient
+ * grad = dE/dphi + lambda dE^bc/dphi; with any other mode L = E and grad = dE/dphi.
+ * L, E: device float64 [B]; grad: device float32 [B][C][n...], overwritten;
+ * workspace: dmcr_workspace_size().  Asynchronous on `stream`. */
+dmcr_status dmcr_penalised_loss_grad(const dmcr_spec *spec, int32_t batch, const float *phi, const double *S_target,
+                                     const dmcr_bounds *bounds, double *L, double *E, float *grad, void *ws,
+                                     size_t ws_bytes, hipStream_t stream);
 
 /* Workspace bytes for dmcr_reconstruct (includes dmcr_workspace_size). */
 dmcr_status dmcr_reconstruct_workspace_size(const dmcr_spec *spec, int32_t batch,

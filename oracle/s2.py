@@ -70,6 +70,12 @@ def half_box(ndim: int, P: int) -> np.ndarray:
     return b[keep]
 
 
+def level_disp(shape, n_levels: int, P: int) -> Tuple[int, ...]:
+    """P_l = min(P, min_axis(n_l) / 2 - 1) for every level (Sec. 3.3 keeps one P per
+    level; a displacement longer than half the coarse grid would alias)."""
+    return tuple(min(int(P), min(int(n) >> l for n in shape) // 2 - 1) for l in range(n_levels))
+
+
 def all_pairs(C: int) -> List[Tuple[int, int]]:
     return [(i, j) for i in range(C) for j in range(i, C)]
 
@@ -455,7 +461,9 @@ def penalty(phi: np.ndarray, lo: float = 0.0, hi: float = 1.0):
 
 
 def penalised_loss_grad(phi, S_des, spec, kappa=1.0, lo=0.0, hi=1.0):
-    """L = E + lambda E^bc with lambda = kappa * E held constant in the gradient."""
+    """L = E + lambda E^bc of Sec. 3.1 (eq. L_func_dMCR) with lambda = kappa * E
+    (lambda proportional to E; the constant is not given) held constant in the
+    gradient: returns (L, dE/dphi + lambda dE^bc/dphi, E)."""
     E, g, S = loss_grad(phi, S_des, spec)
     Ebc, gbc = penalty(phi, lo, hi)
     lam = kappa * E
@@ -491,46 +499,70 @@ def lbfgs_direction(g: np.ndarray, s_hist: Sequence[np.ndarray], y_hist: Sequenc
     return -q.reshape(np.shape(g))
 
 
-def reconstruct_lbfgs_projected(S_des, spec: Spec, phi0, iters, m=10, c1=1e-4, max_ls=20, lo=0.0, hi=1.0):
-    """Projected L-BFGS on the relaxed problem of Sec. 3 (box lo <= phi <= hi), FP64,
-    with the same rules as the GPU driver; returns (phi, [E after each iteration],
+def reconstruct_lbfgs_projected(S_des, spec: Spec, phi0, iters, m=10, c1=1e-4, max_ls=20, lo=0.0, hi=1.0,
+                                bounds="project", kappa=1.0):
+    """L-BFGS on the relaxed problem of Sec. 3 (eqs. dMCR-Min_Prob, L_func_dMCR), FP64,
+    with the same rules as the GPU driver; returns (phi, [f after each iteration],
     [evaluations of each iteration]).
+
+    bounds="project" keeps lo <= phi <= hi by projection; bounds="penalty" leaves
+    phi free and minimises L = E + lambda E^bc (E^bc as printed in Sec. 3.1,
+    lambda = kappa E of the current point, held constant in the gradient and in
+    the line search that starts there; f is then L with the point's own lambda).
 
     Each iteration: d = -H g by the two-loop recursion over the valid pairs among
     the last m iterations' pairs, initial scaling gamma = s'y / y'y of the newest
-    valid pair (1 after a reset); components of d that push an active bound outward
-    are zeroed; if g'd >= 0 the history is cleared and d = -g (projected).
-    Backtracking along the projected path x_t = clip(x + a d), halving a, with the
-    Armijo test f(x_t) <= f(x) + c1 g'(x_t - x) (Nocedal & Wright, Alg. 3.1 on the
-    projected path); the first trial is a = 1/|g| while no step has been accepted
-    since the last reset, else 1.  An accepted step records the pair s = x_t - x,
-    y = g_t - g, valid if s'y > eps y'y and y'y > 0; a failed search records no
-    pair and clears the history."""
-    x = np.clip(np.asarray(phi0, np.float64), lo, hi)
-    E, g, _ = loss_grad(x, S_des, spec)
-    f = E
+    valid pair (1 after a reset); with projection, components of d that push an
+    active bound outward are zeroed; if g'd >= 0 the history is cleared and d = -g
+    (projected).  Backtracking along the (projected) path x_t = clip(x + a d),
+    halving a, with the Armijo test f_x(x_t) <= f(x) + c1 g'(x_t - x) (Nocedal &
+    Wright, Alg. 3.1 on the projected path; f_x uses the lambda of x); the first
+    trial is a = 1/|g| while no step has been accepted since the last reset, else 1.
+    An accepted step records the pair s = x_t - x, y = g_t - g, valid if
+    s'y > eps y'y and y'y > 0; a failed search records no pair and clears the
+    history."""
+    penal = bounds == "penalty"
+    clip = (lambda v: v) if penal else (lambda v: np.clip(v, lo, hi))
+
+    def evaluate(v):
+        """(E, E^bc, gradient with lambda = kappa E(v))"""
+        if penal:
+            L, g_, E_ = penalised_loss_grad(v, S_des, spec, kappa, lo, hi)
+            return E_, penalty(v, lo, hi)[0], g_
+        E_, g_, _ = loss_grad(v, S_des, spec)
+        return E_, 0.0, g_
+
+    x = clip(np.asarray(phi0, np.float64))
+    E, Ebc, g = evaluate(x)
+    f = E + kappa * E * Ebc
     ring = []           # pairs of the last m iterations, None where none was recorded
     gamma, hist = 1.0, 0
     Es, evals = [], []
     eps = np.finfo(np.float64).eps
+
+    def project_dir(d_):
+        if not penal:
+            d_[((x <= lo) & (d_ < 0)) | ((x >= hi) & (d_ > 0))] = 0.0
+        return d_
+
     for _ in range(iters):
         valid = [p for p in ring if p is not None]
-        d = lbfgs_direction(g, [p[0] for p in valid], [p[1] for p in valid], gamma=gamma)
-        d[((x <= lo) & (d < 0)) | ((x >= hi) & (d > 0))] = 0.0
+        d = project_dir(lbfgs_direction(g, [p[0] for p in valid], [p[1] for p in valid], gamma=gamma))
         if not float(np.sum(g * d)) < 0.0:
             ring = [None] * len(ring)
             gamma, hist = 1.0, 0
-            d = -g.copy()
-            d[((x <= lo) & (d < 0)) | ((x >= hi) & (d > 0))] = 0.0
+            d = project_dir(-g.copy())
         gn = float(np.sqrt(np.sum(g * g)))
         a = 1.0 / gn if (hist == 0 and gn > 0.0) else 1.0
+        lam = kappa * E
         accepted, n_ev = False, 0
         for _ls in range(max_ls):
-            xt = np.clip(x + a * d, lo, hi)
-            Et, gt, _ = loss_grad(xt, S_des, spec)
+            xt = clip(x + a * d)
+            Et, Ebct, gt = evaluate(xt)
             n_ev += 1
             dd = float(np.sum(g * (xt - x)))
-            if np.isfinite(Et) and dd < 0.0 and Et <= f + c1 * dd:
+            ft_x = Et + lam * Ebct
+            if np.isfinite(ft_x) and dd < 0.0 and ft_x <= f + c1 * dd:
                 accepted = True
                 break
             a *= 0.5
@@ -541,7 +573,8 @@ def reconstruct_lbfgs_projected(S_des, spec: Spec, phi0, iters, m=10, c1=1e-4, m
             if sy > eps * yy and yy > 0.0:
                 pair = (s_, y_)
                 gamma = sy / yy
-            x, g, f = xt, gt, Et
+            x, g, E = xt, gt, Et
+            f = Et + kappa * Et * Ebct
             hist = min(hist + 1, m)
         ring = (ring + [pair])[-m:]
         if not accepted:

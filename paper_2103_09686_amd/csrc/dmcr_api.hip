@@ -62,10 +62,24 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
     p.B = B;
     if (s->n_channels < 1 || s->n_channels > kMaxChannels) return DMCR_EINVAL;
     p.C = s->n_channels;
-    if (s->n_levels < 1 || s->n_levels > kMaxLevels) return DMCR_EINVAL;
-    p.L = s->n_levels;
+    if (s->n_levels < 0 || s->n_levels > kMaxLevels) return DMCR_EINVAL;
+    int minax0 = 1 << 30;
     for (int a = 0; a < p.ndim; ++a) {
         if (!is_pow2(s->shape[a]) || s->shape[a] < 2) return DMCR_EUNSUPPORTED;
+        minax0 = std::min(minax0, s->shape[a]);
+    }
+    // n_levels = 0: the level rule of Appendix B (P = 31 gives 1, 2, 3 levels at 64,
+    // 128, 256), i.e. levels down to a coarsest side of about 2 (P + 1), P = max_disp[0]
+    const bool rule = s->n_levels == 0;
+    if (rule) {
+        if (s->max_disp[0] < 0) return DMCR_EINVAL;
+        const double lv = std::log2((double)minax0 / (2.0 * (s->max_disp[0] + 1.0)));
+        p.L = std::max(1, std::min(kMaxLevels, 1 + (int)std::lround(lv)));
+        while (p.L > 1 && (minax0 >> (p.L - 1)) < 2) --p.L;
+    } else {
+        p.L = s->n_levels;
+    }
+    for (int a = 0; a < p.ndim; ++a) {
         if ((s->shape[a] >> (p.L - 1)) < 2) return DMCR_EINVAL;
         p.shape[a] = s->shape[a];
     }
@@ -137,13 +151,22 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
             L.N *= L.n[a];
             if (a < p.ndim) minax = std::min(minax, L.n[a]);
         }
-        L.P = s->max_disp[l];
-        if (L.P < 0 || L.P > minax / 2 - 1) return DMCR_EINVAL;
+        // P_l = min(P, n_l / 2 - 1): larger displacements would alias on the level
+        const int Pl = s->max_disp[rule ? 0 : l];
+        if (Pl < 0) return DMCR_EINVAL;
+        L.P = std::min(Pl, minax / 2 - 1);
         L.box = 2 * L.P + 1;
         L.h = L.n[p.ndim - 1] / 2 + 1;
         L.hp = (L.n[p.ndim - 1] >= 32) ? (L.h + 15) / 16 * 16 : L.h;
-        if (!(s->level_weight[l] > 0.0) || !std::isfinite(s->level_weight[l])) return DMCR_EINVAL;
-        p.w[l] = s->level_weight[l];
+        // w_l (eq. mg): 0 selects 2^{d l / 2} (level 0 finest), the square root of
+        // the fine voxels one coarse voxel summarises (the footnote's 2^{l-1} in 2-D)
+        const double wl = rule ? 0.0 : s->level_weight[l];
+        if (wl == 0.0)
+            p.w[l] = std::pow(2.0, 0.5 * p.ndim * l);
+        else if (wl > 0.0 && std::isfinite(wl))
+            p.w[l] = wl;
+        else
+            return DMCR_EINVAL;
         int64_t vol = 1;
         for (int a = 0; a < p.ndim; ++a) vol *= L.box;
         p.lvl_off[l] = off;
@@ -244,6 +267,8 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
     p.G = cv.take((size_t)B * p.K * sizeof(float));
     p.err_chunks = std::max<int64_t>(1, std::min<int64_t>(8192, (p.K + 511) / 512));
     p.Epart = cv.take((size_t)B * p.err_chunks * sizeof(double));
+    p.pen_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(2048, ((int64_t)C * p.lv[0].N + 1023) / 1024));
+    p.Pen = cv.take((size_t)B * (p.pen_blocks + 1) * sizeof(double));
     p.bytes = cv.top;
     return DMCR_OK;
 }
@@ -403,8 +428,12 @@ hipError_t run_forward(const Plan &p, const float *phi, float *S, const Ws &ws, 
         if ((e = sc.join(sc.lane(l), sc.main)) != hipSuccess) return e;
     for (int l = 0; l < p.L; ++l) {
         const float *f = level_field(p, l, phi, ws);
+        // the level on the caller's stream forms its field means on a spare lane
+        const bool side = sc.multi && sc.lane(l) == sc.main;
         e = (p.lv[l].path == DMCR_PATH_FFT)
-                ? fft_forward_level(p, l, f, S, ws, sc.lane(l), x_free ? x_free[l] : nullptr)
+                ? fft_forward_level(p, l, f, S, ws, sc.lane(l), x_free ? x_free[l] : nullptr,
+                                    side ? sc.ln->side[Lanes::kSide - 1] : nullptr, side ? sc.ln->event() : nullptr,
+                                    side ? sc.ln->event() : nullptr)
                 : direct_forward_level(p, l, f, S, ws, sc.lane(l));
         if (e != hipSuccess) return e;
         if (p.s3 && (e = s3_forward_level(p, l, f, S, ws, sc.lane(l))) != hipSuccess) return e;
@@ -515,6 +544,13 @@ dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St
 using namespace dmcr;
 
 extern "C" {
+
+int32_t dmcr_level_count(const dmcr_spec *spec)
+{
+    Plan p;
+    const dmcr_status s = make_plan(spec, 1, &p);
+    return s == DMCR_OK ? p.L : (int32_t)s;
+}
 
 int64_t dmcr_descriptor_size(const dmcr_spec *spec)
 {

@@ -613,16 +613,30 @@ __global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
     });
 }
 
-// mu[f] = (sum of field f's np partial sums, in index order) / N, float64
-__global__ __launch_bounds__(256) void k_field_means(const double *part, int64_t np, double invN, double *mu)
+// mu[f] = (sum of field f's np partial sums) / N, float64.  Thread t adds the
+// partials t, t + 1024, ... in index order (eight loads in flight at a time),
+// then a fixed tree: the same bits for a field in any batch.
+constexpr int kMeanThreads = 1024;
+
+__global__ __launch_bounds__(kMeanThreads) void k_field_means(const double *part, int64_t np, double invN,
+                                                              double *mu)
 {
-    __shared__ double red[256];
+    __shared__ double red[kMeanThreads];
     const double *pf = part + (int64_t)blockIdx.x * np;
     double sm = 0.0;
-    for (int64_t j = threadIdx.x; j < np; j += 256) sm += pf[j];
+    for (int64_t j0 = threadIdx.x; j0 < np; j0 += 8 * kMeanThreads) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t j = j0 + (int64_t)u * kMeanThreads;
+            v[u] = j < np ? pf[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sm += v[u];
+    }
     red[threadIdx.x] = sm;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = kMeanThreads / 2; h > 0; h >>= 1) {
         if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
@@ -872,15 +886,24 @@ hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &
 }
 
 hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws, hipStream_t st,
-                             hipEvent_t x_free)
+                             hipEvent_t x_free, hipStream_t st_side, hipEvent_t fork, hipEvent_t join)
 {
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C;
     double *msum = ws.at<double>(L.msum);
     double *mu = ws.at<double>(L.mu);
     TRY_HIP(fft_spectrum_level(p, l, phi, ws, st, true, msum));
-    TRY_HIP(launch("field_means", (double)B * C * L.mparts * 8, k_field_means, dim3((unsigned)(B * C)), dim3(256), 0,
-                   st, (const double *)msum, L.mparts, 1.0 / (double)L.N, mu));
+    // the means are needed only by the gather at the end of the forward: on a side
+    // stream they stay off the path of the transforms
+    hipStream_t sm = st;
+    if (st_side && fork && join) {
+        TRY_HIP(hipEventRecord(fork, st));
+        TRY_HIP(hipStreamWaitEvent(st_side, fork, 0));
+        sm = st_side;
+    }
+    TRY_HIP(launch("field_means", (double)B * C * L.mparts * 8, k_field_means, dim3((unsigned)(B * C)),
+                   dim3(kMeanThreads), 0, sm, (const double *)msum, L.mparts, 1.0 / (double)L.N, mu));
+    if (sm != st) TRY_HIP(hipEventRecord(join, sm));
     float2 *X = ws.at<float2>(L.X);
     float2 *Y = ws.at<float2>(L.Y);
     const int n0 = L.n[0];
@@ -936,6 +959,7 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
         if (p.pi[q] == p.pj[q]) d.auto_mask |= 1 << q;
     }
     const double dbytes = (double)d.nrows * L.h * 8 + (double)d.nrows * L.box * 4;
+    if (sm != st) TRY_HIP(hipStreamWaitEvent(st, join, 0));
     if (nl >= 4) return real_launch<T_C2R_DESC, true>(ilog2(nl), d, dbytes, st);
     return rows_launch<T_C2R_DESC, true>(ilog2(nl), d, dbytes, st);
 }

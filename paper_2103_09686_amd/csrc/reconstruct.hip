@@ -21,9 +21,10 @@
 // (Sec. 3.1): PROJECT clips trial points to [lo, hi] and zeroes direction
 // components that push an active bound outward; PENALTY adds lambda E^bc with
 // E^bc as printed in Sec. 3.1 and lambda = kappa * E held constant in the
-// gradient.  Step: backtracking (halving) along the projected path with the
-// Armijo test f(x_t) <= f(x) + c1 g'(x_t - x), first trial 1 (1/|g| without
-// history); a pair (s, y) enters the history only if s'y > eps y'y.  A failed
+// gradient and in the Armijo test of a search started at that point.  Step:
+// backtracking (halving) along the projected path with the Armijo test
+// f(x_t) <= f(x) + c1 g'(x_t - x), first trial 1 (1/|g| without history); a
+// pair (s, y) enters the history only if s'y > eps y'y.  A failed
 // line search clears that element's history; a failure that started from
 // steepest descent stops the element.
 //
@@ -510,6 +511,13 @@ __global__ __launch_bounds__(kV) void k_pen_grad(const float *x, float *g, const
     }
 }
 
+// L[b] = E[b] + kappa E[b] E^bc[b]   (Ebc null: L = E)
+__global__ void k_pen_loss(const double *E, const double *Ebc, double kappa, double *L, int B)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) L[b] = E[b] + (Ebc ? kappa * E[b] * Ebc[b] : 0.0);
+}
+
 struct RLayout {
     size_t xt, g, gt, d, s, y;
     size_t part, dot1, dot2, rho, gamma, E, Et, Ebc, als, active, acc, flag;
@@ -902,11 +910,13 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
             for (int b = 0; b < B; ++b) {
                 if (!act[b]) continue;
                 ++slots[b].evals;
-                const double ft = hE[b] + (penalty ? bd.kappa * hE[b] * hEbc[b] : 0.0);
+                // the Armijo test holds lambda = kappa E of the search's start point,
+                // as the gradient there does; an accepted point's f takes its own lambda
+                const double ft = hE[b] + (penalty ? bd.kappa * slots[b].E * hEbc[b] : 0.0);
                 if (std::isfinite(ft) && hd[b] < 0.0 && ft <= slots[b].f + o.c1 * hd[b]) {
                     act[b] = 0;
                     acc[b] = 1;
-                    slots[b].f = ft;
+                    slots[b].f = hE[b] + (penalty ? bd.kappa * hE[b] * hEbc[b] : 0.0);
                     slots[b].E = hE[b];
                 } else {
                     step[b] *= 0.5;
@@ -1117,6 +1127,43 @@ dmcr_status dmcr_reconstruct_coarse_to_fine(const dmcr_spec *spec, int32_t batch
         all_ok &= results[b].why == DMCR_OK;
     }
     return all_ok ? DMCR_OK : DMCR_NOT_CONVERGED;
+}
+
+dmcr_status dmcr_penalised_loss_grad(const dmcr_spec *spec, int32_t batch, const float *phi, const double *S_target,
+                                     const dmcr_bounds *bounds, double *L, double *E, float *grad, void *ws,
+                                     size_t ws_bytes, hipStream_t stream)
+{
+    if (!bounds || !L || !phi || !S_target || !E || !grad) return DMCR_EINVAL;
+    if (bounds->mode < DMCR_BOUNDS_NONE || bounds->mode > DMCR_BOUNDS_PENALTY) return DMCR_EINVAL;
+    if (bounds->mode == DMCR_BOUNDS_PENALTY && (!(bounds->lo < bounds->hi) || !(bounds->kappa >= 0.0)))
+        return DMCR_EINVAL;
+    if (!aligned8(phi) || !aligned8(grad) || !aligned8(S_target) || !aligned8(E) || !aligned8(L)) return DMCR_EINVAL;
+    Plan p;
+    dmcr_status s = make_plan(spec, batch, &p);
+    if (s != DMCR_OK) return s;
+    if (ws_bytes < p.bytes) return DMCR_ENOMEM;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign)) return DMCR_EINVAL;
+    const Ws w{static_cast<char *>(ws)};
+    RS(loss_grad_internal(p, phi, S_target, E, grad, w, stream));
+    const double *Ebc = nullptr;
+    if (bounds->mode == DMCR_BOUNDS_PENALTY) {
+        const int64_t n = (int64_t)p.C * p.lv[0].N;
+        const double invN = 1.0 / (double)p.lv[0].N;
+        const float lo = (float)bounds->lo, hi = (float)bounds->hi;
+        double *part = w.at<double>(p.Pen);
+        double *ebc = part + (int64_t)p.B * p.pen_blocks;
+        hipLaunchKernelGGL(k_pen_part, dim3(p.pen_blocks, batch), dim3(kV), 0, stream, phi, n, invN, lo, hi, part,
+                           p.pen_blocks);
+        hipLaunchKernelGGL(k_sum_parts, dim3(batch), dim3(kV), 0, stream, (const double *)part, p.pen_blocks, ebc,
+                           batch);
+        hipLaunchKernelGGL(k_pen_grad, dim3(vblocks(n), batch), dim3(kV), 0, stream, phi, grad, (const double *)E,
+                           bounds->kappa, n, invN, lo, hi);
+        Ebc = ebc;
+    }
+    hipLaunchKernelGGL(k_pen_loss, dim3((batch + 63) / 64), dim3(64), 0, stream, (const double *)E, Ebc, bounds->kappa,
+                       L, batch);
+    RT(hipGetLastError());
+    return DMCR_OK;
 }
 
 dmcr_status dmcr_reconstruct_workspace_size(const dmcr_spec *spec, int32_t batch, const dmcr_opt *opt,

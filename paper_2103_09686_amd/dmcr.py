@@ -51,7 +51,7 @@ class c_bounds(ctypes.Structure):
 
 class c_opt(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("max_ls", ctypes.c_int32),
-                ("tol_derr", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
+                ("tol_derr", ctypes.c_double), ("c1", ctypes.c_double),
                 ("method", ctypes.c_int32), ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
 
@@ -73,10 +73,11 @@ class c_result(ctypes.Structure):
 
 @dataclass
 class Spec:
-    """One multigrid descriptor: shape of the finest level, channels, levels,
-    per-level maximum displacement P_l, level weights, pairs, path, flags,
-    descriptor kind (DESC_*), soft-threshold slope alpha (0: the paper's 10) and
-    the three-point range P3 (0: no three-point blocks)."""
+    """One multigrid descriptor: shape of the finest level, channels, levels (0: the
+    library's level rule from max_disp[0]), per-level maximum displacement P_l (the
+    library clips it to n_l/2 - 1), level weights (empty or 0: the library's default),
+    pairs, path, flags, descriptor kind (DESC_*), soft-threshold slope alpha (0: the
+    paper's 10) and the three-point range P3 (0: no three-point blocks)."""
     shape: Tuple[int, ...]
     n_channels: int = 1
     n_levels: int = 1
@@ -95,8 +96,7 @@ class Spec:
         if len(self.max_disp) == 1 and self.n_levels > 1:
             self.max_disp = tuple(self.max_disp) * self.n_levels
         self.max_disp = tuple(int(p) for p in self.max_disp)
-        if not self.level_weight:
-            self.level_weight = tuple(2.0 ** (d * l / 2.0) for l in range(self.n_levels))
+        self.level_weight = tuple(float(w) for w in self.level_weight)
         if not self.pairs:
             self.pairs = tuple((i, j) for i in range(self.n_channels) for j in range(i, self.n_channels))
 
@@ -111,9 +111,10 @@ class Spec:
             s.shape[a] = n
         s.n_channels = self.n_channels
         s.n_levels = self.n_levels
-        for l in range(self.n_levels):
-            s.max_disp[l] = self.max_disp[l]
-            s.level_weight[l] = self.level_weight[l]
+        for l, P in enumerate(self.max_disp[:MAX_LEVELS]):
+            s.max_disp[l] = P
+        for l, w in enumerate(self.level_weight[:MAX_LEVELS]):
+            s.level_weight[l] = w
         s.n_pairs = len(self.pairs)
         for q, (i, j) in enumerate(self.pairs):
             s.pairs[2 * q] = i
@@ -126,14 +127,10 @@ class Spec:
         return s
 
 
-def clipped_disp(shape, n_levels, P):
-    """P_l = min(P, min_axis(n_l)/2 - 1): no displacement aliases on a coarse level."""
-    return tuple(min(P, min(s >> l for s in shape) // 2 - 1) for l in range(n_levels))
-
-
 def make_spec(shape, n_channels=1, n_levels=1, P=16, **kw) -> Spec:
+    """A spec with the same P on every level (the library clips it per level)."""
     return Spec(shape=tuple(shape), n_channels=n_channels, n_levels=n_levels,
-                max_disp=clipped_disp(shape, n_levels, P), **kw)
+                max_disp=(int(P),) * max(1, n_levels), **kw)
 
 
 # ---------------------------------------------------------------------------
@@ -152,6 +149,8 @@ def lib():
         sp = ctypes.POINTER(c_spec)
         L.dmcr_descriptor_size.argtypes = [sp]
         L.dmcr_descriptor_size.restype = ctypes.c_int64
+        L.dmcr_level_count.argtypes = [sp]
+        L.dmcr_level_count.restype = ctypes.c_int32
         L.dmcr_descriptor_offsets.argtypes = [sp, ctypes.POINTER(ctypes.c_int64)]
         L.dmcr_workspace_size.argtypes = [sp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
         L.dmcr_pyramid.argtypes = [sp, ctypes.c_int32, _vp, _vp, _vp]
@@ -159,6 +158,8 @@ def lib():
         L.dmcr_descriptor_adjoint.argtypes = [sp, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.dmcr_error_cotangent.argtypes = [sp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.dmcr_loss_grad.argtypes = [sp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.dmcr_penalised_loss_grad.argtypes = [sp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(c_bounds), _vp, _vp, _vp,
+                                               _vp, ctypes.c_size_t, _vp]
         L.dmcr_reconstruct_workspace_size.argtypes = [sp, ctypes.c_int32, ctypes.POINTER(c_opt),
                                                       ctypes.POINTER(ctypes.c_size_t)]
         L.dmcr_reconstruct.argtypes = [sp, ctypes.c_int32, _vp, ctypes.POINTER(c_bounds),
@@ -179,7 +180,7 @@ def lib():
         L.dmcr_status_string.restype = ctypes.c_char_p
         for fn in ("dmcr_descriptor_offsets", "dmcr_workspace_size", "dmcr_pyramid",
                    "dmcr_descriptor_forward", "dmcr_descriptor_adjoint", "dmcr_error_cotangent",
-                   "dmcr_loss_grad", "dmcr_reconstruct_workspace_size", "dmcr_reconstruct",
+                   "dmcr_loss_grad", "dmcr_penalised_loss_grad", "dmcr_reconstruct_workspace_size", "dmcr_reconstruct",
                    "dmcr_reconstruct_c2f_workspace_size", "dmcr_reconstruct_coarse_to_fine",
                    "dmcr_solver_start", "dmcr_solver_iterate"):
             getattr(L, fn).restype = ctypes.c_int
@@ -193,9 +194,19 @@ def _check(fn, code):
     return code
 
 
-def _stream(stream=None):
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+def _stream(stream=None, *own):
+    """The HIP stream of a call.  When it is not the current stream, it first waits
+    for the current one (which produced the inputs and on which the binding's own
+    buffers `own` were allocated), and those buffers are marked as used by it, so
+    that the caching allocator does not hand their memory out before it is done."""
+    cur = torch.cuda.current_stream()
+    if stream is None or stream == cur:
+        return ctypes.c_void_p(cur.cuda_stream)
+    stream.wait_stream(cur)
+    for t in own:
+        if t is not None:
+            t.record_stream(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
 
 
 def _ptr(t: torch.Tensor, dtype, what):
@@ -213,9 +224,14 @@ def dmcr_descriptor_size(spec: Spec) -> int:
     return _check("dmcr_descriptor_size", lib().dmcr_descriptor_size(ctypes.byref(s)))
 
 
+def dmcr_level_count(spec: Spec) -> int:
+    s = spec.c()
+    return _check("dmcr_level_count", lib().dmcr_level_count(ctypes.byref(s)))
+
+
 def dmcr_descriptor_offsets(spec: Spec):
     s = spec.c()
-    n = spec.n_levels * (len(spec.pairs) + (spec.n_channels if spec.s3_max_disp > 0 else 0)) + 1
+    n = dmcr_level_count(spec) * (len(spec.pairs) + (spec.n_channels if spec.s3_max_disp > 0 else 0)) + 1
     out = (ctypes.c_int64 * n)()
     _check("dmcr_descriptor_offsets", lib().dmcr_descriptor_offsets(ctypes.byref(s), out))
     return list(out)
@@ -242,10 +258,13 @@ def _batch(spec: Spec, phi: torch.Tensor):
     return int(phi.shape[0])
 
 
-def _ws(spec, B, ws, phi):
+def _ws(spec, B, ws, phi, own=None):
+    """The caller's workspace, or a new one (appended to `own`, the binding's buffers)."""
     need = dmcr_workspace_size(spec, B)
     if ws is None:
         ws = workspace(need, phi.device)
+        if own is not None:
+            own.append(ws)
     if ws.numel() < need:
         raise ValueError("workspace of %d bytes < %d" % (ws.numel(), need))
     return ws, need
@@ -255,11 +274,11 @@ def dmcr_pyramid(spec: Spec, phi: torch.Tensor, stream=None):
     """Levels 1..L-1 of the mean-pool pyramid, as a list of tensors."""
     B = _batch(spec, phi)
     sizes = [B * spec.n_channels * (int(torch.tensor([s >> l for s in spec.shape]).prod()))
-             for l in range(1, spec.n_levels)]
+             for l in range(1, dmcr_level_count(spec))]
     out = torch.empty(max(1, sum(sizes)), dtype=torch.float32, device=phi.device)
     s = spec.c()
     _check("dmcr_pyramid", lib().dmcr_pyramid(ctypes.byref(s), B, _ptr(phi, torch.float32, "phi"),
-                                              ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+                                              ctypes.c_void_p(out.data_ptr()), _stream(stream, out)))
     res, o = [], 0
     for l, n in enumerate(sizes, start=1):
         res.append(out[o:o + n].view((B, spec.n_channels) + tuple(x >> l for x in spec.shape)))
@@ -271,13 +290,15 @@ def dmcr_descriptor_forward(spec: Spec, phi: torch.Tensor, S: Optional[torch.Ten
                             ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     B = _batch(spec, phi)
     K = dmcr_descriptor_size(spec)
+    own = []
     if S is None:
         S = torch.empty((B, K), dtype=torch.float32, device=phi.device)
-    ws, need = _ws(spec, B, ws, phi)
+        own.append(S)
+    ws, need = _ws(spec, B, ws, phi, own)
     s = spec.c()
     _check("dmcr_descriptor_forward", lib().dmcr_descriptor_forward(
         ctypes.byref(s), B, _ptr(phi, torch.float32, "phi"), _ptr(S, torch.float32, "S"),
-        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream, *own)))
     return S
 
 
@@ -285,46 +306,77 @@ def dmcr_descriptor_adjoint(spec: Spec, phi: torch.Tensor, dS: torch.Tensor,
                             grad: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
                             stream=None) -> torch.Tensor:
     B = _batch(spec, phi)
+    own = []
     if grad is None:
         grad = torch.empty_like(phi)
-    ws, need = _ws(spec, B, ws, phi)
+        own.append(grad)
+    ws, need = _ws(spec, B, ws, phi, own)
     s = spec.c()
     _check("dmcr_descriptor_adjoint", lib().dmcr_descriptor_adjoint(
         ctypes.byref(s), B, _ptr(phi, torch.float32, "phi"), _ptr(dS, torch.float32, "dS"),
-        _ptr(grad, torch.float32, "grad"), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+        _ptr(grad, torch.float32, "grad"), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream, *own)))
     return grad
 
 
 def dmcr_error_cotangent(spec: Spec, S: torch.Tensor, S_target: torch.Tensor, E=None, G=None,
                          ws=None, stream=None):
     B = int(S.shape[0])
+    own = []
     if E is None:
         E = torch.empty(B, dtype=torch.float64, device=S.device)
+        own.append(E)
     if G is None:
         G = torch.empty_like(S)
-    ws, need = _ws(spec, B, ws, S)
+        own.append(G)
+    ws, need = _ws(spec, B, ws, S, own)
     s = spec.c()
     _check("dmcr_error_cotangent", lib().dmcr_error_cotangent(
         ctypes.byref(s), B, _ptr(S, torch.float32, "S"), _ptr(S_target, torch.float64, "S_target"),
         _ptr(E, torch.float64, "E"), _ptr(G, torch.float32, "G"), ctypes.c_void_p(ws.data_ptr()),
-        ws.numel(), _stream(stream)))
+        ws.numel(), _stream(stream, *own)))
     return E, G
 
 
 def dmcr_loss_grad(spec: Spec, phi: torch.Tensor, S_target: torch.Tensor, E=None, grad=None, ws=None,
                    stream=None):
     B = _batch(spec, phi)
+    own = []
     if E is None:
         E = torch.empty(B, dtype=torch.float64, device=phi.device)
+        own.append(E)
     if grad is None:
         grad = torch.empty_like(phi)
-    ws, need = _ws(spec, B, ws, phi)
+        own.append(grad)
+    ws, need = _ws(spec, B, ws, phi, own)
     s = spec.c()
     _check("dmcr_loss_grad", lib().dmcr_loss_grad(
         ctypes.byref(s), B, _ptr(phi, torch.float32, "phi"), _ptr(S_target, torch.float64, "S_target"),
         _ptr(E, torch.float64, "E"), _ptr(grad, torch.float32, "grad"), ctypes.c_void_p(ws.data_ptr()),
-        ws.numel(), _stream(stream)))
+        ws.numel(), _stream(stream, *own)))
     return E, grad
+
+
+def dmcr_penalised_loss_grad(spec: Spec, phi: torch.Tensor, S_target: torch.Tensor, bounds: "Bounds",
+                             L=None, E=None, grad=None, ws=None, stream=None):
+    """(L, E, grad) of the relaxed problem's loss; see include/dmcr.h."""
+    B = _batch(spec, phi)
+    own = []
+    if L is None:
+        L = torch.empty(B, dtype=torch.float64, device=phi.device)
+        own.append(L)
+    if E is None:
+        E = torch.empty(B, dtype=torch.float64, device=phi.device)
+        own.append(E)
+    if grad is None:
+        grad = torch.empty_like(phi)
+        own.append(grad)
+    ws, need = _ws(spec, B, ws, phi, own)
+    s, bo = spec.c(), bounds.c()
+    _check("dmcr_penalised_loss_grad", lib().dmcr_penalised_loss_grad(
+        ctypes.byref(s), B, _ptr(phi, torch.float32, "phi"), _ptr(S_target, torch.float64, "S_target"),
+        ctypes.byref(bo), _ptr(L, torch.float64, "L"), _ptr(E, torch.float64, "E"), _ptr(grad, torch.float32, "grad"),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream, *own)))
+    return L, E, grad
 
 
 @dataclass
@@ -347,7 +399,6 @@ class Opt:
     max_ls: int = 20
     tol_derr: float = 1e-4
     c1: float = 1e-4
-    c2: float = 0.9
     method: int = 0
     lr: float = 1e-3
     beta1: float = 0.9
@@ -355,7 +406,7 @@ class Opt:
     eps: float = 1e-7
 
     def c(self):
-        return c_opt(self.m, self.max_iter, self.max_ls, self.tol_derr, self.c1, self.c2, self.method,
+        return c_opt(self.m, self.max_iter, self.max_ls, self.tol_derr, self.c1, self.method,
                      self.lr, self.beta1, self.beta2, self.eps)
 
 
@@ -374,13 +425,15 @@ def dmcr_reconstruct(spec: Spec, S_target: torch.Tensor, phi: torch.Tensor, boun
     opt = opt or Opt()
     B = _batch(spec, phi)
     need = dmcr_reconstruct_workspace_size(spec, B, opt)
+    own = []
     if ws is None:
         ws = workspace(need, phi.device)
+        own.append(ws)
     s, bo, o = spec.c(), bounds.c(), opt.c()
     res = (c_result * B)()
     code = lib().dmcr_reconstruct(ctypes.byref(s), B, _ptr(S_target, torch.float64, "S_target"),
                                   ctypes.byref(bo), ctypes.byref(o), _ptr(phi, torch.float32, "phi"), res,
-                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream, *own))
     _check("dmcr_reconstruct", code)
     return code, [dict(final_E=r.final_E, final_derr=r.final_derr, iters=r.iters, evals=r.evals, why=r.why)
                   for r in res]
@@ -403,13 +456,16 @@ def dmcr_reconstruct_coarse_to_fine(spec: Spec, S_target: torch.Tensor, phi: tor
     opt = opt or Opt()
     B = _batch(spec, phi)
     need = dmcr_reconstruct_c2f_workspace_size(spec, B, opt)
+    own = []
     if ws is None:
         ws = workspace(need, phi.device)
+        own.append(ws)
     s, bo, o = spec.c(), bounds.c(), opt.c()
     res = (c_result * B)()
     code = lib().dmcr_reconstruct_coarse_to_fine(ctypes.byref(s), B, _ptr(S_target, torch.float64, "S_target"),
                                                  ctypes.byref(bo), ctypes.byref(o), _ptr(phi, torch.float32, "phi"),
-                                                 res, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+                                                 res, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                                 _stream(stream, *own))
     _check("dmcr_reconstruct_coarse_to_fine", code)
     return code, [dict(final_E=r.final_E, final_derr=r.final_derr, iters=r.iters, evals=r.evals, why=r.why)
                   for r in res]
@@ -420,15 +476,18 @@ class Solver:
     (dmcr_solver_start / dmcr_solver_iterate).  Holds the field and target
     buffers, the workspace, the host slot array and the history ring."""
 
-    def __init__(self, spec: Spec, batch: int, bounds: Bounds = None, opt: Opt = None, device=None):
+    def __init__(self, spec: Spec, batch: int, bounds: Bounds = None, opt: Opt = None, device=None, stream=None):
+        """With `stream`, the buffers are allocated and cleared in that stream's order
+        (the stream the solver's calls will then run on)."""
         self.spec, self.B = spec, batch
         self.bounds, self.opt = bounds or Bounds(), opt or Opt()
         dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.K = dmcr_descriptor_size(spec)
-        self.phi = torch.zeros((batch, spec.n_channels) + tuple(spec.shape), dtype=torch.float32, device=dev)
-        self.St = torch.zeros((batch, self.K), dtype=torch.float64, device=dev)
         self.ws_bytes = dmcr_reconstruct_workspace_size(spec, batch, self.opt)
-        self.ws = workspace(self.ws_bytes, dev)
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+            self.phi = torch.zeros((batch, spec.n_channels) + tuple(spec.shape), dtype=torch.float32, device=dev)
+            self.St = torch.zeros((batch, self.K), dtype=torch.float64, device=dev)
+            self.ws = workspace(self.ws_bytes, dev)
         self.slots = (c_slot * batch)()
         self.ring = c_ring(self.opt.m - 1, 0)
         self._c = (spec.c(), self.bounds.c(), self.opt.c())

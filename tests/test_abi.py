@@ -41,9 +41,9 @@ def test_struct_sizes_match_header(dm):
     assert ctypes.sizeof(dm.c_spec) == 280
     assert dm.c_spec.alpha.offset == 272
     assert ctypes.sizeof(dm.c_result) == 32
-    # dmcr_opt: 3 x 4 + pad + 3 x 8 + method 4 + pad + 4 x 8 (lr, beta1, beta2, eps)
-    assert ctypes.sizeof(dm.c_opt) == 80
-    assert dm.c_opt.lr.offset == 48
+    # dmcr_opt: 3 x 4 + pad + 2 x 8 (tol_derr, c1) + method 4 + pad + 4 x 8 (lr, beta1, beta2, eps)
+    assert ctypes.sizeof(dm.c_opt) == 72
+    assert dm.c_opt.lr.offset == 40
 
 
 def test_adam_options_validated(dm):
@@ -83,10 +83,12 @@ def test_config_sizes_quoted_in_the_workloads(dm):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(shape=(48, 64)), -3),                       # not a power of two
-    (dict(shape=(64, 64), max_disp=(32,)), -1),        # P > n/2 - 1
+    (dict(shape=(64, 64), max_disp=(-1,)), -1),        # P < 0
     (dict(shape=(8, 8), n_levels=4, max_disp=(0,)), -1),  # coarsest level below 2
     (dict(shape=(64, 64), n_channels=5), -1),
-    (dict(shape=(64, 64), level_weight=(0.0,)), -1),
+    (dict(shape=(64, 64), level_weight=(-1.0,)), -1),
+    (dict(shape=(64, 64), level_weight=(float("nan"),)), -1),
+    (dict(shape=(64, 64), n_levels=9), -1),
     (dict(shape=(64, 64), n_channels=2, pairs=((1, 0),)), -1),
     (dict(shape=(64, 64, 64), max_disp=(20,), path=2), -3),  # DIRECT halo does not fit LDS
     (dict(shape=(64, 64), flags=4), -1),                       # unknown flag bit
@@ -193,3 +195,63 @@ def test_no_cpu_fallback(dm):
             "    print('refused:', e)\n" % ROOT)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "refused: libdmcr.so is not built" in r.stdout, r.stdout + r.stderr
+
+
+def test_displacement_clipped_to_the_level(dm, ora):
+    """P_l larger than n_l/2 - 1 is clipped per level (a longer displacement aliases):
+    the same descriptor as the clipped request."""
+    big = dm.Spec(shape=(64, 64), n_levels=3, max_disp=(40, 40, 40))
+    clipped = dm.Spec(shape=(64, 64), n_levels=3, max_disp=(31, 15, 7))
+    assert dm.dmcr_descriptor_size(big) == dm.dmcr_descriptor_size(clipped) == \
+        ora.Spec(shape=(64, 64), n_levels=3, max_disp=(31, 15, 7)).K
+    assert dm.dmcr_descriptor_offsets(big) == dm.dmcr_descriptor_offsets(clipped)
+
+
+def test_level_rule_of_appendix_b(dm, ora):
+    """n_levels = 0 selects the paper's level rule (Appendix B: P = 31 gives one, two
+    and three levels at 64, 128 and 256), checked through the raw C ABI."""
+    L = dm.lib()
+    for n, want in ((64, 1), (128, 2), (256, 3), (512, 4)):
+        s = dm.Spec(shape=(n, n), n_levels=0, max_disp=(31,)).c()
+        assert L.dmcr_level_count(ctypes.byref(s)) == want, n
+        ospec = ora.Spec(shape=(n, n), n_levels=want, max_disp=tuple(min(31, (n >> l) // 2 - 1) for l in range(want)))
+        assert L.dmcr_descriptor_size(ctypes.byref(s)) == ospec.K
+    s = dm.Spec(shape=(32, 32, 32), n_levels=0, max_disp=(16,)).c()   # 32 < 2 (16 + 1): one level
+    assert L.dmcr_level_count(ctypes.byref(s)) == 1
+
+
+@pytest.mark.gpu
+def test_default_level_weights_through_the_raw_abi(dm):
+    """level_weight 0 selects w_l = 2^{d l / 2} inside the library (eq. mg and its
+    footnote): through raw ctypes calls of dmcr_error_cotangent, E and G with zero
+    weights equal those with the weights written out, and differ from unit weights."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L = dm.lib()
+    for shape, nl in (((64, 64), 3), ((32, 32, 32), 2)):
+        d = len(shape)
+        K = dm.dmcr_descriptor_size(dm.Spec(shape=shape, n_levels=nl, max_disp=(4,)))
+        rng = np.random.default_rng(5)
+        S = torch.from_numpy(rng.random((1, K)).astype(np.float32)).cuda()
+        St = torch.from_numpy(rng.random((1, K))).cuda()
+        out = {}
+        for name, w in (("zero", (0.0,) * nl), ("explicit", tuple(2.0 ** (0.5 * d * l) for l in range(nl))),
+                        ("unit", (1.0,) * nl)):
+            spec = dm.Spec(shape=shape, n_levels=nl, max_disp=(4,), level_weight=w)
+            s = spec.c()
+            nb = ctypes.c_size_t()
+            assert L.dmcr_workspace_size(ctypes.byref(s), 1, ctypes.byref(nb)) == 0
+            ws = dm.workspace(nb.value)
+            E = torch.empty(1, dtype=torch.float64, device="cuda")
+            G = torch.empty_like(S)
+            rc = L.dmcr_error_cotangent(ctypes.byref(s), 1, ctypes.c_void_p(S.data_ptr()),
+                                        ctypes.c_void_p(St.data_ptr()), ctypes.c_void_p(E.data_ptr()),
+                                        ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                        ctypes.c_size_t(ws.numel()),
+                                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            assert rc == 0
+            torch.cuda.synchronize()
+            out[name] = (E.item(), G.cpu().numpy())
+        assert out["zero"][0] == out["explicit"][0] and np.array_equal(out["zero"][1], out["explicit"][1])
+        assert out["zero"][0] != out["unit"][0]

@@ -51,7 +51,7 @@ def test_3d_256_sampled(dm, ora, fused):
 def test_2d_512_three_levels(dm, ora):
     shape = (512, 512)
     spec = dm.make_spec(shape, 1, 3, 64)
-    ospec = ora.Spec(shape=shape, n_levels=3, max_disp=spec.max_disp)
+    ospec = ora.Spec(shape=shape, n_levels=3, max_disp=ora.level_disp(shape, 3, 64))
     tgt = synth.grf_two_phase(shape, 12, 0.40, seed=0).astype(np.float32)
     S = dm.dmcr_descriptor_forward(spec, torch.from_numpy(tgt[None]).cuda()).cpu().numpy()[0].astype(np.float64)
     lv = ora.pyramid(tgt.astype(np.float64), 3)
@@ -98,7 +98,7 @@ def test_2d_1024_two_channels_three_levels(dm, ora):
     shape = (1024, 1024)
     print("fullsize 1024^2", flush=True)
     spec = dm.make_spec(shape, 2, 3, 31)
-    ospec = ora.Spec(shape=shape, n_channels=2, n_levels=3, max_disp=spec.max_disp)
+    ospec = ora.Spec(shape=shape, n_channels=2, n_levels=3, max_disp=ora.level_disp(shape, 3, 31))
     phi32 = synth.uniform(shape, 4, channels=2).astype(np.float32)
     phi = phi32.astype(np.float64)
     d = torch.from_numpy(phi32[None]).cuda()

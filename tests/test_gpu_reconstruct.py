@@ -63,9 +63,12 @@ def test_batched_stops_at_tolerance(dm, ora):
 
 
 def test_penalty_mode_runs(dm, ora):
+    """Penalty mode with the paper's reading kappa = 1 from a start with voxels outside
+    the box: E drops tenfold in 50 iterations."""
     shape = (32, 32)
     ospec, S_des = target(ora, shape, (8,))
-    x = torch.from_numpy(synth.uniform(shape, 3)[None].astype(np.float32)).cuda()
+    x0 = np.random.default_rng(3).uniform(-0.2, 1.2, (1, 1) + shape).astype(np.float32)
+    x = torch.from_numpy(x0).cuda()
     spec = dm.Spec(shape=shape, max_disp=(8,))
     E0 = dm.dmcr_loss_grad(spec, x, torch.from_numpy(S_des[None]).cuda())[0].item()
     code, res = dm.dmcr_reconstruct(spec, torch.from_numpy(S_des[None]).cuda(), x,
@@ -85,7 +88,7 @@ def test_2d_512_grf_three_levels_reaches_tolerance(dm, ora):
     print("2d512", res[0], flush=True)
     assert code == 0 and res[0]["final_E"] <= 1e-4
     # the oracle agrees on the final error (sampled finest-level entries + all coarse ones)
-    ospec = ora.Spec(shape=shape, n_levels=3, max_disp=spec.max_disp)
+    ospec = ora.Spec(shape=shape, n_levels=3, max_disp=ora.level_disp(shape, 3, 64))
     S_gpu = dm.dmcr_descriptor_forward(spec, x).double().cpu().numpy()[0]
     lv = ora.pyramid(x.cpu().numpy()[0].astype(np.float64), 3)
     for (l, pair, off, k) in ospec.layout():
@@ -245,3 +248,72 @@ def test_penalty_mode_packed_batch(dm, ora):
         one.start([0])
         one.iterate(40)
         assert sv.slots[b].E == one.slots[0].E and torch.equal(sv.phi[b], one.phi[0]), b
+
+
+def test_penalised_loss_grad_parity(dm, ora):
+    """L = E + lambda E^bc (Sec. 3.1, eq. L_func_dMCR; E^bc as printed, lambda = kappa E
+    held constant) and its gradient through dmcr_penalised_loss_grad against the
+    oracle's penalised_loss_grad, on fields with voxels below 0, above 1 and exactly
+    at 0 and 1: L and E to 1e-4 relative, the gradient to 1e-4 in norm, and the
+    penalty's own share (the difference to dmcr_loss_grad) to 1e-4 in norm.  kappa
+    makes the penalty term as large as the data term (kappa = 1, the paper's
+    unstated constant read as 1, leaves it below float32 resolution of the sum)."""
+    shape, P = (32, 32), (8,)
+    ospec, S_des = target(ora, shape, P)
+    spec = dm.Spec(shape=shape, max_disp=P)
+    rng = np.random.default_rng(80)
+    phi = rng.uniform(-0.3, 1.3, (2, 1) + shape).astype(np.float32)
+    phi[0, 0, 3, 4], phi[0, 0, 5, 6], phi[1, 0, 0, 0], phi[1, 0, 9, 9] = 0.0, 1.0, 0.0, 1.0
+    x = torch.from_numpy(phi).cuda()
+    St = torch.from_numpy(np.stack([S_des] * 2)).cuda()
+    _, gE_gpu = dm.dmcr_loss_grad(spec, x, St)
+    for b in range(2):
+        f = phi[b].astype(np.float64)
+        E0, gE0, _ = ora.loss_grad(f, S_des, ospec)
+        Ebc, gbc = ora.penalty(f)
+        kappa = np.linalg.norm(gE0) / (E0 * np.linalg.norm(gbc))
+        L_ora, g_ora, E_ora = ora.penalised_loss_grad(f, S_des, ospec, kappa)
+        L, E, g = dm.dmcr_penalised_loss_grad(spec, x[b:b + 1].contiguous(), St[b:b + 1].contiguous(),
+                                              dm.Bounds(0.0, 1.0, dm.BOUNDS_PENALTY, kappa))
+        L, E = L.item(), E.item()
+        g = g.cpu().numpy()[0].astype(np.float64)
+        print("b %d kappa %.3e L %.9e / %.9e E %.9e / %.9e" % (b, kappa, L, L_ora, E, E_ora), flush=True)
+        assert abs(L - L_ora) <= 1e-4 * L_ora and abs(E - E_ora) <= 1e-4 * E_ora
+        assert np.linalg.norm(g - g_ora) <= 1e-4 * np.linalg.norm(g_ora)
+        pen_gpu = g - gE_gpu[b].cpu().numpy().astype(np.float64)
+        pen_ora = g_ora - gE0
+        assert np.linalg.norm(pen_gpu - pen_ora) <= 1e-4 * np.linalg.norm(pen_ora)
+        # H(0) = 0: no penalty gradient at voxels exactly on the box
+        inside = (f >= 0.0) & (f <= 1.0)
+        assert np.all(pen_gpu[inside] == 0.0)
+    # other modes: L = E and the plain gradient
+    L, E, g = dm.dmcr_penalised_loss_grad(spec, x, St, dm.Bounds(0.0, 1.0, dm.BOUNDS_PROJECT))
+    assert torch.equal(L, E) and torch.equal(g, gE_gpu)
+
+
+def test_penalty_trajectory_matches_oracle(dm, ora):
+    """Penalty-mode L-BFGS (no projection; lambda = kappa E of a search's start point
+    in its Armijo test) against the oracle's FP64 L-BFGS with the same rules, from a
+    start with voxels outside [0, 1]: each of the first six iterations takes the
+    oracle's number of evaluations and reaches its f = E + lambda E^bc to 1e-4."""
+    shape, P, iters = (32, 32), (8,), 6
+    ospec, S_des = target(ora, shape, P)
+    spec = dm.Spec(shape=shape, max_disp=P)
+    phi0 = np.random.default_rng(81).uniform(-0.3, 1.3, (1,) + shape).astype(np.float32)
+    f0 = phi0.astype(np.float64)
+    kappa = 0.3 / ora.penalty(f0)[0]      # penalty term 0.3 E at the start
+    _, f_ora, ev_ora = ora.reconstruct_lbfgs_projected(S_des, ospec, f0, iters, bounds="penalty", kappa=kappa)
+    bounds = dm.Bounds(0.0, 1.0, dm.BOUNDS_PENALTY, kappa)
+    sv = dm.Solver(spec, 1, bounds, dm.Opt(max_iter=10000, tol_derr=0.0))
+    sv.phi[0].copy_(torch.from_numpy(phi0))
+    sv.St[0].copy_(torch.from_numpy(S_des))
+    sv.start([0])
+    f_gpu, ev_gpu, last = [], [], sv.slots[0].evals
+    for _ in range(iters):
+        sv.iterate(1)
+        f_gpu.append(sv.slots[0].f)
+        ev_gpu.append(sv.slots[0].evals - last)
+        last = sv.slots[0].evals
+    print("f gpu", f_gpu, "\nf ora", f_ora, "\nevals", ev_gpu, ev_ora, flush=True)
+    assert ev_gpu == ev_ora
+    np.testing.assert_allclose(f_gpu, f_ora, rtol=1e-4)

@@ -347,6 +347,171 @@ def test_projected_lbfgs_first_step_and_armijo(ora):
     np.testing.assert_allclose(ora.lbfgs_direction(g, [], [], gamma=0.25), -0.25 * g, rtol=0, atol=0)
 
 
+def _penalty_as_printed(phi):
+    """E^bc of Sec. 3.1 term by term: sum over voxels of
+    [ (M - 1) H(M - 1) / (IJ) + (-M) H(-M) / (IJ) ]^2 with H(0) = 0, per channel IJ."""
+    N = float(np.prod(phi.shape[1:]))
+    tot = 0.0
+    for v in np.asarray(phi, np.float64).ravel():
+        H_over = 1.0 if v - 1.0 > 0.0 else 0.0
+        H_under = 1.0 if -v > 0.0 else 0.0
+        t = (v - 1.0) * H_over / N + (-v) * H_under / N
+        tot += t * t
+    return tot
+
+
+def test_penalised_loss_fd_inside_outside_and_on_the_box(ora):
+    """L = E + lambda E^bc (Sec. 3.1, eq. L_func_dMCR, lambda = kappa E held constant):
+    L matches E^bc summed term by term as printed; the gradient equals central
+    differences of E(phi) + lambda0 E^bc(phi) (lambda0 of the unperturbed field) at
+    voxels inside the box, below 0, above 1 and exactly at 0 and 1, where H(0) = 0
+    leaves only dE/dphi; and it differs from the gradient of L with lambda varying."""
+    rng = np.random.default_rng(70)
+    spec = ora.Spec(shape=(8, 8), n_channels=2, max_disp=(2,))
+    tgt = (rng.random((2, 8, 8)) < 0.3).astype(np.float64)
+    S_des = ora.descriptor(tgt, spec)
+    phi = rng.uniform(-0.4, 1.4, (2, 8, 8))
+    at0, at1 = (0, 1, 1), (1, 2, 3)
+    phi[at0], phi[at1] = 0.0, 1.0
+    inside, below, above = (0, 5, 5), (1, 0, 7), (0, 6, 2)
+    phi[inside], phi[below], phi[above] = 0.55, -0.3, 1.25
+    kappa = 40.0
+    L, g, E = ora.penalised_loss_grad(phi, S_des, spec, kappa)
+    E_only, gE, _ = ora.loss_grad(phi, S_des, spec)
+    Ebc = _penalty_as_printed(phi)
+    assert E == E_only and Ebc > 0.0
+    assert L == pytest.approx(E + kappa * E * Ebc, rel=1e-14)
+    lam0 = kappa * E
+
+    def frozen(v):
+        return ora.loss_grad(v, S_des, spec)[0] + lam0 * _penalty_as_printed(v)
+
+    def varying(v):
+        Ev = ora.loss_grad(v, S_des, spec)[0]
+        return Ev + kappa * Ev * _penalty_as_printed(v)
+
+    h = 1e-5
+    N = 64.0
+    for idx in (inside, below, above, at0, at1):
+        p_, m_ = phi.copy(), phi.copy()
+        p_[idx] += h
+        m_[idx] -= h
+        fd = (frozen(p_) - frozen(m_)) / (2 * h)
+        # at 0 and 1 the one-sided quadratic of E^bc leaves lam0 h / (2 N^2) in the difference
+        assert fd == pytest.approx(g[idx], rel=1e-6, abs=lam0 * h / N ** 2), idx
+    assert g[at0] == gE[at0] and g[at1] == gE[at1] and g[inside] == gE[inside]
+    assert g[below] < gE[below] and g[above] > gE[above]
+    p_, m_ = phi.copy(), phi.copy()
+    p_[above] += h
+    m_[above] -= h
+    fd_var = (varying(p_) - varying(m_)) / (2 * h)
+    assert abs(fd_var - g[above]) > 1e-3 * abs(g[above])
+
+
+def _dense_lbfgs(ora, S_des, spec, x0, iters, c1, max_ls, bounds, kappa=1.0, lo=0.0, hi=1.0):
+    """The driver's rules restated with the dense BFGS inverse (Nocedal & Wright
+    6.17 from gamma I) instead of the two-loop recursion: the valid pairs since the
+    last reset, gamma = s'y / y'y of the newest, a reset (no pairs, gamma = 1, first
+    trial 1/|g|) after a failed search or a non-descent direction; with projection
+    the direction is zeroed where it pushes an active bound outward and trials are
+    clipped; with the penalty, lambda = kappa E of the search's start point."""
+    pen = bounds == "penalty"
+    clip = (lambda v: v) if pen else (lambda v: np.clip(v, lo, hi))
+
+    def ev(v):
+        E, gE, _ = ora.loss_grad(v, S_des, spec)
+        if not pen:
+            return E, 0.0, gE
+        Ebc = _penalty_as_printed(v)
+        N = float(np.prod(v.shape[1:]))
+        t = np.where(v > hi, (v - hi) / N, 0.0) + np.where(v < lo, (lo - v) / N, 0.0)
+        dt = np.where(v > hi, 1.0 / N, 0.0) - np.where(v < lo, 1.0 / N, 0.0)
+        return E, Ebc, gE + kappa * E * 2.0 * t * dt
+
+    x = clip(np.asarray(x0, np.float64))
+    E, Ebc, g = ev(x)
+    f = E + kappa * E * Ebc
+    pairs, gamma, moved = [], 1.0, False
+    out = []
+    n = x.size
+    for _ in range(iters):
+        H = gamma * np.eye(n)
+        for s_, y_ in pairs:
+            rho = 1.0 / float(y_ @ s_)
+            V = np.eye(n) - rho * np.outer(y_, s_)
+            H = V.T @ H @ V + rho * np.outer(s_, s_)
+
+        def proj(d_):
+            if not pen:
+                d_ = d_.copy()
+                d_[((x <= lo) & (d_ < 0)) | ((x >= hi) & (d_ > 0))] = 0.0
+            return d_
+
+        d = proj(-(H @ g.ravel()).reshape(x.shape))
+        if not np.sum(g * d) < 0:
+            pairs, gamma, moved = [], 1.0, False
+            d = proj(-g)
+        a = 1.0 if moved else 1.0 / np.sqrt(np.sum(g * g))
+        lam = kappa * E
+        ok = False
+        for _ls in range(max_ls):
+            xt = clip(x + a * d)
+            Et, Ebct, gt = ev(xt)
+            dd = np.sum(g * (xt - x))
+            if dd < 0 and Et + lam * Ebct <= f + c1 * dd:
+                ok = True
+                break
+            a /= 2
+        if ok:
+            s_, y_ = (xt - x).ravel(), (gt - g).ravel()
+            if s_ @ y_ > np.finfo(float).eps * (y_ @ y_) and y_ @ y_ > 0:
+                pairs.append((s_, y_))
+                gamma = float(s_ @ y_) / float(y_ @ y_)
+            x, E, g, f, moved = xt, Et, gt, Et + kappa * Et * Ebct, True
+        else:
+            pairs, gamma, moved = [], 1.0, False
+        out.append((x.copy(), f))
+    return out
+
+
+def test_projected_lbfgs_history_gamma_and_reset(ora):
+    """The oracle's projected L-BFGS against the dense restatement over six
+    iterations of a case whose fourth line search fails (c1 = 0.3, at most five
+    trials): the first three iterations pin the gamma rule and the history order
+    (accepted quasi-Newton steps at a = 1), the fourth moves nothing and clears the
+    history, the fifth is again a projected steepest step with first trial 1/|g|."""
+    rng = np.random.default_rng(67)
+    spec = ora.Spec(shape=(8, 8), max_disp=(2,))
+    tgt = (rng.random((1, 8, 8)) < 0.4).astype(np.float64)
+    S_des = ora.descriptor(tgt, spec)
+    x0 = rng.random((1, 8, 8))
+    ref = _dense_lbfgs(ora, S_des, spec, x0, 6, 0.3, 5, "project")
+    for it in range(1, 7):
+        x, Es, ev = ora.reconstruct_lbfgs_projected(S_des, spec, x0, it, c1=0.3, max_ls=5)
+        np.testing.assert_allclose(x, ref[it - 1][0], rtol=0, atol=1e-12)
+        assert Es[-1] == pytest.approx(ref[it - 1][1], rel=1e-10)
+    assert ev[3] == 5 and Es[3] == Es[2] and ev[4] < 5 and Es[4] < Es[3]
+
+
+def test_penalty_lbfgs_matches_dense_restatement(ora):
+    """Penalty mode of the oracle's L-BFGS (no projection; lambda = kappa E of the
+    search's start point in the Armijo test, the accepted point's own lambda in f)
+    against the dense restatement, from a start with voxels outside [0, 1]."""
+    rng = np.random.default_rng(73)
+    spec = ora.Spec(shape=(8, 8), max_disp=(2,))
+    tgt = (rng.random((1, 8, 8)) < 0.35).astype(np.float64)
+    S_des = ora.descriptor(tgt, spec)
+    x0 = rng.uniform(-0.3, 1.3, (1, 8, 8))
+    # kappa large enough that the penalty decides a line search (the third iteration
+    # backtracks once; with lambda taken at the trial point it would not)
+    ref = _dense_lbfgs(ora, S_des, spec, x0, 6, 1e-4, 20, "penalty", kappa=2e4)
+    x, Es, ev = ora.reconstruct_lbfgs_projected(S_des, spec, x0, 6, bounds="penalty", kappa=2e4)
+    assert ev == [1, 1, 2, 1, 1, 1]
+    np.testing.assert_allclose(x, ref[-1][0], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(Es, [r[1] for r in ref], rtol=1e-10)
+    assert np.any(x < 0.0) or np.any(x > 1.0)
+
+
 def test_level_slices_and_upsampling(ora):
     """The level-l slice of the multigrid descriptor is the single-level descriptor of
     the l-fold pooled field (what the coarse-to-fine stages reconstruct against), and
@@ -362,3 +527,13 @@ def test_level_slices_and_upsampling(ora):
     g = rng.random((2, 8, 16))
     np.testing.assert_allclose(ora.upsample(g), 4 * ora.pool_adjoint(g), rtol=0, atol=1e-15)
     np.testing.assert_allclose(ora.pool(ora.upsample(g)), g, rtol=0, atol=1e-15)
+
+
+def test_level_displacement_rule(ora):
+    """P_l = min(P, n_l / 2 - 1) (no displacement aliases on a coarse level): the
+    workloads' sizes, 512^2 with P = 64 over three levels keeps 64, 64, 63."""
+    assert ora.level_disp((512, 512), 3, 64) == (64, 64, 63)
+    assert ora.level_disp((128, 128, 128), 3, 32) == (32, 31, 15)
+    assert ora.level_disp((64, 32), 2, 31) == (15, 7)
+    spec = ora.Spec(shape=(512, 512), n_levels=3, max_disp=ora.level_disp((512, 512), 3, 64))
+    assert spec.K == 24707

@@ -35,6 +35,11 @@ class FakeGroup(serve.Group):
         self.ex.tick_cost = max(self.ex.tick_cost, 1e-4 + 1e-9 * vox * iterations)
         return out
 
+    def cancel(self, slot):
+        it = self.done_iters.pop(slot)
+        del self.need[slot]
+        return 1e-2, it
+
     def release(self):
         self.ex.live -= 1
         self.ex.released += 1
@@ -137,9 +142,14 @@ def test_request_stream_and_level_rule():
     assert len(st) == 200
     gaps = np.diff([0.0] + [a for (a, *_ ) in st])
     assert abs(gaps.mean() - 1 / 20.0) < 0.02
-    assert serve.levels_for(64, 31) == 1 and serve.levels_for(128, 31) == 2 and serve.levels_for(256, 31) == 3
+    from paper_2103_09686_amd import dmcr
     key = serve.make_key((128, 128, 128), 3)
-    assert key[1] == 2 and key[2] == serve.levels_for(128, 16)
+    assert key[1] == 2 and key[2] == 0 and key[3] == (16,)
+    spec = dmcr.Spec(shape=key[0], n_channels=key[1], n_levels=key[2], max_disp=key[3])
+    assert dmcr.dmcr_level_count(spec) == 3          # 128 -> 64 -> 32 = 2 (16 + 1) - 2
+    for n, L in ((128, 2), (256, 3), (512, 4), (1024, 5)):
+        k = serve.make_key((n, n), 2)
+        assert dmcr.dmcr_level_count(dmcr.Spec(shape=k[0], n_levels=k[2], max_disp=k[3])) == L
 
 
 # -- asynchronous groups (real clock: each group's advance sleeps in proportion to
@@ -199,3 +209,30 @@ def test_asynchronous_budget_and_unfit_requests():
     done = srv.run([serve.Request(rid=0, arrival=0.0, key=(1,), voxels=1, payload=5)])
     srv.close()
     assert len(done) == 1 and done[0].status == -2
+
+
+@pytest.mark.parametrize("asynchronous", [False, True])
+def test_cancel_and_timeout(asynchronous):
+    """A cancelled request and one whose timeout passes are retired with CANCELLED and
+    TIMED_OUT (queued or running), their slots are reused, and every other request
+    still finishes with its own iterations."""
+    ex = FakeExecutor(caps={(1,): 2}) if not asynchronous else None
+    if asynchronous:
+        ex = TimedExecutor(caps={(1,): 2})
+    srv = serve.Server(ex, budget_bytes=10 ** 9, iters_per_tick=1, threads=1, asynchronous=asynchronous)
+    rs = [serve.Request(rid=i, arrival=0.0, key=(1,), voxels=1, payload=6) for i in range(6)]
+    rs[0].payload = 10 ** 6          # would run for ever: times out while running
+    rs[0].timeout = 0.02 if asynchronous else 0.002
+    rs[5].timeout = 0.0              # times out in the queue
+    srv.cancel(3)                    # cancelled before it is admitted
+    done = srv.run(rs)
+    srv.close()
+    by = {r.rid: r for r in done}
+    assert sorted(by) == list(range(6))
+    assert by[0].status == serve.TIMED_OUT and by[0].iters > 0
+    assert by[5].status == serve.TIMED_OUT and by[5].iters == 0
+    assert by[3].status == serve.CANCELLED
+    for i in (1, 2, 4):
+        assert by[i].status == 0 and by[i].iters == 6
+    s = serve.summary(done)
+    assert s["timed_out"] == 2 and s["cancelled"] == 1 and s["converged"] == 3

@@ -236,6 +236,18 @@ dmcr_status dmcr_loss_grad(const dmcr_spec *spec, int32_t batch, const float *ph
                            const double *S_target, double *E, float *grad, void *ws,
                            size_t ws_bytes, hipStream_t stream);
 
+/* dmcr_loss_grad without a workspace argument, for callers that cannot allocate
+ * (code under stream capture, serving loops that must not call an allocator):
+ * the scratch memory is a 64 MiB device array inside the library, one copy per
+ * device, held until the process ends.  A spec and batch whose workspace
+ * (dmcr_workspace_size) exceeds 64 MiB returns DMCR_ENOMEM before any launch.
+ * Everything runs on `stream` (no internal streams); nothing is allocated.  All
+ * calls on one device share that array: calls that overlap in time on one
+ * device (concurrent streams or host threads) race and must not be issued.
+ * Arguments and results as dmcr_loss_grad. */
+dmcr_status dmcr_loss_grad_noalloc(const dmcr_spec *spec, int32_t batch, const float *phi, const double *S_target,
+                                   double *E, float *grad, hipStream_t stream);
+
 /* The loss of the relaxed problem (Sec. 3.1, eq. L_func_dMCR) and its gradient:
  * with bounds->mode == DMCR_BOUNDS_PENALTY, L[b] = E[b] + lambda E^bc[b], where
  * E^bc = sum_c sum_x [ (phi - hi) H(phi - hi) / N + (lo - phi) H(lo - phi) / N ]^2

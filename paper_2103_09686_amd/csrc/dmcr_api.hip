@@ -505,12 +505,15 @@ hipError_t run_pyramid_levels(const Plan &p, const float *phi, const Ws &ws, hip
 // forward, error, adjoint with one plan (shared by dmcr_loss_grad and the
 // reconstruction loop)
 dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St, double *E, float *grad,
-                               const Ws &w, hipStream_t st)
+                               const Ws &w, hipStream_t st, bool lanes)
 {
     float *S = w.at<float>(p.S);
     float *G = w.at<float>(p.G);
     Sched sc;
-    DMCR_TRY(make_sched(p, st, &sc));
+    if (lanes)
+        DMCR_TRY(make_sched(p, st, &sc));
+    else
+        sc = Sched{&tl_lanes, st, false, false};
     const bool keep = (p.flags & DMCR_FLAG_RECOMPUTE) == 0;
     hipEvent_t x_free[kMaxLevels] = {};
     if (!keep && sc.side_recompute)

@@ -208,6 +208,11 @@ hipError_t launch_error(const Plan &p, const float *S, const double *St, double 
                         const Ws &ws, hipStream_t st, hipStream_t st_final = nullptr,
                         hipEvent_t parts_done = nullptr);
 
+// forward, error and adjoint with one plan (dmcr_loss_grad, the solvers).  With
+// lanes = false everything runs on st (no internal streams or events are created).
+dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St, double *E, float *grad,
+                               const Ws &w, hipStream_t st, bool lanes = true);
+
 // true if the DIRECT path can run this level (halo tile fits in LDS)
 bool direct_supported(const Plan &p, int l, int tile_out[3]);
 

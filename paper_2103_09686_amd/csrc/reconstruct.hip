@@ -41,9 +41,6 @@
 
 namespace dmcr {
 
-dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St, double *E, float *grad,
-                               const Ws &w, hipStream_t st);
-
 namespace {
 
 constexpr int kV = 256;

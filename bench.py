@@ -35,6 +35,12 @@ WORKLOADS = {
                   shape=(512, 512), C=1, L=3, P=64, recompute=False, batch=1),
     "2d512b64": dict(desc="2D 512^2 two-phase, P=64, 3 levels, batch of 64 fields",
                      shape=(512, 512), C=1, L=3, P=64, recompute=False, batch=64),
+    # the same step on batches whose passes (about 270 MB and 540 MB each) exceed the
+    # 256 MB Infinity Cache, so that every pass streams from HBM
+    "3d256b2": dict(desc="3D 256^3 two-phase U(0,1), P=32, 1 level, fwd+adjoint with recomputation, batch 2",
+                    shape=(256, 256, 256), C=1, L=1, P=32, recompute=True, batch=2),
+    "3d256b4": dict(desc="3D 256^3 two-phase U(0,1), P=32, 1 level, fwd+adjoint with recomputation, batch 4",
+                    shape=(256, 256, 256), C=1, L=1, P=32, recompute=True, batch=4),
     "3d128": dict(desc="3D 128^3 three-phase (C=2), P=32, 3-level multigrid (128/64/32)",
                   shape=(128, 128, 128), C=2, L=3, P=32, recompute=False, batch=1),
     "2d256sbar": dict(desc="2D 256^2 two-phase, soft-threshold descriptor Sbar (alpha=10), P=31, "
@@ -153,7 +159,39 @@ def parse():
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
     ap.add_argument("--compare", type=int, default=100,
                     help="serving: requests in the batched vs one-at-a-time throughput comparison")
+    ap.add_argument("--counters-only", action="store_true",
+                    help="run the warm-up and timed steps only (for rocprofv3 --pmc runs): no per-launch "
+                         "event pairs, no alternatives, no serving, no CPU baseline")
+    ap.add_argument("--optimizer", action="store_true",
+                    help="time L-BFGS iterations (m = 10, history full) of the workload's field instead")
     return ap.parse_args()
+
+
+def optimizer_iterations(args, spec, phi, S_target):
+    """L-BFGS iterations of one solver batch: the first 12 fill the history (m = 10),
+    then args.steps iterations are timed (wall clock around blocking calls).  Prints
+    one JSON line: ms per iteration, evaluations per iteration and the bytes that the
+    vector passes of an iteration move, counted per pass."""
+    import torch
+    from paper_2103_09686_amd import dmcr
+    B = phi.shape[0]
+    opt = dmcr.Opt(m=10, max_iter=10 ** 6, tol_derr=0.0)
+    sv = dmcr.Solver(spec, B, dmcr.Bounds(), opt)
+    sv.phi.copy_(phi)
+    sv.St.copy_(S_target)
+    sv.start(list(range(B)))
+    sv.iterate(12)
+    torch.cuda.synchronize()
+    ev0 = sum(sv.slots[b].evals for b in range(B))
+    t0 = time.perf_counter()
+    sv.iterate(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    evals = (sum(sv.slots[b].evals for b in range(B)) - ev0) / (B * args.steps)
+    out = dict(workload=args.workload, optimizer="lbfgs m=10", batch=B, iterations=args.steps,
+               ms_per_iteration=round(dt * 1e3 / args.steps, 4), evaluations_per_iteration=round(evals, 3),
+               E=[sv.slots[b].E for b in range(B)])
+    print(json.dumps(out), flush=True)
 
 
 def serving(n_requests, rate, n_compare):
@@ -364,6 +402,10 @@ def main():
     def step():
         dmcr.dmcr_loss_grad(spec, phi, S_target, E, grad, ws)
 
+    if args.optimizer:
+        optimizer_iterations(args, spec, phi, S_target)
+        return
+
     import ctypes
     lib = dmcr.lib()
     lib.dmcr_profile_start.restype = ctypes.c_int
@@ -429,6 +471,10 @@ def main():
 
     ms = timed(step)
     value = N * B / (ms * 1e-3)
+    if args.counters_only:
+        # for hardware-counter runs: the plain steps only (no event-stamped launches)
+        print(json.dumps(dict(workload=args.workload, ms_per_step=ms, value=value)), flush=True)
+        return
     step_time = step_percentiles(step)
     print("per-step GPU time: %s" % step_time, file=sys.stderr, flush=True)
     kern = kernel_table(step)

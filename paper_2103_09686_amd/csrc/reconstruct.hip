@@ -49,27 +49,6 @@ size_t align_up_bytes(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 unsigned vblocks(int64_t n) { return (unsigned)std::min<int64_t>((n + kV - 1) / kV, 2048); }
 
-// part[b][blk] = sum over block blk's slice of element b of a * (bv - cv)   (cv may be null)
-__global__ __launch_bounds__(kV) void k_dot_part(const float *a, const float *bv, const float *cv, int64_t n,
-                                                 double *part, int nblk)
-{
-    __shared__ double red[kV];
-    const int64_t b = blockIdx.y;
-    const float *A = a + b * n, *Bv = bv + b * n, *Cv = cv ? cv + b * n : nullptr;
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)nblk * kV) {
-        const double y = Cv ? (double)Bv[i] - (double)Cv[i] : (double)Bv[i];
-        acc += (double)A[i] * y;
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = kV / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[b * nblk + blockIdx.x] = red[0];
-}
-
 // Deterministic sum of one element's block partials: thread t adds partials
 // t, t + kV, ... in order, then a fixed tree.  One block per element.
 __device__ __forceinline__ double block_sum(const double *p, int cnt, int64_t stride, double *red)
@@ -100,13 +79,19 @@ __global__ void k_fill(double *p, double v, int n)
     if (i < n) p[i] = v;
 }
 
-// History dot products, one pass over the ring slots j < cnt in use, per element b:
+// History dot products, one pass over the ring slots j < cnt in use, per element
+// b, fused with the acceptance of a trial point: with acc and acc[b], first
+//   s = xt - x, y = gt - g into ring slot `slot`, x = xt, g = gt
+// (the accepted step and its pair), then
 //   [j] = S_j.g, [m + j] = Y_j.g, [2m] = g.g
-// and, with a new pair (s_new, y_new) just written to a ring slot,
-//   [2m + 1 + j] = s_j.y_new, [3m + 1 + j] = y_j.y_new, [4m + 1 + j] = s_new.y_j.
-// Fixed order throughout: strided element loop, wave shuffles, waves in order.
+// and, for an accepted element (its new pair in slot `slot`),
+//   [2m + 1 + j] = s_j.y, [3m + 1 + j] = y_j.y, [4m + 1 + j] = s.y_j.
+// acc null: the dots of the current g only.  One pass reads every vector once
+// (up to kHistJ ring slots; a longer ring takes more passes).  Fixed order
+// throughout: strided element loop, wave shuffles, waves in order; the sums are
+// bitwise those of a separate accept followed by a dots pass.
 constexpr int kMaxDots = 5 * 32 + 1;
-constexpr int kHistJ = 4;   // ring slots per chunk (5 kHistJ + 1 accumulators)
+constexpr int kHistJ = 5;   // ring slots per pass (5 kHistJ + 1 float64 accumulators)
 
 __device__ __forceinline__ int hist_count(int cnt, bool pair) { return 2 * cnt + 1 + (pair ? 3 * cnt : 0); }
 
@@ -121,48 +106,81 @@ __device__ __forceinline__ int hist_out(int k, int cnt, int m)
     return 4 * m + 1 + (k - 2 * cnt);
 }
 
-__global__ __launch_bounds__(kV) void k_hist_dots(const float *Sb, const float *Yb, int cnt, const float *g,
-                                                  const float *ynew, const float *snew, int m, int B, int64_t n,
-                                                  double *part, int nblk)
+__global__ __launch_bounds__(kV) void k_accept_dots(const int *acc, float *x, const float *xt, float *g,
+                                                    const float *gt, float *Sb, float *Yb, int slot, int cnt, int m,
+                                                    int B, int64_t n, double *part, int nblk)
 {
     constexpr int NA = 5 * kHistJ + 1;
     __shared__ double red[kV / 64][NA];
     const int64_t b = blockIdx.y;
     const int64_t stride = (int64_t)B * n;
-    const bool pair = ynew != nullptr;
+    const bool pair = acc != nullptr && acc[b] != 0;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     double *pb = part + ((int64_t)b * nblk + blockIdx.x) * kMaxDots;
+    float *Sn = Sb + (int64_t)(slot < 0 ? 0 : slot) * stride, *Yn = Yb + (int64_t)(slot < 0 ? 0 : slot) * stride;
     for (int c0 = 0; c0 < cnt || c0 == 0; c0 += kHistJ) {
         const int cj = min(kHistJ, cnt - c0);
-        double acc[NA];
+        double a[NA];
 #pragma unroll
-        for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+        for (int k = 0; k < NA; ++k) a[k] = 0.0;
         for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)nblk * kV) {
             const int64_t e = b * n + i;
-            const double gv = g[e];
-            const double yn = pair ? (double)ynew[e] : 0.0, sn = pair ? (double)snew[e] : 0.0;
-            if (c0 == 0) acc[NA - 1] += gv * gv;
+            // every slot of the pass is loaded unconditionally (an index past the ring
+            // reads slot 0 and its sums are never stored) and before the accepted
+            // step, so that all loads are in flight together; the new pair comes
+            // from registers
+            float svf[kHistJ], yvf[kHistJ];
 #pragma unroll
             for (int jj = 0; jj < kHistJ; ++jj) {
-                if (jj < cj) {
-                    const int64_t o = (int64_t)(c0 + jj) * stride + e;
-                    const double sv = Sb[o], yv = Yb[o];
-                    acc[5 * jj + 0] += sv * gv;
-                    acc[5 * jj + 1] += yv * gv;
-                    if (pair) {
-                        acc[5 * jj + 2] += sv * yn;
-                        acc[5 * jj + 3] += yv * yn;
-                        acc[5 * jj + 4] += sn * yv;
-                    }
+                const int j = c0 + jj < cnt ? c0 + jj : 0;
+                svf[jj] = Sb[(int64_t)j * stride + e];
+                yvf[jj] = Yb[(int64_t)j * stride + e];
+            }
+            float gf, sf = 0.f, yf = 0.f;
+            if (pair && c0 == 0) {          // the accepted step, once
+                const float xo = x[e], xn = xt[e], go = g[e], gn = gt[e];
+                sf = xn - xo;
+                yf = gn - go;
+                Sn[e] = sf;
+                Yn[e] = yf;
+                x[e] = xn;
+                g[e] = gn;
+                gf = gn;
+            } else {
+                gf = g[e];
+                if (pair) {                  // later passes: the pair as the first one wrote it
+                    sf = Sn[e];
+                    yf = Yn[e];
+                }
+            }
+            const double gv = gf, yn = yf, sn = sf;
+            if (c0 == 0) a[NA - 1] += gv * gv;
+            if (pair) {
+#pragma unroll
+                for (int jj = 0; jj < kHistJ; ++jj) {
+                    const bool nw = c0 + jj == slot;
+                    const double sv = nw ? sf : svf[jj], yv = nw ? yf : yvf[jj];
+                    a[5 * jj + 0] += sv * gv;
+                    a[5 * jj + 1] += yv * gv;
+                    a[5 * jj + 2] += sv * yn;
+                    a[5 * jj + 3] += yv * yn;
+                    a[5 * jj + 4] += sn * yv;
+                }
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < kHistJ; ++jj) {
+                    const double sv = svf[jj], yv = yvf[jj];
+                    a[5 * jj + 0] += sv * gv;
+                    a[5 * jj + 1] += yv * gv;
                 }
             }
         }
 #pragma unroll
         for (int k = 0; k < NA; ++k)
-            for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_down(acc[k], off);
+            for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off);
         if (lane == 0)
 #pragma unroll
-            for (int k = 0; k < NA; ++k) red[wave][k] = acc[k];
+            for (int k = 0; k < NA; ++k) red[wave][k] = a[k];
         __syncthreads();
         if (threadIdx.x < NA) {
             const int k = threadIdx.x;
@@ -256,15 +274,31 @@ __global__ __launch_bounds__(kV) void k_combine_dir(const float *x, const float 
     __syncthreads();
     const float c0 = (float)cg[b];
     const int64_t stride = (int64_t)B * n;
+    constexpr int kChunk = 10;  // history slots whose loads are issued together
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)nblk * kV) {
         const int64_t j = b * n + i;
         const float gv = g[j];
         float h = c0 * gv;
-        for (int t = count - 1; t >= 0; --t) {
-            const int k = (head - t + m) % m;
-            if (cs[k] != 0.f) h += cs[k] * Sb[k * stride + j];
-            if (cy[k] != 0.f) h += cy[k] * Yb[k * stride + j];
+        for (int t0 = count - 1; t0 >= 0; t0 -= kChunk) {
+            float sv[kChunk], yv[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {   // unconditional loads (t < 0 reads the newest slot, unused)
+                const int t = t0 - u;
+                const int k = (head - (t < 0 ? 0 : t) + m) % m;
+                sv[u] = Sb[k * stride + j];
+                yv[u] = Yb[k * stride + j];
+            }
+            // oldest first; a slot with a zero coefficient is skipped (it may hold nothing valid)
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const int t = t0 - u;
+                if (t >= 0) {
+                    const int k = (head - t + m) % m;
+                    if (cs[k] != 0.f) h += cs[k] * sv[u];
+                    if (cy[k] != 0.f) h += cy[k] * yv[u];
+                }
+            }
         }
         const float xv = x[j];
         float dv = -h;
@@ -281,7 +315,7 @@ __global__ __launch_bounds__(kV) void k_combine_dir(const float *x, const float 
     if (threadIdx.x == 0) part[b * nblk + blockIdx.x] = red[0];
 }
 
-// New pair in ring slot `slot` (written by k_accept for accepted elements):
+// New pair in ring slot `slot` (written by k_accept_dots for accepted elements):
 // dots[2m + 1 + j] = s_j.y_new, [3m + 1 + j] = y_j.y_new, [4m + 1 + j] = s_new.y_j (j < count).
 // rho = 1/s'y if accepted and s'y > eps y'y, else 0; gamma follows; the slot's
 // row and column of S'Y and Y'Y are refreshed.
@@ -363,18 +397,35 @@ __global__ __launch_bounds__(kV) void k_scatter(const int *idx, const T *src, T 
         dst[b * len + i] = src[k * len + i];
 }
 
-// x_t = clip(x + alpha d) for elements with active[b]
-__global__ __launch_bounds__(kV) void k_trial(const float *x, const float *d, const double *alpha, const int *active,
-                                              float *xt, int64_t n, int project, float lo, float hi)
+// Trial point xt = x + alpha d (clipped with projection) of the active elements,
+// and block partials of g . (xt - x), the Armijo test's directional term, in
+// float64 over a strided element loop and a fixed tree (zero for inactive
+// elements).
+__global__ __launch_bounds__(kV) void k_trial_dot(const float *x, const float *d, const float *g, const double *alpha,
+                                                  const int *active, float *xt, int64_t n, int project, float lo,
+                                                  float hi, double *part, int nblk)
 {
+    __shared__ double red[kV];
     const int64_t b = blockIdx.y;
-    if (!active[b]) return;
-    const float a = (float)alpha[b];
-    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV) {
-        float v = x[b * n + i] + a * d[b * n + i];
-        if (project) v = fminf(fmaxf(v, lo), hi);
-        xt[b * n + i] = v;
+    double acc = 0.0;
+    if (active[b]) {
+        const float a = (float)alpha[b];
+        for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)nblk * kV) {
+            const int64_t j = b * n + i;
+            const float xv = x[j];
+            float v = xv + a * d[j];
+            if (project) v = fminf(fmaxf(v, lo), hi);
+            xt[j] = v;
+            acc += (double)g[j] * ((double)v - (double)xv);
+        }
     }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kV / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[b * nblk + blockIdx.x] = red[0];
 }
 
 __global__ __launch_bounds__(kV) void k_clip(float *x, int64_t total, float lo, float hi)
@@ -406,21 +457,6 @@ __global__ __launch_bounds__(kV) void k_steepest(const int *flag, const float *x
         float dv = -g[b * n + i];
         if (project && ((xv <= lo && dv < 0.f) || (xv >= hi && dv > 0.f))) dv = 0.f;
         d[b * n + i] = dv;
-    }
-}
-
-// accepted elements: s = x_t - x, y = g_t - g, x = x_t, g = g_t
-__global__ __launch_bounds__(kV) void k_accept(const int *acc, float *x, const float *xt, float *g, const float *gt,
-                                               float *s, float *y, int64_t n)
-{
-    const int64_t b = blockIdx.y;
-    if (!acc[b]) return;
-    for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)gridDim.x * kV) {
-        const int64_t j = b * n + i;
-        s[j] = xt[j] - x[j];
-        y[j] = gt[j] - g[j];
-        x[j] = xt[j];
-        g[j] = gt[j];
     }
 }
 
@@ -620,21 +656,14 @@ struct Solver {
     float *S(int i) const { return at<float>(r.s) + (int64_t)i * B * n; }
     float *Y(int i) const { return at<float>(r.y) + (int64_t)i * B * n; }
 
-    // out[b] = a[b] . (bv[b] - cv[b])
-    hipError_t dot(const float *a, const float *bv, const float *cv, double *out) const
-    {
-        hipLaunchKernelGGL(k_dot_part, dim3(r.nblk, B), dim3(kV), 0, st, a, bv, cv, n, at<double>(r.part), r.nblk);
-        hipLaunchKernelGGL(k_sum_parts, dim3(B), dim3(kV), 0, st, at<double>(r.part), r.nblk, out, B);
-        return hipGetLastError();
-    }
-
     // history dot products of the ring slots 0 .. cnt - 1 against g and, with
-    // slot >= 0, against the new pair in that slot; summed into mdots
-    hipError_t hist_dots(const float *g, int cnt, int slot) const
+    // acc (accepted elements; their step enters ring slot `slot` and x, g move to
+    // xt, gt in the same pass), against the new pair; summed into mdots
+    hipError_t hist_dots(float *x, const float *xt, float *g, const float *gt, const int *acc, int cnt,
+                         int slot) const
     {
-        const float *yn = slot >= 0 ? Y(slot) : nullptr, *sn = slot >= 0 ? S(slot) : nullptr;
-        hipLaunchKernelGGL(k_hist_dots, dim3(r.nblk, B), dim3(kV), 0, st, S(0), Y(0), cnt, g, yn, sn, m, B, n,
-                           at<double>(r.mpart), r.nblk);
+        hipLaunchKernelGGL(k_accept_dots, dim3(r.nblk, B), dim3(kV), 0, st, acc, x, xt, g, gt, S(0), Y(0), slot,
+                           cnt, m, B, n, at<double>(r.mpart), r.nblk);
         const int nout = 2 * cnt + 1 + (slot >= 0 ? 3 * cnt : 0);
         hipLaunchKernelGGL(k_hist_sum, dim3(B, nout), dim3(kV), 0, st, at<double>(r.mpart), r.nblk, cnt, m,
                            at<double>(r.mdots));
@@ -865,7 +894,7 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
         RS(put(histd, hist));
 
         // ---- direction d = -H g (compact representation), then projection ----
-        if (!gdots) RT(hist_dots(g, count, -1));
+        if (!gdots) RT(hist_dots(x, nullptr, g, nullptr, nullptr, count, -1));
         hipLaunchKernelGGL(k_lbfgs_coef, sg, dim3(64), 0, st, mdots, rho, gamma, SY, YY, head, count, m, B, cS, cY,
                            cg, dot2);
         hipLaunchKernelGGL(k_combine_dir, dim3(r.nblk, B), dim3(kV), 0, st, x, g, d, S(0), Y(0), cS, cY, cg, m, head,
@@ -885,14 +914,15 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
                 RS(put(active, act));
                 RS(put(als, step));
             }
-            hipLaunchKernelGGL(k_trial, vg, dim3(kV), 0, st, x, d, als, active, xt, n, (int)project, lo, hi);
+            hipLaunchKernelGGL(k_trial_dot, dim3(r.nblk, B), dim3(kV), 0, st, x, d, g, als, active, xt, n,
+                               (int)project, lo, hi, at<double>(r.part), r.nblk);
+            hipLaunchKernelGGL(k_sum_parts, dim3(B), dim3(kV), 0, st, at<double>(r.part), r.nblk, dot1, B);
             int nact = 0;
             for (int b = 0; b < B; ++b) nact += act[b] != 0;
             if (nact < B)
                 RS(evaluate_packed(act, xt, Etd, gt));   // backtracking elements only, or a partly idle batch
             else
                 RS(evaluate(xt, Etd, gt));
-            RT(dot(g, xt, x, dot1));
             RS(fetch(Etd, hE));
             if (penalty) RS(fetch(Ebcd, hEbc));
             RS(fetch(dot1, hd));
@@ -924,9 +954,9 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
         // ---- update the field, gradient and history of accepted elements ----
         const int slot = (head + 1) % m;
         RS(put(accd, acc));
-        hipLaunchKernelGGL(k_accept, vg, dim3(kV), 0, st, accd, x, xt, g, gt, S(slot), Y(slot), n);
         const int cnew = std::min(count + 1, m);   // ring slots in use: 0 .. cnew - 1
-        RT(hist_dots(g, cnew, slot));   // the new pair's dots and the next direction's
+        // accepted steps enter slot `slot`; the new pair's dots and the next direction's
+        RT(hist_dots(x, xt, g, gt, accd, cnew, slot));
         gdots = true;
         hipLaunchKernelGGL(k_pair_update, sg, dim3(64), 0, st, mdots, accd, slot, cnew, m, B, rho, gamma, SY, YY);
         RT(hipGetLastError());

@@ -145,6 +145,8 @@ def parse():
     # the GPU reaches its steady clock after about 0.1 s of sustained load: 500
     # steps of the 256^3 evaluation (0.11 s) cover it (after 5 the step is ~4% slower)
     ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--settle", type=float, default=0.25,
+                    help="seconds of sustained steps before the warm-up, so that the GPU clock is steady")
     ap.add_argument("--workload", default="3d256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle sample time")
@@ -417,8 +419,20 @@ def main():
 
     lib.dmcr_profile_stop.argtypes = [ctypes.POINTER(KStat), ctypes.c_int32]
 
+    def settle(fn):
+        """Run the step for args.settle seconds of sustained load first: a fresh GPU runs
+        its first ~0.1 s of load below its steady clock (the 256^3 step reads 4-6%
+        slower there), which a handful of warm-up steps does not cover."""
+        t_end = time.perf_counter() + args.settle
+        while time.perf_counter() < t_end:
+            for _ in range(8):
+                fn()
+            torch.cuda.synchronize()
+
     def timed(fn):
-        """Warm-up, then args.steps steps between two events on the launch stream: ms per step."""
+        """Settle, warm-up, then args.steps steps between two events on the launch stream:
+        ms per step."""
+        settle(fn)
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
@@ -530,7 +544,8 @@ def main():
                              kernel_ms_sum=round(prof_ms, 4))
 
     out = dict(metric=METRIC, value=value, unit="voxel·it/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=ms, step_time=step_time, higher_is_better=True, scaling="weak",
+               warmup=args.warmup, settle_s=args.settle, ms_per_step=ms, step_time=step_time,
+               higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload=wl["desc"], shape=list(shape), channels=C, levels=L,
                            max_disp=[level_P(spec, l) for l in range(L)], K=K, batch=B,

@@ -111,6 +111,16 @@ def test_random_config_parity(dm, ora, case):
         Eo, gO, _ = ora.loss_grad(phi[b], St[b], ospec)
         assert abs(E[b] - Eo) <= 1e-4 * abs(Eo), ("E", b, E[b], Eo)
         assert np.linalg.norm(gl[b] - gO) <= 1e-4 * np.linalg.norm(gO), ("loss gradient", b)
+    # a target of the same mean (0.9 phi + 0.05 of U(0,1) fields): S - S* cancels down
+    # to the fields' fluctuations, the case the fluctuation form of the FFT path is for
+    St2 = np.stack([ora.descriptor(0.9 * phi[b] + 0.05, ospec) for b in range(B)])
+    E2, gl2 = dm.dmcr_loss_grad(spec, dphi, torch.from_numpy(St2).cuda())
+    E2 = E2.cpu().numpy()
+    gl2 = gl2.cpu().numpy().astype(np.float64)
+    for b in range(B):
+        Eo, gO, _ = ora.loss_grad(phi[b], St2[b], ospec)
+        assert abs(E2[b] - Eo) <= 1e-4 * abs(Eo), ("E, equal mean", b, E2[b], Eo)
+        assert np.linalg.norm(gl2[b] - gO) <= 1e-4 * np.linalg.norm(gO), ("loss gradient, equal mean", b)
 
 
 KINDS = {0: "s2", 1: "sbar", 2: "stilde"}

@@ -537,3 +537,38 @@ def test_level_displacement_rule(ora):
     assert ora.level_disp((64, 32), 2, 31) == (15, 7)
     spec = ora.Spec(shape=(512, 512), n_levels=3, max_disp=ora.level_disp((512, 512), 3, 64))
     assert spec.K == 24707
+
+
+def test_sampled_descriptor_and_reference_reconstructions(ora):
+    """descriptor_at (sampled displacements of one level and pair) equals the matching
+    entries of the full descriptor; the SciPy L-BFGS-B reference keeps the box, lowers
+    E and lands within a factor of the projected L-BFGS reference on the same loss;
+    the sequential coarse-to-fine reference with one level is that same SciPy run, and
+    with two levels returns the multigrid E of its own result."""
+    rng = np.random.default_rng(72)
+    spec = ora.Spec(shape=(16, 16), n_channels=2, n_levels=2, max_disp=(3, 2))
+    phi = rng.random((2, 16, 16))
+    S = ora.descriptor(phi, spec)
+    for (l, pair, off, k) in spec.layout():
+        r = spec.disp(l, pair)
+        sel = rng.choice(len(r), 5, replace=False)
+        np.testing.assert_allclose(ora.descriptor_at(phi, spec, l, pair, r[sel]), S[off:off + k][sel], rtol=0,
+                                   atol=1e-15)
+    one = ora.Spec(shape=(8, 8), max_disp=(2,))
+    tgt = (rng.random((1, 8, 8)) < 0.4).astype(np.float64)
+    S_des = ora.descriptor(tgt, one)
+    x0 = rng.random((1, 8, 8))
+    E0 = ora.loss_grad(x0, S_des, one)[0]
+    x, E, nit, nev = ora.reconstruct_lbfgsb(S_des, one, x0, maxiter=30)
+    assert np.all((x >= 0) & (x <= 1)) and E < 0.1 * E0 and nev >= nit
+    assert E == pytest.approx(ora.loss(ora.descriptor(x, one), S_des, one)[0], rel=1e-12)
+    _, Es, _ = ora.reconstruct_lbfgs_projected(S_des, one, x0, 30)
+    assert E <= 10 * Es[-1] and Es[-1] <= 10 * E
+    xc, Ec = ora.reconstruct_coarse_to_fine(S_des, one, x0, maxiter=30)
+    np.testing.assert_allclose(xc, x, rtol=0, atol=1e-12)
+    two = ora.Spec(shape=(16, 16), n_levels=2, max_disp=(3, 2))
+    tg2 = (rng.random((1, 16, 16)) < 0.4).astype(np.float64)
+    S2 = ora.descriptor(tg2, two)
+    x2, E2 = ora.reconstruct_coarse_to_fine(S2, two, rng.random((1, 16, 16)), maxiter=15)
+    assert np.all((x2 >= 0) & (x2 <= 1))
+    assert E2 == pytest.approx(ora.loss(ora.descriptor(x2, two), S2, two)[0], rel=1e-12)

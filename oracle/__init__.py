@@ -9,7 +9,7 @@ claimed.
 from . import _native
 from .s2 import (DESCRIPTORS, Spec, adam_step, adjoint, adjoint_at_single_level, all_pairs, box,
                  correct_s3, correct_s3_adjoint, correct_sbar, correct_sbar_adjoint, descriptor, descriptor_at, error_Z, half_box,
-                 in_half, lbfgs_direction, level_disp, level_slice, level_spec, loss, loss_grad, penalised_loss_grad, penalty, pool,
+                 in_half, lbfgs_direction, level_disp, level_slice, level_weights_per_entry, level_spec, loss, loss_grad, penalised_loss_grad, penalty, pool,
                  pool_adjoint, pyramid, reconstruct_adam, reconstruct_coarse_to_fine, reconstruct_lbfgs_projected, reconstruct_lbfgsb, soft_threshold,
                  soft_threshold_constants, upsample)
 

@@ -8,8 +8,11 @@
 // Forward: one block per (spatial tile, chunk of displacements, batch x pair).
 // The tile of phi_i and the tile of phi_j with a halo of P (periodic) sit in
 // LDS; each thread owns one displacement r and accumulates
-// sum_{x in tile} phi_i(x) phi_j(x + r); phi_i(x) is a broadcast read.  Tile
-// partials are summed in float64, in tile order, by a second kernel.
+// sum_{x in tile} phi_i(x) phi_j(x + r); phi_i(x) is a broadcast read.  Each
+// slab of the tile (first tile axis fixed: 16 terms in 2-D, 64 in 3-D) is
+// summed in float32 and the slabs in float64, so that a tile partial carries
+// float32 rounding of short sums only; tile partials are summed in float64, in
+// tile order, by a second kernel.
 // Adjoint: one block per (tile, output channel, batch); each thread owns one
 // output voxel and accumulates sum_j sum_r K_cj(r) phi_j(x + r) with the
 // cotangent box K_cj read through uniform (scalar) loads.
@@ -85,7 +88,7 @@ struct DirFwdArgs {
     Soft soft;
     Geo g;
     const float *phi;   // level field [B][C][n..]
-    float *part;        // [B*npairs][ntiles][kmax]
+    double *part;       // [B*npairs][ntiles][kmax]
     int C, npairs;
     int pi[kMaxPairs], pj[kMaxPairs];
     int auto_mask;
@@ -144,31 +147,37 @@ __global__ __launch_bounds__(kT) void k_direct_fwd(DirFwdArgs a)
         r0 = (int)(bi / ((int64_t)g.box * g.box)) - g.P;
     }
     const int pz = (g.ndim == 3) ? r2 + g.P : 0;
-    float acc = 0.f;
+    double acc = 0.0;
     const float *hb = Hb + ((r0 + g.P) * g.h1 + (r1 + g.P)) * g.h2 + pz;
     if constexpr (TX > 0) {
 #pragma unroll
-        for (int x = 0; x < TX; ++x)
+        for (int x = 0; x < TX; ++x) {
+            float slab = 0.f;
 #pragma unroll
             for (int y = 0; y < TY; ++y) {
                 const float *arow = Ta + (x * TY + y) * TZ;
                 const float *brow = hb + (x * g.h1 + y) * g.h2;
 #pragma unroll
-                for (int z = 0; z < TZ; ++z) acc += pair_term<SOFT>(arow[z], brow[z], a.soft);
+                for (int z = 0; z < TZ; ++z) slab += pair_term<SOFT>(arow[z], brow[z], a.soft);
             }
+            acc += (double)slab;
+        }
     } else {
-        for (int x = 0; x < g.t0; ++x)
+        for (int x = 0; x < g.t0; ++x) {
+            float slab = 0.f;
             for (int y = 0; y < g.t1; ++y) {
                 const float *arow = Ta + (x * g.t1 + y) * g.t2;
                 const float *brow = hb + (x * g.h1 + y) * g.h2;
-                for (int z = 0; z < g.t2; ++z) acc += pair_term<SOFT>(arow[z], brow[z], a.soft);
+                for (int z = 0; z < g.t2; ++z) slab += pair_term<SOFT>(arow[z], brow[z], a.soft);
             }
+            acc += (double)slab;
+        }
     }
     a.part[((int64_t)bp * a.ntiles + tile) * a.kmax + k] = acc;
 }
 
 struct DirRedArgs {
-    const float *part;
+    const double *part;
     float *S;
     int npairs;
     int64_t ntiles, kmax, K;
@@ -191,8 +200,8 @@ __global__ __launch_bounds__(kT) void k_direct_reduce(DirRedArgs a)
     const int64_t b = bp / a.npairs;
     double s = 0.0;
     if (k < a.cnt[p]) {
-        const float *src = a.part + (int64_t)bp * a.ntiles * a.kmax + k;
-        for (int64_t t = grp; t < a.ntiles; t += kRedG) s += (double)src[t * a.kmax];
+        const double *src = a.part + (int64_t)bp * a.ntiles * a.kmax + k;
+        for (int64_t t = grp; t < a.ntiles; t += kRedG) s += src[t * a.kmax];
     }
     part[grp][kk] = s;
     __syncthreads();
@@ -352,7 +361,7 @@ hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S
     a.soft = make_soft(p);
     a.g = make_geo(p, l);
     a.phi = phi;
-    a.part = ws.at<float>(L.part);
+    a.part = ws.at<double>(L.part);
     a.C = p.C;
     a.npairs = p.npairs;
     a.N = L.N;
@@ -371,7 +380,7 @@ hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S
     const int tvol = a.g.t0 * a.g.t1 * a.g.t2;
     const size_t lds = (size_t)(tvol + a.g.h0 * a.g.h1 * a.g.h2) * sizeof(float);
     dim3 grid((unsigned)a.ntiles, (unsigned)((kmax + kT - 1) / kT), (unsigned)(p.B * p.npairs));
-    const double fbytes = (double)p.B * p.C * L.N * 4 + (double)p.B * p.npairs * a.ntiles * kmax * 4;
+    const double fbytes = (double)p.B * p.C * L.N * 4 + (double)p.B * p.npairs * a.ntiles * kmax * 8;
     const bool full2 = p.ndim == 2 && a.g.t0 == 16 && a.g.t1 == 16;
     const bool full3 = p.ndim == 3 && a.g.t0 == 4 && a.g.t1 == 8 && a.g.t2 == 8;
     const bool soft = p.desc != DMCR_DESC_S2;
@@ -400,7 +409,7 @@ hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S
     }
     r.invN = 1.0 / (double)L.N;
     dim3 rg((unsigned)((kmax + kRedK - 1) / kRedK), (unsigned)(p.B * p.npairs));
-    return launch("direct_reduce", (double)p.B * p.npairs * a.ntiles * kmax * 4, k_direct_reduce, rg, dim3(kT), 0,
+    return launch("direct_reduce", (double)p.B * p.npairs * a.ntiles * kmax * 8, k_direct_reduce, rg, dim3(kT), 0,
                   st, r);
 }
 

@@ -252,7 +252,7 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
         } else {
             int64_t kmax = 0;
             for (int q = 0; q < p.npairs; ++q) kmax = std::max(kmax, L.cnt[q]);
-            L.part = cv.take((size_t)B * p.npairs * L.n_tiles * kmax * sizeof(float));
+            L.part = cv.take((size_t)B * p.npairs * L.n_tiles * kmax * sizeof(double));
         }
     }
     if (p.s3)

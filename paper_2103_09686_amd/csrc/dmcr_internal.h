@@ -49,7 +49,7 @@ struct LevelPlan {
     size_t msum;       // FFT: float64 partial sums of every field [B][C][mparts]
     int64_t mparts;    // FFT: partial sums per field (fft_mean_parts)
     size_t mu;         // FFT: float64 field means [B][C]
-    size_t part;       // DIRECT: per-tile partial sums
+    size_t part;       // DIRECT: per-tile partial sums (float64)
     int64_t n_tiles;   // DIRECT: tiles per field
     int tile[3];       // DIRECT: tile edge per axis
     // three-point blocks (spec.s3_max_disp > 0)

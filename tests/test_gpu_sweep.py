@@ -117,10 +117,23 @@ def test_random_config_parity(dm, ora, case):
     E2, gl2 = dm.dmcr_loss_grad(spec, dphi, torch.from_numpy(St2).cuda())
     E2 = E2.cpu().numpy()
     gl2 = gl2.cpu().numpy().astype(np.float64)
+    w2Z = ora.level_weights_per_entry(ospec) ** 2 / ora.error_Z(ospec)
     for b in range(B):
-        Eo, gO, _ = ora.loss_grad(phi[b], St2[b], ospec)
-        assert abs(E2[b] - Eo) <= 1e-4 * abs(Eo), ("E, equal mean", b, E2[b], Eo)
-        assert np.linalg.norm(gl2[b] - gO) <= 1e-4 * np.linalg.norm(gO), ("loss gradient, equal mean", b)
+        Eo, gO, So = ora.loss_grad(phi[b], St2[b], ospec)
+        # The loss is formed from the float32 descriptor, whose own error against the
+        # oracle (measured above; half an ulp more in case the loss path rounds it
+        # differently) no longer cancels in S - S*: it moves E by up to
+        # sum w^2 (2 |S - S*| dS + dS^2) / Z and the cotangent by 2 w^2 dS / Z, which
+        # reaches the gradient through the Jacobian.  The fields are >= 0, so the
+        # Jacobian is >= 0 and the adjoint of that bound bounds the gradient's error
+        # element by element.  With a single displacement per level (no averaging of
+        # the roundings over many entries) these floors pass 1e-4 relative once the
+        # residual falls to about 1e-4 max|S|.
+        dS = np.abs(S[b] - So) + 2.0 ** -24 * np.abs(So)
+        gtol = 1e-4 * np.linalg.norm(gO) + np.linalg.norm(ora.adjoint(phi[b], 2.0 * w2Z * dS, ospec))
+        assert np.linalg.norm(gl2[b] - gO) <= gtol, ("loss gradient, equal mean", b)
+        tol = 1e-4 * abs(Eo) + np.sum(w2Z * (2.0 * np.abs(So - St2[b]) * dS + dS * dS))
+        assert abs(E2[b] - Eo) <= tol, ("E, equal mean", b, E2[b], Eo)
 
 
 KINDS = {0: "s2", 1: "sbar", 2: "stilde"}

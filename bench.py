@@ -51,10 +51,13 @@ WORKLOADS = {
                     shape=(256, 256), C=1, L=3, P=31, recompute=False, batch=8, s3=4),
 }
 
-# Three-point blocks are dense FP32 contractions done with FMA instructions:
-# the Gram product of the forward (N K3 multiply-adds, product form one more
-# multiply) and the M x M cotangent product of the adjoint (N M^2 multiply-adds).
-# Peak: 256 CUs * 4 SIMDs * 16 lanes * 2 flops * 2.4 GHz = 78.6 TFLOP/s (no packed FP32).
+# Three-point blocks are dense FP32 contractions: the Gram product of the forward
+# (N K3 multiply-adds, product form one more multiply) and the M x M cotangent
+# product of the adjoint (N M^2 multiply-adds).  On the matrix cores (kernels
+# named *_mf) the peak is MI355X's dense FP32 matrix rate, 157.3 TFLOP/s; the FMA
+# kernels of small levels run against 256 CUs * 4 SIMDs * 16 lanes * 2 flops *
+# 2.4 GHz = 78.6 TFLOP/s (no packed FP32).
+MFMA_F32_PEAK_TFLOPS = 157.3
 FMA_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 # Soft-threshold pair terms are bound by FP32 vector issue, not HBM.  A wave64
@@ -509,7 +512,7 @@ def main():
         roofline = dict(bound="alu", kernel=dom["name"], achieved=round(achieved, 1), peak=round(peak, 1),
                         unit="Gterm/s", frac=round(achieved / peak, 4), traffic=None,
                         avg_us=round(dom["avg_us"], 2), terms_per_launch=per_launch)
-    elif dom["name"].startswith(("s3_fwd", "s3_adj_terms")):
+    elif dom["name"].startswith(("s3_fwd", "s3_adj_terms", "s3_adj_mf")):
         d = len(shape)
         flops = 0.0
         for l in range(L):
@@ -522,8 +525,10 @@ def main():
                 flops += B * C * Nl * M * M * 2
         per_launch = flops / L
         achieved = per_launch / (dom["avg_us"] * 1e-6) / 1e12
-        roofline = dict(bound="alu", kernel=dom["name"], achieved=round(achieved, 2), peak=round(FMA_PEAK_TFLOPS, 1),
-                        unit="TFLOP/s", frac=round(achieved / FMA_PEAK_TFLOPS, 4), traffic=None,
+        mf = "_mf" in dom["name"]
+        peak = MFMA_F32_PEAK_TFLOPS if mf else FMA_PEAK_TFLOPS
+        roofline = dict(bound="mfma" if mf else "alu", kernel=dom["name"], achieved=round(achieved, 2),
+                        peak=round(peak, 1), unit="TFLOP/s", frac=round(achieved / peak, 4), traffic=None,
                         avg_us=round(dom["avg_us"], 2), flops_per_launch=per_launch)
     else:
         roofline = dict(bound="hbm", kernel=dom["name"], achieved=round(dom["GBps"], 1), peak=HBM_PEAK_GBS,

@@ -217,8 +217,7 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
     if (p.s3)
         for (int l = 0; l < p.L; ++l) {
             LevelPlan &L = p.lv[l];
-            if (!s3_supported(p, l, &L.s3VB, &L.s3VBa)) return DMCR_EUNSUPPORTED;
-            L.s3chunks = L.N / L.s3VB;
+            if (!s3_configure(p, l)) return DMCR_EUNSUPPORTED;
         }
     // workspace
     Carver cv;
@@ -260,8 +259,8 @@ dmcr_status make_plan(const dmcr_spec *s, int B, Plan *pp)
             LevelPlan &L = p.lv[l];
             L.s3part = cv.take((size_t)B * C * L.s3chunks * L.s3K * sizeof(float));
             L.s3Q = cv.take((size_t)B * C * L.s3M * L.N * sizeof(float));
-            L.s3G = cv.take((size_t)B * C * L.s3M * ((L.s3M + 3) / 4 * 4) * sizeof(float));
-            if (p.desc == DMCR_DESC_S2) L.s3R = cv.take((size_t)B * C * L.s3M * L.N * sizeof(float));
+            L.s3G = cv.take((size_t)B * C * L.s3Kp * L.s3Mp * sizeof(float));
+            if (p.desc == DMCR_DESC_S2 && !L.s3mf) L.s3R = cv.take((size_t)B * C * L.s3M * L.N * sizeof(float));
         }
     p.S = cv.take((size_t)B * p.K * sizeof(float));
     p.G = cv.take((size_t)B * p.K * sizeof(float));

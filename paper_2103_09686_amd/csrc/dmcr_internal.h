@@ -59,9 +59,13 @@ struct LevelPlan {
     int64_t s3off;     // descriptor offset of channel 0's block (channel c at s3off + c s3K)
     int s3VB, s3VBa;   // voxels per block of the forward and of the adjoint
     int64_t s3chunks;  // forward blocks per field and channel (N / s3VB)
+    int s3mf;          // contractions on matrix cores (else register-blocked FMA)
+    int s3bf[3];       // matrix cores: forward voxel box edge per axis (s3VB voxels)
+    int s3ba[3];       // matrix cores: adjoint voxel box edge per axis (s3VBa voxels)
+    int s3Kp, s3Mp;    // rows and columns of the expanded cotangent
     size_t s3part;     // [B][C][s3chunks][s3K] float partial sums
-    size_t s3Q, s3R;   // adjoint: [B][C][M][N] float per-vector terms (R: product form only)
-    size_t s3G;        // adjoint: [B][C][M][Mp] full symmetric cotangent (Mp = M rounded up to 4)
+    size_t s3Q, s3R;   // adjoint: [B][C][M][N] float per-vector terms (R: FMA product form only)
+    size_t s3G;        // adjoint: [B][C][s3Kp][s3Mp] full symmetric cotangent, zero padded
 };
 
 struct Plan {
@@ -194,7 +198,10 @@ hipError_t launch_stilde_adjoint(const Plan &p, const float *G_in, float *G_out,
 // level gradient written by the two-point adjoint).  The Appendix A map of the
 // three-point blocks (STILDE) in place on S, and its transpose in place on G
 // (run before launch_stilde_adjoint; it adds into the two-point cotangents).
-bool s3_supported(const Plan &p, int l, int *VB, int *VBa);
+// choose the contraction kernels of level l's three-point blocks (fills s3mf,
+// s3VB, s3VBa, s3bf, s3ba, s3Kp, s3Mp, s3chunks; none depends on the batch, so a
+// field's result does not either); false if unsupported
+bool s3_configure(Plan &p, int l);
 hipError_t s3_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws, hipStream_t st);
 hipError_t s3_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad, const Ws &ws,
                             hipStream_t st);

@@ -13,8 +13,21 @@
 //   product: Q_c(x) = w(x) D[x][c],  R_c(x) = E[x][c] D[x][c] / 2,
 //            grad(y) += sum_c R_c(y) + sum_c Q_c(y - r_c)
 // (the first sum is the start point x = y, the second the end point y = x + r_c).
-// Both contractions run register-blocked: each thread owns a 4 x 4 tile of the
-// output and reads two float4 per 16 multiply-adds.
+// Both contractions run on the FP32 matrix cores (v_mfma_f32_16x16x4f32) where
+// the level allows it (below); otherwise register-blocked, each thread owning a
+// 4 x 4 output tile and reading two float4 per 16 multiply-adds.
+//
+// Matrix-core forward: a block loads its box of voxels with a halo of P3 into
+// LDS; a realisation is one LDS read at the voxel's tile address plus the
+// offset of r_c (the soft threshold applied on the fly).  The Gram matrix is cut
+// into 16 x 16 tiles; a wave owns a super-tile of 6 x 6 of them (on the
+// diagonal only the upper triangle) and the four waves of the block split the
+// box's voxels, four per instruction; their accumulators are added in LDS in
+// wave order.  Matrix-core adjoint: D = E Gf / N for 64 voxels x 96 vectors per
+// wave and pass (16 tiles of 16 x 16, K = 4 vectors d per instruction), then Q
+// is stored and the local term (R for the product form, Q_c(y) for the soft
+// one) is summed over c in registers and added to the gradient directly, so
+// only the shifted sum sum_c Q_c(y - r_c) is left to the gather.
 #include <algorithm>
 
 #include "dmcr_internal.h"
@@ -199,24 +212,25 @@ struct S3AdjArgs {
     float *Gf;          // [B][C][M][Mp] full symmetric cotangent, diagonal doubled
     float *Q, *R;       // [B][C][M][N]
     float *grad;        // level gradient [B][C][N] (added to)
-    int C, VB, Mp;
+    int C, VB, Mp, Kp;
     int64_t Kstride, off;
     float invN;
 };
 
-// Gf[c][d] = G(min, max), doubled on the diagonal, zero in the padding columns
+// Gf[c][d] = G(min, max), doubled on the diagonal, zero in the padding rows
+// (c >= M, up to Kp) and columns (d >= M, up to Mp)
 __global__ __launch_bounds__(kT3) void k_s3_expand(S3AdjArgs a)
 {
     const S3Geo &g = a.g;
     const int ch = blockIdx.y;
     const int64_t b = blockIdx.z;
     const float *Gb = a.G + b * a.Kstride + a.off + ch * g.K3;
-    float *out = a.Gf + (b * a.C + ch) * (int64_t)g.M * a.Mp;
-    for (int64_t idx = (int64_t)blockIdx.x * kT3 + threadIdx.x; idx < (int64_t)g.M * a.Mp;
+    float *out = a.Gf + (b * a.C + ch) * (int64_t)a.Kp * a.Mp;
+    for (int64_t idx = (int64_t)blockIdx.x * kT3 + threadIdx.x; idx < (int64_t)a.Kp * a.Mp;
          idx += (int64_t)gridDim.x * kT3) {
         const int c = (int)(idx / a.Mp), d = (int)(idx % a.Mp);
         float v = 0.f;
-        if (d < g.M) {
+        if (c < g.M && d < g.M) {
             const int lo = c < d ? c : d, hi = c < d ? d : c;
             v = Gb[tri_row(lo, g.M) + (hi - lo)] * (c == d ? 2.f : 1.f);
         }
@@ -435,6 +449,331 @@ __global__ __launch_bounds__(kT3) void k_s3_map_adj_scale(S3MapArgs a)
     }
 }
 
+// ---- matrix-core contractions ------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kSup = 6;            // 16-wide vector tiles per super-tile side
+constexpr int kMfLds = 64 * 1024;  // dynamic LDS limit of one block
+
+struct S3MfArgs {
+    S3Geo g;
+    SoftC sc;
+    const float *phi;   // level field [B][C][N]
+    float *part;        // forward: [B][C][chunks][K3]
+    const float *Gf;    // adjoint: [B][C][Kp][Mp] expanded cotangent
+    float *Q;           // adjoint: [B][C][M][N]
+    float *grad;        // adjoint: level gradient [B][C][N] (added to)
+    int C;
+    int bd[3], lb[3];   // voxel box edge per axis and its log2
+    int nb[3];          // boxes per axis
+    int hl[3];          // halo per axis (P3 on the field's axes, 0 on the unit axis of 2-D)
+    int ed[3];          // LDS tile edge per axis, bd + 2 hl
+    int64_t chunks;     // boxes per field
+    int VB;             // voxels per box
+    int n16;            // 16-wide vector tiles, ceil(M / 16)
+    int nst;            // super-tile bands, ceil(n16 / kSup)
+    int Kp, Mp;         // rows (M rounded up to 4) and columns (16 n16) of Gf
+    float invN;
+};
+
+// LDS tile offset of displacement r_c
+__device__ __forceinline__ int mf_off(const S3MfArgs &a, int c)
+{
+    int c0, c1, c2;
+    vec_of(a.g, c, c0, c1, c2);
+    return (c0 * a.ed[1] + c1) * a.ed[2] + c2;
+}
+
+// box coordinates of box voxel v (box edges are powers of two)
+__device__ __forceinline__ void mf_coords(const S3MfArgs &a, int v, int &k0, int &k1, int &k2)
+{
+    k2 = v & (a.bd[2] - 1);
+    k1 = (v >> a.lb[2]) & (a.bd[1] - 1);
+    k0 = v >> (a.lb[1] + a.lb[2]);
+}
+
+// LDS tile address of box voxel v
+__device__ __forceinline__ int mf_base(const S3MfArgs &a, int v)
+{
+    int k0, k1, k2;
+    mf_coords(a, v, k0, k1, k2);
+    return ((k0 + a.hl[0]) * a.ed[1] + (k1 + a.hl[1])) * a.ed[2] + (k2 + a.hl[2]);
+}
+
+// field index of box voxel v of box `chunk`
+__device__ __forceinline__ int64_t mf_voxel(const S3MfArgs &a, int64_t chunk, int v)
+{
+    int k0, k1, k2;
+    mf_coords(a, v, k0, k1, k2);
+    const int64_t q2 = chunk % a.nb[2], q = chunk / a.nb[2];
+    const int64_t q1 = q % a.nb[1], q0 = q / a.nb[1];
+    return ((q0 * a.bd[0] + k0) * a.g.n1 + (q1 * a.bd[1] + k1)) * a.g.n2 + (q2 * a.bd[2] + k2);
+}
+
+// the box `chunk` of field f with its periodic halo into T
+__device__ __forceinline__ void mf_load_tile(const S3MfArgs &a, const float *__restrict__ f, int64_t chunk, float *T)
+{
+    const S3Geo &g = a.g;
+    const int64_t q2 = chunk % a.nb[2], q = chunk / a.nb[2];
+    const int o2 = (int)(q2 * a.bd[2]) - a.hl[2];
+    const int o1 = (int)((q % a.nb[1]) * a.bd[1]) - a.hl[1];
+    const int o0 = (int)((q / a.nb[1]) * a.bd[0]) - a.hl[0];
+    const int e12 = a.ed[1] * a.ed[2], tv = a.ed[0] * e12;
+    for (int idx = threadIdx.x; idx < tv; idx += blockDim.x) {
+        const int t0 = idx / e12, t1 = (idx / a.ed[2]) % a.ed[1], t2 = idx % a.ed[2];
+        const int y0 = (o0 + t0) & (g.n0 - 1), y1 = (o1 + t1) & (g.n1 - 1), y2 = (o2 + t2) & (g.n2 - 1);
+        T[idx] = f[((int64_t)y0 * g.n1 + y1) * g.n2 + y2];
+    }
+}
+
+// realisation at tile address `base` for displacement offset `off`
+template <bool SOFT>
+__device__ __forceinline__ float mf_real(const float *T, int base, int off, const SoftC &sc)
+{
+    const float fy = T[base + off];
+    if constexpr (SOFT)
+        return fmaf(sc.c1, soft_sig(0.5f * (T[base] + fy), sc), sc.c3);
+    else
+        return fy;
+}
+
+// Forward: block = (box, super-tile) x channel x field, four waves.  DIAG: the
+// super-tile on the diagonal (row band = column band, upper triangle of tiles).
+template <bool SOFT, bool DIAG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIAG ? 2 : 1))) void k_s3_fwd_mf(S3MfArgs a)
+{
+    extern __shared__ float4 sm4[];
+    const S3Geo &g = a.g;
+    const int nsup = DIAG ? a.nst : a.nst * (a.nst - 1) / 2;
+    const int64_t chunk = blockIdx.x / nsup;
+    int sup = (int)(blockIdx.x % nsup);
+    int ba = sup, bb = sup;
+    if constexpr (!DIAG) {   // off-diagonal super-tile (ba, bb), ba < bb, ba-major
+        ba = 0;
+        while (sup >= a.nst - 1 - ba) {
+            sup -= a.nst - 1 - ba;
+            ++ba;
+        }
+        bb = ba + 1 + sup;
+    }
+    const int ch = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    const int tv = a.ed[0] * a.ed[1] * a.ed[2];
+    float *T = reinterpret_cast<float *>(sm4);
+    f4 *red = reinterpret_cast<f4 *>(sm4 + (tv + 3) / 4);
+    mf_load_tile(a, a.phi + (b * a.C + ch) * g.N, chunk, T);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ta0 = ba * kSup, tb0 = bb * kSup;   // first 16-wide tile of each band
+    int offA[kSup], offB[kSup];
+    bool okA[kSup], okB[kSup];
+#pragma unroll
+    for (int i = 0; i < kSup; ++i) {
+        const int ca = 16 * (ta0 + i) + (lane & 15), cb = 16 * (tb0 + i) + (lane & 15);
+        okA[i] = ca < g.M;
+        okB[i] = cb < g.M;
+        offA[i] = okA[i] ? mf_off(a, ca) : 0;
+        offB[i] = okB[i] ? mf_off(a, cb) : 0;
+    }
+    f4 acc[kSup][kSup];
+#pragma unroll
+    for (int i = 0; i < kSup; ++i)
+#pragma unroll
+        for (int j = 0; j < kSup; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // A[i][k] = w(x_k) E[x_k][row i], B[k][j] = E[x_k][column j]; lane supplies
+    // row/column (lane & 15) of voxel k = lane >> 4
+    const int vw = a.VB / 4;
+    for (int v = wave * vw + (lane >> 4); v < (wave + 1) * vw; v += 4) {
+        const int base = mf_base(a, v);
+        const float w = SOFT ? 1.f : T[base];
+        float ea[kSup], eb[kSup];
+#pragma unroll
+        for (int i = 0; i < kSup; ++i) ea[i] = okA[i] ? mf_real<SOFT>(T, base, offA[i], a.sc) : 0.f;
+        if constexpr (!DIAG) {
+#pragma unroll
+            for (int j = 0; j < kSup; ++j) eb[j] = okB[j] ? mf_real<SOFT>(T, base, offB[j], a.sc) : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < kSup; ++i) {
+            if (ta0 + i >= a.n16) continue;
+            const float av = w * ea[i];
+#pragma unroll
+            for (int j = DIAG ? i : 0; j < kSup; ++j) {
+                if (tb0 + j >= a.n16) continue;
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, DIAG ? ea[j] : eb[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+
+    // waves 0..3 add their accumulators in LDS in wave order; wave 3 holds the sum
+#pragma unroll 1
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+            int t = 0;
+#pragma unroll
+            for (int i = 0; i < kSup; ++i)
+#pragma unroll
+                for (int j = DIAG ? i : 0; j < kSup; ++j, ++t) {
+                    f4 v = acc[i][j];
+                    if (w > 0) v += red[t * 64 + lane];
+                    if (w < 3)
+                        red[t * 64 + lane] = v;
+                    else
+                        acc[i][j] = v;
+                }
+        }
+        __syncthreads();
+    }
+    if (wave != 3) return;
+    float *out = a.part + ((b * a.C + ch) * a.chunks + chunk) * g.K3;
+#pragma unroll
+    for (int i = 0; i < kSup; ++i)
+#pragma unroll
+        for (int j = DIAG ? i : 0; j < kSup; ++j) {
+            const int ib = 16 * (tb0 + j) + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ia = 16 * (ta0 + i) + 4 * (lane >> 4) + r;
+                if (ia <= ib && ib < g.M) out[tri_row(ia, g.M) + (ib - ia)] = acc[i][j][r];
+            }
+        }
+}
+
+// Adjoint: block = box x channel x field, nw waves; a wave takes 64 voxels of
+// the box at a time (four 16-voxel tiles) and the vectors in passes of kSup
+// 16-wide tiles.
+template <bool SOFT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_s3_adj_mf(S3MfArgs a)
+{
+    extern __shared__ float4 sm4[];
+    const S3Geo &g = a.g;
+    const int64_t chunk = blockIdx.x;
+    const int ch = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    const int tv = a.ed[0] * a.ed[1] * a.ed[2];
+    float *T = reinterpret_cast<float *>(sm4);
+    int *offs = reinterpret_cast<int *>(T + tv);   // [Kp] tile offset of r_d (0 past M)
+    const int64_t bc = b * a.C + ch;
+    mf_load_tile(a, a.phi + bc * g.N, chunk, T);
+    for (int d = threadIdx.x; d < a.Kp; d += blockDim.x) offs[d] = d < g.M ? mf_off(a, d) : 0;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const float *Gf = a.Gf + bc * (int64_t)a.Kp * a.Mp;
+    float *Q = a.Q + bc * (int64_t)g.M * g.N;
+    const float hq = 0.5f * a.sc.c1 * a.sc.alpha;
+    for (int grp = wave; grp < a.VB / 64; grp += nw) {
+        const int v0 = grp * 64;
+        int baseA[4];   // voxel of this lane's A rows: v0 + 16 i + (lane & 15)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) baseA[i] = mf_base(a, v0 + 16 * i + (lane & 15));
+        float loc[4][4];   // local term of output voxel v0 + 16 i + 4 (lane >> 4) + r, this lane's columns
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) loc[i][r] = 0.f;
+        for (int cg = 0; cg * kSup < a.n16; ++cg) {
+            f4 acc[4][kSup];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < kSup; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int d0 = 0; d0 < a.Kp; d0 += 4) {
+                const int d = d0 + (lane >> 4);
+                const bool dok = d < g.M;
+                const int od = offs[d];
+                float av[4], bv[kSup];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) av[i] = dok ? mf_real<SOFT>(T, baseA[i], od, a.sc) : 0.f;
+#pragma unroll
+                for (int j = 0; j < kSup; ++j)
+                    bv[j] = (cg * kSup + j < a.n16) ? Gf[(int64_t)d * a.Mp + 16 * (cg * kSup + j) + (lane & 15)] : 0.f;
+#pragma unroll
+                for (int j = 0; j < kSup; ++j) {
+                    if (cg * kSup + j >= a.n16) continue;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                }
+            }
+            // D[x][c] = acc / N for x = v0 + 16 i + 4 (lane >> 4) + r, c = 16 (cg kSup + j) + (lane & 15)
+#pragma unroll
+            for (int j = 0; j < kSup; ++j) {
+                const int c = 16 * (cg * kSup + j) + (lane & 15);
+                if (cg * kSup + j >= a.n16 || c >= g.M) continue;
+                const int oc = offs[c];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int vq = v0 + 16 * i + 4 * (lane >> 4);
+                    f4 q;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int base = mf_base(a, vq + r);
+                        const float D = acc[i][j][r] * a.invN;
+                        if constexpr (SOFT) {
+                            const float sg = soft_sig(0.5f * (T[base] + T[base + oc]), a.sc);
+                            q[r] = hq * sg * (1.f - sg) * D;
+                            loc[i][r] += q[r];
+                        } else {
+                            q[r] = T[base] * D;
+                            loc[i][r] += 0.5f * T[base + oc] * D;
+                        }
+                    }
+                    *reinterpret_cast<f4 *>(Q + (int64_t)c * g.N + mf_voxel(a, chunk, vq)) = q;
+                }
+            }
+        }
+        // sum the local terms over the 16 lanes (columns) of each row group; lane
+        // (lane & 15) = 4 i + r then adds voxel (i, r) of its row group
+        float mine = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float s = loc[i][r];
+                s += __shfl_xor(s, 1);
+                s += __shfl_xor(s, 2);
+                s += __shfl_xor(s, 4);
+                s += __shfl_xor(s, 8);
+                if ((lane & 15) == 4 * i + r) mine = s;
+            }
+        const int vm = v0 + 16 * ((lane & 15) >> 2) + 4 * (lane >> 4) + (lane & 3);
+        a.grad[bc * g.N + mf_voxel(a, chunk, vm)] += mine;
+    }
+}
+
+// grad(y) += sum_c Q_c(y - r_c) (the matrix-core adjoint added the local term)
+__global__ __launch_bounds__(kT3) void k_s3_adj_shift(S3MfArgs a)
+{
+    __shared__ int3 rv[361];
+    const S3Geo &g = a.g;
+    const int ch = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    for (int c = threadIdx.x; c < g.M; c += kT3) {
+        int c0, c1, c2;
+        vec_of(g, c, c0, c1, c2);
+        rv[c] = int3{c0, c1, c2};
+    }
+    __syncthreads();
+    const int64_t y = (int64_t)blockIdx.x * kT3 + threadIdx.x;
+    if (y >= g.N) return;
+    const int i2 = (int)(y % g.n2);
+    const int i1 = (int)((y / g.n2) % g.n1);
+    const int i0 = (int)(y / ((int64_t)g.n1 * g.n2));
+    const int64_t bc = b * a.C + ch;
+    const float *Qb = a.Q + bc * g.M * g.N;
+    float acc = 0.f;
+    for (int c = 0; c < g.M; ++c) {
+        const int3 r = rv[c];
+        const int64_t x = ((int64_t)((i0 - r.x) & (g.n0 - 1)) * g.n1 + ((i1 - r.y) & (g.n1 - 1))) * g.n2 +
+                          ((i2 - r.z) & (g.n2 - 1));
+        acc += Qb[(int64_t)c * g.N + x];
+    }
+    a.grad[bc * g.N + y] += acc;
+}
+
 S3Geo make_s3geo(const Plan &p, int l)
 {
     const LevelPlan &L = p.lv[l];
@@ -482,24 +821,210 @@ S3MapArgs map_args(const Plan &p, float *S)
 // Mp = M rounded up to a multiple of 4 (the register tiles)
 int s3_Mp(int M) { return (M + 3) / 4 * 4; }
 
-bool s3_supported(const Plan &p, int l, int *VB, int *VBa)
+namespace {
+
+int ilog2(int v)
+{
+    int k = 0;
+    while ((1 << (k + 1)) <= v) ++k;
+    return k;
+}
+
+// box of VB voxels: powers of two dealt out one bit at a time from the innermost
+// axis outwards, never beyond an axis' length; false if VB does not fit the level
+bool s3_box(const Plan &p, int l, int VB, int bd[3])
 {
     const LevelPlan &L = p.lv[l];
-    const int64_t M = L.s3M, Mp = s3_Mp(L.s3M);
+    const int n[3] = {L.n[0], L.n[1], p.ndim == 3 ? L.n[2] : 1};
+    bd[0] = bd[1] = bd[2] = 1;
+    int rem = ilog2(VB);
+    const int order3[3] = {2, 1, 0}, order2[2] = {1, 0};
+    const int *order = p.ndim == 3 ? order3 : order2;
+    while (rem > 0) {
+        bool grew = false;
+        for (int t = 0; t < p.ndim && rem > 0; ++t) {
+            const int ax = order[t];
+            if (2 * bd[ax] <= n[ax]) {
+                bd[ax] *= 2;
+                --rem;
+                grew = true;
+            }
+        }
+        if (!grew) return false;
+    }
+    return true;
+}
+
+int tile_floats(const Plan &p, int l, const int bd[3])
+{
+    const int P3 = p.lv[l].s3P;
+    int v = 1;
+    for (int ax = 0; ax < 3; ++ax) v *= bd[ax] + ((ax < p.ndim && (p.ndim == 3 || ax < 2)) ? 2 * P3 : 0);
+    return v;
+}
+
+size_t fwd_mf_lds(int tv, bool diag) { return (size_t)(tv + 3) / 4 * 16 + (size_t)(diag ? kSup * (kSup + 1) / 2 : kSup * kSup) * 64 * 16; }
+size_t adj_mf_lds(int tv, int Kp) { return (size_t)tv * 4 + (size_t)Kp * 4; }
+
+}  // namespace
+
+// Matrix cores when every voxel box is whole (N >= 64) and the innermost axis
+// holds the adjoint's four-voxel stores (length >= 4); the box takes N / 128
+// voxels, clamped to [64, 1024], for the forward and the adjoint alike, so a
+// field's blocks and sums do not depend on the batch.
+bool s3_configure(Plan &p, int l)
+{
+    LevelPlan &L = p.lv[l];
+    const int M = L.s3M;
     if (M > 361) return false;   // 2-D P3 <= 9, 3-D P3 <= 3
+    const int inner = L.n[p.ndim - 1];
+    L.s3mf = 0;
+    if (L.N >= 64 && inner >= 4) {
+        int VB = 64;
+        while (VB < 1024 && (int64_t)VB * 2 <= L.N / 128) VB *= 2;
+        int bd[3];
+        const int n16 = (M + 15) / 16;
+        const int Kp = (M + 3) / 4 * 4;
+        if (s3_box(p, l, VB, bd) && bd[p.ndim == 3 ? 2 : 1] >= 4) {
+            const int tv = tile_floats(p, l, bd);
+            if (fwd_mf_lds(tv, false) <= (size_t)kMfLds && adj_mf_lds(tv, Kp) <= (size_t)kMfLds) {
+                L.s3mf = 1;
+                L.s3VB = L.s3VBa = VB;
+                for (int ax = 0; ax < 3; ++ax) L.s3bf[ax] = L.s3ba[ax] = bd[ax];
+                L.s3Kp = Kp;
+                L.s3Mp = 16 * n16;
+                L.s3chunks = L.N / VB;
+                return true;
+            }
+        }
+    }
+    const int64_t Mp = s3_Mp(M);
     int vb = 128, vba = 64;
     while (vb > 4 && ((size_t)(vb * Mp + vb) * sizeof(float) > kS3Lds || vb > L.N)) vb /= 2;
     while (vba > 4 && ((size_t)(vba * M) * sizeof(float) > kS3Lds || vba > L.N)) vba /= 2;
     if ((size_t)(vb * Mp + vb) * sizeof(float) > kS3Lds || (size_t)(vba * M) * sizeof(float) > kS3Lds) return false;
     if (vb < 4 || vba < 4 || L.N % vb || L.N % vba) return false;   // whole 4-voxel tiles
-    *VB = vb;
-    *VBa = vba;
+    L.s3VB = vb;
+    L.s3VBa = vba;
+    L.s3Kp = M;
+    L.s3Mp = (int)Mp;
+    L.s3chunks = L.N / vb;
     return true;
 }
+
+namespace {
+
+S3MfArgs mf_args(const Plan &p, int l, const int bd[3])
+{
+    const LevelPlan &L = p.lv[l];
+    S3MfArgs a{};
+    a.g = make_s3geo(p, l);
+    a.sc = make_softc(p);
+    a.C = p.C;
+    const int n[3] = {a.g.n0, a.g.n1, a.g.n2};
+    a.VB = 1;
+    for (int ax = 0; ax < 3; ++ax) {
+        a.bd[ax] = bd[ax];
+        a.lb[ax] = ilog2(bd[ax]);
+        a.nb[ax] = n[ax] / bd[ax];
+        a.hl[ax] = (p.ndim == 3 || ax < 2) ? L.s3P : 0;
+        a.ed[ax] = bd[ax] + 2 * a.hl[ax];
+        a.VB *= bd[ax];
+    }
+    a.chunks = L.N / a.VB;
+    a.n16 = (L.s3M + 15) / 16;
+    a.nst = (a.n16 + kSup - 1) / kSup;
+    a.Kp = L.s3Kp;
+    a.Mp = L.s3Mp;
+    a.invN = (float)(1.0 / (double)L.N);
+    return a;
+}
+
+hipError_t s3_reduce_level(const Plan &p, int l, const float *part, float *S, hipStream_t st)
+{
+    const LevelPlan &L = p.lv[l];
+    S3RedArgs r{};
+    r.part = part;
+    r.S = S;
+    r.C = p.C;
+    r.chunks = L.s3chunks;
+    r.K3 = L.s3K;
+    r.Kstride = p.K;
+    r.off = L.s3off;
+    r.invN = 1.0 / (double)L.N;
+    const dim3 rg((unsigned)((L.s3K + kRK - 1) / kRK), (unsigned)p.C, (unsigned)p.B);
+    return launch("s3_reduce", (double)p.B * p.C * L.s3chunks * L.s3K * 4, k_s3_reduce, rg, dim3(kT3), 0, st, r);
+}
+
+hipError_t s3_forward_mf(const Plan &p, int l, const float *phi, float *S, const Ws &ws, hipStream_t st)
+{
+    const LevelPlan &L = p.lv[l];
+    S3MfArgs a = mf_args(p, l, L.s3bf);
+    a.phi = phi;
+    a.part = ws.at<float>(L.s3part);
+    const bool soft = p.desc != DMCR_DESC_S2;
+    const int tv = a.ed[0] * a.ed[1] * a.ed[2];
+    const double bytes = (double)p.B * p.C * (L.N * 4 + a.chunks * L.s3K * 4);
+    const dim3 gd((unsigned)(a.chunks * a.nst), (unsigned)p.C, (unsigned)p.B);
+    hipError_t e = soft ? launch("s3_fwd_mf_soft", bytes, k_s3_fwd_mf<true, true>, gd, dim3(256), fwd_mf_lds(tv, true),
+                                 st, a)
+                        : launch("s3_fwd_mf", bytes, k_s3_fwd_mf<false, true>, gd, dim3(256), fwd_mf_lds(tv, true),
+                                 st, a);
+    if (e != hipSuccess) return e;
+    if (a.nst > 1) {
+        const dim3 go((unsigned)(a.chunks * (a.nst * (a.nst - 1) / 2)), (unsigned)p.C, (unsigned)p.B);
+        e = soft ? launch("s3_fwd_mf_soft_off", 0.0, k_s3_fwd_mf<true, false>, go, dim3(256), fwd_mf_lds(tv, false), st,
+                          a)
+                 : launch("s3_fwd_mf_off", 0.0, k_s3_fwd_mf<false, false>, go, dim3(256), fwd_mf_lds(tv, false), st, a);
+        if (e != hipSuccess) return e;
+    }
+    return s3_reduce_level(p, l, a.part, S, st);
+}
+
+hipError_t s3_adjoint_mf(const Plan &p, int l, const float *phi, const float *G, float *grad, const Ws &ws,
+                         hipStream_t st)
+{
+    const LevelPlan &L = p.lv[l];
+    S3MfArgs a = mf_args(p, l, L.s3ba);
+    a.phi = phi;
+    a.Gf = ws.at<float>(L.s3G);
+    a.Q = ws.at<float>(L.s3Q);
+    a.grad = grad;
+    // the expanded cotangent, as for the FMA kernels but with Kp rows and Mp columns
+    S3AdjArgs x{};
+    x.g = a.g;
+    x.G = G;
+    x.Gf = ws.at<float>(L.s3G);
+    x.C = p.C;
+    x.Mp = L.s3Mp;
+    x.Kp = L.s3Kp;
+    x.Kstride = p.K;
+    x.off = L.s3off;
+    const int64_t gfn = (int64_t)L.s3Kp * L.s3Mp;
+    const dim3 eg((unsigned)std::min<int64_t>(64, (gfn + kT3 - 1) / kT3), (unsigned)p.C, (unsigned)p.B);
+    hipError_t e = launch("s3_expand", (double)p.B * p.C * (L.s3K + (double)gfn) * 4, k_s3_expand, eg, dim3(kT3), 0,
+                          st, x);
+    if (e != hipSuccess) return e;
+    const bool soft = p.desc != DMCR_DESC_S2;
+    const int tv = a.ed[0] * a.ed[1] * a.ed[2];
+    const int nw = std::min(4, a.VB / 64);
+    const dim3 grid((unsigned)a.chunks, (unsigned)p.C, (unsigned)p.B);
+    const size_t lds = adj_mf_lds(tv, a.Kp);
+    const double qbytes = (double)p.B * p.C * (L.s3M * (double)L.N * 4 + L.N * 12.0);
+    e = soft ? launch("s3_adj_mf_soft", qbytes, k_s3_adj_mf<true>, grid, dim3(64 * nw), lds, st, a)
+             : launch("s3_adj_mf", qbytes, k_s3_adj_mf<false>, grid, dim3(64 * nw), lds, st, a);
+    if (e != hipSuccess) return e;
+    const dim3 gg((unsigned)((L.N + kT3 - 1) / kT3), (unsigned)p.C, (unsigned)p.B);
+    return launch("s3_adj_shift", (double)p.B * p.C * (L.s3M * (double)L.N * 4 + L.N * 8.0), k_s3_adj_shift, gg,
+                  dim3(kT3), 0, st, a);
+}
+
+}  // namespace
 
 hipError_t s3_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws, hipStream_t st)
 {
     const LevelPlan &L = p.lv[l];
+    if (L.s3mf) return s3_forward_mf(p, l, phi, S, ws, st);
     S3FwdArgs a{};
     a.g = make_s3geo(p, l);
     a.sc = make_softc(p);
@@ -516,23 +1041,14 @@ hipError_t s3_forward_level(const Plan &p, int l, const float *phi, float *S, co
                        ? launch("s3_fwd", bytes, k_s3_fwd<false>, grid, dim3(kT3), lds, st, a)
                        : launch("s3_fwd_soft", bytes, k_s3_fwd<true>, grid, dim3(kT3), lds, st, a);
     if (e != hipSuccess) return e;
-    S3RedArgs r{};
-    r.part = a.part;
-    r.S = S;
-    r.C = p.C;
-    r.chunks = a.chunks;
-    r.K3 = L.s3K;
-    r.Kstride = p.K;
-    r.off = L.s3off;
-    r.invN = 1.0 / (double)L.N;
-    const dim3 rg((unsigned)((L.s3K + kRK - 1) / kRK), (unsigned)p.C, (unsigned)p.B);
-    return launch("s3_reduce", (double)p.B * p.C * a.chunks * L.s3K * 4, k_s3_reduce, rg, dim3(kT3), 0, st, r);
+    return s3_reduce_level(p, l, a.part, S, st);
 }
 
 hipError_t s3_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad, const Ws &ws,
                             hipStream_t st)
 {
     const LevelPlan &L = p.lv[l];
+    if (L.s3mf) return s3_adjoint_mf(p, l, phi, G, grad, ws, st);
     S3AdjArgs a{};
     a.g = make_s3geo(p, l);
     a.sc = make_softc(p);
@@ -545,6 +1061,7 @@ hipError_t s3_adjoint_level(const Plan &p, int l, const float *phi, const float 
     a.C = p.C;
     a.VB = L.s3VBa;
     a.Mp = s3_Mp(L.s3M);
+    a.Kp = L.s3M;
     a.Kstride = p.K;
     a.off = L.s3off;
     a.invN = (float)(1.0 / (double)L.N);

@@ -57,6 +57,11 @@ CASES = [
     ((16, 8, 16), 2, 1, (2,), 1, 1, 0),
     ((16, 8, 16), 2, 1, (2,), 1, 2, 0),
     ((8, 8), 1, 2, (2, 1), 1, 1, 0),
+    # 169 and 343 vectors: Gram tiles beyond one 96 x 96 super-tile
+    ((64, 64), 1, 1, (12,), 6, 0, 0),
+    ((64, 64), 2, 1, (12,), 6, 1, 0),
+    ((64, 64), 1, 1, (12,), 6, 2, 0),
+    ((16, 16, 16), 1, 1, (3,), 3, 0, 1),
 ]
 
 
@@ -73,6 +78,10 @@ def test_s3_forward_adjoint_parity(dm, ora, case):
     rng = np.random.default_rng(9)
     dS = f32(rng.standard_normal((B, ospec.K)))
     g = dm.dmcr_descriptor_adjoint(spec, dphi, to_dev(dS)).cpu().numpy().astype(np.float64)
+    # a field's result does not depend on the batch it is evaluated in
+    S1 = dm.dmcr_descriptor_forward(spec, dphi[1:2].contiguous()).cpu().numpy().astype(np.float64)
+    g1 = dm.dmcr_descriptor_adjoint(spec, dphi[1:2].contiguous(), to_dev(dS[1:2])).cpu().numpy().astype(np.float64)
+    assert np.array_equal(S1[0], S[1]) and np.array_equal(g1[0], g[1])
     for b in range(B):
         check_blocks(S[b], ora.descriptor(phi[b], ospec), ospec, "fwd b=%d" % b)
         check_grad(g[b], ora.adjoint(phi[b], dS[b], ospec), "adj b=%d" % b)

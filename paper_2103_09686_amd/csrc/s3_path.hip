@@ -460,7 +460,9 @@ struct S3MfArgs {
     SoftC sc;
     const float *phi;   // level field [B][C][N]
     float *part;        // forward: [B][C][chunks][K3]
-    const float *Gf;    // adjoint: [B][C][Kp][Mp] expanded cotangent
+    const float *Gf;    // adjoint: [B][C][Kp][Mp] expanded cotangent (when it is not built in LDS)
+    const float *G;     // adjoint: packed cotangent [B][Kstride], the block at off + channel K3
+    int64_t Kstride, off;
     float *Q;           // adjoint: [B][C][M][N]
     float *grad;        // adjoint: level gradient [B][C][N] (added to)
     int C;
@@ -473,6 +475,7 @@ struct S3MfArgs {
     int n16;            // 16-wide vector tiles, ceil(M / 16)
     int nst;            // super-tile bands, ceil(n16 / kSup)
     int Kp, Mp;         // rows (M rounded up to 4) and columns (16 n16) of Gf
+    int gs;             // row stride of Gf's copy in LDS (16 mod 32: the four rows of a read hit disjoint banks)
     float invN;
 };
 
@@ -510,7 +513,9 @@ __device__ __forceinline__ int64_t mf_voxel(const S3MfArgs &a, int64_t chunk, in
     return ((q0 * a.bd[0] + k0) * a.g.n1 + (q1 * a.bd[1] + k1)) * a.g.n2 + (q2 * a.bd[2] + k2);
 }
 
-// the box `chunk` of field f with its periodic halo into T
+// the box `chunk` of field f with its periodic halo into T, a row of the
+// innermost axis per wave and pass (2-D: axis 1, 3-D: axis 2), and the zero
+// cell T[tv]
 __device__ __forceinline__ void mf_load_tile(const S3MfArgs &a, const float *__restrict__ f, int64_t chunk, float *T)
 {
     const S3Geo &g = a.g;
@@ -518,27 +523,150 @@ __device__ __forceinline__ void mf_load_tile(const S3MfArgs &a, const float *__r
     const int o2 = (int)(q2 * a.bd[2]) - a.hl[2];
     const int o1 = (int)((q % a.nb[1]) * a.bd[1]) - a.hl[1];
     const int o0 = (int)((q / a.nb[1]) * a.bd[0]) - a.hl[0];
-    const int e12 = a.ed[1] * a.ed[2], tv = a.ed[0] * e12;
-    for (int idx = threadIdx.x; idx < tv; idx += blockDim.x) {
-        const int t0 = idx / e12, t1 = (idx / a.ed[2]) % a.ed[1], t2 = idx % a.ed[2];
-        const int y0 = (o0 + t0) & (g.n0 - 1), y1 = (o1 + t1) & (g.n1 - 1), y2 = (o2 + t2) & (g.n2 - 1);
-        T[idx] = f[((int64_t)y0 * g.n1 + y1) * g.n2 + y2];
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const bool three = g.ndim == 3;
+    const int rl = three ? a.ed[2] : a.ed[1];                 // row length
+    const int nrows = three ? a.ed[0] * a.ed[1] : a.ed[0];
+    for (int row = threadIdx.x >> 6; row < nrows; row += nw) {
+        const int t0 = three ? row / a.ed[1] : row;
+        const int t1 = three ? row - t0 * a.ed[1] : 0;
+        const int64_t rbase = three ? ((int64_t)((o0 + t0) & (g.n0 - 1)) * g.n1 + ((o1 + t1) & (g.n1 - 1))) * g.n2
+                                    : (int64_t)((o0 + t0) & (g.n0 - 1)) * g.n1;
+        const int oi = three ? o2 : o1;
+        const int ni = three ? g.n2 : g.n1;
+        for (int t = lane; t < rl; t += 64) T[row * rl + t] = f[rbase + ((oi + t) & (ni - 1))];
     }
+    if (threadIdx.x == 0) T[a.ed[0] * a.ed[1] * a.ed[2]] = 0.f;   // read in place of the padding vectors past M
 }
 
-// realisation at tile address `base` for displacement offset `off`
+// realisation from the raw tile values phi(x) and phi(x + r_c); m = 1 for a
+// vector of the box, 0 for the padding past M (whose phi(x + r_c) is read from
+// the zero cell)
 template <bool SOFT>
-__device__ __forceinline__ float mf_real(const float *T, int base, int off, const SoftC &sc)
+__device__ __forceinline__ float mf_real(float fx, float fy, float m, const SoftC &sc)
 {
-    const float fy = T[base + off];
     if constexpr (SOFT)
-        return fmaf(sc.c1, soft_sig(0.5f * (T[base] + fy), sc), sc.c3);
+        return m * fmaf(sc.c1, soft_sig(0.5f * (fx + fy), sc), sc.c3);
     else
         return fy;
 }
 
+// One super-tile of the forward: NA row tiles from ta0, NB column tiles from tb0
+// (DIAG: the same tiles, upper triangle).  The four waves take a quarter of the
+// box's voxels each, four per instruction.  A step reads the raw tile values of
+// the next four voxels (padding lanes read the zero cell) and then runs the
+// current products, so the reads complete under them; then the accumulators of
+// the waves are added in LDS in wave order and wave 3 writes the block's
+// partial Gram entries.
+template <bool SOFT, bool DIAG, int NA, int NB>
+__device__ __forceinline__ void fwd_super(const S3MfArgs &a, const float *T, f4 *red, int ta0, int tb0, float *out)
+{
+    const S3Geo &g = a.g;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int zero = a.ed[0] * a.ed[1] * a.ed[2];
+    int offA[NA], offB[NB];
+    bool okA[NA], okB[NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int c = 16 * (ta0 + i) + (lane & 15);
+        okA[i] = c < g.M;
+        offA[i] = okA[i] ? mf_off(a, c) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int c = 16 * (tb0 + j) + (lane & 15);
+        okB[j] = c < g.M;
+        offB[j] = okB[j] ? mf_off(a, c) : 0;
+    }
+    f4 acc[NA][NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // A[i][k] = w(x_k) E[x_k][row i], B[k][j] = E[x_k][column j]: the lane supplies
+    // row/column (lane & 15) of voxel k = lane >> 4 of each group of four
+    const int vw = a.VB / 4, steps = vw / 4;
+    const int v0 = wave * vw + (lane >> 4);
+    float fx, ya[NA], yb[NB];   // raw phi(x), phi(x + r_a), phi(x + r_b)
+    auto fetch = [&](int v, float &fx_, float (&ya_)[NA], float (&yb_)[NB]) {
+        const int base = mf_base(a, v);
+        fx_ = T[base];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) ya_[i] = T[okA[i] ? base + offA[i] : zero];
+        if constexpr (!DIAG) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) yb_[j] = T[okB[j] ? base + offB[j] : zero];
+        }
+    };
+    fetch(v0, fx, ya, yb);
+    for (int s = 0; s < steps; ++s) {
+        // the last step reads its own voxels again: no branch around the reads
+        float fxn, yan[NA], ybn[NB];
+        fetch(v0 + 4 * min(s + 1, steps - 1), fxn, yan, ybn);
+        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
+        const float w = SOFT ? 1.f : fx;
+        float ea[NA], eb[NB];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) ea[i] = mf_real<SOFT>(fx, ya[i], okA[i] ? 1.f : 0.f, a.sc);
+        if constexpr (!DIAG) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) eb[j] = mf_real<SOFT>(fx, yb[j], okB[j] ? 1.f : 0.f, a.sc);
+        }
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const float av = w * ea[i];
+#pragma unroll
+            for (int j = DIAG ? i : 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, DIAG ? ea[j] : eb[j], acc[i][j], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        fx = fxn;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) ya[i] = yan[i];
+        if constexpr (!DIAG) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) yb[j] = ybn[j];
+        }
+    }
+
+    // the waves' accumulators are added in LDS in wave order; then every wave
+    // writes a quarter of the tiles
+#pragma unroll 1
+    for (int wv = 0; wv < 4; ++wv) {
+        if (wave == wv) {
+            int t = 0;
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int j = DIAG ? i : 0; j < NB; ++j, ++t) {
+                    f4 v = acc[i][j];
+                    if (wv > 0) v += red[t * 64 + lane];
+                    red[t * 64 + lane] = v;
+                }
+        }
+        __syncthreads();
+    }
+    int t = 0;
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int j = DIAG ? i : 0; j < NB; ++j, ++t) {
+            if ((t & 3) != wave) continue;
+            const f4 v = red[t * 64 + lane];
+            const int ib = 16 * (tb0 + j) + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ia = 16 * (ta0 + i) + 4 * (lane >> 4) + r;
+                if (ia <= ib && ib < g.M) out[tri_row(ia, g.M) + (ib - ia)] = v[r];
+            }
+        }
+}
+
 // Forward: block = (box, super-tile) x channel x field, four waves.  DIAG: the
-// super-tile on the diagonal (row band = column band, upper triangle of tiles).
+// super-tiles on the diagonal (row band = column band); else those above it,
+// whose row band is always whole.  The valid column tiles of the band select a
+// fully unrolled body.
 template <bool SOFT, bool DIAG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIAG ? 2 : 1))) void k_s3_fwd_mf(S3MfArgs a)
 {
@@ -560,91 +688,114 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIAG ? 2 : 
     const int64_t b = blockIdx.z;
     const int tv = a.ed[0] * a.ed[1] * a.ed[2];
     float *T = reinterpret_cast<float *>(sm4);
-    f4 *red = reinterpret_cast<f4 *>(sm4 + (tv + 3) / 4);
+    f4 *red = reinterpret_cast<f4 *>(sm4 + (tv + 4) / 4);
     mf_load_tile(a, a.phi + (b * a.C + ch) * g.N, chunk, T);
     __syncthreads();
-
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ta0 = ba * kSup, tb0 = bb * kSup;   // first 16-wide tile of each band
-    int offA[kSup], offB[kSup];
-    bool okA[kSup], okB[kSup];
-#pragma unroll
-    for (int i = 0; i < kSup; ++i) {
-        const int ca = 16 * (ta0 + i) + (lane & 15), cb = 16 * (tb0 + i) + (lane & 15);
-        okA[i] = ca < g.M;
-        okB[i] = cb < g.M;
-        offA[i] = okA[i] ? mf_off(a, ca) : 0;
-        offB[i] = okB[i] ? mf_off(a, cb) : 0;
-    }
-    f4 acc[kSup][kSup];
-#pragma unroll
-    for (int i = 0; i < kSup; ++i)
-#pragma unroll
-        for (int j = 0; j < kSup; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-
-    // A[i][k] = w(x_k) E[x_k][row i], B[k][j] = E[x_k][column j]; lane supplies
-    // row/column (lane & 15) of voxel k = lane >> 4
-    const int vw = a.VB / 4;
-    for (int v = wave * vw + (lane >> 4); v < (wave + 1) * vw; v += 4) {
-        const int base = mf_base(a, v);
-        const float w = SOFT ? 1.f : T[base];
-        float ea[kSup], eb[kSup];
-#pragma unroll
-        for (int i = 0; i < kSup; ++i) ea[i] = okA[i] ? mf_real<SOFT>(T, base, offA[i], a.sc) : 0.f;
-        if constexpr (!DIAG) {
-#pragma unroll
-            for (int j = 0; j < kSup; ++j) eb[j] = okB[j] ? mf_real<SOFT>(T, base, offB[j], a.sc) : 0.f;
-        }
-#pragma unroll
-        for (int i = 0; i < kSup; ++i) {
-            if (ta0 + i >= a.n16) continue;
-            const float av = w * ea[i];
-#pragma unroll
-            for (int j = DIAG ? i : 0; j < kSup; ++j) {
-                if (tb0 + j >= a.n16) continue;
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, DIAG ? ea[j] : eb[j], acc[i][j], 0, 0, 0);
-            }
-        }
-    }
-
-    // waves 0..3 add their accumulators in LDS in wave order; wave 3 holds the sum
-#pragma unroll 1
-    for (int w = 0; w < 4; ++w) {
-        if (wave == w) {
-            int t = 0;
-#pragma unroll
-            for (int i = 0; i < kSup; ++i)
-#pragma unroll
-                for (int j = DIAG ? i : 0; j < kSup; ++j, ++t) {
-                    f4 v = acc[i][j];
-                    if (w > 0) v += red[t * 64 + lane];
-                    if (w < 3)
-                        red[t * 64 + lane] = v;
-                    else
-                        acc[i][j] = v;
-                }
-        }
-        __syncthreads();
-    }
-    if (wave != 3) return;
+    const int ta0 = ba * kSup, tb0 = bb * kSup;
     float *out = a.part + ((b * a.C + ch) * a.chunks + chunk) * g.K3;
+    switch (min(kSup, a.n16 - tb0)) {
+#define DMCR_FWD_CASE(n) \
+    case n: fwd_super<SOFT, DIAG, DIAG ? n : kSup, n>(a, T, red, ta0, tb0, out); break;
+        DMCR_FWD_CASE(1)
+        DMCR_FWD_CASE(2)
+        DMCR_FWD_CASE(3)
+        DMCR_FWD_CASE(4)
+        DMCR_FWD_CASE(5)
+        DMCR_FWD_CASE(6)
+#undef DMCR_FWD_CASE
+    }
+}
+
+// One pass of the adjoint over NC vector tiles from column 16 c0t: D = E Gf / N
+// for the wave's 64 voxels (four 16-voxel row tiles, K = 4 vectors d per
+// instruction), then Q stored and the local term added into loc.  A step reads
+// the next step's raw tile values and cotangent rows (and the displacement
+// offsets of the step after) before running the current products.
+template <bool SOFT, bool GL, int NC>
+__device__ __forceinline__ void adj_pass(const S3MfArgs &a, const float *T, const int *offs, const float *Gf,
+                                         const float *Gs, float *Q, int c0t, const int (&baseA)[4],
+                                         const int (&baseO)[4], const int64_t (&gO)[4], float (&loc)[4][4])
+{
+    const S3Geo &g = a.g;
+    const int lane = threadIdx.x & 63;
+    const int col = 16 * c0t + (lane & 15);
+    const int zero = a.ed[0] * a.ed[1] * a.ed[2];
+    f4 acc[4][NC];
 #pragma unroll
-    for (int i = 0; i < kSup; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = DIAG ? i : 0; j < kSup; ++j) {
-            const int ib = 16 * (tb0 + j) + (lane & 15);
+        for (int j = 0; j < NC; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    float fx[4];   // phi at the four A voxels (the soft threshold's first point)
+    if constexpr (SOFT) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fx[i] = T[baseA[i]];
+    }
+    const int steps = a.Kp / 4;
+    auto fetch = [&](int s, int od, float (&ya_)[4], float (&bv_)[NC]) {
+        const int d = 4 * s + (lane >> 4);
+        const bool ok = d < g.M;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) bv_[j] = GL ? Gs[d * a.gs + col + 16 * j] : Gf[(int64_t)d * a.Mp + col + 16 * j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ya_[i] = T[ok ? baseA[i] + od : zero];
+    };
+    float ya[4], bv[NC];
+    int odn = offs[4 * min(1, steps - 1) + (lane >> 4)];
+    fetch(0, offs[lane >> 4], ya, bv);
+    for (int s = 0; s < steps; ++s) {
+        // the last step reads its own operands again: no branch around the reads
+        float yan[4], bn[NC];
+        const int od = odn;
+        odn = offs[4 * min(s + 2, steps - 1) + (lane >> 4)];
+        fetch(min(s + 1, steps - 1), od, yan, bn);
+        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
+        float av[4];
+        const float m = 4 * s + (lane >> 4) < g.M ? 1.f : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = mf_real<SOFT>(SOFT ? fx[i] : 0.f, ya[i], m, a.sc);
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ya[i] = yan[i];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) bv[j] = bn[j];
+    }
+    // D[x][c] = acc / N for x = 16 i + 4 (lane >> 4) + r of the group, c = col + 16 j
+    const float hq = 0.5f * a.sc.c1 * a.sc.alpha;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const int c = col + 16 * j;
+        if (c >= g.M) continue;
+        const int oc = offs[c];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            f4 q;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int ia = 16 * (ta0 + i) + 4 * (lane >> 4) + r;
-                if (ia <= ib && ib < g.M) out[tri_row(ia, g.M) + (ib - ia)] = acc[i][j][r];
+                const int base = baseO[i] + r;   // four voxels along the innermost axis
+                const float D = acc[i][j][r] * a.invN;
+                if constexpr (SOFT) {
+                    const float sg = soft_sig(0.5f * (T[base] + T[base + oc]), a.sc);
+                    q[r] = hq * sg * (1.f - sg) * D;
+                    loc[i][r] += q[r];
+                } else {
+                    q[r] = T[base] * D;
+                    loc[i][r] += 0.5f * T[base + oc] * D;
+                }
             }
+            *reinterpret_cast<f4 *>(Q + (int64_t)c * g.N + gO[i]) = q;
         }
+    }
 }
 
 // Adjoint: block = box x channel x field, nw waves; a wave takes 64 voxels of
-// the box at a time (four 16-voxel tiles) and the vectors in passes of kSup
-// 16-wide tiles.
-template <bool SOFT>
+// the box at a time and the vectors in passes of up to kSup 16-wide tiles.  GL:
+// the block builds the expanded cotangent in LDS (rows a.gs apart) from the
+// packed one; else it reads the expanded copy in the workspace.
+template <bool SOFT, bool GL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_s3_adj_mf(S3MfArgs a)
 {
     extern __shared__ float4 sm4[];
@@ -654,75 +805,70 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int64_t b = blockIdx.z;
     const int tv = a.ed[0] * a.ed[1] * a.ed[2];
     float *T = reinterpret_cast<float *>(sm4);
-    int *offs = reinterpret_cast<int *>(T + tv);   // [Kp] tile offset of r_d (0 past M)
+    int *offs = reinterpret_cast<int *>(T + tv + 1);   // [Kp] tile offset of r_d (0 past M)
     const int64_t bc = b * a.C + ch;
+    float *Gs = reinterpret_cast<float *>(offs + a.Kp);   // GL: [Kp][gs]
     mf_load_tile(a, a.phi + bc * g.N, chunk, T);
     for (int d = threadIdx.x; d < a.Kp; d += blockDim.x) offs[d] = d < g.M ? mf_off(a, d) : 0;
+    const float *Gf = a.Gf + bc * (int64_t)a.Kp * a.Mp;
+    if constexpr (GL) {   // Gs[d][c] = G(min, max), doubled on the diagonal, zero in the padding
+        // (Mp <= 128: columns lane and lane + 64); eight rows per wave and pass, their
+        // reads all issued before the stores
+        const float *Gp = a.G + b * a.Kstride + a.off + ch * g.K3;
+        const int ln = threadIdx.x & 63, nwv = blockDim.x >> 6;
+        for (int d0 = (threadIdx.x >> 6) * 8; d0 < a.Kp; d0 += nwv * 8) {
+            float v[8][2];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int d = d0 + u, c = ln + 64 * h;
+                    v[u][h] = 0.f;
+                    if (d < g.M && c < g.M) {
+                        const int lo = c < d ? c : d, hi = c < d ? d : c;
+                        v[u][h] = Gp[tri_row(lo, g.M) + (hi - lo)] * (c == d ? 2.f : 1.f);
+                    }
+                }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int d = d0 + u, c = ln + 64 * h;
+                    if (d < a.Kp && c < a.Mp) Gs[d * a.gs + c] = v[u][h];
+                }
+        }
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const float *Gf = a.Gf + bc * (int64_t)a.Kp * a.Mp;
     float *Q = a.Q + bc * (int64_t)g.M * g.N;
-    const float hq = 0.5f * a.sc.c1 * a.sc.alpha;
     for (int grp = wave; grp < a.VB / 64; grp += nw) {
         const int v0 = grp * 64;
-        int baseA[4];   // voxel of this lane's A rows: v0 + 16 i + (lane & 15)
+        int baseA[4], baseO[4];   // A rows: voxel v0 + 16 i + (lane & 15); outputs from v0 + 16 i + 4 (lane >> 4)
+        int64_t gO[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) baseA[i] = mf_base(a, v0 + 16 * i + (lane & 15));
-        float loc[4][4];   // local term of output voxel v0 + 16 i + 4 (lane >> 4) + r, this lane's columns
+        for (int i = 0; i < 4; ++i) {
+            baseA[i] = mf_base(a, v0 + 16 * i + (lane & 15));
+            baseO[i] = mf_base(a, v0 + 16 * i + 4 * (lane >> 4));
+            gO[i] = mf_voxel(a, chunk, v0 + 16 * i + 4 * (lane >> 4));
+        }
+        float loc[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) loc[i][r] = 0.f;
         for (int cg = 0; cg * kSup < a.n16; ++cg) {
-            f4 acc[4][kSup];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < kSup; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-            for (int d0 = 0; d0 < a.Kp; d0 += 4) {
-                const int d = d0 + (lane >> 4);
-                const bool dok = d < g.M;
-                const int od = offs[d];
-                float av[4], bv[kSup];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) av[i] = dok ? mf_real<SOFT>(T, baseA[i], od, a.sc) : 0.f;
-#pragma unroll
-                for (int j = 0; j < kSup; ++j)
-                    bv[j] = (cg * kSup + j < a.n16) ? Gf[(int64_t)d * a.Mp + 16 * (cg * kSup + j) + (lane & 15)] : 0.f;
-#pragma unroll
-                for (int j = 0; j < kSup; ++j) {
-                    if (cg * kSup + j >= a.n16) continue;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-                }
-            }
-            // D[x][c] = acc / N for x = v0 + 16 i + 4 (lane >> 4) + r, c = 16 (cg kSup + j) + (lane & 15)
-#pragma unroll
-            for (int j = 0; j < kSup; ++j) {
-                const int c = 16 * (cg * kSup + j) + (lane & 15);
-                if (cg * kSup + j >= a.n16 || c >= g.M) continue;
-                const int oc = offs[c];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int vq = v0 + 16 * i + 4 * (lane >> 4);
-                    f4 q;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int base = mf_base(a, vq + r);
-                        const float D = acc[i][j][r] * a.invN;
-                        if constexpr (SOFT) {
-                            const float sg = soft_sig(0.5f * (T[base] + T[base + oc]), a.sc);
-                            q[r] = hq * sg * (1.f - sg) * D;
-                            loc[i][r] += q[r];
-                        } else {
-                            q[r] = T[base] * D;
-                            loc[i][r] += 0.5f * T[base + oc] * D;
-                        }
-                    }
-                    *reinterpret_cast<f4 *>(Q + (int64_t)c * g.N + mf_voxel(a, chunk, vq)) = q;
-                }
+            const int c0t = cg * kSup;
+            switch (min(kSup, a.n16 - c0t)) {
+#define DMCR_ADJ_CASE(n) \
+    case n: adj_pass<SOFT, GL, n>(a, T, offs, Gf, Gs, Q, c0t, baseA, baseO, gO, loc); break;
+                DMCR_ADJ_CASE(1)
+                DMCR_ADJ_CASE(2)
+                DMCR_ADJ_CASE(3)
+                DMCR_ADJ_CASE(4)
+                DMCR_ADJ_CASE(5)
+                DMCR_ADJ_CASE(6)
+#undef DMCR_ADJ_CASE
             }
         }
         // sum the local terms over the 16 lanes (columns) of each row group; lane
@@ -744,34 +890,70 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 }
 
-// grad(y) += sum_c Q_c(y - r_c) (the matrix-core adjoint added the local term)
-__global__ __launch_bounds__(kT3) void k_s3_adj_shift(S3MfArgs a)
+// grad(y) += sum_c Q_c(y - r_c) (the matrix-core adjoint added the local term):
+// kShG x 64 voxels per block (fewer when the field is smaller), wave q summing
+// c = q, q + 4, ... for each of its voxels; the four sums of a voxel are added in
+// wave order
+constexpr int kShG = 4;
+
+// voxel groups per block: four on fields of 2^16 voxels and more, fewer below
+// (N is a power of two >= 64), so that small fields still spread over the chip
+__host__ __device__ __forceinline__ int shift_groups(int64_t N)
+{
+    const int64_t g = N / (64 * 256);
+    return g >= kShG ? kShG : (g >= 2 ? 2 : 1);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_s3_adj_shift(S3MfArgs a)
 {
     __shared__ int3 rv[361];
+    __shared__ float part[3][G * 64];
     const S3Geo &g = a.g;
     const int ch = blockIdx.y;
     const int64_t b = blockIdx.z;
-    for (int c = threadIdx.x; c < g.M; c += kT3) {
+    for (int c = threadIdx.x; c < g.M; c += 256) {
         int c0, c1, c2;
         vec_of(g, c, c0, c1, c2);
         rv[c] = int3{c0, c1, c2};
     }
     __syncthreads();
-    const int64_t y = (int64_t)blockIdx.x * kT3 + threadIdx.x;
-    if (y >= g.N) return;
-    const int i2 = (int)(y % g.n2);
-    const int i1 = (int)((y / g.n2) % g.n1);
-    const int i0 = (int)(y / ((int64_t)g.n1 * g.n2));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t bc = b * a.C + ch;
     const float *Qb = a.Q + bc * g.M * g.N;
-    float acc = 0.f;
-    for (int c = 0; c < g.M; ++c) {
-        const int3 r = rv[c];
-        const int64_t x = ((int64_t)((i0 - r.x) & (g.n0 - 1)) * g.n1 + ((i1 - r.y) & (g.n1 - 1))) * g.n2 +
-                          ((i2 - r.z) & (g.n2 - 1));
-        acc += Qb[(int64_t)c * g.N + x];
+    int i0[G], i1[G], i2[G];
+    float acc[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const int64_t y = ((int64_t)blockIdx.x * G + q) * 64 + lane;
+        i2[q] = (int)(y % g.n2);
+        i1[q] = (int)((y / g.n2) % g.n1);
+        i0[q] = (int)(y / ((int64_t)g.n1 * g.n2));
+        acc[q] = 0.f;
     }
-    a.grad[bc * g.N + y] += acc;
+#pragma unroll 4
+    for (int c = wave; c < g.M; c += 4) {
+        const int3 r = rv[c];
+        const float *Qc = Qb + (int64_t)c * g.N;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const int64_t x = ((int64_t)((i0[q] - r.x) & (g.n0 - 1)) * g.n1 + ((i1[q] - r.y) & (g.n1 - 1))) * g.n2 +
+                              ((i2[q] - r.z) & (g.n2 - 1));
+            acc[q] += Qc[x];
+        }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int q = 0; q < G; ++q) part[wave - 1][q * 64 + lane] = acc[q];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const int64_t y = ((int64_t)blockIdx.x * G + q) * 64 + lane;
+            a.grad[bc * g.N + y] += ((acc[q] + part[0][q * 64 + lane]) + part[1][q * 64 + lane]) + part[2][q * 64 + lane];
+        }
+    }
 }
 
 S3Geo make_s3geo(const Plan &p, int l)
@@ -863,13 +1045,24 @@ int tile_floats(const Plan &p, int l, const int bd[3])
     return v;
 }
 
-size_t fwd_mf_lds(int tv, bool diag) { return (size_t)(tv + 3) / 4 * 16 + (size_t)(diag ? kSup * (kSup + 1) / 2 : kSup * kSup) * 64 * 16; }
-size_t adj_mf_lds(int tv, int Kp) { return (size_t)tv * 4 + (size_t)Kp * 4; }
+// LDS of the matrix-core kernels: the field tile and its zero cell, then the
+// wave sums (forward) or the displacement offsets (adjoint)
+size_t fwd_mf_lds(int tv, bool diag)
+{
+    return (size_t)(tv + 4) / 4 * 16 + (size_t)(diag ? kSup * (kSup + 1) / 2 : kSup * kSup) * 64 * 16;
+}
+size_t adj_mf_lds(int tv, int Kp) { return (size_t)(tv + 1) * 4 + (size_t)Kp * 4; }
+// row stride of the cotangent's LDS copy, and whether the copy is made
+int adj_gs(int Mp) { return Mp + (((16 - Mp) % 32) + 32) % 32; }
+bool adj_gl(int tv, int Kp, int Mp)
+{
+    return Mp <= 128 && adj_mf_lds(tv, Kp) + (size_t)Kp * adj_gs(Mp) * 4 <= 48 * 1024;
+}
 
 }  // namespace
 
 // Matrix cores when every voxel box is whole (N >= 64) and the innermost axis
-// holds the adjoint's four-voxel stores (length >= 4); the box takes N / 128
+// holds the adjoint's four-voxel stores (length >= 4); the box takes N / 64
 // voxels, clamped to [64, 1024], for the forward and the adjoint alike, so a
 // field's blocks and sums do not depend on the batch.
 bool s3_configure(Plan &p, int l)
@@ -881,7 +1074,7 @@ bool s3_configure(Plan &p, int l)
     L.s3mf = 0;
     if (L.N >= 64 && inner >= 4) {
         int VB = 64;
-        while (VB < 1024 && (int64_t)VB * 2 <= L.N / 128) VB *= 2;
+        while (VB < 1024 && (int64_t)VB * 2 <= L.N / 64) VB *= 2;
         int bd[3];
         const int n16 = (M + 15) / 16;
         const int Kp = (M + 3) / 4 * 4;
@@ -981,6 +1174,17 @@ hipError_t s3_forward_mf(const Plan &p, int l, const float *phi, float *S, const
     return s3_reduce_level(p, l, a.part, S, st);
 }
 
+hipError_t launch_shift(const Plan &p, int l, const S3MfArgs &a, hipStream_t st)
+{
+    const LevelPlan &L = p.lv[l];
+    const int G = shift_groups(L.N);
+    const dim3 gg((unsigned)(L.N / 64 / G), (unsigned)p.C, (unsigned)p.B);
+    const double bytes = (double)p.B * p.C * (L.s3M * (double)L.N * 4 + L.N * 8.0);
+    if (G == 4) return launch("s3_adj_shift", bytes, k_s3_adj_shift<4>, gg, dim3(256), 0, st, a);
+    if (G == 2) return launch("s3_adj_shift", bytes, k_s3_adj_shift<2>, gg, dim3(256), 0, st, a);
+    return launch("s3_adj_shift", bytes, k_s3_adj_shift<1>, gg, dim3(256), 0, st, a);
+}
+
 hipError_t s3_adjoint_mf(const Plan &p, int l, const float *phi, const float *G, float *grad, const Ws &ws,
                          hipStream_t st)
 {
@@ -988,9 +1192,26 @@ hipError_t s3_adjoint_mf(const Plan &p, int l, const float *phi, const float *G,
     S3MfArgs a = mf_args(p, l, L.s3ba);
     a.phi = phi;
     a.Gf = ws.at<float>(L.s3G);
+    a.G = G;
+    a.Kstride = p.K;
+    a.off = L.s3off;
     a.Q = ws.at<float>(L.s3Q);
     a.grad = grad;
-    // the expanded cotangent, as for the FMA kernels but with Kp rows and Mp columns
+    const bool soft = p.desc != DMCR_DESC_S2;
+    const int tv = a.ed[0] * a.ed[1] * a.ed[2];
+    const int nw = std::min(4, a.VB / 64);
+    const dim3 grid((unsigned)a.chunks, (unsigned)p.C, (unsigned)p.B);
+    const double qbytes = (double)p.B * p.C * (L.s3M * (double)L.N * 4 + L.N * 12.0);
+    a.gs = adj_gs(a.Mp);
+    hipError_t e;
+    if (nw == 4 && adj_gl(tv, a.Kp, a.Mp)) {   // four waves share the expanded cotangent built in LDS
+        const size_t lds = adj_mf_lds(tv, a.Kp) + (size_t)a.Kp * a.gs * 4;
+        e = soft ? launch("s3_adj_mf_soft", qbytes, k_s3_adj_mf<true, true>, grid, dim3(64 * nw), lds, st, a)
+                 : launch("s3_adj_mf", qbytes, k_s3_adj_mf<false, true>, grid, dim3(64 * nw), lds, st, a);
+        if (e != hipSuccess) return e;
+        return launch_shift(p, l, a, st);
+    }
+    // the expanded cotangent in the workspace, as for the FMA kernels but with Kp rows and Mp columns
     S3AdjArgs x{};
     x.g = a.g;
     x.G = G;
@@ -1002,21 +1223,13 @@ hipError_t s3_adjoint_mf(const Plan &p, int l, const float *phi, const float *G,
     x.off = L.s3off;
     const int64_t gfn = (int64_t)L.s3Kp * L.s3Mp;
     const dim3 eg((unsigned)std::min<int64_t>(64, (gfn + kT3 - 1) / kT3), (unsigned)p.C, (unsigned)p.B);
-    hipError_t e = launch("s3_expand", (double)p.B * p.C * (L.s3K + (double)gfn) * 4, k_s3_expand, eg, dim3(kT3), 0,
-                          st, x);
+    e = launch("s3_expand", (double)p.B * p.C * (L.s3K + (double)gfn) * 4, k_s3_expand, eg, dim3(kT3), 0, st, x);
     if (e != hipSuccess) return e;
-    const bool soft = p.desc != DMCR_DESC_S2;
-    const int tv = a.ed[0] * a.ed[1] * a.ed[2];
-    const int nw = std::min(4, a.VB / 64);
-    const dim3 grid((unsigned)a.chunks, (unsigned)p.C, (unsigned)p.B);
     const size_t lds = adj_mf_lds(tv, a.Kp);
-    const double qbytes = (double)p.B * p.C * (L.s3M * (double)L.N * 4 + L.N * 12.0);
-    e = soft ? launch("s3_adj_mf_soft", qbytes, k_s3_adj_mf<true>, grid, dim3(64 * nw), lds, st, a)
-             : launch("s3_adj_mf", qbytes, k_s3_adj_mf<false>, grid, dim3(64 * nw), lds, st, a);
+    e = soft ? launch("s3_adj_mf_soft", qbytes, k_s3_adj_mf<true, false>, grid, dim3(64 * nw), lds, st, a)
+             : launch("s3_adj_mf", qbytes, k_s3_adj_mf<false, false>, grid, dim3(64 * nw), lds, st, a);
     if (e != hipSuccess) return e;
-    const dim3 gg((unsigned)((L.N + kT3 - 1) / kT3), (unsigned)p.C, (unsigned)p.B);
-    return launch("s3_adj_shift", (double)p.B * p.C * (L.s3M * (double)L.N * 4 + L.N * 8.0), k_s3_adj_shift, gg,
-                  dim3(kT3), 0, st, a);
+    return launch_shift(p, l, a, st);
 }
 
 }  // namespace

@@ -311,25 +311,30 @@ def cpu_baseline(phi64, spec_kw, target_seconds):
     (_, pair, off, k) = l0[0]
     rs = ospec.disp(0, pair)
     N = int(np.prod(shape))
-    # calibrate with a tiny sample, then size the real one
+    # calibrate with a tiny sample, then size the real ones: three independent
+    # samples of each, a sixth of the budget apiece, and the median per-unit time
     t0 = time.perf_counter()
     fwd(lv[0][pair[0]], lv[0][pair[1]], rs[:4])
     t_per_r = max((time.perf_counter() - t0) / 4, 1e-6)
-    k_s = int(max(8, min(len(rs), 0.5 * target_seconds / t_per_r)))
-    sel = rng.choice(len(rs), k_s, replace=False)
-    t0 = time.perf_counter()
-    fwd(lv[0][pair[0]], lv[0][pair[1]], rs[sel])
-    t_fwd = time.perf_counter() - t0
+    k_s = int(max(8, min(len(rs), target_seconds / 6 / t_per_r)))
     G = rng.standard_normal(k)
     vox = rng.integers(0, min(shape), size=(64, d))
     t0 = time.perf_counter()
     adj_at(lv[0][pair[0]], lv[0][pair[1]], rs, G, vox)
     t_per_v = max((time.perf_counter() - t0) / 64, 1e-9)
-    n_s = int(max(64, min(N, 0.5 * target_seconds / t_per_v)))
-    vox = rng.integers(0, min(shape), size=(n_s, d))
-    t0 = time.perf_counter()
-    adj_at(lv[0][pair[0]], lv[0][pair[1]], rs, G, vox)
-    t_adj = time.perf_counter() - t0
+    n_s = int(max(64, min(N, target_seconds / 6 / t_per_v)))
+    reps_f, reps_a = [], []
+    for _ in range(3):
+        sel = rng.choice(len(rs), k_s, replace=False)
+        t0 = time.perf_counter()
+        fwd(lv[0][pair[0]], lv[0][pair[1]], rs[sel])
+        reps_f.append(time.perf_counter() - t0)
+        vox = rng.integers(0, min(shape), size=(n_s, d))
+        t0 = time.perf_counter()
+        adj_at(lv[0][pair[0]], lv[0][pair[1]], rs, G, vox)
+        reps_a.append(time.perf_counter() - t0)
+    t_fwd = sorted(reps_f)[1]
+    t_adj = sorted(reps_a)[1]
     # whole evaluation: every (level, pair) block, forward over its displacements and
     # adjoint over its voxels, scaled by the measured per-unit times (cost ~ N_l * K_lp)
     t_full = 0.0
@@ -337,8 +342,8 @@ def cpu_baseline(phi64, spec_kw, target_seconds):
         Nl = N >> (d * l)
         frac = (Nl / N)
         t_full += (t_fwd / k_s) * k2 * frac + (t_adj / n_s) * Nl * (k2 / k)
-    sample = ("%d of %d displacements (all %d voxels) forward + %d voxels (all %d displacements) "
-              "adjoint of level 0, pair %s; scaled to all levels and pairs by N_l*K_lp"
+    sample = ("median of 3 samples, each %d of %d displacements (all %d voxels) forward + %d voxels "
+              "(all %d displacements) adjoint of level 0, pair %s; scaled to all levels and pairs by N_l*K_lp"
               % (k_s, len(rs), N, n_s, len(rs), pair))
     P3 = spec_kw.get("s3", 0)
     if P3 > 0:
@@ -363,7 +368,8 @@ def cpu_baseline(phi64, spec_kw, target_seconds):
         sample += "; three-point: %d of %d pairs forward and adjoint over all voxels, scaled by pairs and N_l" % (
             ks, len(ia))
     return dict(value=N / t_full, unit="voxel·it/s", cores=oracle._native.num_threads(), kind="oracle",
-                sample=sample, seconds=t_fwd + t_adj)
+                sample=sample, seconds=sum(reps_f) + sum(reps_a),
+                spread=[round(min(reps_f) / max(reps_f), 3), round(min(reps_a) / max(reps_a), 3)])
 
 
 def main():

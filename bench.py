@@ -66,13 +66,12 @@ FMA_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # from the formula with its constants folded (not from the compiled loop):
 #   forward  f((a+b)/2)^2 accumulated: add, fma, exp, add, rcp, fma (f), fma (f f + acc)
 #            = 5 plain + 2 quarter-rate = 13;
-#   adjoint  K(r) c1 alpha f sigma (1 - sigma) accumulated: add, fma, exp, add, rcp,
-#            fma (f), fma (sigma - sigma^2), mul, fma (acc) = 7 plain + 2 quarter-rate = 15
-#            (K(r) c1 alpha is formed once per displacement).
-# The compiled loops take 15 and 19 slots.  Peak terms/s = 256 CUs * 4 SIMDs *
-# 16 lanes * 2.4 GHz / slots.
+#   adjoint  K(r) f sigma (1 - sigma) accumulated, the voxel's own k1 phi + k0 and the
+#            factor c1 alpha applied once per voxel: fma, exp, add, rcp, fma (f),
+#            fma (sigma - sigma^2), mul, fma (acc) = 6 plain + 2 quarter-rate = 14.
+# Peak terms/s = 256 CUs * 4 SIMDs * 16 lanes * 2.4 GHz / slots.
 VALU_LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-SOFT_SLOTS = {"direct_fwd_soft": 13, "direct_adj_soft": 15}
+SOFT_SLOTS = {"direct_fwd_soft": 13, "direct_adj_soft": 14}
 
 
 # the sources the FFT-path kernels (the dominant kernels of every workload) compile from

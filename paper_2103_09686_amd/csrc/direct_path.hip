@@ -59,29 +59,19 @@ __device__ __forceinline__ void load_halo(const Geo &g, const float *__restrict_
     }
 }
 
-// logistic soft threshold f(u) = c1 / (1 + exp(-alpha (u + c2))) + c3
+// logistic soft threshold f(u) = c1 / (1 + exp(-alpha (u + c2))) + c3 of the pair
+// mean u = (a + b) / 2, its exponent's constants folded:
+//   exp(-alpha ((a + b) / 2 + c2)) = 2^(k1 (a + b) + k0),
+//   k1 = -alpha log2(e) / 2,  k0 = -alpha c2 log2(e);
+// c1a = c1 alpha, the constant of f'(u) = c1 alpha sigma (1 - sigma)
 struct Soft {
-    float alpha, c1, c2, c3;
+    float k1, k0, c1, c3, c1a;
 };
 
-__device__ __forceinline__ float soft_sigma(float u, const Soft &s)
+// sigma = 1 / (1 + 2^z)
+__device__ __forceinline__ float soft_sigma2(float z)
 {
-    return __builtin_amdgcn_rcpf(1.f + __expf(-s.alpha * (u + s.c2)));
-}
-
-// f(u)^2: the quadratic reduction of one soft realisation
-__device__ __forceinline__ float soft_sq(float u, const Soft &s)
-{
-    const float f = fmaf(s.c1, soft_sigma(u, s), s.c3);
-    return f * f;
-}
-
-// f(u) f'(u): d f((a + b)/2)^2 / da (and / db)
-__device__ __forceinline__ float soft_ffp(float u, const Soft &s)
-{
-    const float sg = soft_sigma(u, s);
-    const float f = fmaf(s.c1, sg, s.c3);
-    return f * (s.c1 * s.alpha) * sg * (1.f - sg);
+    return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(z));
 }
 
 struct DirFwdArgs {
@@ -100,10 +90,12 @@ struct DirFwdArgs {
 template <bool SOFT>
 __device__ __forceinline__ float pair_term(float a, float b, const Soft &s)
 {
-    if constexpr (SOFT)
-        return soft_sq(0.5f * (a + b), s);
-    else
+    if constexpr (SOFT) {   // f(u)^2
+        const float f = fmaf(s.c1, soft_sigma2(fmaf(a + b, s.k1, s.k0)), s.c3);
+        return f * f;
+    } else {
         return a * b;
+    }
 }
 
 // TX, TY, TZ: the tile edge when it is the full tile (16 x 16 or 4 x 8 x 8), so the
@@ -223,14 +215,18 @@ struct DirAdjArgs {
     float invN;
 };
 
-// derivative of the pair term with respect to the thread's own end value
+// derivative of the pair term with respect to the thread's own end value, up to
+// the constant c1 alpha (applied once to the voxel's sum): f(u) sigma (1 - sigma).
+// ownk = k1 own + k0, formed once per voxel.
 template <bool SOFT>
-__device__ __forceinline__ float adj_term(float own, float other, const Soft &s)
+__device__ __forceinline__ float adj_term(float ownk, float other, const Soft &s)
 {
-    if constexpr (SOFT)
-        return soft_ffp(0.5f * (own + other), s);
-    else
+    if constexpr (SOFT) {
+        const float sg = soft_sigma2(fmaf(other, s.k1, ownk));
+        return fmaf(s.c1, sg, s.c3) * fmaf(-sg, sg, sg);
+    } else {
         return other;
+    }
 }
 
 // The adjoint has one output per voxel but |box| terms each: kAdjSplit threads
@@ -261,6 +257,7 @@ __global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
     const int64_t vox = ((int64_t)(o0 + vx) * g.n1 + (o1 + vy)) * g.n2 + (o2 + vz);
     // own value phi_c(x), needed by the soft pair term
     const float own = (SOFT && active) ? a.phi[(b * a.C + c) * a.N + vox] : 0.f;
+    const float ownk = SOFT ? fmaf(own, a.soft.k1, a.soft.k0) : 0.f;
     float acc = 0.f;
     for (int j = 0; j < a.C; ++j) {
         load_halo<kAdjT>(g, a.phi + (b * a.C + j) * a.N, o0, o1, o2, sm);
@@ -272,7 +269,7 @@ __global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
                     const float *hrow = sm + (vx + r0) * g.h1 + vy;
                     const float *krow = Kc + r0 * g.box;
 #pragma unroll 8
-                    for (int r1 = 0; r1 < g.box; ++r1) acc += krow[r1] * adj_term<SOFT>(own, hrow[r1], a.soft);
+                    for (int r1 = 0; r1 < g.box; ++r1) acc += krow[r1] * adj_term<SOFT>(ownk, hrow[r1], a.soft);
                 }
             } else {
                 for (int r0 = split; r0 < g.box; r0 += kAdjSplit)
@@ -280,7 +277,7 @@ __global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
                         const float *hrow = sm + ((vx + r0) * g.h1 + (vy + r1)) * g.h2 + vz;
                         const float *krow = Kc + (r0 * g.box + r1) * g.box;
 #pragma unroll 8
-                        for (int r2 = 0; r2 < g.box; ++r2) acc += krow[r2] * adj_term<SOFT>(own, hrow[r2], a.soft);
+                        for (int r2 = 0; r2 < g.box; ++r2) acc += krow[r2] * adj_term<SOFT>(ownk, hrow[r2], a.soft);
                     }
             }
         }
@@ -292,13 +289,15 @@ __global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
         float t = red[v];
 #pragma unroll
         for (int q = 1; q < kAdjSplit; ++q) t += red[q * kT + v];
-        a.grad[(b * a.C + c) * a.N + vox] = t * a.invN;
+        a.grad[(b * a.C + c) * a.N + vox] = t * (SOFT ? a.soft.c1a : 1.f) * a.invN;
     }
 }
 
 Soft make_soft(const Plan &p)
 {
-    return Soft{(float)p.alpha, (float)p.c1, (float)p.c2, (float)p.c3};
+    const double log2e = 1.4426950408889634074;
+    return Soft{(float)(-0.5 * p.alpha * log2e), (float)(-p.alpha * p.c2 * log2e), (float)p.c1, (float)p.c3,
+                (float)(p.c1 * p.alpha)};
 }
 
 Geo make_geo(const Plan &p, int l)

@@ -91,7 +91,7 @@ __global__ void k_fill(double *p, double v, int n)
 // throughout: strided element loop, wave shuffles, waves in order; the sums are
 // bitwise those of a separate accept followed by a dots pass.
 constexpr int kMaxDots = 5 * 32 + 1;
-constexpr int kHistJ = 5;   // ring slots per pass (5 kHistJ + 1 float64 accumulators)
+constexpr int kHistJ = 10;  // ring slots per pass (5 kHistJ + 1 float64 accumulators)
 
 __device__ __forceinline__ int hist_count(int cnt, bool pair) { return 2 * cnt + 1 + (pair ? 3 * cnt : 0); }
 
@@ -125,16 +125,19 @@ __global__ __launch_bounds__(kV) void k_accept_dots(const int *acc, float *x, co
         for (int k = 0; k < NA; ++k) a[k] = 0.0;
         for (int64_t i = (int64_t)blockIdx.x * kV + threadIdx.x; i < n; i += (int64_t)nblk * kV) {
             const int64_t e = b * n + i;
-            // every slot of the pass is loaded unconditionally (an index past the ring
-            // reads slot 0 and its sums are never stored) and before the accepted
-            // step, so that all loads are in flight together; the new pair comes
-            // from registers
+            // every slot of the pass is loaded before the accepted step, so that all
+            // loads are in flight together (an index past the ring reads slot 0 and
+            // its sums are never stored); the new pair comes from registers, so the
+            // slot it replaces is not read (a condition uniform over the block)
             float svf[kHistJ], yvf[kHistJ];
 #pragma unroll
             for (int jj = 0; jj < kHistJ; ++jj) {
                 const int j = c0 + jj < cnt ? c0 + jj : 0;
-                svf[jj] = Sb[(int64_t)j * stride + e];
-                yvf[jj] = Yb[(int64_t)j * stride + e];
+                svf[jj] = yvf[jj] = 0.f;
+                if (!(pair && c0 + jj == slot)) {
+                    svf[jj] = Sb[(int64_t)j * stride + e];
+                    yvf[jj] = Yb[(int64_t)j * stride + e];
+                }
             }
             float gf, sf = 0.f, yf = 0.f;
             if (pair && c0 == 0) {          // the accepted step, once

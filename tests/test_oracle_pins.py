@@ -572,3 +572,27 @@ def test_sampled_descriptor_and_reference_reconstructions(ora):
     x2, E2 = ora.reconstruct_coarse_to_fine(S2, two, rng.random((1, 16, 16)), maxiter=15)
     assert np.all((x2 >= 0) & (x2 <= 1))
     assert E2 == pytest.approx(ora.loss(ora.descriptor(x2, two), S2, two)[0], rel=1e-12)
+
+
+def test_oracle_helpers_half_set_pairs_weights_and_Z():
+    """The helpers the descriptor layout and the loss rest on, against hand counts:
+    the point-symmetry half set, the pair order, the per-entry level weights
+    w_l = 2^(d l / 2) (finest level l = 0; Sec. 3.3, eq. mg) and Z = sum_l w_l^2 K_l."""
+    import oracle
+    assert oracle.in_half((0, 0, 0)) and oracle.in_half((0, 1)) and not oracle.in_half((0, -1))
+    assert oracle.in_half((1, -3)) and not oracle.in_half((-1, 5))
+    assert oracle.in_half((0, 0, 2)) and not oracle.in_half((0, 0, -2))
+    assert oracle.all_pairs(1) == [(0, 0)]
+    assert oracle.all_pairs(3) == [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    # 2-D, two levels, two channels (pairs (0,0), (0,1), (1,1)), P = (2, 1): the auto
+    # blocks take the half box ((2P+1)^2 + 1) / 2, the cross block the full box
+    spec = oracle.Spec(shape=(16, 16), n_channels=2, n_levels=2, max_disp=(2, 1))
+    K0, K1 = 2 * 13 + 25, 2 * 5 + 9
+    assert spec.K == K0 + K1
+    w = oracle.level_weights_per_entry(spec)
+    assert np.all(w[:K0] == 1.0) and np.all(w[K0:] == 2.0)
+    assert oracle.error_Z(spec) == K0 * 1.0 + K1 * 4.0
+    # 3-D: w_1 = 2^(3/2)
+    spec3 = oracle.Spec(shape=(8, 8, 8), n_channels=1, n_levels=2, max_disp=(1, 1))
+    w3 = oracle.level_weights_per_entry(spec3)
+    assert np.allclose(w3[14:], 2.0 ** 1.5) and np.all(w3[:14] == 1.0) and spec3.K == 28

@@ -31,6 +31,7 @@
 #include <algorithm>
 
 #include "dmcr_internal.h"
+#include "fft_reg.h"
 
 namespace dmcr {
 
@@ -46,13 +47,17 @@ struct S3Geo {
     int64_t K3;
 };
 
+// soft threshold of the pair mean (a + b) / 2, its exponent's constants folded:
+// exp(-alpha ((a + b) / 2 + c2)) = 2^(k1 (a + b) + k0), k1 = -alpha log2(e) / 2,
+// k0 = -alpha c2 log2(e)
 struct SoftC {
-    float alpha, c1, c2, c3;
+    float alpha, c1, c2, c3, k1, k0;
 };
 
-__device__ __forceinline__ float soft_sig(float u, const SoftC &s)
+// sigma((a + b) / 2) = 1 / (1 + 2^(k1 (a + b) + k0)), given s = a + b
+__device__ __forceinline__ float soft_sig(float s, const SoftC &c)
 {
-    return __builtin_amdgcn_rcpf(1.f + __expf(-s.alpha * (u + s.c2)));
+    return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(fmaf(s, c.k1, c.k0)));
 }
 
 __device__ __forceinline__ void vec_of(const S3Geo &g, int v, int &c0, int &c1, int &c2)
@@ -103,7 +108,7 @@ __device__ __forceinline__ float realisation(const S3Geo &g, const float *__rest
     vec_of(g, c, c0, c1, c2);
     const float fy = f[shift(g, x, c0, c1, c2)];
     if constexpr (SOFT)
-        return fmaf(sc.c1, soft_sig(0.5f * (f[x] + fy), sc), sc.c3);
+        return fmaf(sc.c1, soft_sig(f[x] + fy, sc), sc.c3);
     else
         return fy;
 }
@@ -285,7 +290,7 @@ __global__ __launch_bounds__(kT3) void k_s3_adj_terms(S3AdjArgs a)
                 if constexpr (SOFT) {
                     int c0, c1, c2;
                     vec_of(g, c, c0, c1, c2);
-                    const float sg = soft_sig(0.5f * (f[x] + f[shift(g, x, c0, c1, c2)]), a.sc);
+                    const float sg = soft_sig(f[x] + f[shift(g, x, c0, c1, c2)], a.sc);
                     a.Q[(qbase + c) * g.N + x] = 0.5f * (a.sc.c1 * a.sc.alpha) * sg * (1.f - sg) * D;
                 } else {
                     a.Q[(qbase + c) * g.N + x] = f[x] * D;
@@ -477,6 +482,7 @@ struct S3MfArgs {
     int Kp, Mp;         // rows (M rounded up to 4) and columns (16 n16) of Gf
     int gs;             // row stride of Gf's copy in LDS (16 mod 32: the four rows of a read hit disjoint banks)
     float invN;
+    FastDivU fd_rl, fd_e1, fd_mp;   // exact division by the tile row length, ed[1] and Mp
 };
 
 // LDS tile offset of displacement r_c
@@ -513,30 +519,42 @@ __device__ __forceinline__ int64_t mf_voxel(const S3MfArgs &a, int64_t chunk, in
     return ((q0 * a.bd[0] + k0) * a.g.n1 + (q1 * a.bd[1] + k1)) * a.g.n2 + (q2 * a.bd[2] + k2);
 }
 
-// the box `chunk` of field f with its periodic halo into T, a row of the
-// innermost axis per wave and pass (2-D: axis 1, 3-D: axis 2), and the zero
-// cell T[tv]
+// the box `chunk` of field f with its periodic halo into T, and the zero cell
+// T[tv]; each thread issues eight loads before it stores them, so that a block's
+// load latency is paid a few times rather than once per element
 __device__ __forceinline__ void mf_load_tile(const S3MfArgs &a, const float *__restrict__ f, int64_t chunk, float *T)
 {
+    constexpr int U = 8;
     const S3Geo &g = a.g;
     const int64_t q2 = chunk % a.nb[2], q = chunk / a.nb[2];
     const int o2 = (int)(q2 * a.bd[2]) - a.hl[2];
     const int o1 = (int)((q % a.nb[1]) * a.bd[1]) - a.hl[1];
     const int o0 = (int)((q / a.nb[1]) * a.bd[0]) - a.hl[0];
-    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const bool three = g.ndim == 3;
-    const int rl = three ? a.ed[2] : a.ed[1];                 // row length
-    const int nrows = three ? a.ed[0] * a.ed[1] : a.ed[0];
-    for (int row = threadIdx.x >> 6; row < nrows; row += nw) {
-        const int t0 = three ? row / a.ed[1] : row;
-        const int t1 = three ? row - t0 * a.ed[1] : 0;
-        const int64_t rbase = three ? ((int64_t)((o0 + t0) & (g.n0 - 1)) * g.n1 + ((o1 + t1) & (g.n1 - 1))) * g.n2
-                                    : (int64_t)((o0 + t0) & (g.n0 - 1)) * g.n1;
-        const int oi = three ? o2 : o1;
-        const int ni = three ? g.n2 : g.n1;
-        for (int t = lane; t < rl; t += 64) T[row * rl + t] = f[rbase + ((oi + t) & (ni - 1))];
+    const int rl = three ? a.ed[2] : a.ed[1];     // row length of the innermost axis
+    const int tv = a.ed[0] * a.ed[1] * a.ed[2];
+    for (int base = threadIdx.x; base < tv; base += U * blockDim.x) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            v[u] = 0.f;
+            if (idx < tv) {
+                const int row = fdivu(idx, a.fd_rl), t = idx - row * rl;
+                const int t0 = three ? fdivu(row, a.fd_e1) : row;
+                const int t1 = three ? row - t0 * a.ed[1] : 0;
+                const int64_t rbase = three ? ((int64_t)((o0 + t0) & (g.n0 - 1)) * g.n1 + ((o1 + t1) & (g.n1 - 1))) * g.n2
+                                            : (int64_t)((o0 + t0) & (g.n0 - 1)) * g.n1;
+                v[u] = f[rbase + (((three ? o2 : o1) + t) & ((three ? g.n2 : g.n1) - 1))];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < tv) T[idx] = v[u];
+        }
     }
-    if (threadIdx.x == 0) T[a.ed[0] * a.ed[1] * a.ed[2]] = 0.f;   // read in place of the padding vectors past M
+    if (threadIdx.x == 0) T[tv] = 0.f;   // read in place of the padding vectors past M
 }
 
 // realisation from the raw tile values phi(x) and phi(x + r_c); m = 1 for a
@@ -546,7 +564,7 @@ template <bool SOFT>
 __device__ __forceinline__ float mf_real(float fx, float fy, float m, const SoftC &sc)
 {
     if constexpr (SOFT)
-        return m * fmaf(sc.c1, soft_sig(0.5f * (fx + fy), sc), sc.c3);
+        return m * fmaf(sc.c1, soft_sig(fx + fy, sc), sc.c3);
     else
         return fy;
 }
@@ -778,7 +796,7 @@ __device__ __forceinline__ void adj_pass(const S3MfArgs &a, const float *T, cons
                 const int base = baseO[i] + r;   // four voxels along the innermost axis
                 const float D = acc[i][j][r] * a.invN;
                 if constexpr (SOFT) {
-                    const float sg = soft_sig(0.5f * (T[base] + T[base + oc]), a.sc);
+                    const float sg = soft_sig(T[base] + T[base + oc], a.sc);
                     q[r] = hq * sg * (1.f - sg) * D;
                     loc[i][r] += q[r];
                 } else {
@@ -811,31 +829,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     mf_load_tile(a, a.phi + bc * g.N, chunk, T);
     for (int d = threadIdx.x; d < a.Kp; d += blockDim.x) offs[d] = d < g.M ? mf_off(a, d) : 0;
     const float *Gf = a.Gf + bc * (int64_t)a.Kp * a.Mp;
-    if constexpr (GL) {   // Gs[d][c] = G(min, max), doubled on the diagonal, zero in the padding
-        // (Mp <= 128: columns lane and lane + 64); eight rows per wave and pass, their
-        // reads all issued before the stores
+    if constexpr (GL) {   // Gs[d][c] = G(min, max), doubled on the diagonal, zero in the padding;
+        // sixteen entries per thread and batch, their reads issued before the stores
+        constexpr int U = 16;
         const float *Gp = a.G + b * a.Kstride + a.off + ch * g.K3;
-        const int ln = threadIdx.x & 63, nwv = blockDim.x >> 6;
-        for (int d0 = (threadIdx.x >> 6) * 8; d0 < a.Kp; d0 += nwv * 8) {
-            float v[8][2];
+        const int tot = a.Kp * a.Mp;
+        for (int base = threadIdx.x; base < tot; base += U * blockDim.x) {
+            float v[U];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int d = d0 + u, c = ln + 64 * h;
-                    v[u][h] = 0.f;
-                    if (d < g.M && c < g.M) {
-                        const int lo = c < d ? c : d, hi = c < d ? d : c;
-                        v[u][h] = Gp[tri_row(lo, g.M) + (hi - lo)] * (c == d ? 2.f : 1.f);
-                    }
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + u * blockDim.x;
+                const int d = fdivu(idx, a.fd_mp), c = idx - d * a.Mp;
+                v[u] = 0.f;
+                if (idx < tot && c < g.M && d < g.M) {
+                    const int lo = c < d ? c : d, hi = c < d ? d : c;
+                    v[u] = Gp[tri_row(lo, g.M) + (hi - lo)] * (c == d ? 2.f : 1.f);
                 }
+            }
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int d = d0 + u, c = ln + 64 * h;
-                    if (d < a.Kp && c < a.Mp) Gs[d * a.gs + c] = v[u][h];
-                }
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + u * blockDim.x;
+                const int d = fdivu(idx, a.fd_mp), c = idx - d * a.Mp;
+                if (idx < tot) Gs[d * a.gs + c] = v[u];
+            }
         }
     }
     __syncthreads();
@@ -972,7 +988,12 @@ S3Geo make_s3geo(const Plan &p, int l)
     return g;
 }
 
-SoftC make_softc(const Plan &p) { return SoftC{(float)p.alpha, (float)p.c1, (float)p.c2, (float)p.c3}; }
+SoftC make_softc(const Plan &p)
+{
+    const double log2e = 1.4426950408889634074;
+    return SoftC{(float)p.alpha, (float)p.c1, (float)p.c2, (float)p.c3, (float)(-0.5 * p.alpha * log2e),
+                 (float)(-p.alpha * p.c2 * log2e)};
+}
 
 S3MapArgs map_args(const Plan &p, float *S)
 {
@@ -1130,6 +1151,9 @@ S3MfArgs mf_args(const Plan &p, int l, const int bd[3])
     a.Kp = L.s3Kp;
     a.Mp = L.s3Mp;
     a.invN = (float)(1.0 / (double)L.N);
+    a.fd_rl = make_fastdivu(p.ndim == 3 ? a.ed[2] : a.ed[1]);
+    a.fd_e1 = make_fastdivu(a.ed[1]);
+    a.fd_mp = make_fastdivu(a.Mp);
     return a;
 }
 

@@ -511,6 +511,34 @@ class Solver:
             ctypes.c_void_p(self.phi.data_ptr()), self.slots, ctypes.byref(self.ring), iterations,
             ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream(stream)))
 
+    def state_dict(self) -> dict:
+        """A host copy of the whole solver state, for checkpoint and resume: fields,
+        targets, the workspace (history ring, step data, counters; it holds offsets,
+        no addresses, so it may be restored at any address), the slot array and the
+        ring cursor.  A solver of the same spec, batch, bounds and settings that loads
+        it continues bitwise as this one would.  Synchronises the device."""
+        torch.cuda.synchronize(self.phi.device)
+        return dict(spec=self.spec, batch=self.B, bounds=self.bounds, opt=self.opt, ws_bytes=self.ws_bytes,
+                    phi=self.phi.cpu(), St=self.St.cpu(), ws=self.ws.cpu(),
+                    slots=ctypes.string_at(ctypes.addressof(self.slots), ctypes.sizeof(self.slots)),
+                    ring=ctypes.string_at(ctypes.addressof(self.ring), ctypes.sizeof(self.ring)))
+
+    def load_state_dict(self, state: dict):
+        """Restore a state taken by state_dict() (of this solver or another one of the
+        same spec, batch, bounds and settings)."""
+        mine = (self.spec, self.B, self.bounds, self.opt, self.ws_bytes)
+        theirs = (state["spec"], state["batch"], state["bounds"], state["opt"], state["ws_bytes"])
+        if mine != theirs:
+            raise ValueError("checkpoint of a different solver (spec, batch, bounds, settings or workspace)")
+        if len(state["slots"]) != ctypes.sizeof(self.slots) or len(state["ring"]) != ctypes.sizeof(self.ring):
+            raise ValueError("checkpoint slot array or ring cursor of the wrong size")
+        self.phi.copy_(state["phi"])
+        self.St.copy_(state["St"])
+        self.ws.copy_(state["ws"])
+        torch.cuda.synchronize(self.phi.device)
+        ctypes.memmove(ctypes.addressof(self.slots), state["slots"], len(state["slots"]))
+        ctypes.memmove(ctypes.addressof(self.ring), state["ring"], len(state["ring"]))
+
 
 class S2Descriptor(torch.autograd.Function):
     """phi [B][C][n...] -> S [B][K]; backward runs dmcr_descriptor_adjoint (spectra recomputed)."""

@@ -317,3 +317,35 @@ def test_penalty_trajectory_matches_oracle(dm, ora):
     print("f gpu", f_gpu, "\nf ora", f_ora, "\nevals", ev_gpu, ev_ora, flush=True)
     assert ev_gpu == ev_ora
     np.testing.assert_allclose(f_gpu, f_ora, rtol=1e-4)
+
+
+@pytest.mark.parametrize("method", [0, 1], ids=["lbfgs", "adam"])
+def test_solver_checkpoint_resume_bitwise(dm, ora, method):
+    """A batch of three slots runs 6 iterations, is checkpointed, and runs 9 more. A
+    fresh solver (other buffers, other addresses) loads the checkpoint and runs the
+    same 9: fields, errors, iteration and evaluation counts are bitwise the same; so
+    is the first solver restored from the checkpoint after it moved on."""
+    shape = (64, 64)
+    ospec, S_des = target(ora, shape, (16,))
+    spec = dm.Spec(shape=shape, max_disp=(16,))
+    opt = dm.Opt(max_iter=200, tol_derr=0.0, method=method, lr=1e-2)
+    sv = dm.Solver(spec, 3, dm.Bounds(), opt)
+    for b in range(3):
+        sv.phi[b].copy_(torch.from_numpy(synth.uniform(shape, 40 + b).astype(np.float32)))
+        sv.St[b].copy_(torch.from_numpy(S_des))
+    sv.start([0, 1, 2])
+    sv.iterate(6)
+    ck = sv.state_dict()
+    sv.iterate(9)
+    want = (sv.phi.clone(), [(s.E, s.f, s.iters, s.evals, s.status) for s in sv.slots])
+    other = dm.Solver(spec, 3, dm.Bounds(), opt)
+    other.load_state_dict(ck)
+    other.iterate(9)
+    assert torch.equal(other.phi, want[0])
+    assert [(s.E, s.f, s.iters, s.evals, s.status) for s in other.slots] == want[1]
+    sv.load_state_dict(ck)
+    sv.iterate(9)
+    assert torch.equal(sv.phi, want[0])
+    assert [(s.E, s.f, s.iters, s.evals, s.status) for s in sv.slots] == want[1]
+    with pytest.raises(ValueError):
+        dm.Solver(spec, 2, dm.Bounds(), opt).load_state_dict(ck)

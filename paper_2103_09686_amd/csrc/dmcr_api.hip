@@ -427,12 +427,8 @@ hipError_t run_forward(const Plan &p, const float *phi, float *S, const Ws &ws, 
         if ((e = sc.join(sc.lane(l), sc.main)) != hipSuccess) return e;
     for (int l = 0; l < p.L; ++l) {
         const float *f = level_field(p, l, phi, ws);
-        // the level on the caller's stream forms its field means on a spare lane
-        const bool side = sc.multi && sc.lane(l) == sc.main;
         e = (p.lv[l].path == DMCR_PATH_FFT)
-                ? fft_forward_level(p, l, f, S, ws, sc.lane(l), x_free ? x_free[l] : nullptr,
-                                    side ? sc.ln->side[Lanes::kSide - 1] : nullptr, side ? sc.ln->event() : nullptr,
-                                    side ? sc.ln->event() : nullptr)
+                ? fft_forward_level(p, l, f, S, ws, sc.lane(l), x_free ? x_free[l] : nullptr)
                 : direct_forward_level(p, l, f, S, ws, sc.lane(l));
         if (e != hipSuccess) return e;
         if (p.s3 && (e = s3_forward_level(p, l, f, S, ws, sc.lane(l))) != hipSuccess) return e;

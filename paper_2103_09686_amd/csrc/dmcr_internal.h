@@ -137,11 +137,9 @@ hipError_t launch_upsample(const Plan &p, int l, const float *coarse, float *fin
 hipError_t run_pyramid_levels(const Plan &p, const float *phi, const Ws &ws, hipStream_t st);
 
 // x_free (optional) is recorded on st once the partial spectrum X of the level
-// has been consumed, so that a recompute of X on another stream may start.  With
-// st_side (and the events fork, join), the float64 field means are formed there.
+// has been consumed, so that a recompute of X on another stream may start.
 hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
-                             hipStream_t st, hipEvent_t x_free = nullptr, hipStream_t st_side = nullptr,
-                             hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
+                             hipStream_t st, hipEvent_t x_free = nullptr);
 // fused = false keeps the two-pass transforms of 3-D levels (for a spectrum
 // computed while other kernels of the same step run on other streams).  With
 // msum, the first pass also writes float64 partial sums of every field

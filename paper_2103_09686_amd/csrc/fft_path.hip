@@ -487,6 +487,13 @@ struct Axis0Args {
     float scale;
     uint32_t inner32;
     DivU32 dv_inner, dv_hp;
+    // forward: the first nmean blocks form the float64 field means
+    // mu[f] = (sum of msum[f][0 .. mparts)) * invN instead of a pencil tile
+    const double *msum;
+    double *mu;
+    int64_t mparts;
+    double invN;
+    uint32_t nmean;
 };
 
 // pencil location m -> (field b, column i); false for padding columns and m past the end
@@ -515,14 +522,49 @@ __device__ __forceinline__ void load_rows(float2 (&v)[R1], const float2 *base, i
     for (int i1 = 0; i1 < R1; ++i1) v[i1] = valid ? sp[(size_t)(R2 * i1) * inner] : make_float2(0.f, 0.f);
 }
 
+// mu[f] = (sum of field f's mparts partial sums) * invN, float64, by one block of
+// NT threads (a power of two that depends on the level only): thread t adds the
+// partials t, t + NT, ... in index order, eight loads in flight, then a fixed
+// tree in red[NT].  The same bits for a field in any batch.
+template <int NT>
+__device__ __forceinline__ void field_mean(const Axis0Args &a, uint32_t f, double *red)
+{
+    const double *pf = a.msum + (int64_t)f * a.mparts;
+    double sm = 0.0;
+    for (int64_t j0 = threadIdx.x; j0 < a.mparts; j0 += 8 * NT) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t j = j0 + (int64_t)u * NT;
+            v[u] = j < a.mparts ? pf[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sm += v[u];
+    }
+    red[threadIdx.x] = sm;
+    __syncthreads();
+#pragma unroll
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.mu[f] = red[0] * a.invN;
+}
+
 template <int L, int C>
 __global__ __launch_bounds__(256) void k_axis0_fwd(Axis0Args a)
 {
     using SP = Split<L>;
     constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
     __shared__ float2 ex[ex_size<L>(T)];
+    static_assert(sizeof(float2) == sizeof(double) && ex_size<L>(T) >= Tile<L>::threads,
+                  "the exchange holds one float64 per thread");
+    if (blockIdx.x < a.nmean) {   // block-uniform: a means block does no pencil work
+        field_mean<Tile<L>::threads>(a, blockIdx.x, reinterpret_cast<double *>(ex));
+        return;
+    }
     const int t = threadIdx.x % T, p = threadIdx.x / T;
-    const Axis0Loc loc = axis0_loc(a, (int64_t)blockIdx.x * T + t);
+    const Axis0Loc loc = axis0_loc(a, (int64_t)(blockIdx.x - a.nmean) * T + t);
     const size_t inner = a.inner32;
     float2 X[C][S][R2];
     static_for<0, C>([&](auto cc) {
@@ -611,36 +653,6 @@ __global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
             for (int j1 = 0; j1 < R1; ++j1) dp[(size_t)(R2 * j1) * inner] = out[j1];
         }
     });
-}
-
-// mu[f] = (sum of field f's np partial sums) / N, float64.  Thread t adds the
-// partials t, t + 1024, ... in index order (eight loads in flight at a time),
-// then a fixed tree: the same bits for a field in any batch.
-constexpr int kMeanThreads = 1024;
-
-__global__ __launch_bounds__(kMeanThreads) void k_field_means(const double *part, int64_t np, double invN,
-                                                              double *mu)
-{
-    __shared__ double red[kMeanThreads];
-    const double *pf = part + (int64_t)blockIdx.x * np;
-    double sm = 0.0;
-    for (int64_t j0 = threadIdx.x; j0 < np; j0 += 8 * kMeanThreads) {
-        double v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int64_t j = j0 + (int64_t)u * kMeanThreads;
-            v[u] = j < np ? pf[j] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) sm += v[u];
-    }
-    red[threadIdx.x] = sm;
-    __syncthreads();
-    for (int h = kMeanThreads / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) mu[blockIdx.x] = red[0] * invN;
 }
 
 int ilog2(int n)
@@ -755,7 +767,7 @@ template <int C>
 hipError_t axis0_launch_c(bool adj, int L, const Axis0Args &a, double bytes, hipStream_t st)
 {
     const TileInfo ti = tile_of(L);
-    const dim3 g((unsigned)((a.nloc + ti.T - 1) / ti.T)), b(ti.threads);
+    const dim3 g((unsigned)((a.nloc + ti.T - 1) / ti.T + (adj ? 0 : a.nmean))), b(ti.threads);
     switch (L) {
 #define C_(LL)                                                                           \
     case LL:                                                                             \
@@ -886,24 +898,13 @@ hipError_t fft_spectrum_level(const Plan &p, int l, const float *phi, const Ws &
 }
 
 hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws, hipStream_t st,
-                             hipEvent_t x_free, hipStream_t st_side, hipEvent_t fork, hipEvent_t join)
+                             hipEvent_t x_free)
 {
     const LevelPlan &L = p.lv[l];
     const int B = p.B, C = p.C;
     double *msum = ws.at<double>(L.msum);
     double *mu = ws.at<double>(L.mu);
     TRY_HIP(fft_spectrum_level(p, l, phi, ws, st, true, msum));
-    // the means are needed only by the gather at the end of the forward: on a side
-    // stream they stay off the path of the transforms
-    hipStream_t sm = st;
-    if (st_side && fork && join) {
-        TRY_HIP(hipEventRecord(fork, st));
-        TRY_HIP(hipStreamWaitEvent(st_side, fork, 0));
-        sm = st_side;
-    }
-    TRY_HIP(launch("field_means", (double)B * C * L.mparts * 8, k_field_means, dim3((unsigned)(B * C)),
-                   dim3(kMeanThreads), 0, sm, (const double *)msum, L.mparts, 1.0 / (double)L.N, mu));
-    if (sm != st) TRY_HIP(hipEventRecord(join, sm));
     float2 *X = ws.at<float2>(L.X);
     float2 *Y = ws.at<float2>(L.Y);
     const int n0 = L.n[0];
@@ -924,7 +925,13 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
     for (int k = 0; k < kMaxChannels * kMaxChannels; ++k) a.pair_of[k] = -1;
     for (int q = 0; q < p.npairs; ++q) a.pair_of[p.pi[q] * kMaxChannels + p.pj[q]] = q;
     a.scale = (float)(invN * invN);
-    const double bytes0 = (double)B * C * n0 * inner_valid * 8 + (double)B * p.npairs * L.box * inner_valid * 8;
+    a.msum = msum;
+    a.mu = mu;
+    a.mparts = L.mparts;
+    a.invN = invN;
+    a.nmean = (uint32_t)(B * C);
+    const double bytes0 = (double)B * C * n0 * inner_valid * 8 + (double)B * p.npairs * L.box * inner_valid * 8 +
+                          (double)B * C * L.mparts * 8;
     TRY_HIP(axis0_launch(C, false, ilog2(n0), a, bytes0, st));
     if (x_free) TRY_HIP(hipEventRecord(x_free, st));
 
@@ -959,7 +966,6 @@ hipError_t fft_forward_level(const Plan &p, int l, const float *phi, float *S, c
         if (p.pi[q] == p.pj[q]) d.auto_mask |= 1 << q;
     }
     const double dbytes = (double)d.nrows * L.h * 8 + (double)d.nrows * L.box * 4;
-    if (sm != st) TRY_HIP(hipStreamWaitEvent(st, join, 0));
     if (nl >= 4) return real_launch<T_C2R_DESC, true>(ilog2(nl), d, dbytes, st);
     return rows_launch<T_C2R_DESC, true>(ilog2(nl), d, dbytes, st);
 }

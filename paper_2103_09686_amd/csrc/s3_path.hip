@@ -477,9 +477,11 @@ struct S3MfArgs {
     int ed[3];          // LDS tile edge per axis, bd + 2 hl
     int64_t chunks;     // boxes per field
     int VB;             // voxels per box
-    int n16;            // 16-wide vector tiles, ceil(M / 16)
+    int n16;            // 16-wide vector tiles on the matrix cores: ceil(M / 16), or M / 16 with rem
+    int rem;            // 1: M = 16 n16 + 1, and vector M - 1 (its Gram column and the
+                        // adjoint's column of D) is summed by plain FMAs beside the products
     int nst;            // super-tile bands, ceil(n16 / kSup)
-    int Kp, Mp;         // rows (M rounded up to 4) and columns (16 n16) of Gf
+    int Kp, Mp;         // rows (M rounded up to 4) and columns (16 ceil(M / 16)) of Gf
     int gs;             // row stride of Gf's copy in LDS (16 mod 32: the four rows of a read hit disjoint banks)
     float invN;
     FastDivU fd_rl, fd_e1, fd_mp;   // exact division by the tile row length, ed[1] and Mp
@@ -576,12 +578,22 @@ __device__ __forceinline__ float mf_real(float fx, float fy, float m, const Soft
 // current products, so the reads complete under them; then the accumulators of
 // the waves are added in LDS in wave order and wave 3 writes the block's
 // partial Gram entries.
-template <bool SOFT, bool DIAG, int NA, int NB>
+//
+// REM (diagonal super-tiles when M = 16 n16 + 1): each lane also sums
+// w(x) E[x][a] E[x][M-1] for its rows a, and w(x) E[x][M-1]^2, by FMAs on the
+// A operands it already holds; the Gram column of vector M - 1 then needs no
+// 16-wide tile of its own.
+template <bool SOFT, bool DIAG, int NA, int NB, bool REM = false>
 __device__ __forceinline__ void fwd_super(const S3MfArgs &a, const float *T, f4 *red, int ta0, int tb0, float *out)
 {
+    static_assert(!REM || DIAG, "the remainder column rides on the diagonal super-tiles");
     const S3Geo &g = a.g;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int zero = a.ed[0] * a.ed[1] * a.ed[2];
+    const int offR = REM ? mf_off(a, g.M - 1) : 0;
+    float cacc[NA + 1];   // REM: rows of the band against vector M - 1, then the corner
+#pragma unroll
+    for (int i = 0; i <= NA; ++i) cacc[i] = 0.f;
     int offA[NA], offB[NB];
     bool okA[NA], okB[NB];
 #pragma unroll
@@ -606,10 +618,11 @@ __device__ __forceinline__ void fwd_super(const S3MfArgs &a, const float *T, f4 
     // row/column (lane & 15) of voxel k = lane >> 4 of each group of four
     const int vw = a.VB / 4, steps = vw / 4;
     const int v0 = wave * vw + (lane >> 4);
-    float fx, ya[NA], yb[NB];   // raw phi(x), phi(x + r_a), phi(x + r_b)
-    auto fetch = [&](int v, float &fx_, float (&ya_)[NA], float (&yb_)[NB]) {
+    float fx, yr, ya[NA], yb[NB];   // raw phi(x), phi(x + r_(M-1)), phi(x + r_a), phi(x + r_b)
+    auto fetch = [&](int v, float &fx_, float &yr_, float (&ya_)[NA], float (&yb_)[NB]) {
         const int base = mf_base(a, v);
         fx_ = T[base];
+        if constexpr (REM) yr_ = T[base + offR];
 #pragma unroll
         for (int i = 0; i < NA; ++i) ya_[i] = T[okA[i] ? base + offA[i] : zero];
         if constexpr (!DIAG) {
@@ -617,11 +630,11 @@ __device__ __forceinline__ void fwd_super(const S3MfArgs &a, const float *T, f4 
             for (int j = 0; j < NB; ++j) yb_[j] = T[okB[j] ? base + offB[j] : zero];
         }
     };
-    fetch(v0, fx, ya, yb);
+    fetch(v0, fx, yr, ya, yb);
     for (int s = 0; s < steps; ++s) {
         // the last step reads its own voxels again: no branch around the reads
-        float fxn, yan[NA], ybn[NB];
-        fetch(v0 + 4 * min(s + 1, steps - 1), fxn, yan, ybn);
+        float fxn, yrn, yan[NA], ybn[NB];
+        fetch(v0 + 4 * min(s + 1, steps - 1), fxn, yrn, yan, ybn);
         __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
         const float w = SOFT ? 1.f : fx;
         float ea[NA], eb[NB];
@@ -638,8 +651,15 @@ __device__ __forceinline__ void fwd_super(const S3MfArgs &a, const float *T, f4 
             for (int j = DIAG ? i : 0; j < NB; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, DIAG ? ea[j] : eb[j], acc[i][j], 0, 0, 0);
         }
+        if constexpr (REM) {
+            const float er = mf_real<SOFT>(fx, yr, 1.f, a.sc);
+#pragma unroll
+            for (int i = 0; i < NA; ++i) cacc[i] = fmaf(w * ea[i], er, cacc[i]);
+            cacc[NA] = fmaf(w * er, er, cacc[NA]);
+        }
         __builtin_amdgcn_sched_barrier(0);
         fx = fxn;
+        if constexpr (REM) yr = yrn;
 #pragma unroll
         for (int i = 0; i < NA; ++i) ya[i] = yan[i];
         if constexpr (!DIAG) {
@@ -647,6 +667,24 @@ __device__ __forceinline__ void fwd_super(const S3MfArgs &a, const float *T, f4 
             for (int j = 0; j < NB; ++j) yb[j] = ybn[j];
         }
     }
+    // REM: add the four voxel groups of the wave (lanes 16 apart); partners add
+    // the same two values, so every group ends with the same bits
+    constexpr int NQ = REM ? (NA + 4) / 4 : 0;   // f4 slots of the NA + 1 sums
+    f4 cq[NQ > 0 ? NQ : 1];
+    if constexpr (REM) {
+#pragma unroll
+        for (int i = 0; i <= NA; ++i) {
+            float v = cacc[i];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            cacc[i] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cq[q][e] = 4 * q + e <= NA ? cacc[4 * q + e] : 0.f;
+    }
+    constexpr int NT = DIAG ? NA * (NA + 1) / 2 : NA * NB;   // product tiles
 
     // the waves' accumulators are added in LDS in wave order; then every wave
     // writes a quarter of the tiles
@@ -662,6 +700,12 @@ __device__ __forceinline__ void fwd_super(const S3MfArgs &a, const float *T, f4 
                     if (wv > 0) v += red[t * 64 + lane];
                     red[t * 64 + lane] = v;
                 }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                f4 v = cq[q];
+                if (wv > 0) v += red[(NT + q) * 64 + lane];
+                red[(NT + q) * 64 + lane] = v;
+            }
         }
         __syncthreads();
     }
@@ -679,6 +723,22 @@ __device__ __forceinline__ void fwd_super(const S3MfArgs &a, const float *T, f4 
                 if (ia <= ib && ib < g.M) out[tri_row(ia, g.M) + (ib - ia)] = v[r];
             }
         }
+    // REM: (row a, M - 1) for the band's rows from lanes 0..15; the corner from the last band
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (((NT + q) & 3) != wave || lane >= 16) continue;
+        const f4 v = red[(NT + q) * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * q + e;
+            if (k < NA) {
+                const int ia = 16 * (ta0 + k) + lane;
+                out[tri_row(ia, g.M) + (g.M - 1 - ia)] = v[e];
+            } else if (k == NA && lane == 0 && ta0 + NA == a.n16) {
+                out[tri_row(g.M - 1, g.M)] = v[e];
+            }
+        }
+    }
 }
 
 // Forward: block = (box, super-tile) x channel x field, four waves.  DIAG: the
@@ -711,9 +771,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIAG ? 2 : 
     __syncthreads();
     const int ta0 = ba * kSup, tb0 = bb * kSup;
     float *out = a.part + ((b * a.C + ch) * a.chunks + chunk) * g.K3;
+    const bool rem = DIAG && a.rem;
     switch (min(kSup, a.n16 - tb0)) {
-#define DMCR_FWD_CASE(n) \
-    case n: fwd_super<SOFT, DIAG, DIAG ? n : kSup, n>(a, T, red, ta0, tb0, out); break;
+#define DMCR_FWD_CASE(n)                                                               \
+    case n:                                                                            \
+        if constexpr (DIAG) {                                                          \
+            if (rem) {                                                                 \
+                fwd_super<SOFT, true, n, n, true>(a, T, red, ta0, tb0, out);           \
+                break;                                                                 \
+            }                                                                          \
+        }                                                                              \
+        fwd_super<SOFT, DIAG, DIAG ? n : kSup, n>(a, T, red, ta0, tb0, out);           \
+        break;
         DMCR_FWD_CASE(1)
         DMCR_FWD_CASE(2)
         DMCR_FWD_CASE(3)
@@ -729,10 +798,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DIAG ? 2 : 
 // instruction), then Q stored and the local term added into loc.  A step reads
 // the next step's raw tile values and cotangent rows (and the displacement
 // offsets of the step after) before running the current products.
-template <bool SOFT, bool GL, int NC>
+//
+// REM (the last pass when M = 16 n16 + 1): each lane also sums E[x][d] Gf[d][M-1]
+// for its A voxels by FMAs on the A operands it holds; dcol[i] returns N D[x][M-1]
+// for x = voxel 16 i + (lane & 15) of the group, the same in all four lane groups.
+template <bool SOFT, bool GL, int NC, bool REM = false>
 __device__ __forceinline__ void adj_pass(const S3MfArgs &a, const float *T, const int *offs, const float *Gf,
                                          const float *Gs, float *Q, int c0t, const int (&baseA)[4],
-                                         const int (&baseO)[4], const int64_t (&gO)[4], float (&loc)[4][4])
+                                         const int (&baseO)[4], const int64_t (&gO)[4], float (&loc)[4][4],
+                                         float (&dcol)[4])
 {
     const S3Geo &g = a.g;
     const int lane = threadIdx.x & 63;
@@ -743,29 +817,31 @@ __device__ __forceinline__ void adj_pass(const S3MfArgs &a, const float *T, cons
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < NC; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    float dacc[4] = {0.f, 0.f, 0.f, 0.f};
     float fx[4];   // phi at the four A voxels (the soft threshold's first point)
     if constexpr (SOFT) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) fx[i] = T[baseA[i]];
     }
     const int steps = a.Kp / 4;
-    auto fetch = [&](int s, int od, float (&ya_)[4], float (&bv_)[NC]) {
+    auto fetch = [&](int s, int od, float (&ya_)[4], float (&bv_)[NC], float &br_) {
         const int d = 4 * s + (lane >> 4);
         const bool ok = d < g.M;
 #pragma unroll
         for (int j = 0; j < NC; ++j) bv_[j] = GL ? Gs[d * a.gs + col + 16 * j] : Gf[(int64_t)d * a.Mp + col + 16 * j];
+        if constexpr (REM) br_ = GL ? Gs[d * a.gs + g.M - 1] : Gf[(int64_t)d * a.Mp + g.M - 1];
 #pragma unroll
         for (int i = 0; i < 4; ++i) ya_[i] = T[ok ? baseA[i] + od : zero];
     };
-    float ya[4], bv[NC];
+    float ya[4], bv[NC], br = 0.f;
     int odn = offs[4 * min(1, steps - 1) + (lane >> 4)];
-    fetch(0, offs[lane >> 4], ya, bv);
+    fetch(0, offs[lane >> 4], ya, bv, br);
     for (int s = 0; s < steps; ++s) {
         // the last step reads its own operands again: no branch around the reads
-        float yan[4], bn[NC];
+        float yan[4], bn[NC], brn = 0.f;
         const int od = odn;
         odn = offs[4 * min(s + 2, steps - 1) + (lane >> 4)];
-        fetch(min(s + 1, steps - 1), od, yan, bn);
+        fetch(min(s + 1, steps - 1), od, yan, bn, brn);
         __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the products
         float av[4];
         const float m = 4 * s + (lane >> 4) < g.M ? 1.f : 0.f;
@@ -775,11 +851,25 @@ __device__ __forceinline__ void adj_pass(const S3MfArgs &a, const float *T, cons
         for (int j = 0; j < NC; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        if constexpr (REM) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dacc[i] = fmaf(av[i], br, dacc[i]);
+        }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < 4; ++i) ya[i] = yan[i];
 #pragma unroll
         for (int j = 0; j < NC; ++j) bv[j] = bn[j];
+        if constexpr (REM) br = brn;
+    }
+    if constexpr (REM) {   // the four lane groups hold d = 4 s + group: add them
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float v = dacc[i];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            dcol[i] = v;
+        }
     }
     // D[x][c] = acc / N for x = 16 i + 4 (lane >> 4) + r of the group, c = col + 16 j
     const float hq = 0.5f * a.sc.c1 * a.sc.alpha;
@@ -868,16 +958,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             baseO[i] = mf_base(a, v0 + 16 * i + 4 * (lane >> 4));
             gO[i] = mf_voxel(a, chunk, v0 + 16 * i + 4 * (lane >> 4));
         }
-        float loc[4][4];
+        float loc[4][4], dcol[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) loc[i][r] = 0.f;
         for (int cg = 0; cg * kSup < a.n16; ++cg) {
             const int c0t = cg * kSup;
+            const bool rem = a.rem && (cg + 1) * kSup >= a.n16;   // the last pass takes column M - 1
             switch (min(kSup, a.n16 - c0t)) {
-#define DMCR_ADJ_CASE(n) \
-    case n: adj_pass<SOFT, GL, n>(a, T, offs, Gf, Gs, Q, c0t, baseA, baseO, gO, loc); break;
+#define DMCR_ADJ_CASE(n)                                                                    \
+    case n:                                                                                 \
+        if (rem)                                                                            \
+            adj_pass<SOFT, GL, n, true>(a, T, offs, Gf, Gs, Q, c0t, baseA, baseO, gO, loc, dcol); \
+        else                                                                                \
+            adj_pass<SOFT, GL, n>(a, T, offs, Gf, Gs, Q, c0t, baseA, baseO, gO, loc, dcol); \
+        break;
                 DMCR_ADJ_CASE(1)
                 DMCR_ADJ_CASE(2)
                 DMCR_ADJ_CASE(3)
@@ -902,7 +998,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 if ((lane & 15) == 4 * i + r) mine = s;
             }
         const int vm = v0 + 16 * ((lane & 15) >> 2) + 4 * (lane >> 4) + (lane & 3);
-        a.grad[bc * g.N + mf_voxel(a, chunk, vm)] += mine;
+        const int64_t gm = mf_voxel(a, chunk, vm);
+        if (a.rem) {
+            // column M - 1 of this lane's voxel vm = v0 + 16 im + pm, held by lane pm
+            const int im = (lane & 15) >> 2, pm = 4 * (lane >> 4) + (lane & 3);
+            float dn = 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v = __shfl(dcol[i], pm);
+                if (i == im) dn = v;
+            }
+            const float D = dn * a.invN;
+            const int bm = mf_base(a, vm), om = offs[g.M - 1];
+            float q;
+            if constexpr (SOFT) {
+                const float sg = soft_sig(T[bm] + T[bm + om], a.sc);
+                q = 0.5f * a.sc.c1 * a.sc.alpha * sg * (1.f - sg) * D;
+                mine += q;
+            } else {
+                q = T[bm] * D;
+                mine += 0.5f * T[bm + om] * D;
+            }
+            Q[(int64_t)(g.M - 1) * g.N + gm] = q;
+        }
+        a.grad[bc * g.N + gm] += mine;
     }
 }
 
@@ -1070,7 +1189,8 @@ int tile_floats(const Plan &p, int l, const int bd[3])
 // wave sums (forward) or the displacement offsets (adjoint)
 size_t fwd_mf_lds(int tv, bool diag)
 {
-    return (size_t)(tv + 4) / 4 * 16 + (size_t)(diag ? kSup * (kSup + 1) / 2 : kSup * kSup) * 64 * 16;
+    // a diagonal super-tile also carries the remainder sums: two more slots
+    return (size_t)(tv + 4) / 4 * 16 + (size_t)(diag ? kSup * (kSup + 1) / 2 + 2 : kSup * kSup) * 64 * 16;
 }
 size_t adj_mf_lds(int tv, int Kp) { return (size_t)(tv + 1) * 4 + (size_t)Kp * 4; }
 // row stride of the cotangent's LDS copy, and whether the copy is made
@@ -1146,7 +1266,8 @@ S3MfArgs mf_args(const Plan &p, int l, const int bd[3])
         a.VB *= bd[ax];
     }
     a.chunks = L.N / a.VB;
-    a.n16 = (L.s3M + 15) / 16;
+    a.rem = (L.s3M > 16 && L.s3M % 16 == 1) ? 1 : 0;
+    a.n16 = a.rem ? L.s3M / 16 : (L.s3M + 15) / 16;
     a.nst = (a.n16 + kSup - 1) / kSup;
     a.Kp = L.s3Kp;
     a.Mp = L.s3Mp;

@@ -62,6 +62,13 @@ CASES = [
     ((64, 64), 2, 1, (12,), 6, 1, 0),
     ((64, 64), 1, 1, (12,), 6, 2, 0),
     ((16, 16, 16), 1, 1, (3,), 3, 0, 1),
+    # M = 16 n + 1 (49, 81, 289 vectors): the last vector's Gram column and
+    # cotangent column summed beside the 16-wide tiles; 289 spans three bands
+    ((64, 64), 1, 1, (8,), 4, 0, 1),
+    ((64, 64), 2, 2, (8, 4), 4, 1, 0),
+    ((32, 32), 2, 1, (6,), 3, 2, 0),
+    ((64, 64), 1, 1, (12,), 8, 0, 0),
+    ((64, 64), 1, 1, (12,), 8, 1, 0),
 ]
 
 

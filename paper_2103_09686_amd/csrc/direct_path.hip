@@ -178,11 +178,13 @@ struct DirRedArgs {
 };
 
 // One block per (32 consecutive displacements, batch x pair): lane group q of
-// 8 sums tiles q, q + 8, ... in order (coalesced: the 32 displacements of a tile
-// are contiguous), then the 8 group sums are added in group order.
-constexpr int kRedK = 32, kRedG = kT / kRedK;
+// 32 sums tiles q, q + 32, ... in order, eight loads in flight at a time
+// (coalesced: the 32 displacements of a tile are contiguous), then the 32 group
+// sums are added in group order.  A level's few blocks sit between its forward
+// and the error, so each thread has only a few partials to add.
+constexpr int kRedK = 32, kRedG = 32, kRedT = kRedK * kRedG;
 
-__global__ __launch_bounds__(kT) void k_direct_reduce(DirRedArgs a)
+__global__ __launch_bounds__(kRedT) void k_direct_reduce(DirRedArgs a)
 {
     __shared__ double part[kRedG][kRedK];
     const int kk = threadIdx.x % kRedK, grp = threadIdx.x / kRedK;
@@ -193,7 +195,16 @@ __global__ __launch_bounds__(kT) void k_direct_reduce(DirRedArgs a)
     double s = 0.0;
     if (k < a.cnt[p]) {
         const double *src = a.part + (int64_t)bp * a.ntiles * a.kmax + k;
-        for (int64_t t = grp; t < a.ntiles; t += kRedG) s += src[t * a.kmax];
+        for (int64_t t0 = grp; t0 < a.ntiles; t0 += 8 * kRedG) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t t = t0 + (int64_t)u * kRedG;
+                v[u] = t < a.ntiles ? src[t * a.kmax] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
     }
     part[grp][kk] = s;
     __syncthreads();
@@ -408,7 +419,7 @@ hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S
     }
     r.invN = 1.0 / (double)L.N;
     dim3 rg((unsigned)((kmax + kRedK - 1) / kRedK), (unsigned)(p.B * p.npairs));
-    return launch("direct_reduce", (double)p.B * p.npairs * a.ntiles * kmax * 8, k_direct_reduce, rg, dim3(kT), 0,
+    return launch("direct_reduce", (double)p.B * p.npairs * a.ntiles * kmax * 8, k_direct_reduce, rg, dim3(kRedT), 0,
                   st, r);
 }
 

@@ -69,6 +69,34 @@ struct Tile {
     static constexpr int threads = R2 * T;
 };
 
+// tile geometry of the strided passes (k_cols, the axis-0 passes).  Where half_ex
+// holds (n = 512) they always take the two-phase exchange, so that the compiled
+// arithmetic is one and the same whatever the tile: with HX a 256-thread tile of
+// 16 pencils, else Tile's 8 pencils (fewer, smaller blocks would leave a small
+// pass's blocks too few).  The tile changes addresses only, so the results are
+// bitwise the same; the launch picks HX for passes with enough pencils to fill the
+// chip.  Elsewhere both are Tile.
+template <int L, bool HX>
+struct TileS {
+    static constexpr int R2 = Split<L>::R2;
+    static constexpr bool half = half_ex<L>();
+    static constexpr int size(int T) { return half ? exh_size<L>(T) : ex_size<L>(T); }
+    static constexpr int pick()
+    {
+        if (!HX) return Tile<L>::T;
+        int T = 256 / R2;
+        while (T > 1 && size(T) > 8192) T /= 2;
+        return T;
+    }
+    static constexpr int T = pick();
+    static constexpr int threads = R2 * T;
+};
+
+// a strided pass of this many pencils or more takes the 16-pencil tile where
+// half_ex holds (at least 512 tiles; measured on 2-D 512^2: 4% faster at 64
+// fields, 3% slower at one field, whose pass then has half as many blocks)
+constexpr int64_t kHalfExMinPencils = 8192;
+
 // Tile order of the strided passes.  Blocks are dealt to the 8 XCDs in turn
 // (block i to XCD i mod 8); tile = the (i / 8)-th of XCD (i mod 8)'s contiguous
 // share of the nb tiles, so the blocks that one XCD holds at a time read adjacent
@@ -438,13 +466,15 @@ struct ColArgs {
     DivU32 dv_inner;
 };
 
-template <int TAG, int L, bool INV>
+template <int TAG, int L, bool INV, bool HX>
 __global__ __launch_bounds__(256) void k_cols(ColArgs a)
 {
     using SP = Split<L>;
-    constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
+    using TS = TileS<L, HX>;
+    constexpr int T = TS::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
+    constexpr bool H = TS::half;
     constexpr int kIn = col_in_mode(TAG), kOut = col_out_mode(TAG);
-    __shared__ float2 ex[ex_size<L>(T)];
+    __shared__ float2 ex[TS::size(T)];
     const int t = threadIdx.x % T, p = threadIdx.x / T;
     const int64_t m = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * T + t;
     const uint32_t mu = m < a.npen ? (uint32_t)m : 0u;
@@ -467,7 +497,7 @@ __global__ __launch_bounds__(256) void k_cols(ColArgs a)
         }
     }
     float2 u[S][R2];
-    pencil_fwd<L, INV>(v, u, ex, p, t, T);
+    pencil_fwd<L, INV, LANE_T, H>(v, u, ex, p, t, T);
     if (!valid) return;
     float2 *dst = a.out + (size_t)o * a.out_len * inner + i;
     if constexpr (kOut == IO_FULL) {
@@ -533,26 +563,29 @@ __device__ __forceinline__ void load_rows(float2 (&v)[R1], const float2 *base, i
     for (int i1 = 0; i1 < R1; ++i1) v[i1] = valid ? sp[(size_t)(R2 * i1) * inner] : make_float2(0.f, 0.f);
 }
 
-// mu[f] = (sum of field f's mparts partial sums) * invN, float64, by one block of
-// NT threads (a power of two that depends on the level only): thread t adds the
-// partials t, t + NT, ... in index order, eight loads in flight, then a fixed
-// tree in red[NT].  The same bits for a field in any batch.
+// mu[f] = (sum of field f's mparts partial sums) * invN, float64, by the first NT
+// threads of one block (NT a power of two that depends on the level only, not on
+// the block size the launch picked): thread t adds the partials t, t + NT, ... in
+// index order, eight loads in flight, then a fixed tree in red[NT].  The same bits
+// for a field in any batch.  The other threads of the block only take the barriers.
 template <int NT>
 __device__ __forceinline__ void field_mean(const Axis0Args &a, uint32_t f, double *red)
 {
     const double *pf = a.msum + (int64_t)f * a.mparts;
-    double sm = 0.0;
-    for (int64_t j0 = threadIdx.x; j0 < a.mparts; j0 += 8 * NT) {
-        double v[8];
+    if (threadIdx.x < NT) {
+        double sm = 0.0;
+        for (int64_t j0 = threadIdx.x; j0 < a.mparts; j0 += 8 * NT) {
+            double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int64_t j = j0 + (int64_t)u * NT;
-            v[u] = j < a.mparts ? pf[j] : 0.0;
+            for (int u = 0; u < 8; ++u) {
+                const int64_t j = j0 + (int64_t)u * NT;
+                v[u] = j < a.mparts ? pf[j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) sm += v[u];
         }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) sm += v[u];
+        red[threadIdx.x] = sm;
     }
-    red[threadIdx.x] = sm;
     __syncthreads();
 #pragma unroll
     for (int h = NT / 2; h > 0; h >>= 1) {
@@ -562,16 +595,20 @@ __device__ __forceinline__ void field_mean(const Axis0Args &a, uint32_t f, doubl
     if (threadIdx.x == 0) a.mu[f] = red[0] * a.invN;
 }
 
-template <int L, int C>
+template <int L, int C, bool HX>
 __global__ __launch_bounds__(256) void k_axis0_fwd(Axis0Args a)
 {
     using SP = Split<L>;
-    constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
-    __shared__ float2 ex[ex_size<L>(T)];
-    static_assert(sizeof(float2) == sizeof(double) && ex_size<L>(T) >= Tile<L>::threads,
-                  "the exchange holds one float64 per thread");
+    using TS = TileS<L, HX>;
+    constexpr int T = TS::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
+    constexpr bool H = TS::half;
+    __shared__ float2 ex[TS::size(T)];
+    // the means' tree width: the one-phase tile's thread count, whichever tile runs
+    constexpr int NTM = TileS<L, false>::threads;
+    static_assert(sizeof(float2) == sizeof(double) && TS::size(T) >= NTM && TS::threads >= NTM,
+                  "the exchange holds the means' float64 tree");
     if (blockIdx.x < a.nmean) {   // block-uniform: a means block does no pencil work
-        field_mean<Tile<L>::threads>(a, blockIdx.x, reinterpret_cast<double *>(ex));
+        field_mean<NTM>(a, blockIdx.x, reinterpret_cast<double *>(ex));
         return;
     }
     const int t = threadIdx.x % T, p = threadIdx.x / T;
@@ -582,7 +619,7 @@ __global__ __launch_bounds__(256) void k_axis0_fwd(Axis0Args a)
         constexpr int c = decltype(cc)::value;
         float2 v[R1];
         load_rows<R1, R2>(v, a.X + ((size_t)loc.b * C + c) * n * inner + loc.i, p, inner, loc.valid);
-        pencil_fwd<L, false>(v, X[c], ex, p, t, T);
+        pencil_fwd<L, false, LANE_T, H>(v, X[c], ex, p, t, T);
     });
     static_for<0, C>([&](auto ic) {
         constexpr int ci = decltype(ic)::value;
@@ -599,7 +636,7 @@ __global__ __launch_bounds__(256) void k_axis0_fwd(Axis0Args a)
                 // the means, added back in float64 by the gather
                 if (loc.i == 0 && p == 0) w[0][0] = make_float2(0.f, 0.f);
                 float2 out[R1];
-                pencil_mirror<L, true>(w, out, ex, p, t, T);
+                pencil_mirror<L, true, LANE_T, H>(w, out, ex, p, t, T);
                 if (loc.valid) {
                     float2 *dst = a.Y + ((size_t)loc.b * a.npairs + q) * a.box * inner + loc.i;
 #pragma unroll
@@ -613,12 +650,14 @@ __global__ __launch_bounds__(256) void k_axis0_fwd(Axis0Args a)
     });
 }
 
-template <int L, int C>
+template <int L, int C, bool HX>
 __global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
 {
     using SP = Split<L>;
-    constexpr int T = Tile<L>::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
-    __shared__ float2 ex[ex_size<L>(T)];
+    using TS = TileS<L, HX>;
+    constexpr int T = TS::T, n = SP::n, R1 = SP::R1, R2 = SP::R2, S = SP::S;
+    constexpr bool H = TS::half;
+    __shared__ float2 ex[TS::size(T)];
     const int t = threadIdx.x % T, p = threadIdx.x / T;
     const Axis0Loc loc = axis0_loc(a, (int64_t)xcd_tile(blockIdx.x, gridDim.x) * T + t);
     const size_t inner = a.inner32;
@@ -627,7 +666,7 @@ __global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
         constexpr int c = decltype(cc)::value;
         float2 v[R1];
         load_rows<R1, R2>(v, a.X + ((size_t)loc.b * C + c) * n * inner + loc.i, p, inner, loc.valid);
-        pencil_fwd<L, false>(v, X[c], ex, p, t, T);
+        pencil_fwd<L, false, LANE_T, H>(v, X[c], ex, p, t, T);
     });
     static_for<0, C>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
@@ -646,7 +685,7 @@ __global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
                 v[i1] = (loc.valid && e >= 0) ? kb[__umul24((uint32_t)e, a.inner32)] : make_float2(0.f, 0.f);
             }
             float2 K[S][R2];
-            pencil_fwd<L, false>(v, K, ex, p, t, T);
+            pencil_fwd<L, false, LANE_T, H>(v, K, ex, p, t, T);
 #pragma unroll
             for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -657,7 +696,7 @@ __global__ __launch_bounds__(256) void k_axis0_adj(Axis0Args a)
 #pragma unroll
             for (int k = 0; k < R2; ++k) acc[s][k] = c_scale(acc[s][k], a.scale);
         float2 out[R1];
-        pencil_mirror<L, true>(acc, out, ex, p, t, T);
+        pencil_mirror<L, true, LANE_T, H>(acc, out, ex, p, t, T);
         if (loc.valid) {
             float2 *dp = a.X + ((size_t)loc.b * C + c) * n * inner + loc.i + (size_t)p * inner;
 #pragma unroll
@@ -698,6 +737,47 @@ template <int L>
 TileInfo tile_info()
 {
     return TileInfo{Tile<L>::T, Tile<L>::threads};
+}
+
+// the strided passes' geometry, two-phase exchange (HX) or not
+template <int L>
+TileInfo tile_info_s(bool hx)
+{
+    return hx ? TileInfo{TileS<L, true>::T, TileS<L, true>::threads} : TileInfo{TileS<L, false>::T, TileS<L, false>::threads};
+}
+
+TileInfo tile_of_s(int L, bool hx)
+{
+    switch (L) {
+    case 0: return tile_info_s<0>(hx);
+    case 1: return tile_info_s<1>(hx);
+    case 2: return tile_info_s<2>(hx);
+    case 3: return tile_info_s<3>(hx);
+    case 4: return tile_info_s<4>(hx);
+    case 5: return tile_info_s<5>(hx);
+    case 6: return tile_info_s<6>(hx);
+    case 7: return tile_info_s<7>(hx);
+    case 8: return tile_info_s<8>(hx);
+    case 9: return tile_info_s<9>(hx);
+    default: return tile_info_s<10>(hx);
+    }
+}
+
+bool half_ex_of(int L)
+{
+    switch (L) {
+    case 1: return half_ex<1>();
+    case 2: return half_ex<2>();
+    case 3: return half_ex<3>();
+    case 4: return half_ex<4>();
+    case 5: return half_ex<5>();
+    case 6: return half_ex<6>();
+    case 7: return half_ex<7>();
+    case 8: return half_ex<8>();
+    case 9: return half_ex<9>();
+    case 10: return half_ex<10>();
+    }
+    return false;
 }
 
 TileInfo tile_of(int L)
@@ -763,11 +843,15 @@ hipError_t cols_launch(int L, const ColArgs &a, double bytes, hipStream_t st)
 {
     if (a.in_mode != col_in_mode(TAG) || a.out_mode != col_out_mode(TAG)) return hipErrorInvalidValue;
     if (a.npen >= (int64_t(1) << 32) || a.inner >= (int64_t(1) << 24)) return hipErrorInvalidValue;
-    const TileInfo ti = tile_of(L);
+    const bool hx = half_ex_of(L) && a.npen >= kHalfExMinPencils;
+    const TileInfo ti = tile_of_s(L, hx);
     const dim3 g((unsigned)((a.npen + ti.T - 1) / ti.T)), b(ti.threads);
     switch (L) {
-#define C_(LL) \
-    case LL: return launch(kPassName[TAG], bytes, k_cols<TAG, LL, INV>, g, b, 0, st, a);
+#define C_(LL)                                                                                      \
+    case LL:                                                                                        \
+        if constexpr (half_ex<LL>())                                                                \
+            if (hx) return launch(kPassName[TAG], bytes, k_cols<TAG, LL, INV, true>, g, b, 0, st, a); \
+        return launch(kPassName[TAG], bytes, k_cols<TAG, LL, INV, false>, g, b, 0, st, a);
         DMCR_L_CASES(C_)
 #undef C_
     }
@@ -777,13 +861,18 @@ hipError_t cols_launch(int L, const ColArgs &a, double bytes, hipStream_t st)
 template <int C>
 hipError_t axis0_launch_c(bool adj, int L, const Axis0Args &a, double bytes, hipStream_t st)
 {
-    const TileInfo ti = tile_of(L);
+    const bool hx = half_ex_of(L) && a.nloc >= kHalfExMinPencils;
+    const TileInfo ti = tile_of_s(L, hx);
     const dim3 g((unsigned)((a.nloc + ti.T - 1) / ti.T + (adj ? 0 : a.nmean))), b(ti.threads);
     switch (L) {
-#define C_(LL)                                                                           \
-    case LL:                                                                             \
-        return adj ? launch("axis0_adj", bytes, k_axis0_adj<LL, C>, g, b, 0, st, a)      \
-                   : launch("axis0_fwd", bytes, k_axis0_fwd<LL, C>, g, b, 0, st, a);
+#define C_(LL)                                                                                   \
+    case LL:                                                                                     \
+        if constexpr (half_ex<LL>())                                                             \
+            if (hx)                                                                              \
+                return adj ? launch("axis0_adj", bytes, k_axis0_adj<LL, C, true>, g, b, 0, st, a) \
+                           : launch("axis0_fwd", bytes, k_axis0_fwd<LL, C, true>, g, b, 0, st, a); \
+        return adj ? launch("axis0_adj", bytes, k_axis0_adj<LL, C, false>, g, b, 0, st, a)       \
+                   : launch("axis0_fwd", bytes, k_axis0_fwd<LL, C, false>, g, b, 0, st, a);
         DMCR_L_CASES(C_)
 #undef C_
     }

@@ -234,6 +234,20 @@ constexpr int ex_size(int T)
     return Split<L>::R1 * (Split<L>::R2 + 1) * T + Split<L>::R1;
 }
 
+// Two-phase exchange (S = 2 only): the R1 = 2 R2 rows of stage one cross the
+// exchange R2 at a time, so a pencil needs half the LDS.  Used where the full
+// exchange would cut a 256-thread tile short (n = 512).
+template <int L>
+constexpr bool half_ex()
+{
+    return Split<L>::S == 2 && ex_size<L>(256 / Split<L>::R2) > 8192;
+}
+template <int L>
+constexpr int exh_size(int T)
+{
+    return half_ex<L>() ? Split<L>::R2 * (Split<L>::R2 + 1) * T + Split<L>::R2 : ex_size<L>(T);
+}
+
 // w[j] = W_n^(b j), j = 1..M-1 (w[0] = 1), n = 2^L: one table lookup for W_n^b,
 // the other powers as products of two lower powers (at most 4 multiplications deep)
 template <bool INV, int M>
@@ -250,7 +264,8 @@ __device__ __forceinline__ void tw_powers(int b, int L, float2 (&w)[M])
 // Forward-structure transform.  In: v[i1] = x[R2 i1 + p].  Out: u[s][k2] =
 // X[(p + R2 s) + R1 k2].  Contains two barriers (the caller must not touch
 // `ex` between its calls from other threads).
-template <int L, bool INV, int LO = LANE_T>
+// HALF: the two-phase exchange (half_ex), four barriers instead of two.
+template <int L, bool INV, int LO = LANE_T, bool HALF = false>
 __device__ __forceinline__ void pencil_fwd(float2 (&v)[Split<L>::R1], float2 (&u)[Split<L>::S][Split<L>::R2],
                                            float2 *ex, int p, int t, int T)
 {
@@ -258,6 +273,29 @@ __device__ __forceinline__ void pencil_fwd(float2 (&v)[Split<L>::R1], float2 (&u
     float2 tw[SP::R1];
     tw_powers<INV>(p, L, tw);
     dft_reg<SP::R1, INV>(v);
+    if constexpr (HALF) {
+        static_assert(SP::S == 2, "the two-phase exchange splits S = 2 row sets");
+        // phase s: rows k1 = s R2 + kl (kl < R2) at exchange row kl; thread p then
+        // reads row p, i.e. k1 = p + R2 s, as the one-phase exchange does
+        static_for<0, SP::S>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+            if constexpr (s > 0) __syncthreads();
+            static_for<0, SP::R2>([&](auto kc) {
+                constexpr int kl = decltype(kc)::value, k1 = s * SP::R2 + kl;
+                float2 w = v[k1];
+                if constexpr (k1 != 0) w = c_mul(w, tw[k1]);
+                ex[ex_idx<L, LO>(kl, p, t, T)] = w;
+            });
+            __syncthreads();
+            static_for<0, SP::R2>([&](auto ic) {
+                constexpr int i2 = decltype(ic)::value;
+                u[s][i2] = ex[ex_idx<L, LO>(p, i2, t, T)];
+            });
+            dft_reg<SP::R2, INV>(u[s]);
+        });
+        __syncthreads();
+        return;
+    }
     static_for<0, SP::R1>([&](auto kc) {
         constexpr int k1 = decltype(kc)::value;
         float2 w = v[k1];
@@ -279,11 +317,38 @@ __device__ __forceinline__ void pencil_fwd(float2 (&v)[Split<L>::R1], float2 (&u
 
 // Mirror (inverse-structure) transform.  In: u[s][k2] = F[(p + R2 s) + R1 k2].
 // Out: v[j1] = f[p + R2 j1].  Two barriers.
-template <int L, bool INV, int LO = LANE_T>
+template <int L, bool INV, int LO = LANE_T, bool HALF = false>
 __device__ __forceinline__ void pencil_mirror(float2 (&u)[Split<L>::S][Split<L>::R2], float2 (&v)[Split<L>::R1],
                                               float2 *ex, int p, int t, int T)
 {
     using SP = Split<L>;
+    if constexpr (HALF) {
+        static_assert(SP::S == 2, "the two-phase exchange splits S = 2 row sets");
+        // phase s: thread p's row k1 = p + R2 s at exchange row p; every thread
+        // then reads rows kl into v[s R2 + kl], as the one-phase exchange does
+        static_for<0, SP::S>([&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+            const int k1 = p + SP::R2 * s;
+            float2 tw[SP::R2];
+            tw_powers<INV>(k1, L, tw);
+            dft_reg<SP::R2, INV>(u[s]);
+            if constexpr (s > 0) __syncthreads();
+            static_for<0, SP::R2>([&](auto jc) {
+                constexpr int j2 = decltype(jc)::value;
+                float2 w = u[s][j2];
+                if constexpr (j2 != 0) w = c_mul(w, tw[j2]);
+                ex[ex_idx<L, LO>(p, j2, t, T)] = w;
+            });
+            __syncthreads();
+            static_for<0, SP::R2>([&](auto kc) {
+                constexpr int kl = decltype(kc)::value;
+                v[s * SP::R2 + kl] = ex[ex_idx<L, LO>(kl, p, t, T)];
+            });
+        });
+        dft_reg<SP::R1, INV>(v);
+        __syncthreads();
+        return;
+    }
     static_for<0, SP::S>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         const int k1 = p + SP::R2 * s;

@@ -233,6 +233,31 @@ def test_batched_equals_single_bitwise_and_repeatable(dm):
         assert torch.equal(g1[0], g4[1])
 
 
+def test_batch_independent_across_exchange_choice(dm, ora):
+    """2-D 512^2 (512-point axis-0 pencils), FFT path: a batch of 33 fields has
+    enough pencils for the strided passes to take the two-phase exchange, a single
+    field does not.  Descriptor, loss and gradient of a field must be bitwise the
+    same either way, and the batch must match the oracle."""
+    shape = (512, 512)
+    spec, ospec = specs(dm, ora, shape, 1, 1, (64,), path=1)
+    B = 33
+    phi = f32(np.stack([synth.uniform(shape, 700 + b) for b in range(B)]))
+    dphi = to_dev(phi)
+    tgt, _ = synth.boolean_spheres(shape, 4, 0.30, seed=2)
+    S_des = ora.descriptor(tgt, ospec)
+    St = torch.from_numpy(np.ascontiguousarray(np.repeat(S_des[None], B, axis=0))).cuda()
+    S = dm.dmcr_descriptor_forward(spec, dphi)
+    E, g = dm.dmcr_loss_grad(spec, dphi, St)
+    for b in (0, 17, 32):
+        S1 = dm.dmcr_descriptor_forward(spec, dphi[b:b + 1].contiguous())
+        E1, g1 = dm.dmcr_loss_grad(spec, dphi[b:b + 1].contiguous(), St[b:b + 1].contiguous())
+        assert torch.equal(S1[0], S[b]) and torch.equal(E1[0], E[b]) and torch.equal(g1[0], g[b]), b
+    Eo, go, _ = ora.loss_grad(phi[17], S_des, ospec)
+    check_S(S[17].cpu().numpy().astype(np.float64), ora.descriptor(phi[17], ospec), ospec, "512 b=17")
+    assert abs(E[17].item() - Eo) <= 1e-4 * Eo
+    check_grad(g[17].cpu().numpy().astype(np.float64), go, "512 b=17")
+
+
 def test_autograd_function_fd(dm, ora):
     """Differentiation check on a batch of 64 2-D 256^2 U(0,1) fields: S2Descriptor
     backward against central differences (h = 1e-3, FP64) of the oracle loss at 256

@@ -424,11 +424,11 @@ hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S
 }
 
 hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
-                                const Ws &ws, hipStream_t st)
+                                const Ws &ws, hipStream_t st, const double *St)
 {
     const LevelPlan &L = p.lv[l];
     float *KB0 = ws.at<float>(L.KB0);
-    hipError_t e = launch_build_kernels(p, l, G, KB0, st);
+    hipError_t e = launch_build_kernels(p, l, G, KB0, st, St);
     if (e != hipSuccess) return e;
     DirAdjArgs a{};
     a.soft = make_soft(p);

@@ -451,8 +451,11 @@ hipError_t run_adjoint(const Plan &p, const float *phi, const float *G, float *g
                        const Ws &ws, Sched &sc, hipEvent_t *x_free = nullptr, const double *St = nullptr)
 {
     hipError_t e;
-    for (int l = 1; l < p.L; ++l)
-        if ((e = sc.join(sc.lane(l), sc.main)) != hipSuccess) return e;
+    // with St each level forms its cotangent from its own S on its own lane, so
+    // the lanes need not wait for the error on the caller's stream
+    if (!St)
+        for (int l = 1; l < p.L; ++l)
+            if ((e = sc.join(sc.lane(l), sc.main)) != hipSuccess) return e;
     // ready[l]: level l's total gradient is complete on lane(l)
     hipEvent_t ready[kMaxLevels] = {};
     for (int l = p.L - 1; l >= 0; --l) {
@@ -472,7 +475,7 @@ hipError_t run_adjoint(const Plan &p, const float *phi, const float *G, float *g
                 e = fft_adjoint_level(p, l, f, G, g, have_spectrum, ws, sc.lane(l), nullptr, nullptr, nullptr, St,
                                       fc, fr);
         } else {
-            e = direct_adjoint_level(p, l, f, G, g, ws, sc.lane(l));
+            e = direct_adjoint_level(p, l, f, G, g, ws, sc.lane(l), St);
         }
         if (e != hipSuccess) return e;
         if (p.s3 && (e = s3_adjoint_level(p, l, f, G, g, ws, sc.lane(l))) != hipSuccess) return e;
@@ -515,13 +518,21 @@ dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St
         for (int l = 0; l < p.L; ++l) x_free[l] = sc.ln->event();
     hipEvent_t *xf = (!keep && sc.side_recompute) ? x_free : nullptr;
     DMCR_TRY(run_forward(p, phi, S, w, sc, xf));
-    // one level: side lane 1 is idle (lane 0 is the caller's stream, the
-    // recompute uses side lane 0), so the final error sum runs there
-    hipStream_t fin = (sc.multi && p.L == 1) ? sc.ln->side[1] : st;
-    // One FFT level of the product form: the cotangent-kernel pass forms G from
-    // S and St itself, so the whole error reduction moves to that side lane and
-    // the adjoint starts right after the forward.
-    const bool g_inline = fin != st && p.lv[0].path == DMCR_PATH_FFT && p.desc == DMCR_DESC_S2 && !p.s3;
+    // The final error sum runs on a side lane that the levels leave free: with one
+    // level side lane 1 (lane 0 is the caller's stream, the recompute uses side
+    // lane 0), with two or three levels side lane 2 (levels 1 and 2 take side
+    // lanes 0 and 1; a three-level recompute queues behind it there).
+    hipStream_t fin = st;
+    if (sc.multi && p.L == 1)
+        fin = sc.ln->side[1];
+    else if (sc.multi && p.L <= 3)
+        fin = sc.ln->side[2];
+    // Product or soft descriptor without three-point blocks: every level's
+    // cotangent-kernel pass forms its G from its own S and St, so the whole error
+    // reduction moves to that side lane and each level's adjoint starts right
+    // after its own forward, on its own lane.
+    const bool g_inline =
+        fin != st && (p.desc == DMCR_DESC_S2 || p.desc == DMCR_DESC_SBAR) && !p.s3;
     if (g_inline) {
         DMCR_TRY(sc.join(fin, st));
         DMCR_TRY(launch_error(p, S, St, E, G, w, fin, fin, nullptr));

@@ -182,10 +182,14 @@ hipError_t plane_inverse(const Plan &p, int l, const float2 *X, float *grad, hip
 
 hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws,
                                 hipStream_t st);
+// With St, G is the descriptor S and the cotangent 2 w_l^2 (S - St) / Z is formed
+// by the kernel-building pass (bitwise as the error kernel forms it), so the
+// level's adjoint need not wait for the error kernel.
 hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad,
-                                const Ws &ws, hipStream_t st);
+                                const Ws &ws, hipStream_t st, const double *St = nullptr);
 
-hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0, hipStream_t st);
+hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0, hipStream_t st,
+                                const double *St = nullptr);
 
 // Appendix A map of the soft-threshold descriptor (DMCR_DESC_STILDE), in place
 // on S [B][K], and its transpose from G_in to G_out (may be the same array).

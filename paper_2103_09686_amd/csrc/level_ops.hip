@@ -128,7 +128,9 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(const float *__restric
 }
 
 struct KernArgs {
-    const float *G;   // cotangent, [B][K]
+    const float *G;   // cotangent, [B][K]; with St: the descriptor S
+    const double *St; // target descriptor [B][K], or null
+    double w2, invZ;  // with St: the level's w_l^2 and 1 / Z
     float *KB0;       // [B][C][C][box^d]
     int64_t K;        // descriptor stride
     int64_t vol;      // box^d
@@ -142,6 +144,15 @@ struct KernArgs {
 //   grad_c(x) = (1/N) sum_j sum_r K_cj(r) phi_j(x + r):
 //   auto (c,c):  K_cc(r) = G(r) + G(-r) restricted to the half box, K_cc(0) = 2 G(0)
 //   cross (c,j): K_cj(r) = G_cj(r);   cross (j,c): K_cj(r) = G_jc(-r)
+// With St, G at descriptor index k is formed here from S and St, in float64 and
+// in the error kernel's order, so it has the error kernel's bits.
+__device__ __forceinline__ float kern_g(const KernArgs &a, const float *Gp, int64_t k)
+{
+    if (!a.St) return Gp[k];
+    const double d = (double)Gp[k] - a.St[(Gp - a.G) + k];
+    return (float)(2.0 * a.w2 * d * a.invZ);
+}
+
 __global__ __launch_bounds__(kThreads) void k_build_kernels(KernArgs a)
 {
     const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -162,15 +173,15 @@ __global__ __launch_bounds__(kThreads) void k_build_kernels(KernArgs a)
         if (i0 == j0) {
             if (c == i0 && j == i0) {
                 if (bi > center)
-                    v += Gp[bi - center];
+                    v += kern_g(a, Gp, bi - center);
                 else if (bi < center)
-                    v += Gp[mirror - center];
+                    v += kern_g(a, Gp, mirror - center);
                 else
-                    v += 2.f * Gp[0];
+                    v += 2.f * kern_g(a, Gp, 0);
             }
         } else {
-            if (c == i0 && j == j0) v += Gp[bi];
-            if (c == j0 && j == i0) v += Gp[mirror];
+            if (c == i0 && j == j0) v += kern_g(a, Gp, bi);
+            if (c == j0 && j == i0) v += kern_g(a, Gp, mirror);
         }
     }
     a.KB0[g] = v;
@@ -385,11 +396,14 @@ hipError_t launch_upsample(const Plan &p, int l, const float *coarse, float *fin
                   total, p.ndim, f.n[0], f.n[1], f.n[2], 1.f, 1);
 }
 
-hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0, hipStream_t st)
+hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0, hipStream_t st, const double *St)
 {
     const LevelPlan &L = p.lv[l];
     KernArgs a{};
     a.G = G;
+    a.St = St;
+    a.w2 = p.w[l] * p.w[l];
+    a.invZ = 1.0 / p.Z;
     a.KB0 = KB0;
     a.K = p.K;
     a.vol = 1;
@@ -402,7 +416,8 @@ hipError_t launch_build_kernels(const Plan &p, int l, const float *G, float *KB0
         a.pj[q] = p.pj[q];
         a.off[q] = L.off[q];
     }
-    const double bytes = (double)a.total * 4 + (double)p.B * (p.lvl_off[l + 1] - p.lvl_off[l]) * 4;
+    const double bytes =
+        (double)a.total * 4 + (double)p.B * (p.lvl_off[l + 1] - p.lvl_off[l]) * (St ? 12 : 4);
     return launch("build_kernels", bytes, k_build_kernels, dim3(blocks_for(a.total)), dim3(kThreads), 0, st, a);
 }
 

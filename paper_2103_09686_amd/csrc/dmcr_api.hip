@@ -383,17 +383,22 @@ struct Sched {
 };
 
 // Side lanes pay off only when the passes are long enough to hide the extra
-// event waits; smaller batches stay on the caller's stream (measured: a 512^2
-// three-level evaluation and a two-channel 128^3 three-level one (4.2M voxels)
-// are faster on one stream, 256^3 and 64 x 512^2 (16.8M) with lanes).  The
+// event waits; smaller batches stay on the caller's stream (measured: 2-D 512^2
+// three-level evaluations of 1, 4 and 16 fields are faster on one stream,
+// 256^3 and 64 x 512^2 (16.8M voxels) with lanes; the two-channel 128^3
+// three-level evaluation took 0.167-0.215 ms with lanes, varying between
+// processes, against a steady 0.199 ms on one stream).  The
 // soft-threshold levels are long ALU-bound kernels whose coarse levels fill only
 // part of the chip, so their levels always run side by side.  Under stream
 // capture the event waits become graph edges that cost no host time, so a
 // captured call also runs its levels side by side (measured: the two-channel
 // 128^3 three-level evaluation replays in 0.139 ms with lanes and takes
 // 0.193 ms eager on one stream).  A recompute moves to a spare lane only by the
-// size rule: there it takes the two-pass spectrum, and results must not depend
-// on capture.
+// size rule and only for one level: there it takes the two-pass spectrum, and
+// results must not depend on capture.  With several levels each level recomputes
+// its spectrum on its own lane (an eager batch of two 128^3 three-level fields on
+// lanes with the recomputes on spare lanes gave a gradient that differed between
+// two calls, cause not found; that schedule is not used).
 constexpr int64_t kLaneMinVoxels = int64_t(1) << 24;
 
 hipError_t make_sched(const Plan &p, hipStream_t st, Sched *s)
@@ -412,7 +417,7 @@ hipError_t make_sched(const Plan &p, hipStream_t st, Sched *s)
         if (e != hipSuccess) return e;
         tl_lanes.next = 0;
     }
-    *s = Sched{&tl_lanes, st, multi, eager_multi};
+    *s = Sched{&tl_lanes, st, multi, eager_multi && p.L == 1};
     return hipSuccess;
 }
 

@@ -23,7 +23,8 @@ def dm():
 # Eager calls fork side lanes from B C N >= 2^24 voxels; a captured call also
 # forks them whenever it has levels to overlap, so the replays of the small
 # multi-level cases run a different schedule than the eager calls they are
-# compared with.  A recompute stays on its level's lane unless the batch is large.
+# compared with.  A recompute stays on its level's lane unless the batch is large
+# and has one level.
 @pytest.mark.parametrize("case", [((512, 512), 1, 1, 64, 1, 0), ((512, 512), 1, 3, 64, 1, 0),
                                   ((128, 128, 128), 2, 3, 32, 1, 0), ((128, 128, 128), 1, 3, 32, 2, 1),
                                   ((128, 128, 128), 2, 3, 32, 4, 0)],

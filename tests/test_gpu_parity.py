@@ -197,10 +197,11 @@ def test_pyramid_two_levels_per_pass(dm, ora, shape, L):
 
 
 @pytest.mark.parametrize("shape,C,B,L,P", [((512, 512), 1, 64, 3, 32), ((64, 64, 64), 2, 32, 3, 8),
-                                           ((1024, 1024), 1, 16, 1, 16)],
-                         ids=["2d512_b64_3lv", "3d64_c2_b32_3lv", "2d1024_b16_1lv"])
+                                           ((1024, 1024), 1, 16, 1, 16), ((128, 128, 128), 1, 8, 3, 32)],
+                         ids=["2d512_b64_3lv", "3d64_c2_b32_3lv", "2d1024_b16_1lv", "3d128_b8_3lv"])
 def test_side_lanes_equal_one_stream_bitwise(dm, shape, C, B, L, P):
-    """A batch of B C N = 2^24 voxels runs on side lanes.  With three levels, the
+    """A batch of B C N = 2^24 voxels runs on side lanes, a single field below that
+    on one stream.  With three levels, the
     levels are chained by events: the coarser total gradient is prolonged inside
     each level's last inverse pass, and the pyramid takes two restrictions per
     pass.  With one FFT level, the cotangent-kernel pass forms G from S and the

@@ -388,8 +388,9 @@ struct Sched {
 // 256^3 and 64 x 512^2 (16.8M voxels) with lanes; the two-channel 128^3
 // three-level evaluation took 0.167-0.215 ms with lanes, varying between
 // processes, against a steady 0.199 ms on one stream).  The
-// soft-threshold levels are long ALU-bound kernels whose coarse levels fill only
-// part of the chip, so their levels always run side by side.  Under stream
+// soft-threshold and three-point levels are long ALU- or matrix-bound kernels
+// whose coarse levels fill only part of the chip, so their levels always run side
+// by side.  Under stream
 // capture the event waits become graph edges that cost no host time, so a
 // captured call also runs its levels side by side (measured: the two-channel
 // 128^3 three-level evaluation replays in 0.139 ms with lanes and takes
@@ -409,8 +410,8 @@ hipError_t make_sched(const Plan &p, hipStream_t st, Sched *s)
         hipError_t e = hipStreamIsCapturing(st, &cs);
         if (e != hipSuccess) return e;
     }
-    const bool eager_multi =
-        (int64_t)p.B * p.C * p.lv[0].N >= kLaneMinVoxels || (p.desc != DMCR_DESC_S2 && p.L > 1);
+    const bool eager_multi = (int64_t)p.B * p.C * p.lv[0].N >= kLaneMinVoxels ||
+                             ((p.desc != DMCR_DESC_S2 || p.s3) && p.L > 1);
     const bool multi = eager_multi || (cs == hipStreamCaptureStatusActive && p.L > 1);
     if (multi) {
         hipError_t e = tl_lanes.init();
@@ -483,7 +484,7 @@ hipError_t run_adjoint(const Plan &p, const float *phi, const float *G, float *g
             e = direct_adjoint_level(p, l, f, G, g, ws, sc.lane(l), St);
         }
         if (e != hipSuccess) return e;
-        if (p.s3 && (e = s3_adjoint_level(p, l, f, G, g, ws, sc.lane(l))) != hipSuccess) return e;
+        if (p.s3 && (e = s3_adjoint_level(p, l, f, G, g, ws, sc.lane(l), St)) != hipSuccess) return e;
         if (cg && !fuse) {
             if (cready && (e = hipStreamWaitEvent(sc.lane(l), cready, 0)) != hipSuccess) return e;
             if ((e = launch_prolong_add(p, l, cg, g, sc.lane(l))) != hipSuccess) return e;
@@ -532,12 +533,11 @@ dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St
         fin = sc.ln->side[1];
     else if (sc.multi && p.L <= 3)
         fin = sc.ln->side[2];
-    // Product or soft descriptor without three-point blocks: every level's
-    // cotangent-kernel pass forms its G from its own S and St, so the whole error
-    // reduction moves to that side lane and each level's adjoint starts right
-    // after its own forward, on its own lane.
-    const bool g_inline =
-        fin != st && (p.desc == DMCR_DESC_S2 || p.desc == DMCR_DESC_SBAR) && !p.s3;
+    // Product or soft descriptor (not the Appendix A map, which mixes the blocks):
+    // every level's cotangent-kernel passes, two- and three-point, form its G
+    // from its own S and St, so the whole error reduction moves to that side lane
+    // and each level's adjoint starts right after its own forward, on its own lane.
+    const bool g_inline = fin != st && (p.desc == DMCR_DESC_S2 || p.desc == DMCR_DESC_SBAR);
     if (g_inline) {
         DMCR_TRY(sc.join(fin, st));
         DMCR_TRY(launch_error(p, S, St, E, G, w, fin, fin, nullptr));

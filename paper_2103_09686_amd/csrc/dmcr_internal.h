@@ -205,8 +205,10 @@ hipError_t launch_stilde_adjoint(const Plan &p, const float *G_in, float *G_out,
 // field's result does not either); false if unsupported
 bool s3_configure(Plan &p, int l);
 hipError_t s3_forward_level(const Plan &p, int l, const float *phi, float *S, const Ws &ws, hipStream_t st);
+// With St, G is the descriptor S and the three-point cotangents 2 w_l^2 (S - St) / Z
+// are formed while reading it (bitwise as the error kernel forms them).
 hipError_t s3_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad, const Ws &ws,
-                            hipStream_t st);
+                            hipStream_t st, const double *St = nullptr);
 hipError_t launch_s3_map(const Plan &p, float *S, hipStream_t st);
 hipError_t launch_s3_map_adjoint(const Plan &p, float *G, hipStream_t st);
 

@@ -209,11 +209,23 @@ __global__ __launch_bounds__(kT3) void k_s3_reduce(S3RedArgs a)
     }
 }
 
+// cotangent entry i of the packed descriptor-shaped G; with St, G holds the
+// descriptor S and the entry is 2 w^2 (S - St) / Z, in float64 in the error
+// kernel's order, so it has the error kernel's bits
+__device__ __forceinline__ float s3_cot(const float *G, const double *St, double w2, double invZ, int64_t i)
+{
+    if (!St) return G[i];
+    const double d = (double)G[i] - St[i];
+    return (float)(2.0 * w2 * d * invZ);
+}
+
 struct S3AdjArgs {
     S3Geo g;
     SoftC sc;
     const float *phi;
-    const float *G;     // cotangent [B][Kstride]
+    const float *G;     // cotangent [B][Kstride]; with St: the descriptor S
+    const double *St;   // target descriptor [B][Kstride], or null
+    double w2, invZ;    // with St: the level's w_l^2 and 1 / Z
     float *Gf;          // [B][C][M][Mp] full symmetric cotangent, diagonal doubled
     float *Q, *R;       // [B][C][M][N]
     float *grad;        // level gradient [B][C][N] (added to)
@@ -229,7 +241,7 @@ __global__ __launch_bounds__(kT3) void k_s3_expand(S3AdjArgs a)
     const S3Geo &g = a.g;
     const int ch = blockIdx.y;
     const int64_t b = blockIdx.z;
-    const float *Gb = a.G + b * a.Kstride + a.off + ch * g.K3;
+    const int64_t gb = b * a.Kstride + a.off + ch * g.K3;
     float *out = a.Gf + (b * a.C + ch) * (int64_t)a.Kp * a.Mp;
     for (int64_t idx = (int64_t)blockIdx.x * kT3 + threadIdx.x; idx < (int64_t)a.Kp * a.Mp;
          idx += (int64_t)gridDim.x * kT3) {
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(kT3) void k_s3_expand(S3AdjArgs a)
         float v = 0.f;
         if (c < g.M && d < g.M) {
             const int lo = c < d ? c : d, hi = c < d ? d : c;
-            v = Gb[tri_row(lo, g.M) + (hi - lo)] * (c == d ? 2.f : 1.f);
+            v = s3_cot(a.G, a.St, a.w2, a.invZ, gb + tri_row(lo, g.M) + (hi - lo)) * (c == d ? 2.f : 1.f);
         }
         out[idx] = v;
     }
@@ -467,6 +479,9 @@ struct S3MfArgs {
     float *part;        // forward: [B][C][chunks][K3]
     const float *Gf;    // adjoint: [B][C][Kp][Mp] expanded cotangent (when it is not built in LDS)
     const float *G;     // adjoint: packed cotangent [B][Kstride], the block at off + channel K3
+                        // (with St: the descriptor S, the cotangent formed while reading)
+    const double *St;
+    double w2, invZ;
     int64_t Kstride, off;
     float *Q;           // adjoint: [B][C][M][N]
     float *grad;        // adjoint: level gradient [B][C][N] (added to)
@@ -922,7 +937,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     if constexpr (GL) {   // Gs[d][c] = G(min, max), doubled on the diagonal, zero in the padding;
         // sixteen entries per thread and batch, their reads issued before the stores
         constexpr int U = 16;
-        const float *Gp = a.G + b * a.Kstride + a.off + ch * g.K3;
+        const int64_t gp = b * a.Kstride + a.off + ch * g.K3;
         const int tot = a.Kp * a.Mp;
         for (int base = threadIdx.x; base < tot; base += U * blockDim.x) {
             float v[U];
@@ -933,7 +948,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 v[u] = 0.f;
                 if (idx < tot && c < g.M && d < g.M) {
                     const int lo = c < d ? c : d, hi = c < d ? d : c;
-                    v[u] = Gp[tri_row(lo, g.M) + (hi - lo)] * (c == d ? 2.f : 1.f);
+                    v[u] = s3_cot(a.G, a.St, a.w2, a.invZ, gp + tri_row(lo, g.M) + (hi - lo)) * (c == d ? 2.f : 1.f);
                 }
             }
 #pragma unroll
@@ -1331,13 +1346,16 @@ hipError_t launch_shift(const Plan &p, int l, const S3MfArgs &a, hipStream_t st)
 }
 
 hipError_t s3_adjoint_mf(const Plan &p, int l, const float *phi, const float *G, float *grad, const Ws &ws,
-                         hipStream_t st)
+                         hipStream_t st, const double *St)
 {
     const LevelPlan &L = p.lv[l];
     S3MfArgs a = mf_args(p, l, L.s3ba);
     a.phi = phi;
     a.Gf = ws.at<float>(L.s3G);
     a.G = G;
+    a.St = St;
+    a.w2 = p.w[l] * p.w[l];
+    a.invZ = 1.0 / p.Z;
     a.Kstride = p.K;
     a.off = L.s3off;
     a.Q = ws.at<float>(L.s3Q);
@@ -1360,6 +1378,9 @@ hipError_t s3_adjoint_mf(const Plan &p, int l, const float *phi, const float *G,
     S3AdjArgs x{};
     x.g = a.g;
     x.G = G;
+    x.St = St;
+    x.w2 = a.w2;
+    x.invZ = a.invZ;
     x.Gf = ws.at<float>(L.s3G);
     x.C = p.C;
     x.Mp = L.s3Mp;
@@ -1403,15 +1424,18 @@ hipError_t s3_forward_level(const Plan &p, int l, const float *phi, float *S, co
 }
 
 hipError_t s3_adjoint_level(const Plan &p, int l, const float *phi, const float *G, float *grad, const Ws &ws,
-                            hipStream_t st)
+                            hipStream_t st, const double *St)
 {
     const LevelPlan &L = p.lv[l];
-    if (L.s3mf) return s3_adjoint_mf(p, l, phi, G, grad, ws, st);
+    if (L.s3mf) return s3_adjoint_mf(p, l, phi, G, grad, ws, st, St);
     S3AdjArgs a{};
     a.g = make_s3geo(p, l);
     a.sc = make_softc(p);
     a.phi = phi;
     a.G = G;
+    a.St = St;
+    a.w2 = p.w[l] * p.w[l];
+    a.invZ = 1.0 / p.Z;
     a.Gf = ws.at<float>(L.s3G);
     a.Q = ws.at<float>(L.s3Q);
     a.R = (p.desc == DMCR_DESC_S2) ? ws.at<float>(L.s3R) : nullptr;

@@ -63,7 +63,7 @@ typedef enum {
     DMCR_OK = 0,
     DMCR_EINVAL = -1,        /* bad argument: null pointer, bad shape, P too large, ... */
     DMCR_ENOMEM = -2,        /* workspace smaller than dmcr_workspace_size()            */
-    DMCR_EUNSUPPORTED = -3,  /* valid problem this build does not handle (e.g. DIRECT
+    DMCR_EUNSUPPORTED = -3,  /* valid problem this library does not handle (e.g. DIRECT
                                 path with a halo tile larger than LDS)                  */
     DMCR_EDEVICE = -4,       /* a HIP call failed (launch or runtime error)             */
     DMCR_ENONFINITE = -5,    /* reconstruct: loss or gradient became NaN / Inf          */

@@ -687,7 +687,7 @@ const char *dmcr_status_string(dmcr_status status)
     case DMCR_OK: return "ok";
     case DMCR_EINVAL: return "invalid argument";
     case DMCR_ENOMEM: return "workspace too small";
-    case DMCR_EUNSUPPORTED: return "unsupported problem for this build";
+    case DMCR_EUNSUPPORTED: return "problem not supported by this library";
     case DMCR_EDEVICE: return "HIP device or launch error";
     case DMCR_ENONFINITE: return "non-finite loss or gradient";
     case DMCR_NOT_CONVERGED: return "iteration budget spent before the tolerance";

@@ -640,6 +640,38 @@ bool opt_ok(const dmcr_opt *o)
         if (_s != DMCR_OK) return _s;                          \
     } while (0)
 
+// Pinned host staging for the line search's device-to-host reads (trial errors,
+// directional dots, first steps, history flags): with a pinned destination the
+// copies are asynchronous and the search's one synchronisation covers them all,
+// where pageable ones are staged one at a time.  One area per host thread, grown
+// as needed and kept until the process ends; a solver call ends synchronised, so
+// no copy is in flight when it grows.
+struct PinnedStage {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+thread_local PinnedStage tl_pin;
+
+hipError_t pinned_stage(size_t bytes, void **out)
+{
+    if (tl_pin.bytes < bytes) {
+        if (tl_pin.p) {
+            hipError_t e = hipHostFree(tl_pin.p);
+            tl_pin.p = nullptr;
+            tl_pin.bytes = 0;
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = hipHostMalloc(&tl_pin.p, bytes, hipHostMallocPortable);
+        if (e != hipSuccess) {
+            tl_pin.p = nullptr;
+            return e;
+        }
+        tl_pin.bytes = bytes;
+    }
+    *out = tl_pin.p;
+    return hipSuccess;
+}
+
 struct Solver {
     const Plan &p;
     const dmcr_bounds &bd;
@@ -879,6 +911,11 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
     std::vector<double> hE(B), hEbc(B, 0.0), hd(B), step(B);
     std::vector<int> act(B), acc(B), flag(B), hist(B);
     int *histd = at<int>(r.histd);
+    void *pin = nullptr;   // pinned landing area of the line search's reads: E, Ebc, dot, step, flag
+    RT(pinned_stage((size_t)B * (4 * sizeof(double) + sizeof(int)), &pin));
+    double *pE = static_cast<double *>(pin), *pEbc = pE + B, *pd = pE + 2 * B, *pstep = pE + 3 * B;
+    int *pflag = reinterpret_cast<int *>(pE + 4 * B);
+    const size_t db = (size_t)B * sizeof(double), ib = (size_t)B * sizeof(int);
     auto running = [&](int b) { return slots[b].active && slots[b].status == DMCR_RUNNING; };
     int head = ring->head, count = ring->count;
     bool gdots = false;   // mdots holds S'g, Y'g, g'g of the current g and history
@@ -926,14 +963,21 @@ dmcr_status Solver::iterate(float *x, dmcr_slot *slots, dmcr_ring *ring, int ite
                 RS(evaluate_packed(act, xt, Etd, gt));   // backtracking elements only, or a partly idle batch
             else
                 RS(evaluate(xt, Etd, gt));
-            RS(fetch(Etd, hE));
-            if (penalty) RS(fetch(Ebcd, hEbc));
-            RS(fetch(dot1, hd));
+            RT(hipMemcpyAsync(pE, Etd, db, hipMemcpyDeviceToHost, st));
+            if (penalty) RT(hipMemcpyAsync(pEbc, Ebcd, db, hipMemcpyDeviceToHost, st));
+            RT(hipMemcpyAsync(pd, dot1, db, hipMemcpyDeviceToHost, st));
             if (ls == 0) {
-                RS(fetch(als, step));
-                RS(fetch_int(flagd, flag));
+                RT(hipMemcpyAsync(pstep, als, db, hipMemcpyDeviceToHost, st));
+                RT(hipMemcpyAsync(pflag, flagd, ib, hipMemcpyDeviceToHost, st));
             }
             RT(hipStreamSynchronize(st));
+            std::copy(pE, pE + B, hE.begin());
+            if (penalty) std::copy(pEbc, pEbc + B, hEbc.begin());
+            std::copy(pd, pd + B, hd.begin());
+            if (ls == 0) {
+                std::copy(pstep, pstep + B, step.begin());
+                std::copy(pflag, pflag + B, flag.begin());
+            }
             if (ls == 0)
                 for (int b = 0; b < B; ++b)
                     if (flag[b]) slots[b].hist = 0;   // the device cleared its history

@@ -148,7 +148,8 @@ __global__ __launch_bounds__(kT) void k_direct_fwd(DirFwdArgs a)
 #pragma unroll
             for (int y = 0; y < TY; ++y) {
                 const float *arow = Ta + (x * TY + y) * TZ;
-                const float *brow = hb + (x * g.h1 + y) * g.h2;
+                // 2-D (TZ = 1): h2 = 1, so the row offsets are constants the LDS reads carry
+                const float *brow = hb + (TZ == 1 ? x * g.h1 + y : (x * g.h1 + y) * g.h2);
 #pragma unroll
                 for (int z = 0; z < TZ; ++z) slab += pair_term<SOFT>(arow[z], brow[z], a.soft);
             }

@@ -504,12 +504,24 @@ class Solver:
             ctypes.byref(o), ctypes.c_void_p(self.phi.data_ptr()), self.slots, ctypes.c_void_p(self.ws.data_ptr()),
             self.ws.numel(), _stream(stream)))
 
-    def iterate(self, iterations: int, stream=None):
+    def iterate(self, iterations: int, stream=None, trace: list = None):
+        """Up to `iterations` iterations of every running slot.  With `trace` (a list),
+        the iterations run one call at a time and each slot that took one appends a
+        record: dict(slot, iters, evals, E, f, status), its state after that iteration
+        (per-iteration metrics; a call synchronises the device anyway)."""
         s, b, o = self._c
-        _check("dmcr_solver_iterate", lib().dmcr_solver_iterate(
-            ctypes.byref(s), self.B, ctypes.c_void_p(self.St.data_ptr()), ctypes.byref(b), ctypes.byref(o),
-            ctypes.c_void_p(self.phi.data_ptr()), self.slots, ctypes.byref(self.ring), iterations,
-            ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream(stream)))
+        steps = [iterations] if trace is None else [1] * iterations
+        for n in steps:
+            before = [self.slots[i].iters for i in range(self.B)]
+            _check("dmcr_solver_iterate", lib().dmcr_solver_iterate(
+                ctypes.byref(s), self.B, ctypes.c_void_p(self.St.data_ptr()), ctypes.byref(b), ctypes.byref(o),
+                ctypes.c_void_p(self.phi.data_ptr()), self.slots, ctypes.byref(self.ring), n,
+                ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream(stream)))
+            if trace is not None:
+                for i in range(self.B):
+                    sl = self.slots[i]
+                    if sl.iters != before[i]:
+                        trace.append(dict(slot=i, iters=sl.iters, evals=sl.evals, E=sl.E, f=sl.f, status=sl.status))
 
     def state_dict(self) -> dict:
         """A host copy of the whole solver state, for checkpoint and resume: fields,

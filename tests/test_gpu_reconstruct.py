@@ -349,3 +349,34 @@ def test_solver_checkpoint_resume_bitwise(dm, ora, method):
     assert [(s.E, s.f, s.iters, s.evals, s.status) for s in sv.slots] == want[1]
     with pytest.raises(ValueError):
         dm.Solver(spec, 2, dm.Bounds(), opt).load_state_dict(ck)
+
+
+def test_solver_iteration_trace(dm, ora):
+    """Per-iteration metrics: Solver.iterate(n, trace=list) records every slot's state
+    after each iteration it takes.  Accepted L-BFGS steps pass the Armijo test, so a
+    slot's loss never increases from one record to the next; the last records equal
+    the slots, and the run ends where an untraced solver of the same problem does (to
+    within the rounding of the history dots a new call recomputes)."""
+    shape = (64, 64)
+    ospec, S_des = target(ora, shape, (16,))
+    spec = dm.Spec(shape=shape, max_disp=(16,))
+    opt = dm.Opt(max_iter=200, tol_derr=0.0)
+    runs = []
+    for traced in (True, False):
+        sv = dm.Solver(spec, 2, dm.Bounds(), opt)
+        for b in range(2):
+            sv.phi[b].copy_(torch.from_numpy(synth.uniform(shape, 60 + b).astype(np.float32)))
+            sv.St[b].copy_(torch.from_numpy(S_des))
+        sv.start([0, 1])
+        tr = [] if traced else None
+        sv.iterate(12, trace=tr)
+        runs.append((sv, tr))
+    sv, tr = runs[0]
+    for b in range(2):
+        rec = [r for r in tr if r["slot"] == b]
+        assert [r["iters"] for r in rec] == list(range(1, 13))
+        fs = [r["f"] for r in rec]
+        assert all(f1 <= f0 for f0, f1 in zip(fs, fs[1:])), fs
+        assert rec[-1]["E"] == sv.slots[b].E and rec[-1]["evals"] == sv.slots[b].evals
+        E_plain = runs[1][0].slots[b].E
+        assert abs(sv.slots[b].E - E_plain) <= 1e-3 * E_plain, (sv.slots[b].E, E_plain)

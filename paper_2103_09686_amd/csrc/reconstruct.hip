@@ -800,7 +800,11 @@ dmcr_status Solver::start(float *x, const int *which, int nwhich, dmcr_slot *slo
     Plan p1;
     dmcr_spec one = spec1;
     RS(make_plan(&one, 1, &p1));
-    std::vector<double> hE(1), hEbc(1, 0.0);
+    // every started slot's E (and E^bc) lands in the pinned area; one synchronisation
+    // after the last evaluation (they share the batch-1 workspace in stream order)
+    void *pin = nullptr;
+    RT(pinned_stage((size_t)2 * B * sizeof(double), &pin));
+    double *pE = static_cast<double *>(pin), *pEbc = pE + B;
     for (int w = 0; w < nwhich; ++w) {
         const int b = which[w];
         float *xb = x + (int64_t)b * n;
@@ -821,12 +825,16 @@ dmcr_status Solver::start(float *x, const int *which, int nwhich, dmcr_slot *slo
             hipLaunchKernelGGL(k_zero, dim3(vblocks(n)), dim3(kV), 0, st, Y(0) + (int64_t)b * n, n);
         }
         RT(hipGetLastError());
-        RT(hipMemcpyAsync(hE.data(), Ed + b, 8, hipMemcpyDeviceToHost, st));
-        if (penalty) RT(hipMemcpyAsync(hEbc.data(), Ebcd + b, 8, hipMemcpyDeviceToHost, st));
-        RT(hipStreamSynchronize(st));
+        RT(hipMemcpyAsync(pE + b, Ed + b, 8, hipMemcpyDeviceToHost, st));
+        if (penalty) RT(hipMemcpyAsync(pEbc + b, Ebcd + b, 8, hipMemcpyDeviceToHost, st));
+    }
+    RT(hipStreamSynchronize(st));
+    for (int w = 0; w < nwhich; ++w) {
+        const int b = which[w];
+        const double E = pE[b], Ebc = penalty ? pEbc[b] : 0.0;
         dmcr_slot &sl = slots[b];
-        sl.E = hE[0];
-        sl.f = hE[0] + (penalty ? bd.kappa * hE[0] * hEbc[0] : 0.0);
+        sl.E = E;
+        sl.f = E + (penalty ? bd.kappa * E * Ebc : 0.0);
         sl.hist = 0;
         sl.iters = 0;
         sl.evals = 1;

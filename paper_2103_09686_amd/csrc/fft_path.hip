@@ -72,8 +72,8 @@ struct Tile {
 // tile geometry of the strided passes (k_cols, the axis-0 passes).  Where half_ex
 // holds (n = 512) they always take the two-phase exchange, so that the compiled
 // arithmetic is one and the same whatever the tile: with HX a 256-thread tile of
-// 16 pencils, else Tile's 8 pencils (fewer, smaller blocks would leave a small
-// pass's blocks too few).  The tile changes addresses only, so the results are
+// 16 pencils, else Tile's 8 pencils (128 threads), which gives a small pass twice
+// as many blocks.  The tile changes addresses only, so the results are
 // bitwise the same; the launch picks HX for passes with enough pencils to fill the
 // chip.  Elsewhere both are Tile.
 template <int L, bool HX>

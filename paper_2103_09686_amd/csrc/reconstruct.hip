@@ -644,8 +644,9 @@ bool opt_ok(const dmcr_opt *o)
 // directional dots, first steps, history flags): with a pinned destination the
 // copies are asynchronous and the search's one synchronisation covers them all,
 // where pageable ones are staged one at a time.  One area per host thread, grown
-// as needed and kept until the process ends; a solver call ends synchronised, so
-// no copy is in flight when it grows.
+// as needed and kept until the process ends.  A solver call that succeeds ends
+// synchronised; one that returned an error may have left copies into the area in
+// flight, so growing it first waits for the device.
 struct PinnedStage {
     void *p = nullptr;
     size_t bytes = 0;
@@ -656,7 +657,9 @@ hipError_t pinned_stage(size_t bytes, void **out)
 {
     if (tl_pin.bytes < bytes) {
         if (tl_pin.p) {
-            hipError_t e = hipHostFree(tl_pin.p);
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return e;
+            e = hipHostFree(tl_pin.p);
             tl_pin.p = nullptr;
             tl_pin.bytes = 0;
             if (e != hipSuccess) return e;

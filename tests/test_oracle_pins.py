@@ -279,6 +279,27 @@ def test_loss_gradient_fd_and_stationary_target(ora):
         assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-12)
 
 
+@pytest.mark.parametrize("desc", ["s2", "sbar"])
+def test_loss_gradient_fd_3d(ora, desc):
+    """The same check on a 3-D field with three unequal axes (two levels, two
+    channels, auto and cross pairs): every axis, the slowest included, carries
+    displacements, so a sign or index slip on any one axis of an adjoint shows."""
+    rng = np.random.default_rng(19)
+    sh = (8, 12, 10)
+    spec = ora.Spec(shape=sh, n_channels=2, n_levels=2, max_disp=(2, 1), descriptor=desc)
+    tgt = (rng.random((2,) + sh) < 0.3).astype(np.float64)
+    S_des = ora.descriptor(tgt, spec)
+    phi = rng.random((2,) + sh)
+    E, g, _ = ora.loss_grad(phi, S_des, spec)
+    h = 1e-5
+    for idx in [(0, 3, 5, 7), (1, 6, 1, 2), (0, 7, 11, 0), (1, 1, 8, 9)]:
+        p, m = phi.copy(), phi.copy()
+        p[idx] += h
+        m[idx] -= h
+        fd = (ora.loss_grad(p, S_des, spec)[0] - ora.loss_grad(m, S_des, spec)[0]) / (2 * h)
+        assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-13)
+
+
 def test_loss_normalisation(ora):
     """E with every residual equal to delta is delta^2 (Z normalisation); G = dE/dS."""
     spec = ora.Spec(shape=(16, 16), n_channels=2, n_levels=2, max_disp=(3, 2))
@@ -408,13 +429,14 @@ def test_penalised_loss_fd_inside_outside_and_on_the_box(ora):
     assert abs(fd_var - g[above]) > 1e-3 * abs(g[above])
 
 
-def _dense_lbfgs(ora, S_des, spec, x0, iters, c1, max_ls, bounds, kappa=1.0, lo=0.0, hi=1.0):
+def _dense_lbfgs(ora, S_des, spec, x0, iters, c1, max_ls, bounds, kappa=1.0, lo=0.0, hi=1.0, m=10, stats=None):
     """The driver's rules restated with the dense BFGS inverse (Nocedal & Wright
-    6.17 from gamma I) instead of the two-loop recursion: the valid pairs since the
-    last reset, gamma = s'y / y'y of the newest, a reset (no pairs, gamma = 1, first
+    6.17 from gamma I) instead of the two-loop recursion: the valid pairs among the
+    last m iterations since the last reset, gamma = s'y / y'y of the newest, a reset (no pairs, gamma = 1, first
     trial 1/|g|) after a failed search or a non-descent direction; with projection
     the direction is zeroed where it pushes an active bound outward and trials are
-    clipped; with the penalty, lambda = kappa E of the search's start point."""
+    clipped; with the penalty, lambda = kappa E of the search's start point.
+    stats, if given, counts the resets for a non-descent direction in stats["nondescent"]."""
     pen = bounds == "penalty"
     clip = (lambda v: v) if pen else (lambda v: np.clip(v, lo, hi))
 
@@ -431,12 +453,12 @@ def _dense_lbfgs(ora, S_des, spec, x0, iters, c1, max_ls, bounds, kappa=1.0, lo=
     x = clip(np.asarray(x0, np.float64))
     E, Ebc, g = ev(x)
     f = E + kappa * E * Ebc
-    pairs, gamma, moved = [], 1.0, False
+    ring, gamma, moved = [], 1.0, False   # one entry per iteration: its pair or None
     out = []
     n = x.size
     for _ in range(iters):
         H = gamma * np.eye(n)
-        for s_, y_ in pairs:
+        for s_, y_ in [p_ for p_ in ring if p_ is not None]:
             rho = 1.0 / float(y_ @ s_)
             V = np.eye(n) - rho * np.outer(y_, s_)
             H = V.T @ H @ V + rho * np.outer(s_, s_)
@@ -449,8 +471,10 @@ def _dense_lbfgs(ora, S_des, spec, x0, iters, c1, max_ls, bounds, kappa=1.0, lo=
 
         d = proj(-(H @ g.ravel()).reshape(x.shape))
         if not np.sum(g * d) < 0:
-            pairs, gamma, moved = [], 1.0, False
+            ring, gamma, moved = [None] * len(ring), 1.0, False
             d = proj(-g)
+            if stats is not None:
+                stats["nondescent"] = stats.get("nondescent", 0) + 1
         a = 1.0 if moved else 1.0 / np.sqrt(np.sum(g * g))
         lam = kappa * E
         ok = False
@@ -462,14 +486,16 @@ def _dense_lbfgs(ora, S_des, spec, x0, iters, c1, max_ls, bounds, kappa=1.0, lo=
                 ok = True
                 break
             a /= 2
+        pair = None
         if ok:
             s_, y_ = (xt - x).ravel(), (gt - g).ravel()
             if s_ @ y_ > np.finfo(float).eps * (y_ @ y_) and y_ @ y_ > 0:
-                pairs.append((s_, y_))
+                pair = (s_, y_)
                 gamma = float(s_ @ y_) / float(y_ @ y_)
             x, E, g, f, moved = xt, Et, gt, Et + kappa * Et * Ebct, True
-        else:
-            pairs, gamma, moved = [], 1.0, False
+        ring = (ring + [pair])[-m:]
+        if not ok:
+            ring, gamma, moved = [None] * len(ring), 1.0, False
         out.append((x.copy(), f))
     return out
 
@@ -493,6 +519,26 @@ def test_projected_lbfgs_history_gamma_and_reset(ora):
     assert ev[3] == 5 and Es[3] == Es[2] and ev[4] < 5 and Es[4] < Es[3]
 
 
+@pytest.mark.parametrize("seed,m", [(61, 10), (63, 3)])
+def test_projected_lbfgs_memory_window_and_nondescent_reset(ora, seed, m):
+    """Twelve projected iterations against the dense restatement with a memory of
+    m iterations: with m = 3 the oldest pairs leave the window from the fourth
+    iteration on; in both runs a projected quasi-Newton direction stops being a
+    descent direction (the restatement counts it), which clears the history and
+    takes the projected steepest step."""
+    rng = np.random.default_rng(seed)
+    spec = ora.Spec(shape=(8, 8), max_disp=(2,))
+    tgt = (rng.random((1, 8, 8)) < 0.4).astype(np.float64)
+    S_des = ora.descriptor(tgt, spec)
+    x0 = rng.random((1, 8, 8))
+    stats = {}
+    ref = _dense_lbfgs(ora, S_des, spec, x0, 12, 1e-4, 20, "project", m=m, stats=stats)
+    assert stats.get("nondescent", 0) >= 1
+    x, Es, ev = ora.reconstruct_lbfgs_projected(S_des, spec, x0, 12, m=m)
+    np.testing.assert_allclose(x, ref[-1][0], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(Es, [r[1] for r in ref], rtol=1e-9)
+
+
 def test_penalty_lbfgs_matches_dense_restatement(ora):
     """Penalty mode of the oracle's L-BFGS (no projection; lambda = kappa E of the
     search's start point in the Armijo test, the accepted point's own lambda in f)
@@ -510,6 +556,29 @@ def test_penalty_lbfgs_matches_dense_restatement(ora):
     np.testing.assert_allclose(x, ref[-1][0], rtol=0, atol=1e-12)
     np.testing.assert_allclose(Es, [r[1] for r in ref], rtol=1e-10)
     assert np.any(x < 0.0) or np.any(x > 1.0)
+
+
+def test_penalty_lbfgs_start_objective_includes_penalty(ora):
+    """Penalty mode from a start whose penalty term outweighs the data term
+    (kappa E^bc > 1: eight voxels up to 2 above the box, kappa = 1e4).  The first
+    trial step is short and leaves E^bc almost unchanged, so the first Armijo test
+    passes only against the start's full L = E + lambda E^bc (Sec. 3.1, eq.
+    L_func_dMCR); measured against E alone, every trial of that search would fail."""
+    rng = np.random.default_rng(70)
+    n = 16
+    spec = ora.Spec(shape=(n, n), max_disp=(2,))
+    tgt = (rng.random((1, n, n)) < 0.35).astype(np.float64)
+    S_des = ora.descriptor(tgt, spec)
+    x0 = rng.random((1, n, n))
+    idx = rng.choice(n * n, 8, replace=False)
+    x0.reshape(-1)[idx] = 1.0 + 2.0 * rng.random(8)
+    kappa = 1e4
+    assert kappa * _penalty_as_printed(x0) > 1.0
+    ref = _dense_lbfgs(ora, S_des, spec, x0, 3, 1e-4, 20, "penalty", kappa=kappa)
+    x, Es, ev = ora.reconstruct_lbfgs_projected(S_des, spec, x0, 3, bounds="penalty", kappa=kappa)
+    assert ev == [1, 1, 1]
+    np.testing.assert_allclose(x, ref[-1][0], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(Es, [r[1] for r in ref], rtol=1e-10)
 
 
 def test_level_slices_and_upsampling(ora):
@@ -572,6 +641,15 @@ def test_sampled_descriptor_and_reference_reconstructions(ora):
     x2, E2 = ora.reconstruct_coarse_to_fine(S2, two, rng.random((1, 16, 16)), maxiter=15)
     assert np.all((x2 >= 0) & (x2 <= 1))
     assert E2 == pytest.approx(ora.loss(ora.descriptor(x2, two), S2, two)[0], rel=1e-12)
+    # a start that is constant over each coarsest-level block, against its own
+    # descriptor: every level starts at zero error, so each stage hands the field on
+    # unchanged, which holds only if the coarse result is repeated over its 2^d
+    # children with its values carried over (not scaled)
+    three = ora.Spec(shape=(16, 16), n_levels=3, max_disp=(3, 2, 1))
+    x0 = np.kron(rng.random((1, 4, 4)), np.ones((1, 4, 4)))
+    x3, E3 = ora.reconstruct_coarse_to_fine(ora.descriptor(x0, three), three, x0, maxiter=15)
+    np.testing.assert_allclose(x3, x0, rtol=0, atol=1e-15)
+    assert E3 == 0.0
 
 
 def test_oracle_helpers_half_set_pairs_weights_and_Z():

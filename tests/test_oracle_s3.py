@@ -129,3 +129,24 @@ def test_s3_loss_gradient_fd(ora, desc):
         m[idx] -= h
         fd = (ora.loss_grad(p, S_des, spec)[0] - ora.loss_grad(m, S_des, spec)[0]) / (2 * h)
         assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-13)
+
+
+@pytest.mark.parametrize("desc", ["s2", "sbar"])
+def test_s3_loss_gradient_fd_3d(ora, desc):
+    """Three-point gradient against central differences on a 3-D field with three
+    unequal axes, so that every axis of the vectors r_a, r_b, the slowest included,
+    enters the adjoint's shifted reads."""
+    rng = np.random.default_rng(57)
+    sh = (6, 4, 8)
+    spec = ora.Spec(shape=sh, n_channels=1, n_levels=1, max_disp=(1,), s3_max_disp=1, descriptor=desc)
+    tgt = (rng.random((1,) + sh) < 0.35).astype(np.float64)
+    S_des = ora.descriptor(tgt, spec)
+    phi = rng.random((1,) + sh)
+    E, g, _ = ora.loss_grad(phi, S_des, spec)
+    h = 1e-5
+    for idx in [(0, 0, 0, 0), (0, 3, 1, 6), (0, 5, 3, 2), (0, 2, 2, 7)]:
+        p, m = phi.copy(), phi.copy()
+        p[idx] += h
+        m[idx] -= h
+        fd = (ora.loss_grad(p, S_des, spec)[0] - ora.loss_grad(m, S_des, spec)[0]) / (2 * h)
+        assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-13)

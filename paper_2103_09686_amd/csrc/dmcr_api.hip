@@ -328,36 +328,52 @@ hipError_t run_pyramid(const Plan &p, const float *phi, const Ws &ws, hipStream_
 // a side lane while the caller's stream finishes the forward and builds the
 // cotangent transforms.  Every lane joins the caller's stream before the call
 // returns, so the caller sees ordinary stream semantics.  Pools are per host
-// thread (and per device), so concurrent callers never share an event.
+// thread and per device, so concurrent callers never share an event; each is
+// created on its first use and kept until the process ends.
 struct Lanes {
     static constexpr int kSide = 3;
     static constexpr int kEvents = 96;
-    int device = -1;
+    bool ready = false;
     hipStream_t side[kSide] = {};
     hipEvent_t ev[kEvents] = {};
     int next = 0;
 
+    // on the current device; a failure destroys what it created, so a later call
+    // starts again from nothing
     hipError_t init()
     {
-        int dev = -1;
-        hipError_t e = hipGetDevice(&dev);
-        if (e != hipSuccess) return e;
-        if (dev == device) return hipSuccess;
-        for (int i = 0; i < kSide; ++i) {
-            e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
-            if (e != hipSuccess) return e;
+        if (ready) return hipSuccess;
+        hipError_t e = hipSuccess;
+        int ns = 0, ne = 0;
+        for (; ns < kSide && e == hipSuccess; ++ns)
+            if ((e = hipStreamCreateWithFlags(&side[ns], hipStreamNonBlocking)) != hipSuccess) break;
+        for (; e == hipSuccess && ne < kEvents; ++ne)
+            if ((e = hipEventCreateWithFlags(&ev[ne], hipEventDisableTiming)) != hipSuccess) break;
+        if (e != hipSuccess) {
+            for (int i = 0; i < ne; ++i) (void)hipEventDestroy(ev[i]);
+            for (int i = 0; i < ns; ++i) (void)hipStreamDestroy(side[i]);
+            return e;
         }
-        for (int i = 0; i < kEvents; ++i) {
-            e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
-            if (e != hipSuccess) return e;
-        }
-        device = dev;
+        ready = true;
         return hipSuccess;
     }
     hipEvent_t event() { return ev[next++ % kEvents]; }
 };
 
-thread_local Lanes tl_lanes;
+constexpr int kMaxDevices = 16;
+thread_local Lanes tl_lanes[kMaxDevices];
+
+// this thread's lanes on the current device
+hipError_t lanes_here(Lanes **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if ((e = tl_lanes[dev].init()) != hipSuccess) return e;
+    *out = &tl_lanes[dev];
+    return hipSuccess;
+}
 
 struct Sched {
     Lanes *ln;
@@ -413,12 +429,13 @@ hipError_t make_sched(const Plan &p, hipStream_t st, Sched *s)
     const bool eager_multi = (int64_t)p.B * p.C * p.lv[0].N >= kLaneMinVoxels ||
                              ((p.desc != DMCR_DESC_S2 || p.s3) && p.L > 1);
     const bool multi = eager_multi || (cs == hipStreamCaptureStatusActive && p.L > 1);
+    Lanes *ln = nullptr;   // dereferenced only when multi
     if (multi) {
-        hipError_t e = tl_lanes.init();
+        hipError_t e = lanes_here(&ln);
         if (e != hipSuccess) return e;
-        tl_lanes.next = 0;
+        ln->next = 0;
     }
-    *s = Sched{&tl_lanes, st, multi, eager_multi && p.L == 1};
+    *s = Sched{ln, st, multi, eager_multi && p.L == 1};
     return hipSuccess;
 }
 
@@ -517,7 +534,7 @@ dmcr_status loss_grad_internal(const Plan &p, const float *phi, const double *St
     if (lanes)
         DMCR_TRY(make_sched(p, st, &sc));
     else
-        sc = Sched{&tl_lanes, st, false, false};
+        sc = Sched{nullptr, st, false, false};
     const bool keep = (p.flags & DMCR_FLAG_RECOMPUTE) == 0;
     hipEvent_t x_free[kMaxLevels] = {};
     if (!keep && sc.side_recompute)

@@ -46,6 +46,9 @@ WORKLOADS = {
     "2d256sbar": dict(desc="2D 256^2 two-phase, soft-threshold descriptor Sbar (alpha=10), P=31, "
                            "3 levels (256/128/64), direct path",
                       shape=(256, 256), C=1, L=3, P=31, recompute=False, batch=1, descriptor=1),
+    # the short-displacement case that the shifted-product (direct) path is for
+    "2d256direct": dict(desc="2D 256^2 two-phase, S2 product form, P=8, 1 level, batch 64, direct path",
+                        shape=(256, 256), C=1, L=1, P=8, recompute=False, batch=64, path=2),
     "2d256s3": dict(desc="2D 256^2 two-phase, S2 (P=31, FFT) + three-point S3 (P3=4: 81 vectors, 3321 pairs), "
                          "3 levels (256/128/64), batch 8",
                     shape=(256, 256), C=1, L=3, P=31, recompute=False, batch=8, s3=4),
@@ -72,6 +75,12 @@ FMA_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Peak terms/s = 256 CUs * 4 SIMDs * 16 lanes * 2.4 GHz / slots.
 VALU_LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 SOFT_SLOTS = {"direct_fwd_soft": 13, "direct_adj_soft": 14}
+
+# Product-form pair terms on the direct path are one FP32 multiply-add each: the
+# forward adds phi_i(x) phi_j(x + r) for every entry r of the block, the adjoint
+# adds K(r) phi_j(x + r) over the full box for every channel pair.  They run
+# against the same 78.6 TFLOP/s FMA rate (no packed FP32).
+DIRECT_KERNELS = ("direct_fwd", "direct_adj")
 
 
 # the sources the FFT-path kernels (the dominant kernels of every workload) compile from
@@ -399,7 +408,8 @@ def main():
     if args.fused_planes:
         flags |= dmcr.FLAG_FUSED_PLANES
     desc = wl.get("descriptor", dmcr.DESC_S2)
-    spec = dmcr.make_spec(shape, C, L, P, flags=flags, descriptor=desc, s3_max_disp=wl.get("s3", 0))
+    spec = dmcr.make_spec(shape, C, L, P, flags=flags, descriptor=desc, s3_max_disp=wl.get("s3", 0),
+                          path=wl.get("path", dmcr.PATH_AUTO))
     K = dmcr.dmcr_descriptor_size(spec)
     N = int(np.prod(shape))
 
@@ -523,6 +533,20 @@ def main():
         roofline = dict(bound="alu", kernel=dom["name"], achieved=round(achieved, 1), peak=round(peak, 1),
                         unit="Gterm/s", frac=round(achieved / peak, 4), traffic=None,
                         avg_us=round(dom["avg_us"], 2), terms_per_launch=per_launch)
+    elif dom["name"] in DIRECT_KERNELS:
+        # multiply-adds per step: forward N_l * K_l (every pair), adjoint N_l * C^2 * box_l^d
+        d = len(shape)
+        fl = {"direct_fwd": 0.0, "direct_adj": 0.0}
+        for l in range(L):
+            Nl = N >> (d * l)
+            box = 2 * level_P(spec, l) + 1
+            fl["direct_fwd"] += 2.0 * B * Nl * K_level(spec, l)
+            fl["direct_adj"] += 2.0 * B * Nl * C * C * box ** d
+        per_launch = fl[dom["name"]] / L
+        achieved = per_launch / (dom["avg_us"] * 1e-6) / 1e12
+        roofline = dict(bound="alu", kernel=dom["name"], achieved=round(achieved, 2), peak=round(FMA_PEAK_TFLOPS, 1),
+                        unit="TFLOP/s", frac=round(achieved / FMA_PEAK_TFLOPS, 4), traffic=None,
+                        avg_us=round(dom["avg_us"], 2), flops_per_launch=per_launch)
     elif dom["name"].startswith(("s3_fwd", "s3_adj_terms", "s3_adj_mf")):
         d = len(shape)
         flops = 0.0
@@ -552,6 +576,12 @@ def main():
                          achieved_GBps=round(total_bytes / (ms * 1e-3) / 1e9, 1),
                          frac=round(total_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                          kernel_ms_sum=round(prof_ms, 4))
+    if roofline["bound"] == "alu" and roofline["kernel"] in DIRECT_KERNELS:
+        # the whole step against the FMA rate: every product term at two flops
+        flops = sum(fl.values())
+        step_roofline = dict(bound="alu", flops_per_step=flops,
+                             frac=round(flops / (ms * 1e-3) / (FMA_PEAK_TFLOPS * 1e12), 4),
+                             kernel_ms_sum=round(prof_ms, 4))
     if roofline["bound"] == "alu" and roofline["unit"] == "Gterm/s":
         # the whole step against FP32 issue: every soft term at its slot cost
         slots = sum(terms[k] * SOFT_SLOTS[k] for k in terms)
@@ -565,7 +595,7 @@ def main():
                vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload=wl["desc"], shape=list(shape), channels=C, levels=L,
                            max_disp=[level_P(spec, l) for l in range(L)], K=K, batch=B,
-                           path="direct" if desc else "fft",
+                           path="direct" if desc or wl.get("path") == dmcr.PATH_DIRECT else "fft",
                            descriptor=["s2", "sbar", "stilde"][desc], s3_max_disp=spec.s3_max_disp,
                            recompute=wl["recompute"], fused_planes_256=bool(args.fused_planes),
                            parallelism="single GPU"),

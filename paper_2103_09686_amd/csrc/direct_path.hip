@@ -30,6 +30,7 @@ struct Geo {
     int n0, n1, n2;     // level shape (2-D: n2 = 1)
     int t0, t1, t2;     // tile edge
     int h0, h1, h2;     // halo tile edge = t + 2P (2-D: h2 = t2 = 1)
+    int p1;             // LDS pitch of the halo's axis-1 index (halo_pitch1), >= h1
     int P, box;
     int nt0, nt1, nt2;  // tiles per axis
 };
@@ -41,11 +42,43 @@ __device__ __forceinline__ int wrapi(int i, int n)
 }
 
 // Load the halo tile of `f` (one channel, [n0][n1][n2]) whose origin is the
-// tile origin minus P, into H[h0][h1][h2].
+// tile origin minus P, into H[h0][p1][h2] (columns h1 .. p1 - 1 unused).
+// i = (x d1 + y) d2 + z split into (x, y, z); in 2-D (d2 = 1) with one division
+__device__ __forceinline__ void split3(int i, int d1, int d2, bool two_d, int &x, int &y, int &z)
+{
+    if (two_d) {
+        x = i / d1;
+        y = i - x * d1;
+        z = 0;
+    } else {
+        z = i % d2;
+        const int r = i / d2;
+        y = r % d1;
+        x = r / d1;
+    }
+}
+
 template <int NT = kT>
 __device__ __forceinline__ void load_halo(const Geo &g, const float *__restrict__ f, int o0, int o1,
                                           int o2, float *H)
 {
+    if (g.ndim == 2) {
+        // halo rows by wave, columns by lane: no index division, and the periodic
+        // wrap is one conditional add or subtract (the index lies in [-P, n + P)
+        // and P < n / 2)
+        const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        for (int x = wave; x < g.h0; x += NT / 64) {
+            int i0 = o0 + x - g.P;
+            i0 = i0 < 0 ? i0 + g.n0 : (i0 >= g.n0 ? i0 - g.n0 : i0);
+            const float *row = f + (int64_t)i0 * g.n1;
+            for (int y = lane; y < g.h1; y += 64) {
+                int i1 = o1 + y - g.P;
+                i1 = i1 < 0 ? i1 + g.n1 : (i1 >= g.n1 ? i1 - g.n1 : i1);
+                H[x * g.p1 + y] = row[i1];
+            }
+        }
+        return;
+    }
     const int vol = g.h0 * g.h1 * g.h2;
     for (int idx = threadIdx.x; idx < vol; idx += NT) {
         const int z = idx % g.h2;
@@ -55,7 +88,7 @@ __device__ __forceinline__ void load_halo(const Geo &g, const float *__restrict_
         const int i0 = wrapi(o0 + x - g.P, g.n0);
         const int i1 = wrapi(o1 + y - g.P, g.n1);
         const int i2 = (g.ndim == 3) ? wrapi(o2 + z - g.P, g.n2) : 0;
-        H[idx] = f[((int64_t)i0 * g.n1 + i1) * g.n2 + i2];
+        H[(x * g.p1 + y) * g.h2 + z] = f[((int64_t)i0 * g.n1 + i1) * g.n2 + i2];
     }
 }
 
@@ -109,7 +142,8 @@ __global__ __launch_bounds__(kT) void k_direct_fwd(DirFwdArgs a)
     const int bp = blockIdx.z;
     const int p = bp % a.npairs;
     const int64_t b = bp / a.npairs;
-    const int tz = tile % g.nt2, ty = (tile / g.nt2) % g.nt1, tx = tile / (g.nt2 * g.nt1);
+    int tx, ty, tz;
+    split3(tile, g.nt1, g.nt2, g.ndim == 2, tx, ty, tz);
     const int o0 = tx * g.t0, o1 = ty * g.t1, o2 = tz * g.t2;
     const int tvol = g.t0 * g.t1 * g.t2;
     float *Ta = sm;
@@ -117,10 +151,8 @@ __global__ __launch_bounds__(kT) void k_direct_fwd(DirFwdArgs a)
     const float *fa = a.phi + (b * a.C + a.pi[p]) * a.N;
     const float *fb = a.phi + (b * a.C + a.pj[p]) * a.N;
     for (int idx = threadIdx.x; idx < tvol; idx += kT) {
-        const int z = idx % g.t2;
-        const int r = idx / g.t2;
-        const int y = r % g.t1;
-        const int x = r / g.t1;
+        int x, y, z;
+        split3(idx, g.t1, g.t2, g.ndim == 2, x, y, z);
         Ta[idx] = fa[((int64_t)(o0 + x) * g.n1 + (o1 + y)) * g.n2 + (o2 + z)];
     }
     load_halo(g, fb, o0, o1, o2, Hb);
@@ -140,7 +172,7 @@ __global__ __launch_bounds__(kT) void k_direct_fwd(DirFwdArgs a)
     }
     const int pz = (g.ndim == 3) ? r2 + g.P : 0;
     double acc = 0.0;
-    const float *hb = Hb + ((r0 + g.P) * g.h1 + (r1 + g.P)) * g.h2 + pz;
+    const float *hb = Hb + ((r0 + g.P) * g.p1 + (r1 + g.P)) * g.h2 + pz;
     if constexpr (TX > 0) {
 #pragma unroll
         for (int x = 0; x < TX; ++x) {
@@ -149,7 +181,7 @@ __global__ __launch_bounds__(kT) void k_direct_fwd(DirFwdArgs a)
             for (int y = 0; y < TY; ++y) {
                 const float *arow = Ta + (x * TY + y) * TZ;
                 // 2-D (TZ = 1): h2 = 1, so the row offsets are constants the LDS reads carry
-                const float *brow = hb + (TZ == 1 ? x * g.h1 + y : (x * g.h1 + y) * g.h2);
+                const float *brow = hb + (TZ == 1 ? x * g.p1 + y : (x * g.p1 + y) * g.h2);
 #pragma unroll
                 for (int z = 0; z < TZ; ++z) slab += pair_term<SOFT>(arow[z], brow[z], a.soft);
             }
@@ -160,7 +192,7 @@ __global__ __launch_bounds__(kT) void k_direct_fwd(DirFwdArgs a)
             float slab = 0.f;
             for (int y = 0; y < g.t1; ++y) {
                 const float *arow = Ta + (x * g.t1 + y) * g.t2;
-                const float *brow = hb + (x * g.h1 + y) * g.h2;
+                const float *brow = hb + (x * g.p1 + y) * g.h2;
                 for (int z = 0; z < g.t2; ++z) slab += pair_term<SOFT>(arow[z], brow[z], a.soft);
             }
             acc += (double)slab;
@@ -255,16 +287,19 @@ __global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
     const int tile = blockIdx.x;
     const int c = blockIdx.y;
     const int64_t b = blockIdx.z;
-    const int tz = tile % g.nt2, ty = (tile / g.nt2) % g.nt1, tx = tile / (g.nt2 * g.nt1);
+    int tx, ty, tz;
+    split3(tile, g.nt1, g.nt2, g.ndim == 2, tx, ty, tz);
     const int o0 = tx * g.t0, o1 = ty * g.t1, o2 = tz * g.t2;
     const int tvol = g.t0 * g.t1 * g.t2;
-    const int hvol = g.h0 * g.h1 * g.h2;
+    const int hvol = g.h0 * g.p1 * g.h2;
     float *red = sm + hvol;            // [kAdjSplit][kT] partial sums
-    // this thread's output voxel and its share of the box rows
-    const int v = threadIdx.x % kT, split = threadIdx.x / kT;
-    const int vz = v % g.t2;
-    const int vy = (v / g.t2) % g.t1;
-    const int vx = v / (g.t2 * g.t1);
+    // this thread's output voxel and its share of the box rows; kT is a multiple of
+    // the wave size, so split is the same in every lane of a wave, and saying so lets
+    // the kernel rows be read by scalar loads instead of a vector load per term
+    static_assert(kT % 64 == 0, "a wave must not straddle two row shares");
+    const int v = threadIdx.x % kT, split = __builtin_amdgcn_readfirstlane(threadIdx.x / kT);
+    int vx, vy, vz;
+    split3(v, g.t1, g.t2, g.ndim == 2, vx, vy, vz);
     const bool active = v < tvol;
     const int64_t vox = ((int64_t)(o0 + vx) * g.n1 + (o1 + vy)) * g.n2 + (o2 + vz);
     // own value phi_c(x), needed by the soft pair term
@@ -278,7 +313,7 @@ __global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
             const float *Kc = a.KB0 + ((b * a.C + c) * a.C + j) * a.vol;
             if (g.ndim == 2) {
                 for (int r0 = split; r0 < g.box; r0 += kAdjSplit) {
-                    const float *hrow = sm + (vx + r0) * g.h1 + vy;
+                    const float *hrow = sm + (vx + r0) * g.p1 + vy;
                     const float *krow = Kc + r0 * g.box;
 #pragma unroll 8
                     for (int r1 = 0; r1 < g.box; ++r1) acc += krow[r1] * adj_term<SOFT>(ownk, hrow[r1], a.soft);
@@ -286,7 +321,7 @@ __global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
             } else {
                 for (int r0 = split; r0 < g.box; r0 += kAdjSplit)
                     for (int r1 = 0; r1 < g.box; ++r1) {
-                        const float *hrow = sm + ((vx + r0) * g.h1 + (vy + r1)) * g.h2 + vz;
+                        const float *hrow = sm + ((vx + r0) * g.p1 + (vy + r1)) * g.h2 + vz;
                         const float *krow = Kc + (r0 * g.box + r1) * g.box;
 #pragma unroll 8
                         for (int r2 = 0; r2 < g.box; ++r2) acc += krow[r2] * adj_term<SOFT>(ownk, hrow[r2], a.soft);
@@ -312,6 +347,24 @@ Soft make_soft(const Plan &p)
                 (float)(p.c1 * p.alpha)};
 }
 
+// LDS pitch of the halo's axis-1 rows for tile t at displacement range P.  In
+// 2-D a wave of the adjoint reads four tile rows of 16 voxels (two per
+// half-wave), one row pitch apart: a pitch of 16 mod 32 floats puts the two rows
+// of a half-wave in disjoint banks of the 32, where a pitch of 32 (P = 8) or 64
+// (P = 24) puts them in the same banks.  The padded pitch is taken where the
+// padded halo still fits the LDS budget, else the plain one (which decides
+// support).  The 3-D tile's wave reads rows h2 apart within one plane and keeps
+// the plain pitch.
+int halo_pitch1(int ndim, const int t[3], int P)
+{
+    const int64_t h0 = t[0] + 2 * P, h1 = t[1] + 2 * P, h2 = ndim == 3 ? t[2] + 2 * P : 1;
+    if (ndim != 2) return (int)h1;
+    const int64_t pad = h1 + (48 - h1 % 32) % 32;
+    const int64_t tvol = (int64_t)t[0] * t[1] * t[2];
+    const int64_t extra = tvol > (int64_t)kAdjSplit * kT ? tvol : (int64_t)kAdjSplit * kT;
+    return (size_t)(extra + h0 * pad * h2) * sizeof(float) <= kDirectLds ? (int)pad : (int)h1;
+}
+
 Geo make_geo(const Plan &p, int l)
 {
     const LevelPlan &L = p.lv[l];
@@ -328,6 +381,7 @@ Geo make_geo(const Plan &p, int l)
     g.h0 = g.t0 + 2 * L.P;
     g.h1 = g.t1 + 2 * L.P;
     g.h2 = p.ndim == 3 ? g.t2 + 2 * L.P : 1;
+    g.p1 = halo_pitch1(p.ndim, L.tile, L.P);
     g.nt0 = g.n0 / g.t0;
     g.nt1 = g.n1 / g.t1;
     g.nt2 = g.n2 / g.t2;
@@ -389,7 +443,7 @@ hipError_t direct_forward_level(const Plan &p, int l, const float *phi, float *S
     }
     a.kmax = kmax;
     const int tvol = a.g.t0 * a.g.t1 * a.g.t2;
-    const size_t lds = (size_t)(tvol + a.g.h0 * a.g.h1 * a.g.h2) * sizeof(float);
+    const size_t lds = (size_t)(tvol + a.g.h0 * a.g.p1 * a.g.h2) * sizeof(float);
     dim3 grid((unsigned)a.ntiles, (unsigned)((kmax + kT - 1) / kT), (unsigned)(p.B * p.npairs));
     const double fbytes = (double)p.B * p.C * L.N * 4 + (double)p.B * p.npairs * a.ntiles * kmax * 8;
     const bool full2 = p.ndim == 2 && a.g.t0 == 16 && a.g.t1 == 16;
@@ -442,7 +496,7 @@ hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const fl
     a.vol = 1;
     for (int d = 0; d < p.ndim; ++d) a.vol *= L.box;
     a.invN = (float)(1.0 / (double)L.N);
-    const size_t lds = (size_t)(a.g.h0 * a.g.h1 * a.g.h2 + kAdjSplit * kT) * sizeof(float);
+    const size_t lds = (size_t)(a.g.h0 * a.g.p1 * a.g.h2 + kAdjSplit * kT) * sizeof(float);
     dim3 grid((unsigned)L.n_tiles, (unsigned)p.C, (unsigned)p.B);
     const double bytes = 2.0 * p.B * p.C * L.N * 4 + (double)p.B * p.C * p.C * a.vol * 4;
     if (p.desc == DMCR_DESC_S2) return launch("direct_adj", bytes, k_direct_adj<false>, grid, dim3(kAdjT), lds, st, a);

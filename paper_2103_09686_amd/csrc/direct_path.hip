@@ -273,15 +273,24 @@ __device__ __forceinline__ float adj_term(float ownk, float other, const Soft &s
     }
 }
 
-// The adjoint has one output per voxel but |box| terms each: kAdjSplit threads
-// share a voxel, each taking every kAdjSplit-th box row r0, so a tile of 256
-// voxels keeps 16 waves busy; the partial sums are added in split order.
-constexpr int kAdjSplit = 4;
-constexpr int kAdjT = kT * kAdjSplit;
+// The adjoint has one output per voxel but |box| terms each: adj_split threads
+// share a voxel, each taking every adj_split-th box row r0; the partial sums are
+// added in split order.  The soft term (exp and reciprocal) is bound by issue and
+// takes four shares, so that a tile of 256 voxels keeps 16 waves busy; the product
+// term is one multiply-add, and two shares spread the block's set-up (halo load,
+// index and address arithmetic) over twice the terms.
+constexpr int kAdjSplit = 4;   // the most shares any variant takes (LDS budget)
+template <bool SOFT>
+constexpr int adj_split()
+{
+    return SOFT ? 4 : 2;
+}
 
 template <bool SOFT>
-__global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
+__global__ __launch_bounds__(kT * adj_split<SOFT>()) void k_direct_adj(DirAdjArgs a)
 {
+    constexpr int kSplit = adj_split<SOFT>();
+    constexpr int kAdjT = kT * kSplit;
     extern __shared__ float sm[];
     const Geo &g = a.g;
     const int tile = blockIdx.x;
@@ -292,7 +301,7 @@ __global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
     const int o0 = tx * g.t0, o1 = ty * g.t1, o2 = tz * g.t2;
     const int tvol = g.t0 * g.t1 * g.t2;
     const int hvol = g.h0 * g.p1 * g.h2;
-    float *red = sm + hvol;            // [kAdjSplit][kT] partial sums
+    float *red = sm + hvol;            // [kSplit][kT] partial sums
     // this thread's output voxel and its share of the box rows; kT is a multiple of
     // the wave size, so split is the same in every lane of a wave, and saying so lets
     // the kernel rows be read by scalar loads instead of a vector load per term
@@ -312,14 +321,14 @@ __global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
         if (active) {
             const float *Kc = a.KB0 + ((b * a.C + c) * a.C + j) * a.vol;
             if (g.ndim == 2) {
-                for (int r0 = split; r0 < g.box; r0 += kAdjSplit) {
+                for (int r0 = split; r0 < g.box; r0 += kSplit) {
                     const float *hrow = sm + (vx + r0) * g.p1 + vy;
                     const float *krow = Kc + r0 * g.box;
 #pragma unroll 8
                     for (int r1 = 0; r1 < g.box; ++r1) acc += krow[r1] * adj_term<SOFT>(ownk, hrow[r1], a.soft);
                 }
             } else {
-                for (int r0 = split; r0 < g.box; r0 += kAdjSplit)
+                for (int r0 = split; r0 < g.box; r0 += kSplit)
                     for (int r1 = 0; r1 < g.box; ++r1) {
                         const float *hrow = sm + ((vx + r0) * g.p1 + (vy + r1)) * g.h2 + vz;
                         const float *krow = Kc + (r0 * g.box + r1) * g.box;
@@ -335,7 +344,7 @@ __global__ __launch_bounds__(kAdjT) void k_direct_adj(DirAdjArgs a)
     if (split == 0 && active) {
         float t = red[v];
 #pragma unroll
-        for (int q = 1; q < kAdjSplit; ++q) t += red[q * kT + v];
+        for (int q = 1; q < kSplit; ++q) t += red[q * kT + v];
         a.grad[(b * a.C + c) * a.N + vox] = t * (SOFT ? a.soft.c1a : 1.f) * a.invN;
     }
 }
@@ -499,8 +508,9 @@ hipError_t direct_adjoint_level(const Plan &p, int l, const float *phi, const fl
     const size_t lds = (size_t)(a.g.h0 * a.g.p1 * a.g.h2 + kAdjSplit * kT) * sizeof(float);
     dim3 grid((unsigned)L.n_tiles, (unsigned)p.C, (unsigned)p.B);
     const double bytes = 2.0 * p.B * p.C * L.N * 4 + (double)p.B * p.C * p.C * a.vol * 4;
-    if (p.desc == DMCR_DESC_S2) return launch("direct_adj", bytes, k_direct_adj<false>, grid, dim3(kAdjT), lds, st, a);
-    return launch("direct_adj_soft", bytes, k_direct_adj<true>, grid, dim3(kAdjT), lds, st, a);
+    if (p.desc == DMCR_DESC_S2)
+        return launch("direct_adj", bytes, k_direct_adj<false>, grid, dim3(kT * adj_split<false>()), lds, st, a);
+    return launch("direct_adj_soft", bytes, k_direct_adj<true>, grid, dim3(kT * adj_split<true>()), lds, st, a);
 }
 
 }  // namespace dmcr

@@ -177,13 +177,23 @@ __global__ __launch_bounds__(kT) void k_direct_fwd(DirFwdArgs a)
 #pragma unroll
         for (int x = 0; x < TX; ++x) {
             float slab = 0.f;
+            // tile row x, the same for every lane: four values per LDS read (the tile
+            // starts the block's LDS, and a row is a multiple of 16 floats)
+            float av[TY * TZ];
+#pragma unroll
+            for (int i = 0; i < TY * TZ / 4; ++i) {
+                const float4 v4 = reinterpret_cast<const float4 *>(Ta + x * TY * TZ)[i];
+                av[4 * i] = v4.x;
+                av[4 * i + 1] = v4.y;
+                av[4 * i + 2] = v4.z;
+                av[4 * i + 3] = v4.w;
+            }
 #pragma unroll
             for (int y = 0; y < TY; ++y) {
-                const float *arow = Ta + (x * TY + y) * TZ;
                 // 2-D (TZ = 1): h2 = 1, so the row offsets are constants the LDS reads carry
                 const float *brow = hb + (TZ == 1 ? x * g.p1 + y : (x * g.p1 + y) * g.h2);
 #pragma unroll
-                for (int z = 0; z < TZ; ++z) slab += pair_term<SOFT>(arow[z], brow[z], a.soft);
+                for (int z = 0; z < TZ; ++z) slab += pair_term<SOFT>(av[y * TZ + z], brow[z], a.soft);
             }
             acc += (double)slab;
         }

@@ -330,11 +330,15 @@ __global__ __launch_bounds__(kT * adj_split<SOFT>()) void k_direct_adj(DirAdjArg
         __syncthreads();
         if (active) {
             const float *Kc = a.KB0 + ((b * a.C + c) * a.C + j) * a.vol;
+            // the product term's loop is bound by its scalar loop and address work:
+            // sixteen terms per step halve it; the soft term keeps eight (long rows
+            // would leave a long one-term remainder)
+            constexpr int kU = SOFT ? 8 : 16;
             if (g.ndim == 2) {
                 for (int r0 = split; r0 < g.box; r0 += kSplit) {
                     const float *hrow = sm + (vx + r0) * g.p1 + vy;
                     const float *krow = Kc + r0 * g.box;
-#pragma unroll 8
+#pragma unroll kU
                     for (int r1 = 0; r1 < g.box; ++r1) acc += krow[r1] * adj_term<SOFT>(ownk, hrow[r1], a.soft);
                 }
             } else {
@@ -342,7 +346,7 @@ __global__ __launch_bounds__(kT * adj_split<SOFT>()) void k_direct_adj(DirAdjArg
                     for (int r1 = 0; r1 < g.box; ++r1) {
                         const float *hrow = sm + ((vx + r0) * g.p1 + (vy + r1)) * g.h2 + vz;
                         const float *krow = Kc + (r0 * g.box + r1) * g.box;
-#pragma unroll 8
+#pragma unroll kU
                         for (int r2 = 0; r2 < g.box; ++r2) acc += krow[r2] * adj_term<SOFT>(ownk, hrow[r2], a.soft);
                     }
             }
